@@ -1,0 +1,307 @@
+/*
+ * kl.h -- C ABI of libkl, staggered-grid stencil kernels for AMD Instinct
+ * MI355X (gfx950).
+ *
+ * Problem statement (the paper's evaluation, Section "Application" and
+ * Section "Tunable Parameters"): two kernels of a finite-difference CFD code
+ * act on 3-D fields stored on a grid of configurable size, in float or
+ * double.  "advec_u" advances the x-velocity u by advection; "diff_uvw"
+ * advances u, v and w by diffusion.  The caller hands over the fields, the
+ * grid dimensions, the grid spacings, the viscosity and the precision; the
+ * library derives every launch parameter itself (Section "Code Example":
+ * block and grid dimensions are computed by the library, not passed by the
+ * user), uses a default configuration when a kernel was never tuned, and
+ * otherwise selects a tuned configuration from wisdom records (Section
+ * "Kernel Selection and Compilation").
+ *
+ * Discretisation fixed by this library (the paper names the kernels but
+ * prints no formulas): Arakawa-C staggering with one ghost cell per side;
+ * u at (xh_i, y_j, z_k), v at (x_i, yh_j, z_k), w at (x_i, y_j, zh_k);
+ * I(a,b) = (a+b)/2;
+ *   advec_u:  ut += -[ (I(u_i,u_{i+1})^2 - I(u_{i-1},u_i)^2) dxi
+ *                    + (I(v_{i-1,j+1},v_{i,j+1}) I(u_j,u_{j+1})
+ *                       - I(v_{i-1,j},v_{i,j}) I(u_{j-1},u_j)) dyi
+ *                    + (I(w_{i-1,k+1},w_{i,k+1}) I(u_k,u_{k+1})
+ *                       - I(w_{i-1,k},w_{i,k}) I(u_{k-1},u_k)) dzi[k] ]
+ *   diff_uvw: phi_t += visc [ (phi_{i+1} - 2 phi + phi_{i-1}) dxi^2
+ *                           + (phi_{j+1} - 2 phi + phi_{j-1}) dyi^2 + Z(phi) ]
+ *     with Z = ((phi_{k+1}-phi) dzhi[k+1] - (phi-phi_{k-1}) dzhi[k]) dzi[k]
+ *     for u and v, and Z = ((w_{k+1}-w) dzi[k] - (w-w_{k-1}) dzi[k-1]) dzhi[k]
+ *     for w.  u and v are advanced on k in [1, ktot]; w on k in [2, ktot]
+ *     with z walls and on [1, ktot] when z is periodic.
+ *
+ * Conventions shared by every entry point:
+ *  - Return value: KL_OK (0) or a negative kl_status_t.  The message of the
+ *    last failure on the calling thread is kl_last_error().  No C++
+ *    exception crosses this boundary.
+ *  - Memory: every field, metric and output pointer is DEVICE memory owned
+ *    by the caller, unless stated otherwise; the library never frees it.
+ *  - Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ *    stream).  Kernel entry points are asynchronous; their return code only
+ *    covers argument checks and launch errors, and a fault during execution
+ *    surfaces at the caller's next synchronisation.
+ *  - Tendency kernels ACCUMULATE (+=) into the interior cells of their
+ *    outputs and never write ghost or padding cells; they read ghost cells
+ *    of u, v, w, which the caller fills first (kl_fill_ghosts).
+ */
+#ifndef KL_H_
+#define KL_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { KL_F32 = 0, KL_F64 = 1 };
+
+/* Boundary conditions.  x and y are always periodic.
+ *  ZWALL_ZEROGRAD: u, v zero gradient at the z walls; w on the wall faces
+ *                  copies the neighbouring inner face (w_1 = w_2,
+ *                  w_{ktot+1} = w_ktot); the unused ghost w_0 = w_2.
+ *  ZWALL_NOPEN:    u, v as above; w = 0 on the wall faces, w_0 = -w_2.
+ *  ZPERIODIC:      periodic in z for all fields (uniform dz expected). */
+enum { KL_BC_ZWALL_ZEROGRAD = 0, KL_BC_ZWALL_NOPEN = 1, KL_BC_ZPERIODIC = 2 };
+
+typedef enum {
+    KL_OK = 0,
+    KL_ERR_INVALID = -1,  /* bad argument: sizes, strides, null pointers, enum values */
+    KL_ERR_DEVICE = -2,   /* HIP runtime error (launch, copy, synchronisation) */
+    KL_ERR_NOMEM = -3,    /* a library-side allocation failed */
+    KL_ERR_BUDGET = -4,   /* a request does not fit the server's memory budget */
+    KL_ERR_AGAIN = -5,    /* not finished yet (kl_poll) */
+    KL_ERR_NOTFOUND = -6, /* unknown ticket / variant / record */
+    KL_ERR_IO = -7        /* wisdom file could not be written */
+} kl_status_t;
+
+enum { KL_KERNEL_ADVEC_U = 0, KL_KERNEL_DIFF_UVW = 1 };
+
+/* One grid.  Element (i, j, k) of every field is at index
+ * off + i + j*jstride + k*kstride (elements of the field dtype), with
+ * i in [0, itot+1] (interior [1, itot]) and likewise for j and k.  The same
+ * layout holds for u, v, w and the tendencies ut, vt, wt.
+ * dzi[k] = 1/(zh_{k+1} - zh_k) and dzhi[k] = 1/(z_k - z_{k-1}) are device
+ * arrays of ktot+2 entries in the field dtype; dxi = 1/dx and dyi = 1/dy are
+ * rounded to the field dtype inside the kernels. */
+typedef struct kl_grid {
+    int32_t itot, jtot, ktot; /* interior points per axis, >= 1 (ktot >= 2 with z walls) */
+    int32_t gc;               /* ghost width, must be 1 */
+    int64_t off, jstride, kstride;
+    double dxi, dyi;
+    const void *dzi, *dzhi;
+    int32_t dtype;            /* KL_F32 or KL_F64 */
+    int32_t bc;               /* KL_BC_* */
+} kl_grid_t;
+
+/* Library version string (static storage). */
+const char *kl_version(void);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *kl_last_error(void);
+
+/* The library's preferred padded layout for a grid: x-contiguous rows padded
+ * to whole 128-byte lines with the first interior element of every row on a
+ * 128-byte boundary, so that 16-byte vector accesses are aligned and the two
+ * x-ghost cells of neighbouring rows share one line.  *alloc_elems is the
+ * element count to allocate per field (it includes tail padding).  Host
+ * pointers; no device work. */
+int kl_layout(int32_t itot, int32_t jtot, int32_t ktot, int32_t dtype,
+              int64_t *off, int64_t *jstride, int64_t *kstride, int64_t *alloc_elems);
+
+/* Fill the ghost cells of u, v and w from the interior by the boundary rules
+ * of g->bc (and, in wall modes, the wall faces w_1 and w_{ktot+1}).  Reads
+ * interior cells only, so all ghosts are filled in one pass. */
+int kl_fill_ghosts(const kl_grid_t *g, void *u, void *v, void *w, void *stream);
+
+/* ut += advec_u(u, v, w) on the interior (formula above).  u, v, w must be
+ * ghost-filled.  Runs the configuration selected for (dtype, itot, jtot,
+ * ktot, device) from the wisdom files, else the default configuration. */
+int kl_advec_u(const kl_grid_t *g, void *ut, const void *u, const void *v, const void *w,
+               void *stream);
+
+/* (ut, vt, wt) += visc * Laplacian(u, v, w) on each field's computed range
+ * (formula above).  u, v, w must be ghost-filled.  Selection as kl_advec_u. */
+int kl_diff_uvw(const kl_grid_t *g, void *ut, void *vt, void *wt,
+                const void *u, const void *v, const void *w, double visc, void *stream);
+
+/* Forward-Euler update f += dt * ft on each field's computed range, fused
+ * with the ghost refill of the updated fields (every ghost cell is written
+ * by the thread that updates its source cell). */
+int kl_euler(const kl_grid_t *g, double dt, void *u, void *v, void *w,
+             const void *ut, const void *vt, const void *wt, void *stream);
+
+/* One time step: tendencies := 0, ut += advec_u, (ut,vt,wt) += diff_uvw,
+ * Euler update with ghost refill.  u, v, w must be ghost-filled on entry and
+ * are ghost-filled on return; ut, vt, wt are overwritten (interior only). */
+int kl_step(const kl_grid_t *g, double visc, double dt, void *u, void *v, void *w,
+            void *ut, void *vt, void *wt, void *stream);
+
+/* FP64 reductions over the interior, accumulated in double for either field
+ * dtype, in a fixed-shape two-pass tree (bitwise reproducible).
+ *  what = 0 (conservation): f0, f1, f2 = ut, vt, wt; out[0] = sum ut*dz_k,
+ *         out[1] = sum vt*dz_k, out[2] = sum wt*dzh_k over w's computed
+ *         faces, with dz_k = 1/dzi[k] and dzh_k = 1/dzhi[k] in double.
+ *  what = 1 (checksums): for each of f0, f1, f2 (NULL skips a field):
+ *         out[3n] = sum f, out[3n+1] = sum f^2, out[3n+2] = max |f|.
+ * `out` is a device array of 3 (what=0) or 9 (what=1) doubles, written
+ * asynchronously on `stream`.  Uses a library-owned device workspace. */
+int kl_reduce_fp64(const kl_grid_t *g, int32_t what, const void *f0, const void *f1,
+                   const void *f2, double *out, void *stream);
+
+/* Fill the interiors of u, v, w with the library's seeded initial state:
+ * U[-1,1) noise plus the mean flow (1, 0.5, 0).  The noise value of
+ * interior point (i, j, k) of field f (0 u, 1 v, 2 w) comes from the
+ * counter-based SplitMix64 generator (Steele, Lea and Flood, OOPSLA 2014):
+ * counter = ((seed*8 + f) << 40) + (i-1) + itot*((j-1) + jtot*(k-1)), one
+ * generator step from state `counter` gives z, r = (z >> 11) * 2^-53 and
+ * the value is (2r - 1) + mean_f in double, rounded to the field dtype.
+ * Ghost cells are not touched (call kl_fill_ghosts next). */
+int kl_generate_fields(const kl_grid_t *g, uint64_t seed, void *u, void *v, void *w, void *stream);
+
+/* Order-independent 64-bit hash of the bit patterns of one field's interior
+ * (sum over cells of a SplitMix64 mix of the value's bits and its (i,j,k));
+ * equal hashes of two fields mean bitwise-equal interiors with overwhelming
+ * probability.  `out` is one device uint64. */
+int kl_hash_interior(const kl_grid_t *g, const void *f, uint64_t *out, void *stream);
+
+/* ---- configurations (the AOT variant registry) --------------------------- */
+
+/* Number of compiled configurations of `kernel` (KL_KERNEL_*) for `dtype`;
+ * index 0 is always the default configuration (one thread per point, blocks
+ * of 256 threads along x, no tiling; the paper's default configuration,
+ * Section "Tunable Parameters"). */
+int kl_num_variants(int32_t kernel, int32_t dtype);
+
+/* Name of configuration `index` into buf (NUL-terminated, truncated to len). */
+int kl_variant_name(int32_t kernel, int32_t dtype, int32_t index, char *buf, size_t len);
+
+/* 1 if configuration `index` can run on this grid and these pointers
+ * (vector width divides itot and the layout/pointer alignment), else 0. */
+int kl_variant_eligible(const kl_grid_t *g, int32_t kernel, int32_t index,
+                        const void *const fields[6]);
+
+/* Launch configuration `index` of `kernel` directly.  fields = {u, v, w, ut,
+ * vt, wt}; advec_u uses u, v, w, ut.  Same semantics as kl_advec_u /
+ * kl_diff_uvw.  KL_ERR_INVALID if the configuration is not eligible. */
+int kl_launch_variant(const kl_grid_t *g, int32_t kernel, int32_t index,
+                      void *const fields[6], double visc, void *stream);
+
+/* Index of the configuration kl_advec_u / kl_diff_uvw would run for this
+ * grid on the current device (consults the wisdom files on first use per
+ * problem size and caches the choice). */
+int kl_selected_variant(const kl_grid_t *g, int32_t kernel);
+
+/* ---- tuning and wisdom (Sections "Kernel Tuning", "Wisdom Files",
+ *      "Kernel Selection and Compilation") --------------------------------- */
+
+/* Directory of the wisdom files (one JSON-lines file per kernel:
+ * <dir>/advec_u.wisdom and <dir>/diff_uvw.wisdom).  NULL or "" restores the
+ * default: $KL_WISDOM_DIR, else "./wisdom".  Clears the selection cache. */
+int kl_set_wisdom_dir(const char *dir);
+
+/* Forget all cached selections (the next launch per problem size re-reads
+ * the wisdom files). */
+int kl_clear_plan_cache(void);
+
+/* Host-only (no GPU work): run the selection heuristic over the wisdom file
+ * of `kernel` in `wisdom_dir` (NULL = current wisdom directory) for a given
+ * device name, architecture (e.g. "gfx950"), dtype and problem size.
+ * *level receives 1 (this GPU, this size), 2 (this GPU, closest size by
+ * Euclidean distance), 3 (this architecture, closest size), 4 (any record,
+ * closest size) or 5 (no usable record: the default configuration);
+ * `variant` receives the configuration name ("default" at level 5).  Lines
+ * that do not parse, other dtypes and unknown configuration names are
+ * skipped; among equally close records the later one in the file wins. */
+int kl_wisdom_lookup(const char *wisdom_dir, int32_t kernel, int32_t dtype, const char *device_name,
+                     const char *arch, int32_t itot, int32_t jtot, int32_t ktot, char *variant,
+                     size_t len, int32_t *level);
+
+/* Tune the kernels in kernel_mask (bit 0 advec_u, bit 1 diff_uvw) for this
+ * grid on the current device: every eligible configuration is checked for
+ * bitwise-equal output against the default configuration, then timed (hip
+ * events, median of repetitions after warm-up) until budget_s seconds are
+ * spent (the default configuration is always measured).  The fastest one is
+ * appended as a record (kernel, dtype, problem size, device, architecture,
+ * configuration, time, provenance) to the kernel's wisdom file in
+ * wisdom_dir (NULL = current wisdom directory), and the selection cache is
+ * cleared.  fields = {u, v, w, ut, vt, wt}: u, v, w must be ghost-filled;
+ * ut, vt, wt are clobbered.  Synchronous (returns after the file is written).
+ * If timings_out is not NULL it receives up to max_timings entries of
+ * (configuration index, median ms) for kernel_mask's lowest kernel, or -1 ms
+ * for a configuration that failed the bitwise check; *n_timings = count. */
+int kl_tune(const kl_grid_t *g, void *const fields[6], uint32_t kernel_mask,
+            const char *wisdom_dir, double budget_s, void *stream,
+            double *timings_out, int32_t max_timings, int32_t *n_timings);
+
+/* ---- batched form: many independent grids in one captured graph ---------- */
+
+/* Build a batch of n grids (fields[6*g + f] = {u, v, w, ut, vt, wt} of grid
+ * g, device pointers owned by the caller) and capture, on `stream`, one HIP
+ * graph that runs, for all grids: tendencies := 0 (when zero_tendencies),
+ * ut += advec_u, (ut,vt,wt) += diff_uvw, as persistent tile-walking kernels
+ * (one per configuration group, configurations taken from the wisdom files)
+ * that each walk a static, deterministic tile list.  The grid descriptors
+ * are copied; the library owns the tile tables and the graph. */
+int kl_batch_create(const kl_grid_t *grids, void *const *fields, int32_t n, double visc,
+                    int32_t zero_tendencies, void *stream, void **batch);
+
+/* Replay the batch's graph on `stream` (asynchronous). */
+int kl_batch_run(void *batch, void *stream);
+
+/* Number of persistent kernels and tiles of a batch (host ints). */
+int kl_batch_info(void *batch, int32_t *n_kernels, int64_t *n_tiles);
+
+int kl_batch_destroy(void *batch);
+
+/* ---- served form: continuous batching of stencil-step requests ----------- */
+
+typedef struct kl_request {
+    int32_t itot, jtot, ktot;
+    int32_t dtype, bc;
+    int32_t nsteps;      /* time steps to advance, >= 1 */
+    double dt, visc;
+    uint64_t seed;       /* initial u, v, w = U[-1,1) noise + mean flow (1, 0.5, 0) */
+} kl_request_t;
+
+typedef struct kl_result {
+    int32_t state;       /* 0 queued, 1 running, 2 done, 3 failed */
+    int32_t err;         /* kl_status_t of a failed request */
+    int64_t t_arrive_ns, t_admit_ns, t_done_ns; /* CLOCK_MONOTONIC */
+    double checksum[9];  /* kl_reduce_fp64(what=1) of the final u, v, w */
+    void *fields[3];     /* device u, v, w (library arena), valid until kl_release */
+    int64_t off, jstride, kstride; /* layout of fields */
+} kl_result_t;
+
+/* Create a server that owns a background thread and one stream of its own.
+ * arena/arena_bytes: caller-owned device memory the server sub-allocates
+ * all request fields from; budget_bytes (<= arena_bytes) caps the bytes held
+ * by admitted requests.  Requests are admitted in arrival order while they
+ * fit; every tick advances all admitted requests by one step in one batched
+ * launch, so requests join and leave between ticks. */
+int kl_server_create(void *arena, size_t arena_bytes, size_t budget_bytes, void **srv);
+
+/* Enqueue a request; *ticket identifies it.  KL_ERR_BUDGET if the request's
+ * footprint alone exceeds the budget, KL_ERR_INVALID for bad sizes. */
+int kl_submit(void *srv, const kl_request_t *req, uint64_t *ticket);
+
+/* Status of a request into *out (host struct).  KL_OK once done (or failed:
+ * see out->state), KL_ERR_AGAIN while queued or running, KL_ERR_NOTFOUND
+ * for an unknown or released ticket. */
+int kl_poll(void *srv, uint64_t ticket, kl_result_t *out);
+
+/* Free a finished request's fields back to the arena. */
+int kl_release(void *srv, uint64_t ticket);
+
+/* Server counters: out[0] ticks, out[1] launches, out[2] requests done,
+ * out[3] peak bytes in use, out[4] points*steps advanced. */
+int kl_server_stats(void *srv, int64_t out[5]);
+
+/* Stop the thread after the queue drains and free the server. */
+int kl_server_destroy(void *srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KL_H_ */

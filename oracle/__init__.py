@@ -67,6 +67,8 @@ def _declare(lib):
     lib.ora_conservation.argtypes = dims + [_I, _P, _P, _P, _P, _P, _P]
     lib.ora_checksums.argtypes = dims + [_P, _P]
     lib.ora_point.argtypes = dims + [_I, _D, _D, _P, _P, _D, _P, _P, _P, _I, _I, _I, _P]
+    lib.ora_threads.argtypes = []
+    lib.ora_threads.restype = ctypes.c_int
     for f in ("ora_fill_ghosts", "ora_advec_u", "ora_diff_uvw", "ora_euler", "ora_step",
               "ora_conservation", "ora_checksums", "ora_point"):
         getattr(lib, f).restype = None

@@ -312,3 +312,11 @@ void ora_point(int itot, int jtot, int ktot, int64_t off, int64_t js, int64_t ks
     out[2] = diff_c_at(&g, v, dxi2, dyi2, dzi, dzhi, visc, i, j, k);
     out[3] = (k >= kw0) ? diff_w_at(&g, w, dxi2, dyi2, dzi, dzhi, visc, i, j, k) : 0.0;
 }
+
+/* Number of OpenMP threads the parallel loops above use. */
+#ifdef _OPENMP
+#include <omp.h>
+int ora_threads(void) { return omp_get_max_threads(); }
+#else
+int ora_threads(void) { return 1; }
+#endif

@@ -1,0 +1,445 @@
+// Auxiliary kernels: ghost fill, fused Euler update + ghost refill, interior
+// zeroing, FP64 reductions, bit hash and the device-side field generator.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kl_internal.hpp"
+
+namespace kl {
+namespace {
+
+struct Dims {
+    int itot, jtot, ktot, bc;
+    int64_t off, js, ks;
+};
+
+inline Dims dims_of(const HostArgs &a) { return Dims{a.itot, a.jtot, a.ktot, a.bc, a.off, a.js, a.ks}; }
+
+__device__ __forceinline__ int64_t at(const Dims &d, int i, int j, int k)
+{
+    return d.off + i + (int64_t)j * d.js + (int64_t)k * d.ks;
+}
+
+__device__ __forceinline__ int wrap_i(const Dims &d, int i) { return i == 0 ? d.itot : (i == d.itot + 1 ? 1 : i); }
+__device__ __forceinline__ int wrap_j(const Dims &d, int j) { return j == 0 ? d.jtot : (j == d.jtot + 1 ? 1 : j); }
+
+// Source level and factor of level k of field f (0 u, 1 v, 2 w) under the
+// boundary rule; factor 0 means the cell is set to zero.
+__device__ __forceinline__ int src_k(const Dims &d, int f, int k, int &sign)
+{
+    sign = 1;
+    const int kt = d.ktot;
+    if (d.bc == KL_BC_ZPERIODIC) return k == 0 ? kt : (k == kt + 1 ? 1 : k);
+    if (f < 2) return k == 0 ? 1 : (k == kt + 1 ? kt : k);
+    if (d.bc == KL_BC_ZWALL_ZEROGRAD) return (k == 0 || k == 1) ? 2 : (k == kt + 1 ? kt : k);
+    // no penetration
+    if (k == 1 || k == kt + 1) {
+        sign = 0;
+        return 2;
+    }
+    if (k == 0) {
+        sign = -1;
+        return 2;
+    }
+    return k;
+}
+
+// One thread per ghost cell (region R0: planes k = 0 and ktot+1; R1: rows
+// j = 0, jtot+1 of levels 1..ktot; R2: columns i = 0, itot+1 of interior
+// rows; R3: the interior of plane k = 1, for w in wall modes).  Every
+// source cell is an interior cell that no thread writes, so the cells can
+// be filled in any order.
+template <typename T>
+__global__ __launch_bounds__(256) void fill_ghosts_kernel(Dims d, T *u, T *v, T *w, int64_t n0,
+                                                         int64_t n1, int64_t n2, int64_t n3)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int ic = d.itot + 2, jc = d.jtot + 2;
+    int i, j, k;
+    bool w_only = false;
+    if (t < n0) {
+        const int64_t p = t % ((int64_t)ic * jc);
+        k = t < (int64_t)ic * jc ? 0 : d.ktot + 1;
+        j = (int)(p / ic);
+        i = (int)(p % ic);
+    } else if (t < n0 + n1) {
+        const int64_t q = t - n0;
+        const int64_t p = q % ((int64_t)ic * d.ktot);
+        j = q < (int64_t)ic * d.ktot ? 0 : d.jtot + 1;
+        k = 1 + (int)(p / ic);
+        i = (int)(p % ic);
+    } else if (t < n0 + n1 + n2) {
+        const int64_t q = t - n0 - n1;
+        const int64_t p = q % ((int64_t)d.jtot * d.ktot);
+        i = q < (int64_t)d.jtot * d.ktot ? 0 : d.itot + 1;
+        k = 1 + (int)(p / d.jtot);
+        j = 1 + (int)(p % d.jtot);
+    } else if (t < n0 + n1 + n2 + n3) {
+        const int64_t q = t - n0 - n1 - n2;
+        k = 1;
+        j = 1 + (int)(q / d.itot);
+        i = 1 + (int)(q % d.itot);
+        w_only = true;
+    } else {
+        return;
+    }
+    const int si = wrap_i(d, i), sj = wrap_j(d, j);
+    const int64_t dst = at(d, i, j, k);
+    T *f3[3] = {u, v, w};
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        if (w_only && f < 2) continue;
+        int sign;
+        const int sk = src_k(d, f, k, sign);
+        T *p = f3[f];
+        p[dst] = sign == 0 ? T(0) : (sign < 0 ? -p[at(d, si, sj, sk)] : p[at(d, si, sj, sk)]);
+    }
+}
+
+// Forward Euler on the computed range, each thread writing its updated cell
+// and every ghost cell whose source it is (the inverse of the fill map).
+template <typename T>
+__global__ __launch_bounds__(256) void euler_kernel(Dims d, T dt, int kw0, T *u, T *v, T *w,
+                                                   const T *ut, const T *vt, const T *wt, int nbx)
+{
+    unsigned b = blockIdx.x;
+    const int bx = b % nbx;
+    b /= nbx;
+    const int j = 1 + (int)(b % d.jtot);
+    const int k = 1 + (int)(b / d.jtot);
+    const int i = 1 + bx * 256 + (int)threadIdx.x;
+    if (i > d.itot) return;
+    const int64_t c = at(d, i, j, k);
+    // x and y images of (i, j)
+    int xi[3], yj[3], nx = 1, ny = 1;
+    xi[0] = i;
+    yj[0] = j;
+    if (i == d.itot) xi[nx++] = 0;
+    if (i == 1) xi[nx++] = d.itot + 1;
+    if (j == d.jtot) yj[ny++] = 0;
+    if (j == 1) yj[ny++] = d.jtot + 1;
+    T *f3[3] = {u, v, w};
+    const T *t3[3] = {ut, vt, wt};
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        if (f == 2 && k < kw0) continue;
+        T *p = f3[f];
+        const T val = p[c] + dt * t3[f][c];
+        // z images with their factors
+        int zk[4], zs[4], nz = 1;
+        zk[0] = k;
+        zs[0] = 1;
+        const int kt = d.ktot;
+        if (d.bc == KL_BC_ZPERIODIC) {
+            if (k == kt) { zk[nz] = 0; zs[nz++] = 1; }
+            if (k == 1) { zk[nz] = kt + 1; zs[nz++] = 1; }
+        } else if (f < 2) {
+            if (k == 1) { zk[nz] = 0; zs[nz++] = 1; }
+            if (k == kt) { zk[nz] = kt + 1; zs[nz++] = 1; }
+        } else if (d.bc == KL_BC_ZWALL_ZEROGRAD) {
+            if (k == 2) { zk[nz] = 0; zs[nz++] = 1; zk[nz] = 1; zs[nz++] = 1; }
+            if (k == kt) { zk[nz] = kt + 1; zs[nz++] = 1; }
+        } else {
+            if (k == 2) { zk[nz] = 0; zs[nz++] = -1; zk[nz] = 1; zs[nz++] = 0; }
+            if (k == kt) { zk[nz] = kt + 1; zs[nz++] = 0; }
+        }
+        for (int a = 0; a < nz; ++a) {
+            const T zv = zs[a] == 0 ? T(0) : (zs[a] < 0 ? -val : val);
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) p[at(d, xi[x], yj[y], zk[a])] = zv;
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void zero_interior_kernel(Dims d, T *f, int nbx)
+{
+    unsigned b = blockIdx.x;
+    const int bx = b % nbx;
+    b /= nbx;
+    const int j = 1 + (int)(b % d.jtot);
+    const int k = 1 + (int)(b / d.jtot);
+    const int i = 1 + bx * 256 + (int)threadIdx.x;
+    if (i > d.itot) return;
+    f[at(d, i, j, k)] = T(0);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 reductions: pass 1 gives each of RB blocks a fixed set of rows
+// (row r = (j, k) pairs, rows b, b + RB, ...), each thread a fixed set of
+// columns; block partials are combined by a fixed LDS tree.  Pass 2 reduces
+// the RB partials in one block the same way.  No atomics, so the result is
+// bitwise reproducible.
+// ---------------------------------------------------------------------------
+constexpr int RB = 1024;   // pass-1 blocks
+constexpr int RT = 256;    // threads per block
+constexpr int RQ = 9;      // values per partial
+
+__device__ __forceinline__ double comb(int q_is_max, double a, double b)
+{
+    return q_is_max ? fmax(a, b) : a + b;
+}
+
+template <int NQ>
+__device__ void block_tree(double (&acc)[NQ], const int (&is_max)[NQ], double *out)
+{
+    __shared__ double sh[RT][NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) sh[threadIdx.x][q] = acc[q];
+    __syncthreads();
+    for (int s = RT / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q)
+                sh[threadIdx.x][q] = comb(is_max[q], sh[threadIdx.x][q], sh[threadIdx.x + s][q]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) out[q] = sh[0][q];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(RT) void reduce_pass1(Dims d, int what, int kw0, const T *f0, const T *f1,
+                                                  const T *f2, const T *dzi, const T *dzhi,
+                                                  double *partial)
+{
+    double acc[RQ];
+    int is_max[RQ];
+#pragma unroll
+    for (int q = 0; q < RQ; ++q) {
+        acc[q] = 0.0;
+        is_max[q] = (what == 1 && q % 3 == 2);
+    }
+    const int64_t nrows = (int64_t)d.jtot * d.ktot;
+    const T *f3[3] = {f0, f1, f2};
+    for (int64_t r = blockIdx.x; r < nrows; r += RB) {
+        const int j = 1 + (int)(r % d.jtot);
+        const int k = 1 + (int)(r / d.jtot);
+        const int64_t base = at(d, 0, j, k);
+        if (what == 0) {
+            const double wz = 1.0 / (double)dzi[k];
+            const double wzh = 1.0 / (double)dzhi[k];
+            for (int i = 1 + (int)threadIdx.x; i <= d.itot; i += RT) {
+                acc[0] += (double)f0[base + i] * wz;
+                acc[1] += (double)f1[base + i] * wz;
+                if (k >= kw0) acc[2] += (double)f2[base + i] * wzh;
+            }
+        } else {
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                if (f3[f] == nullptr) continue;
+                for (int i = 1 + (int)threadIdx.x; i <= d.itot; i += RT) {
+                    const double x = (double)f3[f][base + i];
+                    acc[3 * f] += x;
+                    acc[3 * f + 1] += x * x;
+                    acc[3 * f + 2] = fmax(acc[3 * f + 2], fabs(x));
+                }
+            }
+        }
+    }
+    block_tree<RQ>(acc, is_max, partial + (int64_t)blockIdx.x * RQ);
+}
+
+__global__ __launch_bounds__(RT) void reduce_pass2(int what, const double *partial, double *out)
+{
+    double acc[RQ];
+    int is_max[RQ];
+#pragma unroll
+    for (int q = 0; q < RQ; ++q) {
+        acc[q] = 0.0;
+        is_max[q] = (what == 1 && q % 3 == 2);
+    }
+    for (int b = threadIdx.x; b < RB; b += RT)
+#pragma unroll
+        for (int q = 0; q < RQ; ++q) acc[q] = comb(is_max[q], acc[q], partial[(int64_t)b * RQ + q]);
+    __shared__ double res[RQ];
+    block_tree<RQ>(acc, is_max, res);
+    __syncthreads();
+    const int nout = what == 0 ? 3 : 9;
+    if ((int)threadIdx.x < nout) out[threadIdx.x] = res[threadIdx.x];
+}
+
+// Bit hash: sum over interior cells (mod 2^64) of SplitMix64(bits ^ cell key).
+__device__ __forceinline__ uint64_t mix64(uint64_t z)
+{
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+template <typename T>
+__device__ __forceinline__ uint64_t bits_of(T x)
+{
+    if constexpr (sizeof(T) == 8) {
+        return (uint64_t)__double_as_longlong(x);
+    } else {
+        return (uint64_t)(uint32_t)__float_as_uint(x);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(RT) void hash_pass1(Dims d, const T *f, uint64_t *partial)
+{
+    uint64_t acc = 0;
+    const int64_t nrows = (int64_t)d.jtot * d.ktot;
+    for (int64_t r = blockIdx.x; r < nrows; r += RB) {
+        const int j = 1 + (int)(r % d.jtot);
+        const int k = 1 + (int)(r / d.jtot);
+        const int64_t base = at(d, 0, j, k);
+        for (int i = 1 + (int)threadIdx.x; i <= d.itot; i += RT) {
+            const uint64_t key = (uint64_t)i + ((uint64_t)j << 21) + ((uint64_t)k << 42);
+            acc += mix64(bits_of<T>(f[base + i]) ^ mix64(key));
+        }
+    }
+    __shared__ uint64_t sh[RT];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = RT / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(RT) void hash_pass2(const uint64_t *partial, uint64_t *out)
+{
+    uint64_t acc = 0;
+    for (int b = threadIdx.x; b < RB; b += RT) acc += partial[b];
+    __shared__ uint64_t sh[RT];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = RT / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0];
+}
+
+// Device generator of the served initial state: U[-1,1) noise from the
+// counter-based SplitMix64 recipe plus the mean flow (1, 0.5, 0), rounded to
+// the field type.  Counter of interior point (i-1, j-1, k-1) of field f:
+// ((seed*8 + f) << 40) + (i-1) + itot*((j-1) + jtot*(k-1)).
+template <typename T>
+__global__ __launch_bounds__(256) void gen_uniform_kernel(Dims d, uint64_t seed, T *u, T *v, T *w, int nbx)
+{
+    unsigned b = blockIdx.x;
+    const int bx = b % nbx;
+    b /= nbx;
+    const int j = 1 + (int)(b % d.jtot);
+    const int k = 1 + (int)(b / d.jtot);
+    const int i = 1 + bx * 256 + (int)threadIdx.x;
+    if (i > d.itot) return;
+    const int64_t c = at(d, i, j, k);
+    const uint64_t cnt = (uint64_t)(i - 1) + (uint64_t)d.itot * ((uint64_t)(j - 1) + (uint64_t)d.jtot * (uint64_t)(k - 1));
+    const double mean[3] = {1.0, 0.5, 0.0};
+    T *f3[3] = {u, v, w};
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        const uint64_t key = ((seed * 8u + (uint64_t)f) << 40) + cnt;
+        const double r = (double)(mix64(key) >> 11) * 0x1.0p-53;
+        f3[f][c] = (T)((2.0 * r - 1.0) + mean[f]);
+    }
+}
+
+inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+}  // namespace
+
+size_t reduce_scratch_bytes() { return (size_t)RB * RQ * sizeof(double); }
+
+hipError_t launch_fill_ghosts(const HostArgs &a, void *u, void *v, void *w, hipStream_t s)
+{
+    const Dims d = dims_of(a);
+    const int64_t ic = a.itot + 2, jc = a.jtot + 2;
+    const int64_t n0 = 2 * ic * jc, n1 = 2 * ic * a.ktot, n2 = 2 * (int64_t)a.jtot * a.ktot;
+    const int64_t n3 = a.bc == KL_BC_ZPERIODIC ? 0 : (int64_t)a.itot * a.jtot;
+    const unsigned nb = cdiv(n0 + n1 + n2 + n3, 256);
+    if (a.dtype == KL_F32)
+        hipLaunchKernelGGL(fill_ghosts_kernel<float>, dim3(nb), dim3(256), 0, s, d, (float *)u, (float *)v,
+                           (float *)w, n0, n1, n2, n3);
+    else
+        hipLaunchKernelGGL(fill_ghosts_kernel<double>, dim3(nb), dim3(256), 0, s, d, (double *)u,
+                           (double *)v, (double *)w, n0, n1, n2, n3);
+    return hipGetLastError();
+}
+
+hipError_t launch_euler(const HostArgs &a, double dt, void *u, void *v, void *w, hipStream_t s)
+{
+    const Dims d = dims_of(a);
+    const int nbx = (int)cdiv(a.itot, 256);
+    const unsigned nb = (unsigned)nbx * a.jtot * a.ktot;
+    if (a.dtype == KL_F32)
+        hipLaunchKernelGGL(euler_kernel<float>, dim3(nb), dim3(256), 0, s, d, (float)dt, a.kw0, (float *)u,
+                           (float *)v, (float *)w, (const float *)a.ut, (const float *)a.vt,
+                           (const float *)a.wt, nbx);
+    else
+        hipLaunchKernelGGL(euler_kernel<double>, dim3(nb), dim3(256), 0, s, d, dt, a.kw0, (double *)u,
+                           (double *)v, (double *)w, (const double *)a.ut, (const double *)a.vt,
+                           (const double *)a.wt, nbx);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_interior(const HostArgs &a, void *f, hipStream_t s)
+{
+    const Dims d = dims_of(a);
+    const int nbx = (int)cdiv(a.itot, 256);
+    const unsigned nb = (unsigned)nbx * a.jtot * a.ktot;
+    if (a.dtype == KL_F32)
+        hipLaunchKernelGGL(zero_interior_kernel<float>, dim3(nb), dim3(256), 0, s, d, (float *)f, nbx);
+    else
+        hipLaunchKernelGGL(zero_interior_kernel<double>, dim3(nb), dim3(256), 0, s, d, (double *)f, nbx);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const HostArgs &a, int what, const void *f0, const void *f1, const void *f2,
+                         double *out, void *scratch, hipStream_t s)
+{
+    const Dims d = dims_of(a);
+    double *partial = (double *)scratch;
+    if (a.dtype == KL_F32)
+        hipLaunchKernelGGL(reduce_pass1<float>, dim3(RB), dim3(RT), 0, s, d, what, a.kw0, (const float *)f0,
+                           (const float *)f1, (const float *)f2, (const float *)a.dzi,
+                           (const float *)a.dzhi, partial);
+    else
+        hipLaunchKernelGGL(reduce_pass1<double>, dim3(RB), dim3(RT), 0, s, d, what, a.kw0,
+                           (const double *)f0, (const double *)f1, (const double *)f2,
+                           (const double *)a.dzi, (const double *)a.dzhi, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reduce_pass2, dim3(1), dim3(RT), 0, s, what, (const double *)partial, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_hash(const HostArgs &a, const void *f, uint64_t *out, void *scratch, hipStream_t s)
+{
+    const Dims d = dims_of(a);
+    uint64_t *partial = (uint64_t *)scratch;
+    if (a.dtype == KL_F32)
+        hipLaunchKernelGGL(hash_pass1<float>, dim3(RB), dim3(RT), 0, s, d, (const float *)f, partial);
+    else
+        hipLaunchKernelGGL(hash_pass1<double>, dim3(RB), dim3(RT), 0, s, d, (const double *)f, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(hash_pass2, dim3(1), dim3(RT), 0, s, (const uint64_t *)partial, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gen_uniform(const HostArgs &a, uint64_t seed, void *u, void *v, void *w, hipStream_t s)
+{
+    const Dims d = dims_of(a);
+    const int nbx = (int)cdiv(a.itot, 256);
+    const unsigned nb = (unsigned)nbx * a.jtot * a.ktot;
+    if (a.dtype == KL_F32)
+        hipLaunchKernelGGL(gen_uniform_kernel<float>, dim3(nb), dim3(256), 0, s, d, seed, (float *)u,
+                           (float *)v, (float *)w, nbx);
+    else
+        hipLaunchKernelGGL(gen_uniform_kernel<double>, dim3(nb), dim3(256), 0, s, d, seed, (double *)u,
+                           (double *)v, (double *)w, nbx);
+    return hipGetLastError();
+}
+
+}  // namespace kl

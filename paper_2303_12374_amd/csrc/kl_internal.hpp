@@ -1,0 +1,86 @@
+// Internal host-side declarations of libkl (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "kl.h"
+
+namespace kl {
+
+// dtype-agnostic launch arguments; launchers convert metrics to the field type.
+struct HostArgs {
+    int itot, jtot, ktot, kw0, dtype, bc;
+    int64_t off, js, ks;
+    double dxi, dyi, visc;
+    const void *dzi, *dzhi;
+    void *ut, *vt, *wt;
+    const void *u, *v, *w;
+};
+
+typedef hipError_t (*LaunchFn)(const HostArgs &, hipStream_t);
+
+enum { FAMILY_PLAIN = 0, FAMILY_ZC = 1, FAMILY_ZL = 2 };
+
+// One ahead-of-time compiled configuration of a tendency kernel.
+struct Variant {
+    const char *name;
+    int kernel, dtype, family;
+    int vx, bx, by, kb, xcd;  // x vector width, block shape, z-march length, XCD order
+    LaunchFn launch;
+};
+
+// Registry (index 0 of every list is the default configuration).
+const std::vector<Variant> &variants(int kernel, int dtype);
+const std::vector<Variant> &variants_f32(int kernel);
+const std::vector<Variant> &variants_f64(int kernel);
+
+// Errors: record a message for kl_last_error() and return `code`.
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int hip_fail(hipError_t e, const char *what);
+void clear_error();
+
+// Validation shared by the entry points.
+int check_grid(const kl_grid_t *g);
+HostArgs make_args(const kl_grid_t *g);
+bool variant_eligible(const Variant &v, const kl_grid_t *g, const void *const *ptrs, int nptr);
+
+// Library-owned per-device workspace (for reduction partials).
+void *workspace(size_t bytes, hipStream_t s);
+
+// Auxiliary kernels (aux.hip).
+hipError_t launch_fill_ghosts(const HostArgs &a, void *u, void *v, void *w, hipStream_t s);
+hipError_t launch_euler(const HostArgs &a, double dt, void *u, void *v, void *w, hipStream_t s);
+hipError_t launch_zero_interior(const HostArgs &a, void *f, hipStream_t s);
+hipError_t launch_reduce(const HostArgs &a, int what, const void *f0, const void *f1,
+                         const void *f2, double *out, void *scratch, hipStream_t s);
+hipError_t launch_hash(const HostArgs &a, const void *f, uint64_t *out, void *scratch,
+                       hipStream_t s);
+hipError_t launch_gen_uniform(const HostArgs &a, uint64_t seed, void *u, void *v, void *w,
+                              hipStream_t s);
+size_t reduce_scratch_bytes();
+
+// Wisdom (wisdom.cpp).
+struct DeviceIdent {
+    std::string name, arch;
+    int cu_count;
+};
+int current_device_ident(DeviceIdent *out);
+std::string wisdom_dir();
+std::string wisdom_path(const std::string &dir, int kernel);
+const char *kernel_name(int kernel);
+int wisdom_select(const std::string &dir, int kernel, int dtype, const DeviceIdent &dev,
+                  int itot, int jtot, int ktot, std::string *variant, int *level);
+int wisdom_append(const std::string &dir, int kernel, const std::string &json_line);
+std::string provenance_json(const DeviceIdent &dev);
+
+// Plan cache (api.cpp).
+int select_variant(const kl_grid_t *g, int kernel);
+int run_variant(const kl_grid_t *g, int kernel, int index, void *const fields[6], double visc,
+                hipStream_t s);
+void clear_plans();
+
+}  // namespace kl

@@ -1,0 +1,167 @@
+// kl_tune: measure every eligible configuration of a kernel on one grid and
+// append the fastest to the kernel's wisdom file (Section "Kernel Tuning":
+// the paper drives Kernel Tuner over captured launches for a bounded time;
+// here the configuration space is the small set of ahead-of-time compiled
+// gfx950 configurations, so it is searched exhaustively within the budget).
+#include <hip/hip_runtime.h>
+#include <stdio.h>
+
+#include <algorithm>
+#include <chrono>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "kl_internal.hpp"
+
+using namespace kl;
+
+namespace {
+
+struct Guard {
+    std::vector<hipEvent_t> ev;
+    uint64_t *dhash = nullptr;
+    ~Guard()
+    {
+        for (auto e : ev) (void)hipEventDestroy(e);
+        if (dhash) (void)hipFree(dhash);
+    }
+};
+
+int zero_tendencies(const kl_grid_t *g, void *const f[6], hipStream_t s)
+{
+    const HostArgs a = make_args(g);
+    for (int n = 3; n < 6; ++n) {
+        const hipError_t e = launch_zero_interior(a, f[n], s);
+        if (e != hipSuccess) return hip_fail(e, "zero tendencies");
+    }
+    return KL_OK;
+}
+
+// Hashes of the outputs of `kernel` (ut; or ut, vt, wt) into host h[3].
+int output_hashes(const kl_grid_t *g, int kernel, void *const f[6], uint64_t *dhash, uint64_t h[3], hipStream_t s)
+{
+    void *ws = workspace(reduce_scratch_bytes(), s);
+    if (!ws) return fail(KL_ERR_NOMEM, "tune workspace");
+    const HostArgs a = make_args(g);
+    const int nout = kernel == KL_KERNEL_ADVEC_U ? 1 : 3;
+    for (int n = 0; n < nout; ++n) {
+        hipError_t e = launch_hash(a, f[3 + n], dhash + n, ws, s);
+        if (e != hipSuccess) return hip_fail(e, "hash");
+    }
+    hipError_t e = hipMemcpyAsync(h, dhash, sizeof(uint64_t) * nout, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hash copy");
+    for (int n = nout; n < 3; ++n) h[n] = 0;
+    return KL_OK;
+}
+
+double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+int tune_one(const kl_grid_t *g, int kernel, void *const f[6], const std::string &dir, double budget_s,
+             hipStream_t s, double *timings_out, int max_timings, int *n_timings)
+{
+    Guard gd;
+    hipError_t e = hipMalloc(&gd.dhash, 3 * sizeof(uint64_t));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+    const auto &vs = variants(kernel, g->dtype);
+    const void *ptrs[6] = {f[0], f[1], f[2], f[3], f[4], f[5]};
+    const int nptr = kernel == KL_KERNEL_ADVEC_U ? 4 : 6;
+    const double visc = 1e-5;
+    int rc;
+
+    // reference output of the default configuration
+    uint64_t ref[3];
+    if ((rc = zero_tendencies(g, f, s))) return rc;
+    if ((rc = run_variant(g, kernel, 0, f, visc, s))) return rc;
+    if ((rc = output_hashes(g, kernel, f, gd.dhash, ref, s))) return rc;
+
+    const int reps = 15, warm = 3;
+    gd.ev.resize(2 * reps);
+    for (auto &ev : gd.ev)
+        if ((e = hipEventCreate(&ev)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+
+    const double t0 = now_s();
+    int best = 0;
+    double best_ms = 1e300, default_ms = -1;
+    int count = 0;
+    for (int idx = 0; idx < (int)vs.size(); ++idx) {
+        if (idx > 0 && now_s() - t0 > budget_s) break;
+        if (!variant_eligible(vs[idx], g, ptrs, nptr)) continue;
+        double ms = -1.0;
+        uint64_t h[3];
+        if ((rc = zero_tendencies(g, f, s))) return rc;
+        if ((rc = run_variant(g, kernel, idx, f, visc, s))) return rc;
+        if ((rc = output_hashes(g, kernel, f, gd.dhash, h, s))) return rc;
+        if (h[0] == ref[0] && h[1] == ref[1] && h[2] == ref[2]) {
+            for (int r = 0; r < warm; ++r)
+                if ((rc = run_variant(g, kernel, idx, f, visc, s))) return rc;
+            for (int r = 0; r < reps; ++r) {
+                (void)hipEventRecord(gd.ev[2 * r], s);
+                if ((rc = run_variant(g, kernel, idx, f, visc, s))) return rc;
+                (void)hipEventRecord(gd.ev[2 * r + 1], s);
+            }
+            if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "tune sync");
+            std::vector<float> t(reps);
+            for (int r = 0; r < reps; ++r) (void)hipEventElapsedTime(&t[r], gd.ev[2 * r], gd.ev[2 * r + 1]);
+            std::sort(t.begin(), t.end());
+            ms = t[reps / 2];
+            if (idx == 0) default_ms = ms;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = idx;
+            }
+        }
+        if (timings_out && count < max_timings) {
+            timings_out[2 * count] = idx;
+            timings_out[2 * count + 1] = ms;
+        }
+        ++count;
+    }
+    if (n_timings) *n_timings = std::min(count, max_timings);
+
+    DeviceIdent id;
+    if ((rc = current_device_ident(&id))) return rc;
+    const double npts = (double)g->itot * g->jtot * g->ktot;
+    const double bytes = npts * (kernel == KL_KERNEL_ADVEC_U ? 5 : 9) * (g->dtype == KL_F32 ? 4 : 8);
+    const Variant &v = vs[best];
+    std::ostringstream o;
+    o.precision(6);
+    o << "{\"kernel\":\"" << kernel_name(kernel) << "\",\"dtype\":\"" << (g->dtype == KL_F32 ? "f32" : "f64")
+      << "\",\"problem_size\":[" << g->itot << "," << g->jtot << "," << g->ktot << "],"
+      << "\"variant\":\"" << v.name << "\",\"params\":{\"family\":" << v.family << ",\"vx\":" << v.vx
+      << ",\"bx\":" << v.bx << ",\"by\":" << v.by << ",\"kb\":" << v.kb << ",\"xcd\":" << v.xcd << "},"
+      << "\"time_ms\":" << best_ms << ",\"default_ms\":" << default_ms << ",\"gbps\":" << bytes / (best_ms * 1e6)
+      << ",\"bc\":" << g->bc << ",\"evaluated\":" << count << "," << provenance_json(id) << "}";
+    if ((rc = wisdom_append(dir, kernel, o.str()))) return rc;
+    return KL_OK;
+}
+
+}  // namespace
+
+extern "C" int kl_tune(const kl_grid_t *g, void *const fields[6], uint32_t kernel_mask, const char *wisdom_dir_,
+                       double budget_s, void *stream, double *timings_out, int32_t max_timings, int32_t *n_timings)
+{
+    clear_error();
+    int rc = check_grid(g);
+    if (rc) return rc;
+    if (!fields) return fail(KL_ERR_INVALID, "fields is NULL");
+    for (int n = 0; n < 6; ++n)
+        if (!fields[n]) return fail(KL_ERR_INVALID, "field %d is NULL", n);
+    if (kernel_mask == 0 || kernel_mask > 3) return fail(KL_ERR_INVALID, "kernel_mask %u", kernel_mask);
+    if (n_timings) *n_timings = 0;
+    const std::string dir = wisdom_dir_ && *wisdom_dir_ ? std::string(wisdom_dir_) : wisdom_dir();
+    bool first = true;
+    for (int kernel = 0; kernel < 2; ++kernel) {
+        if (!(kernel_mask & (1u << kernel))) continue;
+        rc = tune_one(g, kernel, fields, dir, budget_s, (hipStream_t)stream, first ? timings_out : nullptr,
+                      max_timings, first ? n_timings : nullptr);
+        if (rc) return rc;
+        first = false;
+    }
+    clear_plans();
+    return KL_OK;
+}

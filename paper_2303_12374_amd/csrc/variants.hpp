@@ -1,0 +1,91 @@
+// Launchers of the tendency-kernel configurations and the macro that
+// builds a registry list.  Included by one translation unit per field type.
+#pragma once
+
+#include "kl_internal.hpp"
+#include "stencil.hpp"
+
+namespace kl {
+
+inline unsigned cdivu(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+template <typename T>
+StencilArgs<T> device_args(const HostArgs &h)
+{
+    StencilArgs<T> a;
+    a.itot = h.itot;
+    a.jtot = h.jtot;
+    a.ktot = h.ktot;
+    a.kw0 = h.kw0;
+    a.off = h.off;
+    a.js = h.js;
+    a.ks = h.ks;
+    a.dxi = (T)h.dxi;
+    a.dyi = (T)h.dyi;
+    a.visc = (T)h.visc;
+    a.dzi = (const T *)h.dzi;
+    a.dzhi = (const T *)h.dzhi;
+    a.ut = (T *)h.ut;
+    a.vt = (T *)h.vt;
+    a.wt = (T *)h.wt;
+    a.u = (const T *)h.u;
+    a.v = (const T *)h.v;
+    a.w = (const T *)h.w;
+    a.nbx = a.nby = a.nbz = 1;
+    return a;
+}
+
+// 1-D grids only: total threads must fit the 32-bit grid size.
+inline bool grid_fits(uint64_t blocks, uint64_t threads) { return blocks * threads < (1ull << 32); }
+
+template <typename T, int KERNEL>
+hipError_t launch_plain(const HostArgs &h, hipStream_t s)
+{
+    StencilArgs<T> a = device_args<T>(h);
+    a.nbx = (int)cdivu(h.itot, 256);
+    a.nby = h.jtot;
+    a.nbz = h.ktot;
+    const uint64_t nb = (uint64_t)a.nbx * a.nby * a.nbz;
+    if (!grid_fits(nb, 256)) return hipErrorInvalidConfiguration;
+    if (KERNEL == KL_KERNEL_ADVEC_U)
+        hipLaunchKernelGGL(advec_u_plain<T>, dim3((unsigned)nb), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(diff_uvw_plain<T>, dim3((unsigned)nb), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, int KERNEL, int VX, int BX, int BY, int KB, int XCD>
+hipError_t launch_zc(const HostArgs &h, hipStream_t s)
+{
+    StencilArgs<T> a = device_args<T>(h);
+    a.nbx = (int)cdivu(h.itot, (int64_t)BX * VX);
+    a.nby = (int)cdivu(h.jtot, BY);
+    a.nbz = (int)cdivu(h.ktot, KB);
+    const uint64_t nb = (uint64_t)a.nbx * a.nby * a.nbz;
+    if (!grid_fits(nb, BX * BY)) return hipErrorInvalidConfiguration;
+    if (KERNEL == KL_KERNEL_ADVEC_U)
+        hipLaunchKernelGGL((advec_u_zc<T, VX, BX, BY, KB, XCD>), dim3((unsigned)nb), dim3(BX, BY), 0, s, a);
+    else
+        hipLaunchKernelGGL((diff_uvw_zc<T, VX, BX, BY, KB, XCD>), dim3((unsigned)nb), dim3(BX, BY), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace kl
+
+#define KL_STR2(x) #x
+#define KL_STR(x) KL_STR2(x)
+
+// One z-marching configuration entry.
+#define KL_ZC(T, DT, KERN, VX, BX, BY, KB, XCD)                                                   \
+    Variant{"zc_v" KL_STR(VX) "_b" KL_STR(BX) "x" KL_STR(BY) "_k" KL_STR(KB) "_x" KL_STR(XCD), \
+            KERN, DT, FAMILY_ZC, VX, BX, BY, KB, XCD, &launch_zc<T, KERN, VX, BX, BY, KB, XCD>}
+
+#define KL_ZC_XCD(T, DT, KERN, VX, BX, BY, KB) \
+    KL_ZC(T, DT, KERN, VX, BX, BY, KB, 0), KL_ZC(T, DT, KERN, VX, BX, BY, KB, 1)
+
+#define KL_ZC_KB(T, DT, KERN, VX, BX, BY) \
+    KL_ZC_XCD(T, DT, KERN, VX, BX, BY, 16), KL_ZC_XCD(T, DT, KERN, VX, BX, BY, 64)
+
+#define KL_ZC_BLOCKS(T, DT, KERN, VX)                                           \
+    KL_ZC_KB(T, DT, KERN, VX, 64, 1), KL_ZC_KB(T, DT, KERN, VX, 64, 4),          \
+        KL_ZC_KB(T, DT, KERN, VX, 128, 2), KL_ZC_KB(T, DT, KERN, VX, 256, 1)

@@ -44,9 +44,15 @@ MEAN_FLOW = (1.0, 0.5, 0.0)
 def splitmix64(keys: np.ndarray) -> np.ndarray:
     """SplitMix64 output for state ``keys`` (uint64 array), wrapping arithmetic."""
     z = np.asarray(keys, dtype=np.uint64) + GAMMA_SM
-    z = (z ^ (z >> np.uint64(30))) * M1
-    z = (z ^ (z >> np.uint64(27))) * M2
-    return z ^ (z >> np.uint64(31))
+    t = z >> np.uint64(30)
+    z ^= t
+    z *= M1
+    np.right_shift(z, np.uint64(27), out=t)
+    z ^= t
+    z *= M2
+    np.right_shift(z, np.uint64(31), out=t)
+    z ^= t
+    return z
 
 
 def uniform01(keys: np.ndarray) -> np.ndarray:
@@ -158,14 +164,20 @@ def sinusoid_fields(seed: int, itot: int, jtot: int, ktot: int, zg: dict,
     Lz = zg["Lz"]
     for f in range(3):
         Z, Y, X = staggered_positions(f, itot, jtot, zg)
-        Z, Y, X = Z[1:ktot + 1], Y[:, 1:jtot + 1], X[:, :, 1:itot + 1]
-        acc = np.zeros((ktot, jtot, itot))
+        Z, Y, X = Z[1:ktot + 1, 0, 0], Y[0, 1:jtot + 1, 0], X[0, 0, 1:itot + 1]
+        # each mode is a separable product, so the sum over modes is a
+        # (ktot x nmodes) @ (nmodes x jtot*itot) matrix product
+        zm = np.empty((ktot, nmodes))
+        xy = np.empty((nmodes, jtot * itot))
         for n in range(1, nmodes + 1):
             a, b, d = (_phase(seed, f, n, w) for w in range(3))
-            acc += (1.0 / n) * (np.sin(2 * math.pi * n * X + a)
-                                * np.cos(2 * math.pi * n * Y + b)
-                                * np.cos(math.pi * n * Z / Lz + d))
-        out.append(mean[f] + acc + noise * uniform_field(seed, f, itot, jtot, ktot))
+            zm[:, n - 1] = np.cos(math.pi * n * Z / Lz + d)
+            xy[n - 1] = ((1.0 / n) * np.outer(np.cos(2 * math.pi * n * Y + b),
+                                              np.sin(2 * math.pi * n * X + a))).ravel()
+        acc = (zm @ xy).reshape(ktot, jtot, itot)
+        acc += mean[f]
+        acc += noise * uniform_field(seed, f, itot, jtot, ktot)
+        out.append(acc)
     return out
 
 

@@ -1,0 +1,127 @@
+"""Host-side checks of libkl that need no GPU: the library loads and exports
+every entry point declared in include/kl.h, the layout rules, argument
+checks, and the wisdom-record selection heuristic."""
+import json
+import os
+import re
+
+import pytest
+
+from paper_2303_12374_amd import kl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "kl.h")).read()
+    return sorted(set(re.findall(r"^(?:int|const char \*)\s*(kl_[a-z0-9_]+)\(", text, re.M)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_symbols()
+    assert len(names) >= 25
+    for n in names:
+        assert hasattr(kl._lib, n), f"{n} declared in kl.h but not exported by libkl.so"
+    assert set(names) == set(kl.DECLARED), "binding and header disagree"
+
+
+def test_version_and_no_error():
+    assert "gfx950" in kl.kl_version()
+
+
+@pytest.mark.parametrize("dtype,s", [(kl.F32, 4), (kl.F64, 8)])
+@pytest.mark.parametrize("shape", [(512, 512, 512), (1024, 1024, 128), (37, 23, 19), (1, 1, 2), (96, 64, 32)])
+def test_layout_alignment(dtype, s, shape):
+    itot, jtot, ktot = shape
+    off, js, ks, alloc = kl.kl_layout(itot, jtot, ktot, dtype)
+    assert ((off + 1) * s) % 128 == 0, "first interior element of row 0 on a 128-byte line"
+    assert (js * s) % 128 == 0 and js >= itot + 2
+    assert ks == js * (jtot + 2)
+    assert alloc >= off + ks * (ktot + 2)
+    # x ghosts of rows j and j+1 share one 128-byte line
+    last_ghost = off + itot + 1
+    next_first = off + js
+    assert (last_ghost * s) // 128 == (next_first * s) // 128
+
+
+def test_layout_rejects_bad_sizes():
+    with pytest.raises(kl.KLError) as e:
+        kl.kl_layout(0, 4, 4, kl.F32)
+    assert e.value.code == kl.ERR_INVALID
+    with pytest.raises(kl.KLError):
+        kl.kl_layout(4, 4, 4, 7)
+
+
+def test_argument_checks_need_no_device():
+    g = kl.kl_grid_t(8, 8, 8, 1, 0, 10, 100, 8.0, 8.0, 16, 16, kl.F32, 0)
+    for bad in (dict(gc=2), dict(itot=0), dict(jstride=5), dict(kstride=50), dict(dtype=3), dict(bc=9),
+                dict(dzi=None), dict(ktot=1)):
+        gg = kl.kl_grid_t.from_buffer_copy(g)
+        for k, v in bad.items():
+            setattr(gg, k, v)
+        with pytest.raises(kl.KLError) as e:
+            kl.kl_advec_u(gg, 1, 1, 1, 1, stream=0)
+        assert e.value.code == kl.ERR_INVALID
+    with pytest.raises(kl.KLError):
+        kl.kl_advec_u(g, None, 1, 1, 1, stream=0)
+    with pytest.raises(kl.KLError):
+        kl.kl_reduce_fp64(g, 5, 1, 1, 1, 1, stream=0)
+
+
+def test_variant_registry():
+    for dt in (kl.F32, kl.F64):
+        for kern in (kl.ADVEC_U, kl.DIFF_UVW):
+            n = kl.kl_num_variants(kern, dt)
+            assert n > 10
+            assert kl.kl_variant_name(kern, dt, 0) == "default"
+            names = [kl.kl_variant_name(kern, dt, i) for i in range(n)]
+            assert len(set(names)) == n
+    with pytest.raises(kl.KLError):
+        kl.kl_variant_name(kl.ADVEC_U, kl.F32, 10 ** 6)
+
+
+def _rec(variant, size, device="AMD Instinct MI355X", arch="gfx950", dtype="f32", kernel="advec_u"):
+    return json.dumps({"kernel": kernel, "dtype": dtype, "problem_size": list(size), "device": device,
+                       "arch": arch, "variant": variant, "time_ms": 1.0})
+
+
+def test_wisdom_selection_levels(tmp_path):
+    """The five cases of the selection heuristic (Section "Kernel Selection
+    and Compilation"), on synthetic records."""
+    v = [kl.kl_variant_name(kl.ADVEC_U, kl.F32, i) for i in range(1, 6)]
+    d = str(tmp_path)
+    look = lambda dev, arch, size, dtype=kl.F32: kl.kl_wisdom_lookup(d, kl.ADVEC_U, dtype, dev, arch, *size)
+    # 5: missing file -> default
+    assert look("AMD Instinct MI355X", "gfx950", (256, 256, 256)) == ("default", 5)
+    lines = [
+        _rec(v[0], (256, 256, 256)),
+        _rec(v[1], (512, 512, 512)),
+        _rec(v[2], (128, 128, 128), device="AMD Instinct MI350X"),
+        _rec(v[3], (64, 64, 64), device="Other GPU", arch="gfx942"),
+        "this line is not json",
+        _rec(v[4], (256, 256, 256), dtype="f64"),
+        _rec("no_such_configuration", (100, 100, 100)),
+    ]
+    (tmp_path / "advec_u.wisdom").write_text("\n".join(lines) + "\n")
+    # 1: exact GPU and size
+    assert look("AMD Instinct MI355X", "gfx950", (256, 256, 256)) == (v[0], 1)
+    # 2: same GPU, nearest size (Euclidean): (400,400,400) is nearer 512^3
+    assert look("AMD Instinct MI355X", "gfx950", (400, 400, 400)) == (v[1], 2)
+    assert look("AMD Instinct MI355X", "gfx950", (300, 300, 300)) == (v[0], 2)
+    # 3: other GPU of the same architecture: nearest among gfx950 records
+    assert look("AMD Instinct MI999", "gfx950", (120, 120, 120)) == (v[2], 3)
+    # 4: unknown architecture: nearest of all records
+    assert look("Some GPU", "gfx1100", (60, 60, 60)) == (v[3], 4)
+    # dtype must match: the only f64 record is chosen for f64 whatever its size
+    assert look("AMD Instinct MI355X", "gfx950", (32, 32, 32), dtype=kl.F64) == (v[4], 2)
+    # a later record for the same GPU and size supersedes the earlier one
+    with open(tmp_path / "advec_u.wisdom", "a") as f:
+        f.write(_rec(v[2], (256, 256, 256)) + "\n")
+    assert look("AMD Instinct MI355X", "gfx950", (256, 256, 256)) == (v[2], 1)
+
+
+def test_wisdom_other_kernel_records_ignored(tmp_path):
+    v1 = kl.kl_variant_name(kl.DIFF_UVW, kl.F32, 1)
+    (tmp_path / "advec_u.wisdom").write_text(_rec(v1, (64, 64, 64), kernel="diff_uvw") + "\n")
+    assert kl.kl_wisdom_lookup(str(tmp_path), kl.ADVEC_U, kl.F32, "AMD Instinct MI355X", "gfx950",
+                               64, 64, 64) == ("default", 5)
