@@ -1,0 +1,333 @@
+// LDS-staged z-marching configurations of the tendency kernels.
+//
+// Workgroup = 64 x BY threads: wave r owns row j0 + r of a tile 64*VX wide
+// in x and BY rows in y, each lane VX consecutive x points, and the tile
+// walks levels [k0, k0 + KB).  Per level each row is read from global memory
+// once:
+//   * z neighbours: a 4-slot register ring per field (levels k-1, k, k+1 and
+//     the prefetch of k+2), unrolled so the slots never move;
+//   * y neighbours: every wave writes its level-k row to a double-buffered
+//     LDS plane, the two halo rows (j0-1 and the row after the last valid
+//     one) are written by wave 0 and by the "top" wave; one barrier a level;
+//   * x neighbours: lane shuffles, with the two values beyond the wave's
+//     segment loaded by the edge lanes.
+// The per-point arithmetic is the shared one of stencil.hpp, so results are
+// bitwise equal to every other configuration.
+#pragma once
+
+#include "stencil.hpp"
+
+namespace kl {
+
+template <typename T>
+__device__ __forceinline__ T shfl_up1(T x)
+{
+    return __shfl_up(x, 1u, 64);
+}
+
+template <typename T>
+__device__ __forceinline__ T shfl_down1(T x)
+{
+    return __shfl_down(x, 1u, 64);
+}
+
+// Geometry of one zl tile as seen by one thread.
+template <int VX, int BY, int KB, int XCD>
+struct ZlTile {
+    int lane, r, i0w, i0, j0, nv, k0, k1, nlanes, top;
+    bool lane_on, own;
+    int xrow_g, xrow_l;  // extra (halo) row of this wave: global row and LDS row, -1 if none
+
+    __device__ __forceinline__ ZlTile(int itot, int jtot, int ktot, int nbx, int nby, int nbz)
+    {
+        constexpr int TX = 64 * VX;
+        int tx, ty, tz;
+        tile_of<64, BY, XCD>(nbx, nby, nbz, tx, ty, tz);
+        lane = (int)threadIdx.x;
+        r = (int)threadIdx.y;
+        i0w = 1 + tx * TX;
+        i0 = i0w + lane * VX;
+        j0 = 1 + ty * BY;
+        nv = min(BY, jtot - j0 + 1);
+        k0 = 1 + tz * KB;
+        k1 = min(k0 + KB, ktot + 1);
+        nlanes = min(64, (itot - i0w + 1) / VX);
+        lane_on = lane < nlanes;
+        own = r < nv;
+        top = nv < BY ? nv : BY - 1;
+        xrow_g = xrow_l = -1;
+        if (r == 0) {
+            xrow_g = j0 - 1;
+            xrow_l = 0;
+        } else if (r == top) {
+            xrow_g = j0 + nv;
+            xrow_l = nv + 1;
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// diff_uvw
+// ---------------------------------------------------------------------------
+template <typename T, int VX, int BY, int KB, int XCD>
+__global__ __launch_bounds__(64 * BY) void diff_uvw_zl(StencilArgs<T> a)
+{
+    static_assert(BY >= 2, "two halo rows need two waves");
+    constexpr int TX = 64 * VX;
+    typedef T RowT[TX];
+    __shared__ __align__(16) RowT sh[2][3][BY + 2];
+
+    const ZlTile<VX, BY, KB, XCD> t(a.itot, a.jtot, a.ktot, a.nbx, a.nby, a.nbz);
+    const int64_t js = a.js, ks = a.ks;
+    const int64_t c_own = a.off + t.i0 + (int64_t)(t.j0 + t.r) * js;
+    const int64_t c_x = a.off + t.i0 + (int64_t)t.xrow_g * js;
+    const bool ld_own = t.own && t.lane_on;
+    const bool ld_x = t.xrow_g >= 0 && t.lane_on;
+    const bool edge_l = t.own && t.lane == 0;
+    const bool edge_r = t.own && t.lane == t.nlanes - 1;
+    const T *F[3] = {a.u, a.v, a.w};
+    T *Tt[3] = {a.ut, a.vt, a.wt};
+    const T dxi2 = a.dxi * a.dxi, dyi2 = a.dyi * a.dyi, visc = a.visc;
+    const int kw0 = a.kw0;
+
+    T R[4][3][VX];        // field ring: slot s%4 holds level kk+s
+    T X[2][3][VX];        // extra row, by level parity
+    T Q[2][3][VX];        // tendencies, by level parity
+    T EL[2][3], ER[2][3]; // x edge values, by level parity
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+#pragma unroll
+        for (int n = 0; n < VX; ++n) {
+            R[0][f][n] = R[1][f][n] = R[2][f][n] = R[3][f][n] = T(0);
+            X[0][f][n] = X[1][f][n] = Q[0][f][n] = Q[1][f][n] = T(0);
+        }
+        EL[0][f] = EL[1][f] = ER[0][f] = ER[1][f] = T(0);
+    }
+
+    const int k0 = t.k0, k1 = t.k1;
+    // prologue: levels k0-1, k0, k0+1 (and the k0+2 prefetch) of the own row
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        if (ld_own) {
+            vload<T, VX>(R[3][f], F[f] + c_own + (int64_t)(k0 - 1) * ks);
+            vload<T, VX>(R[0][f], F[f] + c_own + (int64_t)k0 * ks);
+            vload<T, VX>(R[1][f], F[f] + c_own + (int64_t)(k0 + 1) * ks);
+            if (k0 + 2 <= k1) vload<T, VX>(R[2][f], F[f] + c_own + (int64_t)(k0 + 2) * ks);
+            if (f < 2 || k0 >= kw0) vload<T, VX>(Q[0][f], Tt[f] + c_own + (int64_t)k0 * ks);
+        }
+        if (ld_x) vload<T, VX>(X[0][f], F[f] + c_x + (int64_t)k0 * ks);
+        if (edge_l) EL[0][f] = F[f][c_own + (int64_t)k0 * ks - 1];
+        if (edge_r) ER[0][f] = F[f][c_own + (int64_t)k0 * ks + VX];
+    }
+
+    for (int kk = k0; kk < k1; kk += 4) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int k = kk + s;
+            if (k < k1) {
+                const int p = s & 1, q = p ^ 1;
+                T(&b)[3][VX] = R[(s + 3) & 3];  // level k-1; refilled with k+3 after use
+                T(&c)[3][VX] = R[s & 3];
+                T(&tp)[3][VX] = R[(s + 1) & 3];  // R[(s+2)&3] already holds level k+2
+                // prefetch level k+1 of tendencies, halo row and edges
+#pragma unroll
+                for (int f = 0; f < 3; ++f) {
+                    if (k + 1 < k1) {
+                        if (ld_own && (f < 2 || k + 1 >= kw0))
+                            vload<T, VX>(Q[q][f], Tt[f] + c_own + (int64_t)(k + 1) * ks);
+                        if (ld_x) vload<T, VX>(X[q][f], F[f] + c_x + (int64_t)(k + 1) * ks);
+                        if (edge_l) EL[q][f] = F[f][c_own + (int64_t)(k + 1) * ks - 1];
+                        if (edge_r) ER[q][f] = F[f][c_own + (int64_t)(k + 1) * ks + VX];
+                    }
+                }
+                // level k rows into LDS
+#pragma unroll
+                for (int f = 0; f < 3; ++f) {
+                    if (t.own) vstore<T, VX>(&sh[p][f][t.r + 1][t.lane * VX], c[f]);
+                    if (t.xrow_l >= 0) vstore<T, VX>(&sh[p][f][t.xrow_l][t.lane * VX], X[p][f]);
+                }
+                __syncthreads();
+                const T dzik = a.dzi[k], dzikm1 = a.dzi[k - 1], dzhik = a.dzhi[k], dzhik1 = a.dzhi[k + 1];
+#pragma unroll
+                for (int f = 0; f < 3; ++f) {
+                    T nn[VX], ss[VX];
+                    vload<T, VX>(nn, &sh[p][f][t.r + 2][t.lane * VX]);
+                    vload<T, VX>(ss, &sh[p][f][t.r][t.lane * VX]);
+                    T left = shfl_up1<T>(c[f][VX - 1]);
+                    T right = shfl_down1<T>(c[f][0]);
+                    if (t.lane == 0) left = EL[p][f];
+                    if (t.lane == t.nlanes - 1) right = ER[p][f];
+                    if (ld_own && (f < 2 || k >= kw0)) {
+#pragma unroll
+                        for (int n = 0; n < VX; ++n) {
+                            const T w_ = n == 0 ? left : c[f][n - 1];
+                            const T e_ = n == VX - 1 ? right : c[f][n + 1];
+                            const T d = f < 2 ? diff_c_point<T>(c[f][n], e_, w_, nn[n], ss[n], tp[f][n], b[f][n],
+                                                                dxi2, dyi2, dzik, dzhik1, dzhik, visc)
+                                              : diff_w_point<T>(c[f][n], e_, w_, nn[n], ss[n], tp[f][n], b[f][n],
+                                                                dxi2, dyi2, dzik, dzikm1, dzhik, visc);
+                            Q[p][f][n] = Q[p][f][n] + d;
+                        }
+                        vstore<T, VX>(Tt[f] + c_own + (int64_t)k * ks, Q[p][f]);
+                    }
+                }
+                // level k-1 is no longer needed: its slot takes the k+3 prefetch
+#pragma unroll
+                for (int f = 0; f < 3; ++f)
+                    if (ld_own && k + 3 <= k1) vload<T, VX>(b[f], F[f] + c_own + (int64_t)(k + 3) * ks);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// advec_u
+// ---------------------------------------------------------------------------
+template <typename T, int VX, int BY, int KB, int XCD>
+__global__ __launch_bounds__(64 * BY) void advec_u_zl(StencilArgs<T> a)
+{
+    static_assert(BY >= 2, "two halo rows need two waves");
+    constexpr int TX = 64 * VX;
+    typedef T RowT[TX];
+    __shared__ __align__(16) RowT shu[2][BY + 2];  // u rows j0-1 .. j0+nv
+    __shared__ __align__(16) RowT shv[2][BY + 2];  // v rows j0 .. j0+nv (LDS row r+1 = tile row r)
+    __shared__ T shvl[2][BY + 2];                   // v left of the segment, same rows
+
+    const ZlTile<VX, BY, KB, XCD> t(a.itot, a.jtot, a.ktot, a.nbx, a.nby, a.nbz);
+    const int64_t js = a.js, ks = a.ks;
+    const int64_t c_own = a.off + t.i0 + (int64_t)(t.j0 + t.r) * js;
+    const int64_t c_x = a.off + t.i0 + (int64_t)t.xrow_g * js;
+    const bool ld_own = t.own && t.lane_on;
+    const bool ld_x = t.xrow_g >= 0 && t.lane_on;
+    const bool x_is_top = t.xrow_g >= 0 && t.xrow_l > 0;   // the top halo row also needs v
+    const bool edge_l = t.own && t.lane == 0;
+    const bool edge_r = t.own && t.lane == t.nlanes - 1;
+    const T dxi = a.dxi, dyi = a.dyi;
+    const T *U = a.u, *V = a.v, *W = a.w;
+
+    T RU[4][VX], RW[4][VX];   // u and w rings (u: k-1..k+2, w: k..k+2)
+    T RV[2][VX];              // v at level k, k+1
+    T XU[2][VX], XV[2][VX];   // extra row u (and v for the top halo)
+    T XVL[2];                 // v left edge of the top halo row
+    T Q[2][VX];               // ut
+    T ULe[2], URe[2], VLe[2]; // own-row edges by level parity
+    T WLe[4];                 // w left edge, ring like RW
+#pragma unroll
+    for (int n = 0; n < VX; ++n) {
+        RU[0][n] = RU[1][n] = RU[2][n] = RU[3][n] = T(0);
+        RW[0][n] = RW[1][n] = RW[2][n] = RW[3][n] = T(0);
+        RV[0][n] = RV[1][n] = XU[0][n] = XU[1][n] = XV[0][n] = XV[1][n] = Q[0][n] = Q[1][n] = T(0);
+    }
+    ULe[0] = ULe[1] = URe[0] = URe[1] = VLe[0] = VLe[1] = XVL[0] = XVL[1] = T(0);
+    WLe[0] = WLe[1] = WLe[2] = WLe[3] = T(0);
+
+    const int k0 = t.k0, k1 = t.k1;
+    if (ld_own) {
+        vload<T, VX>(RU[3], U + c_own + (int64_t)(k0 - 1) * ks);
+        vload<T, VX>(RU[0], U + c_own + (int64_t)k0 * ks);
+        vload<T, VX>(RU[1], U + c_own + (int64_t)(k0 + 1) * ks);
+        if (k0 + 2 <= k1) vload<T, VX>(RU[2], U + c_own + (int64_t)(k0 + 2) * ks);
+        vload<T, VX>(RW[0], W + c_own + (int64_t)k0 * ks);
+        vload<T, VX>(RW[1], W + c_own + (int64_t)(k0 + 1) * ks);
+        if (k0 + 2 <= k1) vload<T, VX>(RW[2], W + c_own + (int64_t)(k0 + 2) * ks);
+        vload<T, VX>(RV[0], V + c_own + (int64_t)k0 * ks);
+        vload<T, VX>(Q[0], a.ut + c_own + (int64_t)k0 * ks);
+    }
+    if (ld_x) {
+        vload<T, VX>(XU[0], U + c_x + (int64_t)k0 * ks);
+        if (x_is_top) vload<T, VX>(XV[0], V + c_x + (int64_t)k0 * ks);
+    }
+    if (x_is_top && t.lane == 0) XVL[0] = V[c_x + (int64_t)k0 * ks - 1];
+    if (edge_l) {
+        ULe[0] = U[c_own + (int64_t)k0 * ks - 1];
+        VLe[0] = V[c_own + (int64_t)k0 * ks - 1];
+        WLe[0] = W[c_own + (int64_t)k0 * ks - 1];
+        WLe[1] = W[c_own + (int64_t)(k0 + 1) * ks - 1];
+        if (k0 + 2 <= k1) WLe[2] = W[c_own + (int64_t)(k0 + 2) * ks - 1];
+    }
+    if (edge_r) URe[0] = U[c_own + (int64_t)k0 * ks + VX];
+
+    for (int kk = k0; kk < k1; kk += 4) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int k = kk + s;
+            if (k < k1) {
+                const int p = s & 1, q = p ^ 1;
+                T(&ub)[VX] = RU[(s + 3) & 3];  // level k-1; refilled with k+3 after use
+                T(&uc)[VX] = RU[s & 3];
+                T(&ut_)[VX] = RU[(s + 1) & 3];
+                T(&wc)[VX] = RW[s & 3];
+                T(&wt)[VX] = RW[(s + 1) & 3];
+                T(&wnx)[VX] = RW[(s + 3) & 3];  // w of level k-1 is not needed: prefetch k+3
+                if (ld_own && k + 3 <= k1) vload<T, VX>(wnx, W + c_own + (int64_t)(k + 3) * ks);
+                if (edge_l && k + 3 <= k1) WLe[(s + 3) & 3] = W[c_own + (int64_t)(k + 3) * ks - 1];
+                if (k + 1 < k1) {
+                    if (ld_own) {
+                        vload<T, VX>(RV[q], V + c_own + (int64_t)(k + 1) * ks);
+                        vload<T, VX>(Q[q], a.ut + c_own + (int64_t)(k + 1) * ks);
+                    }
+                    if (ld_x) {
+                        vload<T, VX>(XU[q], U + c_x + (int64_t)(k + 1) * ks);
+                        if (x_is_top) vload<T, VX>(XV[q], V + c_x + (int64_t)(k + 1) * ks);
+                    }
+                    if (x_is_top && t.lane == 0) XVL[q] = V[c_x + (int64_t)(k + 1) * ks - 1];
+                    if (edge_l) {
+                        ULe[q] = U[c_own + (int64_t)(k + 1) * ks - 1];
+                        VLe[q] = V[c_own + (int64_t)(k + 1) * ks - 1];
+                    }
+                    if (edge_r) URe[q] = U[c_own + (int64_t)(k + 1) * ks + VX];
+                }
+                // level-k rows into LDS: u (own + halo rows), v (own + top halo) and v's left edge
+                if (t.own) {
+                    vstore<T, VX>(&shu[p][t.r + 1][t.lane * VX], uc);
+                    vstore<T, VX>(&shv[p][t.r + 1][t.lane * VX], RV[p]);
+                    if (t.lane == 0) shvl[p][t.r + 1] = VLe[p];
+                }
+                if (t.xrow_l >= 0) vstore<T, VX>(&shu[p][t.xrow_l][t.lane * VX], XU[p]);
+                if (x_is_top) {
+                    vstore<T, VX>(&shv[p][t.xrow_l][t.lane * VX], XV[p]);
+                    if (t.lane == 0) shvl[p][t.xrow_l] = XVL[p];
+                }
+                __syncthreads();
+                T un[VX], us[VX], vn[VX];
+                vload<T, VX>(un, &shu[p][t.r + 2][t.lane * VX]);
+                vload<T, VX>(us, &shu[p][t.r][t.lane * VX]);
+                vload<T, VX>(vn, &shv[p][t.r + 2][t.lane * VX]);
+                const T vnl_edge = shvl[p][t.r + 2];
+                T uleft = shfl_up1<T>(uc[VX - 1]);
+                T uright = shfl_down1<T>(uc[0]);
+                T vleft = shfl_up1<T>(RV[p][VX - 1]);
+                T vnleft = shfl_up1<T>(vn[VX - 1]);
+                T wleft = shfl_up1<T>(wc[VX - 1]);
+                T wtleft = shfl_up1<T>(wt[VX - 1]);
+                if (t.lane == 0) {
+                    uleft = ULe[p];
+                    vleft = VLe[p];
+                    vnleft = vnl_edge;
+                    wleft = WLe[s & 3];
+                    wtleft = WLe[(s + 1) & 3];
+                }
+                if (t.lane == t.nlanes - 1) uright = URe[p];
+                if (ld_own) {
+                    const T dzik = a.dzi[k];
+#pragma unroll
+                    for (int n = 0; n < VX; ++n) {
+                        const T uw = n == 0 ? uleft : uc[n - 1];
+                        const T ue = n == VX - 1 ? uright : uc[n + 1];
+                        const T v_w = n == 0 ? vleft : RV[p][n - 1];
+                        const T v_nw = n == 0 ? vnleft : vn[n - 1];
+                        const T w_w = n == 0 ? wleft : wc[n - 1];
+                        const T w_tw = n == 0 ? wtleft : wt[n - 1];
+                        Q[p][n] = Q[p][n] + advec_u_point<T>(uc[n], ue, uw, un[n], us[n], ut_[n], ub[n], v_w,
+                                                             RV[p][n], v_nw, vn[n], w_w, wc[n], w_tw, wt[n], dxi,
+                                                             dyi, dzik);
+                    }
+                    vstore<T, VX>(a.ut + c_own + (int64_t)k * ks, Q[p]);
+                }
+                if (ld_own && k + 3 <= k1) vload<T, VX>(ub, U + c_own + (int64_t)(k + 3) * ks);
+            }
+        }
+    }
+}
+
+}  // namespace kl

@@ -4,6 +4,7 @@
 
 #include "kl_internal.hpp"
 #include "stencil.hpp"
+#include "stencil_zl.hpp"
 
 namespace kl {
 
@@ -70,6 +71,22 @@ hipError_t launch_zc(const HostArgs &h, hipStream_t s)
     return hipGetLastError();
 }
 
+template <typename T, int KERNEL, int VX, int BY, int KB, int XCD>
+hipError_t launch_zl(const HostArgs &h, hipStream_t s)
+{
+    StencilArgs<T> a = device_args<T>(h);
+    a.nbx = (int)cdivu(h.itot, (int64_t)64 * VX);
+    a.nby = (int)cdivu(h.jtot, BY);
+    a.nbz = (int)cdivu(h.ktot, KB);
+    const uint64_t nb = (uint64_t)a.nbx * a.nby * a.nbz;
+    if (!grid_fits(nb, 64 * BY)) return hipErrorInvalidConfiguration;
+    if (KERNEL == KL_KERNEL_ADVEC_U)
+        hipLaunchKernelGGL((advec_u_zl<T, VX, BY, KB, XCD>), dim3((unsigned)nb), dim3(64, BY), 0, s, a);
+    else
+        hipLaunchKernelGGL((diff_uvw_zl<T, VX, BY, KB, XCD>), dim3((unsigned)nb), dim3(64, BY), 0, s, a);
+    return hipGetLastError();
+}
+
 }  // namespace kl
 
 #define KL_STR2(x) #x
@@ -89,3 +106,17 @@ hipError_t launch_zc(const HostArgs &h, hipStream_t s)
 #define KL_ZC_BLOCKS(T, DT, KERN, VX)                                           \
     KL_ZC_KB(T, DT, KERN, VX, 64, 1), KL_ZC_KB(T, DT, KERN, VX, 64, 4),          \
         KL_ZC_KB(T, DT, KERN, VX, 128, 2), KL_ZC_KB(T, DT, KERN, VX, 256, 1)
+
+// One LDS-staged z-marching configuration entry (block 64 x BY).
+#define KL_ZL(T, DT, KERN, VX, BY, KB, XCD)                                                   \
+    Variant{"zl_v" KL_STR(VX) "_b64x" KL_STR(BY) "_k" KL_STR(KB) "_x" KL_STR(XCD), KERN, DT, \
+            FAMILY_ZL, VX, 64, BY, KB, XCD, &launch_zl<T, KERN, VX, BY, KB, XCD>}
+
+#define KL_ZL_XCD(T, DT, KERN, VX, BY, KB) KL_ZL(T, DT, KERN, VX, BY, KB, 0), KL_ZL(T, DT, KERN, VX, BY, KB, 1)
+
+#define KL_ZL_KB(T, DT, KERN, VX, BY)                                                \
+    KL_ZL_XCD(T, DT, KERN, VX, BY, 32), KL_ZL_XCD(T, DT, KERN, VX, BY, 64), \
+        KL_ZL_XCD(T, DT, KERN, VX, BY, 128)
+
+#define KL_ZL_BLOCKS(T, DT, KERN, VX) \
+    KL_ZL_KB(T, DT, KERN, VX, 4), KL_ZL_KB(T, DT, KERN, VX, 8), KL_ZL_KB(T, DT, KERN, VX, 16)

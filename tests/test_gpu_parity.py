@@ -150,11 +150,15 @@ def test_step_increment_matches_oracle(dtype):
     tend = [g.zeros_interior(fill=0.0) for _ in range(3)]
     m.kl_step(g, c.visc, dt, *c.dev, *tend)
     adv, du, dv, dw = c.oracle_tendencies()
-    dte = float(m.NP_DTYPE[dtype](dt))
-    tol = 1e-4 if dtype == 0 else 1e-9  # state rounding relative to the increment
+    npd = m.NP_DTYPE[dtype]
+    dte = float(npd(dt))
+    eps = float(np.finfo(npd).eps)
     for d, b, r in zip(c.dev, before, (adv + du, dv, dw)):
-        inc = c.gpu_interior(d) - b
-        assert rel_err(inc, dte * r) <= tol
+        new = c.gpu_interior(d)
+        inc = new - b
+        # tendency error at the kernel tolerance plus one rounding of the state
+        bound = TOL[dtype] * np.max(np.abs(dte * r)) + eps * np.max(np.abs(new))
+        assert np.max(np.abs(inc - dte * r)) <= bound
 
 
 @pytest.mark.parametrize("dtype", [0, 1], ids=["f32", "f64"])
