@@ -90,6 +90,182 @@ def cpu_baseline(itot, jtot, k_sample, seed, visc, reps=7):
                       f"pair, median of {reps} runs ({best:.3f} s each, {sum(times):.1f} s total)"}
 
 
+def batched_leg(kl, inputs, torch, steps=10, warmup=3):
+    """56 grids (48 with each axis from {32,64,96,128,192}, seed 3, plus 8 of
+    256x256x32), FP32: one graph replay of the persistent tile-walking kernels
+    versus 56 x (advec_u + diff_uvw) single-grid launches."""
+    import numpy as np
+    shapes = inputs.batch_shapes(3)
+    grids, fields = [], []
+    for n, sh in enumerate(shapes):
+        g = kl.Grid(*sh, dtype=kl.F32)
+        f = [g.full(0.0) for _ in range(6)]
+        kl.kl_generate_fields(g, 3000 + n, *f[:3])
+        kl.kl_fill_ghosts(g, *f[:3])
+        grids.append(g)
+        fields.append(f)
+    npts = sum(g.npoints for g in grids)
+    b = kl.kl_batch_create(grids, fields, 1e-5, False)
+    nk, nt = kl.kl_batch_info(b)
+    stream = torch.cuda.current_stream()
+
+    def time_it(fn, k):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(k):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    batched_ms = time_it(lambda: kl.kl_batch_run(b, stream), steps)
+
+    def plain():
+        for g, f in zip(grids, fields):
+            kl.kl_launch_variant(g, kl.ADVEC_U, 0, f, 1e-5, stream)
+            kl.kl_launch_variant(g, kl.DIFF_UVW, 0, f, 1e-5, stream)
+
+    def selected():
+        for g, f in zip(grids, fields):
+            kl.kl_advec_u(g, f[3], *f[:3], stream)
+            kl.kl_diff_uvw(g, *f[3:], *f[:3], 1e-5, stream)
+
+    plain_ms = time_it(plain, max(3, steps // 2))
+    sel_ms = time_it(selected, max(3, steps // 2))
+    kl.kl_batch_destroy(b)
+    del fields
+    torch.cuda.empty_cache()
+    return {"workload": "56 grids FP32 (48 x {32,64,96,128,192}^3 per axis, seed 3; 8 x 256x256x32)",
+            "points": npts, "graph_kernels": nk, "tiles": nt,
+            "batched_ms": batched_ms, "batched_grid_points_per_s": npts / (batched_ms * 1e-3),
+            "plain_112_launches_ms": plain_ms, "selected_112_launches_ms": sel_ms,
+            "speedup_vs_plain": plain_ms / batched_ms, "speedup_vs_selected": sel_ms / batched_ms,
+            "hbm_gbps_algorithmic": 14 * 4 * npts / (batched_ms * 1e6)}
+
+
+def served_trace(n=2000, seed=4, rate=None):
+    """Requests of the served workload: grids uniform over {64^3, 128^3, 256^3,
+    512x512x128}, FP32 with probability 0.75 else FP64, 1..10 steps, Poisson
+    arrivals (exponential gaps) -- all drawn from SplitMix64 counters of seed."""
+    import numpy as np
+    from paper_2303_12374_amd import inputs
+    with np.errstate(over="ignore"):
+        keys = inputs.field_key_base(seed, 6) + np.arange(4 * n, dtype=np.uint64)
+        r = inputs.uniform01(keys).reshape(n, 4)
+    shapes = [(64, 64, 64), (128, 128, 128), (256, 256, 256), (512, 512, 128)]
+    reqs = []
+    for q in range(n):
+        sh = shapes[min(int(r[q, 0] * 4), 3)]
+        dtype = 0 if r[q, 1] < 0.75 else 1
+        steps = 1 + min(int(r[q, 2] * 10), 9)
+        gap = -np.log1p(-r[q, 3])  # unit-rate exponential
+        reqs.append({"shape": sh, "dtype": dtype, "steps": steps, "gap": gap, "seed": 40000 + q})
+    return reqs
+
+
+def served_leg(kl, torch, n_req=2000, budget_gib=8.0, load=0.8):
+    """Continuous batching server on the Poisson trace versus serial plain
+    execution of the same trace; p50/p99 latency of (done - arrival)."""
+    import threading
+    import numpy as np
+    reqs = served_trace(n_req)
+    # calibrate the service rate: serial plain cost of one request of each kind
+    cost = {}
+    plain_dir = os.path.join("/tmp", "kl_empty_wisdom")
+    kl.kl_set_wisdom_dir(plain_dir)
+    stream = torch.cuda.current_stream()
+    for sh in {r["shape"] for r in reqs}:
+        for dt in (0, 1):
+            g = kl.Grid(*sh, dtype=dt)
+            f = [g.full(0.0) for _ in range(6)]
+            kl.kl_generate_fields(g, 1, *f[:3])
+            kl.kl_fill_ghosts(g, *f[:3])
+            kl.kl_step(g, 1e-5, 1e-4, *f, stream)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(3):
+                kl.kl_step(g, 1e-5, 1e-4, *f, stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            cost[(sh, dt)] = e0.elapsed_time(e1) / 3 * 1e-3
+            del f
+    mean_service = float(np.mean([cost[(r["shape"], r["dtype"])] * r["steps"] for r in reqs]))
+    rate = load / mean_service
+    t_arr = np.cumsum([r["gap"] for r in reqs]) / rate
+    # serial plain execution of the trace (measured per request)
+    t_free, lat_serial, t0 = 0.0, [], None
+    for r, ta in zip(reqs, t_arr):
+        sh, dt = r["shape"], r["dtype"]
+        s = cost[(sh, dt)] * r["steps"]
+        start = max(ta, t_free)
+        t_free = start + s
+        lat_serial.append(t_free - ta)
+    serial_makespan = t_free
+    kl.kl_set_wisdom_dir(None)
+    # served
+    arena_bytes = int((budget_gib + 0.5) * (1 << 30))
+    arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
+    srv = kl.kl_server_create(arena, arena_bytes, int(budget_gib * (1 << 30)))
+    tickets = [None] * len(reqs)
+    done = threading.Event()
+
+    def client():
+        base = time.perf_counter()
+        for q, (r, ta) in enumerate(zip(reqs, t_arr)):
+            while time.perf_counter() - base < ta:
+                time.sleep(min(0.0005, max(0.0, ta - (time.perf_counter() - base))))
+            sh = r["shape"]
+            tickets[q] = kl.kl_submit(srv, sh[0], sh[1], sh[2], r["dtype"], 0, r["steps"], 1e-4, 1e-5, r["seed"])
+        done.set()
+
+    th = threading.Thread(target=client)
+    wall0 = time.perf_counter()
+    th.start()
+    lat, first_arr, last_done = [], None, None
+    pending = set()
+    nxt = 0
+    while len(lat) < len(reqs):
+        while nxt < len(reqs) and tickets[nxt] is not None:
+            pending.add(tickets[nxt])
+            nxt += 1
+        for tk in list(pending):
+            rc, res = kl.kl_poll(srv, tk)
+            if rc == kl.OK:
+                if res.state != 2:
+                    raise RuntimeError(f"served request {tk} failed: {res.err}")
+                lat.append((res.t_done_ns - res.t_arrive_ns) * 1e-6)
+                first_arr = res.t_arrive_ns if first_arr is None else min(first_arr, res.t_arrive_ns)
+                last_done = res.t_done_ns if last_done is None else max(last_done, res.t_done_ns)
+                kl.kl_release(srv, tk)
+                pending.discard(tk)
+        time.sleep(0.0002)
+    th.join()
+    wall = time.perf_counter() - wall0
+    stats = kl.kl_server_stats(srv)
+    kl.kl_server_destroy(srv)
+    del arena
+    torch.cuda.empty_cache()
+    pts_steps = sum(r["shape"][0] * r["shape"][1] * r["shape"][2] * r["steps"] for r in reqs)
+    span = (last_done - first_arr) * 1e-9
+    ls = np.array(lat_serial) * 1e3
+    return {"workload": f"{n_req} requests, Poisson (seed 4) at {load:.1f} x serial plain capacity, grids "
+                        "{64^3,128^3,256^3,512x512x128}, 75% FP32, 1-10 steps, budget "
+                        f"{budget_gib:g} GiB",
+            "arrival_rate_per_s": rate, "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(np.mean(lat)),
+            "grid_point_steps_per_s": pts_steps / span, "makespan_s": span, "wall_s": wall,
+            "ticks": stats[0], "launches": stats[1], "peak_bytes": stats[3],
+            "serial_plain": {"p50_ms": float(np.percentile(ls, 50)), "p99_ms": float(np.percentile(ls, 99)),
+                             "grid_point_steps_per_s": pts_steps / serial_makespan,
+                             "makespan_s": serial_makespan,
+                             "method": "each request's measured plain kl_step time x steps, queued serially "
+                                       "on the same arrival times"}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +280,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-k", type=int, default=128)
     ap.add_argument("--no-untuned", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--served-requests", type=int, default=2000)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -228,6 +407,15 @@ def main():
                      "algorithmic_bytes_per_launch": dom_bytes},
         "untuned": untuned,
     }
+    del dev, tend, u, v, w, ut, vt, wt
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        log("batched form: 56 grids in one graph vs 112 single-grid launches")
+        result["batched"] = batched_leg(kl, inputs, torch)
+    if not args.no_served:
+        log(f"served form: {args.served_requests} requests")
+        result["served"] = served_leg(kl, torch, args.served_requests)
+        result["p99_latency_ms"] = result["served"]["p99_ms"]
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         result["cpu_baseline"] = cpu_baseline(itot, jtot, args.cpu_sample_k, seed, float(np.float32(visc)))

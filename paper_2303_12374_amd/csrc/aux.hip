@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include "kl_internal.hpp"
+#include "stencil.hpp"
 
 namespace kl {
 namespace {
@@ -96,19 +97,12 @@ __global__ __launch_bounds__(256) void fill_ghosts_kernel(Dims d, T *u, T *v, T 
     }
 }
 
-// Forward Euler on the computed range, each thread writing its updated cell
+// Forward Euler at one interior point: the thread writes the updated cell
 // and every ghost cell whose source it is (the inverse of the fill map).
 template <typename T>
-__global__ __launch_bounds__(256) void euler_kernel(Dims d, T dt, int kw0, T *u, T *v, T *w,
-                                                   const T *ut, const T *vt, const T *wt, int nbx)
+__device__ __forceinline__ void euler_point(const Dims &d, T dt, int kw0, T *u, T *v, T *w, const T *ut,
+                                            const T *vt, const T *wt, int i, int j, int k)
 {
-    unsigned b = blockIdx.x;
-    const int bx = b % nbx;
-    b /= nbx;
-    const int j = 1 + (int)(b % d.jtot);
-    const int k = 1 + (int)(b / d.jtot);
-    const int i = 1 + bx * 256 + (int)threadIdx.x;
-    if (i > d.itot) return;
     const int64_t c = at(d, i, j, k);
     // x and y images of (i, j)
     int xi[3], yj[3], nx = 1, ny = 1;
@@ -147,6 +141,40 @@ __global__ __launch_bounds__(256) void euler_kernel(Dims d, T dt, int kw0, T *u,
             const T zv = zs[a] == 0 ? T(0) : (zs[a] < 0 ? -val : val);
             for (int y = 0; y < ny; ++y)
                 for (int x = 0; x < nx; ++x) p[at(d, xi[x], yj[y], zk[a])] = zv;
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void euler_kernel(Dims d, T dt, int kw0, T *u, T *v, T *w,
+                                                   const T *ut, const T *vt, const T *wt, int nbx)
+{
+    unsigned b = blockIdx.x;
+    const int bx = b % nbx;
+    b /= nbx;
+    const int j = 1 + (int)(b % d.jtot);
+    const int k = 1 + (int)(b / d.jtot);
+    const int i = 1 + bx * 256 + (int)threadIdx.x;
+    if (i > d.itot) return;
+    euler_point<T>(d, dt, kw0, u, v, w, ut, vt, wt, i, j, k);
+}
+
+// Batched Euler update: tile = (grid, first row, end row), rows j-1 + jtot*(k-1);
+// dts[grid] is the grid's time step.
+template <typename T>
+__global__ __launch_bounds__(256) void euler_batch_kernel(const StencilArgs<T> *__restrict__ grids,
+                                                         const int4 *__restrict__ tiles, int ntiles,
+                                                         const double *__restrict__ dts)
+{
+    for (int n = blockIdx.x; n < ntiles; n += gridDim.x) {
+        const int4 tl = tiles[n];
+        const StencilArgs<T> a = grids[tl.x];
+        const Dims d{a.itot, a.jtot, a.ktot, a.bc, a.off, a.js, a.ks};
+        const T dt = (T)dts[tl.x];
+        for (int r = tl.y; r < tl.z; ++r) {
+            const int j = 1 + r % a.jtot, k = 1 + r / a.jtot;
+            for (int i = 1 + (int)threadIdx.x; i <= a.itot; i += 256)
+                euler_point<T>(d, dt, a.kw0, (T *)a.u, (T *)a.v, (T *)a.w, a.ut, a.vt, a.wt, i, j, k);
         }
     }
 }
@@ -425,6 +453,18 @@ hipError_t launch_hash(const HostArgs &a, const void *f, uint64_t *out, void *sc
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(hash_pass2, dim3(1), dim3(RT), 0, s, (const uint64_t *)partial, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_euler_batch(int dtype, const void *descs, const void *tiles, int ntiles, int nblocks,
+                              const double *dts, hipStream_t s)
+{
+    if (dtype == KL_F32)
+        hipLaunchKernelGGL(euler_batch_kernel<float>, dim3(nblocks), dim3(256), 0, s,
+                           (const StencilArgs<float> *)descs, (const int4 *)tiles, ntiles, dts);
+    else
+        hipLaunchKernelGGL(euler_batch_kernel<double>, dim3(nblocks), dim3(256), 0, s,
+                           (const StencilArgs<double> *)descs, (const int4 *)tiles, ntiles, dts);
     return hipGetLastError();
 }
 

@@ -22,6 +22,10 @@ struct HostArgs {
 };
 
 typedef hipError_t (*LaunchFn)(const HostArgs &, hipStream_t);
+// Persistent batched launch: descriptor table (StencilArgs<T>[]), tile table
+// (int4 {grid, tx, ty, tz}[]), tile count, number of blocks.
+typedef hipError_t (*BatchFn)(const void *, const void *, int, int, hipStream_t);
+typedef int (*OccFn)();  // resident blocks per CU of the batched kernel
 
 enum { FAMILY_PLAIN = 0, FAMILY_ZC = 1, FAMILY_ZL = 2 };
 
@@ -31,6 +35,8 @@ struct Variant {
     int kernel, dtype, family;
     int vx, bx, by, kb, xcd;  // x vector width, block shape, z-march length, XCD order
     LaunchFn launch;
+    BatchFn batch;  // persistent tile-list form (LDS z-march family only), else null
+    OccFn occupancy;
 };
 
 // Registry (index 0 of every list is the default configuration).
@@ -62,6 +68,13 @@ hipError_t launch_hash(const HostArgs &a, const void *f, uint64_t *out, void *sc
 hipError_t launch_gen_uniform(const HostArgs &a, uint64_t seed, void *u, void *v, void *w,
                               hipStream_t s);
 size_t reduce_scratch_bytes();
+// Batched row-tile kernels: descs = StencilArgs<T>[], tiles = int4 {grid, row0, row1, 0}[].
+hipError_t launch_euler_batch(int dtype, const void *descs, const void *tiles, int ntiles, int nblocks,
+                              const double *dts, hipStream_t s);
+hipError_t launch_zero_batch(int dtype, const void *descs, const void *tiles, int ntiles, int nblocks,
+                             hipStream_t s);
+// Configuration of grid g for `kernel` in batched (persistent) form, or -1.
+int batch_variant(const kl_grid_t *g, int kernel, void *const f[6]);
 
 // Wisdom (wisdom.cpp).
 struct DeviceIdent {

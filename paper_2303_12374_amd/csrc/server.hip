@@ -1,0 +1,571 @@
+// Served form: a request loop with continuous batching.
+//
+// A request asks for `nsteps` forward-Euler steps of advec_u + diff_uvw on a
+// grid it names; its fields are generated on the device from its seed and
+// stay resident in the caller's arena until released.  A background thread
+// runs ticks: between ticks it admits queued requests in arrival order while
+// their footprint fits the memory budget (and the arena), and every tick
+// advances all admitted requests by one step with one batched launch per
+// phase (zero tendencies, advec_u groups, diff_uvw groups, Euler update with
+// ghost refill).  Requests therefore join and leave between ticks while
+// others are running.  All per-point arithmetic is shared with the single-
+// grid path, so a request's result does not depend on what it ran beside.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <tuple>
+#include <unordered_map>
+#include <vector>
+
+#include "kl_internal.hpp"
+#include "variants.hpp"
+
+namespace kl {
+namespace {
+
+constexpr size_t ALIGN = 256;
+inline size_t round_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+int64_t now_ns()
+{
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+// First-fit sub-allocator over [0, cap) with coalescing frees.
+class Arena {
+   public:
+    explicit Arena(size_t cap) { free_[0] = cap; }
+    bool alloc(size_t bytes, size_t *off)
+    {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                const size_t rest = it->second - bytes, start = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[start] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes)
+    {
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+
+   private:
+    std::map<size_t, size_t> free_;
+};
+
+struct Req {
+    uint64_t ticket = 0;
+    kl_request_t r;
+    int state = 0, err = 0;
+    int64_t t_arrive = 0, t_admit = 0, t_done = 0;
+    int steps_left = 0;
+    size_t off = 0, bytes = 0;
+    bool fresh = false;
+    double dt = 0;
+    kl_grid_t g;
+    void *f[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    double *d_sum = nullptr;
+    double checksum[9];
+    std::vector<char> metrics;  // host copy of dzi | dzhi in the field dtype
+};
+
+// Vertical metrics of a served grid: centers-primary tanh stretch
+// (gamma = 1.5, Lz = ktot / max(itot, jtot)) with z walls, uniform when
+// z is periodic; ghosts by reflection, faces at midpoints of centers.
+void served_metrics(const kl_request_t &q, std::vector<double> &dzi, std::vector<double> &dzhi, double *dzmin)
+{
+    const int kt = q.ktot, kc = kt + 2;
+    const double Lz = (double)kt / (double)std::max(q.itot, q.jtot);
+    const double gamma = q.bc == KL_BC_ZPERIODIC ? 0.0 : 1.5;
+    std::vector<double> z(kc), zh(kc), dz(kc), dzh(kc);
+    for (int k = 1; k <= kt; ++k) {
+        const double s = (k - 0.5) / kt;
+        z[k] = gamma == 0.0 ? (k - 0.5) * (Lz / kt) : Lz * (1.0 - tanh(gamma * (1.0 - s)) / tanh(gamma));
+    }
+    z[0] = -z[1];
+    z[kt + 1] = 2.0 * Lz - z[kt];
+    for (int k = 1; k <= kt + 1; ++k) zh[k] = 0.5 * (z[k - 1] + z[k]);
+    zh[0] = -zh[2];
+    for (int k = 1; k <= kt; ++k) dz[k] = zh[k + 1] - zh[k];
+    dz[0] = dz[1];
+    dz[kt + 1] = dz[kt];
+    for (int k = 1; k <= kt + 1; ++k) dzh[k] = z[k] - z[k - 1];
+    dzh[0] = dzh[1];
+    dzi.resize(kc);
+    dzhi.resize(kc);
+    *dzmin = INFINITY;
+    for (int k = 0; k < kc; ++k) {
+        dzi[k] = 1.0 / dz[k];
+        dzhi[k] = 1.0 / dzh[k];
+        if (k >= 1 && k <= kt) *dzmin = std::min(*dzmin, dz[k]);
+    }
+}
+
+struct DevBuf {
+    void *d = nullptr;
+    void *h = nullptr;
+    size_t cap = 0;
+    ~DevBuf()
+    {
+        if (d) (void)hipFree(d);
+        if (h) (void)hipHostFree(h);
+    }
+    hipError_t ensure(size_t bytes)
+    {
+        if (bytes <= cap) return hipSuccess;
+        if (d) (void)hipFree(d);
+        if (h) (void)hipHostFree(h);
+        d = h = nullptr;
+        cap = std::max(bytes, (size_t)65536) * 2;
+        hipError_t e = hipMalloc(&d, cap);
+        if (e == hipSuccess) e = hipHostMalloc(&h, cap, hipHostMallocDefault);
+        if (e != hipSuccess) cap = 0;
+        return e;
+    }
+};
+
+struct Server {
+    char *base = nullptr;
+    size_t arena_bytes = 0, budget = 0, used = 0, peak = 0;
+    Arena arena{0};
+    int device = 0, ncu = 256;
+    hipStream_t stream = nullptr;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Req *> queue;
+    std::vector<Req *> active;
+    std::unordered_map<uint64_t, Req *> reqs;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    std::thread th;
+    int64_t ticks = 0, launches = 0, ndone = 0, point_steps = 0;
+    DevBuf tab;  // per-tick tables (descriptors, tiles, time steps)
+
+    Server(void *arena_ptr, size_t ab, size_t bb) : base((char *)arena_ptr), arena_bytes(ab), budget(bb), arena(ab) {}
+};
+
+size_t footprint(const kl_request_t &q, int64_t *off, int64_t *js, int64_t *ks, int64_t *alloc)
+{
+    kl_layout(q.itot, q.jtot, q.ktot, q.dtype, off, js, ks, alloc);
+    const size_t s = q.dtype == KL_F32 ? 4 : 8;
+    return 6 * round_up((size_t)*alloc * s) + 2 * round_up((size_t)(q.ktot + 2) * s) + ALIGN;
+}
+
+// Lay out an admitted request in its arena block and queue its initial state.
+int init_request(Server &S, Req &q)
+{
+    int64_t off, js, ks, alloc;
+    footprint(q.r, &off, &js, &ks, &alloc);
+    const size_t s = q.r.dtype == KL_F32 ? 4 : 8;
+    char *p = S.base + q.off;
+    for (int n = 0; n < 6; ++n) {
+        q.f[n] = p;
+        p += round_up((size_t)alloc * s);
+    }
+    char *dzi = p;
+    p += round_up((size_t)(q.r.ktot + 2) * s);
+    char *dzhi = p;
+    p += round_up((size_t)(q.r.ktot + 2) * s);
+    q.d_sum = (double *)p;
+    std::vector<double> mi, mhi;
+    double dzmin;
+    served_metrics(q.r, mi, mhi, &dzmin);
+    const int kc = q.r.ktot + 2;
+    q.metrics.resize(2 * kc * s);
+    for (int k = 0; k < kc; ++k) {
+        if (s == 4) {
+            ((float *)q.metrics.data())[k] = (float)mi[k];
+            ((float *)q.metrics.data())[kc + k] = (float)mhi[k];
+        } else {
+            ((double *)q.metrics.data())[k] = mi[k];
+            ((double *)q.metrics.data())[kc + k] = mhi[k];
+        }
+    }
+    q.g.itot = q.r.itot;
+    q.g.jtot = q.r.jtot;
+    q.g.ktot = q.r.ktot;
+    q.g.gc = 1;
+    q.g.off = off;
+    q.g.jstride = js;
+    q.g.kstride = ks;
+    q.g.dxi = q.r.dtype == KL_F32 ? (double)(float)q.r.itot : (double)q.r.itot;
+    q.g.dyi = q.r.dtype == KL_F32 ? (double)(float)q.r.jtot : (double)q.r.jtot;
+    q.g.dzi = dzi;
+    q.g.dzhi = dzhi;
+    q.g.dtype = q.r.dtype;
+    q.g.bc = q.r.bc;
+    q.dt = q.r.dt > 0 ? q.r.dt : 0.1 * std::min(std::min(1.0 / q.r.itot, 1.0 / q.r.jtot), dzmin);
+    hipError_t e = hipMemcpyAsync(dzi, q.metrics.data(), kc * s, hipMemcpyHostToDevice, S.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dzhi, q.metrics.data() + kc * s, kc * s, hipMemcpyHostToDevice, S.stream);
+    HostArgs a = make_args(&q.g);
+    if (e == hipSuccess) e = launch_gen_uniform(a, q.r.seed, q.f[0], q.f[1], q.f[2], S.stream);
+    if (e == hipSuccess) e = launch_fill_ghosts(a, q.f[0], q.f[1], q.f[2], S.stream);
+    return e == hipSuccess ? KL_OK : hip_fail(e, "request init");
+}
+
+// One tick: every active request advances one step.
+int run_tick(Server &S)
+{
+    const std::vector<Req *> &act = S.active;
+    // per-dtype descriptor indices
+    std::vector<StencilArgs<float>> df;
+    std::vector<StencilArgs<double>> dd;
+    std::vector<double> dtf, dtd;
+    std::vector<int> didx(act.size());
+    for (size_t n = 0; n < act.size(); ++n) {
+        Req &q = *act[n];
+        HostArgs a = make_args(&q.g);
+        a.u = q.f[0];
+        a.v = q.f[1];
+        a.w = q.f[2];
+        a.ut = q.f[3];
+        a.vt = q.f[4];
+        a.wt = q.f[5];
+        a.visc = q.r.visc;
+        if (q.g.dtype == KL_F32) {
+            didx[n] = (int)df.size();
+            df.push_back(device_args<float>(a));
+            dtf.push_back(q.dt);
+        } else {
+            didx[n] = (int)dd.size();
+            dd.push_back(device_args<double>(a));
+            dtd.push_back(q.dt);
+        }
+    }
+    // tiles
+    std::map<std::tuple<int, int, int>, std::vector<int4>> groups;
+    std::vector<int4> rows[2];
+    for (size_t n = 0; n < act.size(); ++n) {
+        Req &q = *act[n];
+        for (int kernel = 0; kernel < 2; ++kernel) {
+            const int vi = batch_variant(&q.g, kernel, q.f);
+            if (vi < 0) return fail(KL_ERR_INVALID, "no batched configuration for request %llu",
+                                    (unsigned long long)q.ticket);
+            const Variant &v = variants(kernel, q.g.dtype)[vi];
+            auto &tl = groups[std::make_tuple(kernel, q.g.dtype, vi)];
+            const int nbx = (int)cdivu(q.g.itot, 64 * v.vx), nby = (int)cdivu(q.g.jtot, v.by),
+                      nbz = (int)cdivu(q.g.ktot, v.kb);
+            for (int tz = 0; tz < nbz; ++tz)
+                for (int ty = 0; ty < nby; ++ty)
+                    for (int tx = 0; tx < nbx; ++tx) tl.push_back(make_int4(didx[n], tx, ty, tz));
+        }
+        const int nrows = q.g.jtot * q.g.ktot;
+        for (int r0 = 0; r0 < nrows; r0 += 32)
+            rows[q.g.dtype].push_back(make_int4(didx[n], r0, std::min(nrows, r0 + 32), 0));
+    }
+    // pack tables: [desc f32][desc f64][dt f32][dt f64][rows f32][rows f64][group tiles...]
+    size_t off = 0;
+    auto place = [&](size_t bytes) {
+        const size_t o = off;
+        off += round_up(bytes);
+        return o;
+    };
+    const size_t o_df = place(df.size() * sizeof(df[0])), o_dd = place(dd.size() * sizeof(dd[0]));
+    const size_t o_tf = place(dtf.size() * 8), o_td = place(dtd.size() * 8);
+    const size_t o_rf = place(rows[0].size() * sizeof(int4)), o_rd = place(rows[1].size() * sizeof(int4));
+    std::vector<size_t> o_g;
+    for (auto &kv : groups) o_g.push_back(place(kv.second.size() * sizeof(int4)));
+    hipError_t e = S.tab.ensure(off);
+    if (e != hipSuccess) return hip_fail(e, "tick tables");
+    char *h = (char *)S.tab.h;
+    char *d = (char *)S.tab.d;
+    memcpy(h + o_df, df.data(), df.size() * sizeof(df[0]));
+    memcpy(h + o_dd, dd.data(), dd.size() * sizeof(dd[0]));
+    memcpy(h + o_tf, dtf.data(), dtf.size() * 8);
+    memcpy(h + o_td, dtd.data(), dtd.size() * 8);
+    memcpy(h + o_rf, rows[0].data(), rows[0].size() * sizeof(int4));
+    memcpy(h + o_rd, rows[1].data(), rows[1].size() * sizeof(int4));
+    {
+        size_t gi = 0;
+        for (auto &kv : groups) memcpy(h + o_g[gi++], kv.second.data(), kv.second.size() * sizeof(int4));
+    }
+    if ((e = hipMemcpyAsync(d, h, off, hipMemcpyHostToDevice, S.stream)) != hipSuccess) return hip_fail(e, "tables");
+    const size_t o_desc[2] = {o_df, o_dd}, o_dt[2] = {o_tf, o_td}, o_rows[2] = {o_rf, o_rd};
+    // zero tendencies
+    for (int dt = 0; dt < 2; ++dt) {
+        if (rows[dt].empty()) continue;
+        const int nt = (int)rows[dt].size(), nb = std::min(nt, S.ncu * 8);
+        if ((e = launch_zero_batch(dt, d + o_desc[dt], d + o_rows[dt], nt, nb, S.stream)) != hipSuccess)
+            return hip_fail(e, "zero");
+        ++S.launches;
+    }
+    // advec_u groups, then diff_uvw groups (map order: kernel is the first key)
+    {
+        size_t gi = 0;
+        for (auto &kv : groups) {
+            const int kernel = std::get<0>(kv.first), dt = std::get<1>(kv.first), vi = std::get<2>(kv.first);
+            const Variant &v = variants(kernel, dt)[vi];
+            const int nt = (int)kv.second.size();
+            const int nb = (int)std::min<int64_t>(nt, (int64_t)S.ncu * v.occupancy());
+            if ((e = v.batch(d + o_desc[dt], d + o_g[gi], nt, nb, S.stream)) != hipSuccess) return hip_fail(e, v.name);
+            ++S.launches;
+            ++gi;
+        }
+    }
+    // Euler update + ghost refill
+    for (int dt = 0; dt < 2; ++dt) {
+        if (rows[dt].empty()) continue;
+        const int nt = (int)rows[dt].size(), nb = std::min(nt, S.ncu * 8);
+        if ((e = launch_euler_batch(dt, d + o_desc[dt], d + o_rows[dt], nt, nb, (const double *)(d + o_dt[dt]),
+                                    S.stream)) != hipSuccess)
+            return hip_fail(e, "euler");
+        ++S.launches;
+    }
+    if ((e = hipStreamSynchronize(S.stream)) != hipSuccess) return hip_fail(e, "tick");
+    return KL_OK;
+}
+
+// Checksums of finished requests (FP64, on the server stream).
+int finish(Server &S, std::vector<Req *> &done)
+{
+    if (done.empty()) return KL_OK;
+    void *ws = workspace(reduce_scratch_bytes(), S.stream);
+    if (!ws) return fail(KL_ERR_NOMEM, "server workspace");
+    for (Req *q : done) {
+        hipError_t e = launch_reduce(make_args(&q->g), 1, q->f[0], q->f[1], q->f[2], q->d_sum, ws, S.stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(q->checksum, q->d_sum, 9 * sizeof(double), hipMemcpyDeviceToHost, S.stream);
+        if (e != hipSuccess) return hip_fail(e, "checksum");
+        ++S.launches;
+    }
+    const hipError_t e = hipStreamSynchronize(S.stream);
+    return e == hipSuccess ? KL_OK : hip_fail(e, "checksum sync");
+}
+
+void server_loop(Server *Sp)
+{
+    Server &S = *Sp;
+    (void)hipSetDevice(S.device);
+    for (;;) {
+        std::vector<Req *> fresh;
+        {
+            std::unique_lock<std::mutex> lk(S.mu);
+            for (;;) {
+                // admission in arrival order while the head fits budget and arena
+                while (!S.queue.empty()) {
+                    Req *q = S.queue.front();
+                    if (S.used + q->bytes > S.budget) break;
+                    size_t off;
+                    if (!S.arena.alloc(q->bytes, &off)) break;
+                    q->off = off;
+                    S.used += q->bytes;
+                    S.peak = std::max(S.peak, S.used);
+                    q->state = 1;
+                    q->t_admit = now_ns();
+                    q->steps_left = q->r.nsteps;
+                    S.queue.pop_front();
+                    S.active.push_back(q);
+                    fresh.push_back(q);
+                }
+                if (!S.active.empty()) break;
+                if (S.stop) {
+                    // nothing runs and the head cannot be admitted now: fail what is left
+                    for (Req *q : S.queue) {
+                        q->state = 3;
+                        q->err = KL_ERR_BUDGET;
+                        q->t_done = now_ns();
+                    }
+                    S.queue.clear();
+                    return;
+                }
+                S.cv.wait(lk);
+            }
+        }
+        int rc = KL_OK;
+        for (Req *q : fresh)
+            if (rc == KL_OK) rc = init_request(S, *q);
+        if (rc == KL_OK) rc = run_tick(S);
+        std::vector<Req *> done;
+        int64_t pts = 0;
+        for (Req *q : S.active) {
+            --q->steps_left;
+            pts += (int64_t)q->g.itot * q->g.jtot * q->g.ktot;
+            if (q->steps_left == 0 || rc != KL_OK) done.push_back(q);
+        }
+        if (rc == KL_OK) rc = finish(S, done);
+        const int64_t t = now_ns();
+        std::lock_guard<std::mutex> lk(S.mu);
+        ++S.ticks;
+        if (rc == KL_OK) S.point_steps += pts;
+        for (Req *q : done) {
+            q->state = rc == KL_OK ? 2 : 3;
+            q->err = rc;
+            q->t_done = t;
+            ++S.ndone;
+        }
+        std::vector<Req *> still;
+        for (Req *q : S.active)
+            if (q->state == 1) still.push_back(q);
+        S.active.swap(still);
+        S.cv.notify_all();
+    }
+}
+
+}  // namespace
+}  // namespace kl
+
+using namespace kl;
+
+extern "C" {
+
+int kl_server_create(void *arena, size_t arena_bytes, size_t budget_bytes, void **srv)
+{
+    clear_error();
+    if (!arena || !srv || arena_bytes == 0) return fail(KL_ERR_INVALID, "bad server arguments");
+    if (budget_bytes == 0 || budget_bytes > arena_bytes) budget_bytes = arena_bytes;
+    if ((uintptr_t)arena % ALIGN) return fail(KL_ERR_INVALID, "arena must be %zu-byte aligned", ALIGN);
+    Server *S = new (std::nothrow) Server(arena, arena_bytes, budget_bytes);
+    if (!S) return fail(KL_ERR_NOMEM, "server");
+    hipError_t e = hipGetDevice(&S->device);
+    hipDeviceProp_t prop;
+    if (e == hipSuccess) e = hipGetDeviceProperties(&prop, S->device);
+    if (e == hipSuccess) S->ncu = prop.multiProcessorCount;
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete S;
+        return hip_fail(e, "server create");
+    }
+    S->th = std::thread(server_loop, S);
+    *srv = S;
+    return KL_OK;
+}
+
+int kl_submit(void *srv, const kl_request_t *req, uint64_t *ticket)
+{
+    clear_error();
+    if (!srv || !req || !ticket) return fail(KL_ERR_INVALID, "NULL argument");
+    Server &S = *(Server *)srv;
+    const kl_request_t &r = *req;
+    if (r.itot < 1 || r.jtot < 1 || r.ktot < 1 || (r.bc != KL_BC_ZPERIODIC && r.ktot < 2))
+        return fail(KL_ERR_INVALID, "request sizes %d x %d x %d", r.itot, r.jtot, r.ktot);
+    if (r.dtype != KL_F32 && r.dtype != KL_F64) return fail(KL_ERR_INVALID, "request dtype %d", r.dtype);
+    if (r.bc < 0 || r.bc > 2) return fail(KL_ERR_INVALID, "request bc %d", r.bc);
+    if (r.nsteps < 1) return fail(KL_ERR_INVALID, "request nsteps %d", r.nsteps);
+    Req *q = new (std::nothrow) Req();
+    if (!q) return fail(KL_ERR_NOMEM, "request");
+    q->r = r;
+    int64_t off, js, ks, alloc;
+    q->bytes = footprint(r, &off, &js, &ks, &alloc);
+    if (q->bytes > S.budget) {
+        const size_t b = q->bytes;
+        delete q;
+        return fail(KL_ERR_BUDGET, "request needs %zu bytes, budget is %zu", b, S.budget);
+    }
+    q->t_arrive = now_ns();
+    std::lock_guard<std::mutex> lk(S.mu);
+    if (S.stop) {
+        delete q;
+        return fail(KL_ERR_INVALID, "server is stopping");
+    }
+    q->ticket = S.next_ticket++;
+    S.reqs[q->ticket] = q;
+    S.queue.push_back(q);
+    *ticket = q->ticket;
+    S.cv.notify_all();
+    return KL_OK;
+}
+
+int kl_poll(void *srv, uint64_t ticket, kl_result_t *out)
+{
+    clear_error();
+    if (!srv || !out) return fail(KL_ERR_INVALID, "NULL argument");
+    Server &S = *(Server *)srv;
+    std::lock_guard<std::mutex> lk(S.mu);
+    auto it = S.reqs.find(ticket);
+    if (it == S.reqs.end()) return fail(KL_ERR_NOTFOUND, "ticket %llu", (unsigned long long)ticket);
+    const Req &q = *it->second;
+    memset(out, 0, sizeof *out);
+    out->state = q.state;
+    out->err = q.err;
+    out->t_arrive_ns = q.t_arrive;
+    out->t_admit_ns = q.t_admit;
+    out->t_done_ns = q.t_done;
+    if (q.state >= 2) {
+        memcpy(out->checksum, q.checksum, sizeof q.checksum);
+        for (int n = 0; n < 3; ++n) out->fields[n] = q.f[n];
+        out->off = q.g.off;
+        out->jstride = q.g.jstride;
+        out->kstride = q.g.kstride;
+        return KL_OK;
+    }
+    return KL_ERR_AGAIN;
+}
+
+int kl_release(void *srv, uint64_t ticket)
+{
+    clear_error();
+    if (!srv) return fail(KL_ERR_INVALID, "NULL server");
+    Server &S = *(Server *)srv;
+    std::lock_guard<std::mutex> lk(S.mu);
+    auto it = S.reqs.find(ticket);
+    if (it == S.reqs.end()) return fail(KL_ERR_NOTFOUND, "ticket %llu", (unsigned long long)ticket);
+    Req *q = it->second;
+    if (q->state < 2) return fail(KL_ERR_AGAIN, "ticket %llu is not finished", (unsigned long long)ticket);
+    if (q->t_admit) {  // admitted requests hold an arena block until released
+        S.arena.release(q->off, q->bytes);
+        S.used -= q->bytes;
+    }
+    S.reqs.erase(it);
+    delete q;
+    S.cv.notify_all();
+    return KL_OK;
+}
+
+int kl_server_stats(void *srv, int64_t out[5])
+{
+    clear_error();
+    if (!srv || !out) return fail(KL_ERR_INVALID, "NULL argument");
+    Server &S = *(Server *)srv;
+    std::lock_guard<std::mutex> lk(S.mu);
+    out[0] = S.ticks;
+    out[1] = S.launches;
+    out[2] = S.ndone;
+    out[3] = (int64_t)S.peak;
+    out[4] = S.point_steps;
+    return KL_OK;
+}
+
+int kl_server_destroy(void *srv)
+{
+    clear_error();
+    if (!srv) return fail(KL_ERR_INVALID, "NULL server");
+    Server *S = (Server *)srv;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+        S->cv.notify_all();
+    }
+    if (S->th.joinable()) S->th.join();
+    for (auto &kv : S->reqs) delete kv.second;
+    if (S->stream) (void)hipStreamDestroy(S->stream);
+    delete S;
+    return KL_OK;
+}
+
+}  // extern "C"

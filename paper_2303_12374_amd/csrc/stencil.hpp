@@ -18,6 +18,7 @@ template <typename T>
 struct StencilArgs {
     int itot, jtot, ktot;
     int kw0;                 // first w level advanced: 2 with z walls, 1 periodic
+    int bc;                  // KL_BC_* (used by the batched Euler update)
     int64_t off, js, ks;
     T dxi, dyi, visc;
     const T *__restrict__ dzi;

@@ -32,17 +32,15 @@ __device__ __forceinline__ T shfl_down1(T x)
 }
 
 // Geometry of one zl tile as seen by one thread.
-template <int VX, int BY, int KB, int XCD>
+template <int VX, int BY, int KB>
 struct ZlTile {
     int lane, r, i0w, i0, j0, nv, k0, k1, nlanes, top;
     bool lane_on, own;
     int xrow_g, xrow_l;  // extra (halo) row of this wave: global row and LDS row, -1 if none
 
-    __device__ __forceinline__ ZlTile(int itot, int jtot, int ktot, int nbx, int nby, int nbz)
+    __device__ __forceinline__ ZlTile(int itot, int jtot, int ktot, int tx, int ty, int tz)
     {
         constexpr int TX = 64 * VX;
-        int tx, ty, tz;
-        tile_of<64, BY, XCD>(nbx, nby, nbz, tx, ty, tz);
         lane = (int)threadIdx.x;
         r = (int)threadIdx.y;
         i0w = 1 + tx * TX;
@@ -69,15 +67,19 @@ struct ZlTile {
 // ---------------------------------------------------------------------------
 // diff_uvw
 // ---------------------------------------------------------------------------
-template <typename T, int VX, int BY, int KB, int XCD>
-__global__ __launch_bounds__(64 * BY) void diff_uvw_zl(StencilArgs<T> a)
+// One tile (tx, ty, tz) of diff_uvw; called by the single-grid kernel and by
+// the persistent batched kernel.  Starts with a barrier so that a block can
+// run tiles back to back on the same LDS.
+template <typename T, int VX, int BY, int KB>
+__device__ __forceinline__ void diff_uvw_zl_tile(const StencilArgs<T> &a, int tx, int ty, int tz)
 {
     static_assert(BY >= 2, "two halo rows need two waves");
     constexpr int TX = 64 * VX;
     typedef T RowT[TX];
     __shared__ __align__(16) RowT sh[2][3][BY + 2];
+    __syncthreads();
 
-    const ZlTile<VX, BY, KB, XCD> t(a.itot, a.jtot, a.ktot, a.nbx, a.nby, a.nbz);
+    const ZlTile<VX, BY, KB> t(a.itot, a.jtot, a.ktot, tx, ty, tz);
     const int64_t js = a.js, ks = a.ks;
     const int64_t c_own = a.off + t.i0 + (int64_t)(t.j0 + t.r) * js;
     const int64_t c_x = a.off + t.i0 + (int64_t)t.xrow_g * js;
@@ -183,8 +185,8 @@ __global__ __launch_bounds__(64 * BY) void diff_uvw_zl(StencilArgs<T> a)
 // ---------------------------------------------------------------------------
 // advec_u
 // ---------------------------------------------------------------------------
-template <typename T, int VX, int BY, int KB, int XCD>
-__global__ __launch_bounds__(64 * BY) void advec_u_zl(StencilArgs<T> a)
+template <typename T, int VX, int BY, int KB>
+__device__ __forceinline__ void advec_u_zl_tile(const StencilArgs<T> &a, int tx, int ty, int tz)
 {
     static_assert(BY >= 2, "two halo rows need two waves");
     constexpr int TX = 64 * VX;
@@ -192,8 +194,9 @@ __global__ __launch_bounds__(64 * BY) void advec_u_zl(StencilArgs<T> a)
     __shared__ __align__(16) RowT shu[2][BY + 2];  // u rows j0-1 .. j0+nv
     __shared__ __align__(16) RowT shv[2][BY + 2];  // v rows j0 .. j0+nv (LDS row r+1 = tile row r)
     __shared__ T shvl[2][BY + 2];                   // v left of the segment, same rows
+    __syncthreads();
 
-    const ZlTile<VX, BY, KB, XCD> t(a.itot, a.jtot, a.ktot, a.nbx, a.nby, a.nbz);
+    const ZlTile<VX, BY, KB> t(a.itot, a.jtot, a.ktot, tx, ty, tz);
     const int64_t js = a.js, ks = a.ks;
     const int64_t c_own = a.off + t.i0 + (int64_t)(t.j0 + t.r) * js;
     const int64_t c_x = a.off + t.i0 + (int64_t)t.xrow_g * js;
@@ -325,6 +328,69 @@ __global__ __launch_bounds__(64 * BY) void advec_u_zl(StencilArgs<T> a)
                     vstore<T, VX>(a.ut + c_own + (int64_t)k * ks, Q[p]);
                 }
                 if (ld_own && k + 3 <= k1) vload<T, VX>(ub, U + c_own + (int64_t)(k + 3) * ks);
+            }
+        }
+    }
+}
+
+// Single-grid kernels: one block per tile.
+template <typename T, int VX, int BY, int KB, int XCD>
+__global__ __launch_bounds__(64 * BY) void diff_uvw_zl(StencilArgs<T> a)
+{
+    int tx, ty, tz;
+    tile_of<64, BY, XCD>(a.nbx, a.nby, a.nbz, tx, ty, tz);
+    diff_uvw_zl_tile<T, VX, BY, KB>(a, tx, ty, tz);
+}
+
+template <typename T, int VX, int BY, int KB, int XCD>
+__global__ __launch_bounds__(64 * BY) void advec_u_zl(StencilArgs<T> a)
+{
+    int tx, ty, tz;
+    tile_of<64, BY, XCD>(a.nbx, a.nby, a.nbz, tx, ty, tz);
+    advec_u_zl_tile<T, VX, BY, KB>(a, tx, ty, tz);
+}
+
+// Persistent batched kernels: block b runs tiles b, b + gridDim.x, ... of a
+// static tile list; tile = (grid, tx, ty, tz) into a table of per-grid
+// arguments.  The assignment is fixed, so results do not depend on timing.
+template <typename T, int VX, int BY, int KB>
+__global__ __launch_bounds__(64 * BY) void diff_uvw_zl_batch(const StencilArgs<T> *__restrict__ grids,
+                                                            const int4 *__restrict__ tiles, int ntiles)
+{
+    for (int n = blockIdx.x; n < ntiles; n += gridDim.x) {
+        const int4 tl = tiles[n];
+        const StencilArgs<T> a = grids[tl.x];
+        diff_uvw_zl_tile<T, VX, BY, KB>(a, tl.y, tl.z, tl.w);
+    }
+}
+
+template <typename T, int VX, int BY, int KB>
+__global__ __launch_bounds__(64 * BY) void advec_u_zl_batch(const StencilArgs<T> *__restrict__ grids,
+                                                           const int4 *__restrict__ tiles, int ntiles)
+{
+    for (int n = blockIdx.x; n < ntiles; n += gridDim.x) {
+        const int4 tl = tiles[n];
+        const StencilArgs<T> a = grids[tl.x];
+        advec_u_zl_tile<T, VX, BY, KB>(a, tl.y, tl.z, tl.w);
+    }
+}
+
+// Batched zeroing of the tendencies: tile = (grid, first row, end row) over
+// the rows (j, k) of the interior, rows numbered j-1 + jtot*(k-1).
+template <typename T>
+__global__ __launch_bounds__(256) void zero_tendencies_batch(const StencilArgs<T> *__restrict__ grids,
+                                                            const int4 *__restrict__ tiles, int ntiles)
+{
+    for (int n = blockIdx.x; n < ntiles; n += gridDim.x) {
+        const int4 tl = tiles[n];
+        const StencilArgs<T> a = grids[tl.x];
+        for (int r = tl.y; r < tl.z; ++r) {
+            const int j = 1 + r % a.jtot, k = 1 + r / a.jtot;
+            const int64_t base = a.off + (int64_t)j * a.js + (int64_t)k * a.ks;
+            for (int i = 1 + (int)threadIdx.x; i <= a.itot; i += 256) {
+                a.ut[base + i] = T(0);
+                a.vt[base + i] = T(0);
+                a.wt[base + i] = T(0);
             }
         }
     }

@@ -18,6 +18,7 @@ StencilArgs<T> device_args(const HostArgs &h)
     a.jtot = h.jtot;
     a.ktot = h.ktot;
     a.kw0 = h.kw0;
+    a.bc = h.bc;
     a.off = h.off;
     a.js = h.js;
     a.ks = h.ks;
@@ -87,6 +88,30 @@ hipError_t launch_zl(const HostArgs &h, hipStream_t s)
     return hipGetLastError();
 }
 
+template <typename T, int KERNEL, int VX, int BY, int KB>
+hipError_t launch_zl_batch(const void *descs, const void *tiles, int ntiles, int nblocks, hipStream_t s)
+{
+    if (KERNEL == KL_KERNEL_ADVEC_U)
+        hipLaunchKernelGGL((advec_u_zl_batch<T, VX, BY, KB>), dim3(nblocks), dim3(64, BY), 0, s,
+                           (const StencilArgs<T> *)descs, (const int4 *)tiles, ntiles);
+    else
+        hipLaunchKernelGGL((diff_uvw_zl_batch<T, VX, BY, KB>), dim3(nblocks), dim3(64, BY), 0, s,
+                           (const StencilArgs<T> *)descs, (const int4 *)tiles, ntiles);
+    return hipGetLastError();
+}
+
+template <typename T, int KERNEL, int VX, int BY, int KB>
+int zl_batch_occupancy()
+{
+    int n = 0;
+    hipError_t e;
+    if (KERNEL == KL_KERNEL_ADVEC_U)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, advec_u_zl_batch<T, VX, BY, KB>, 64 * BY, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, diff_uvw_zl_batch<T, VX, BY, KB>, 64 * BY, 0);
+    return e == hipSuccess && n > 0 ? n : 1;
+}
+
 }  // namespace kl
 
 #define KL_STR2(x) #x
@@ -95,7 +120,8 @@ hipError_t launch_zl(const HostArgs &h, hipStream_t s)
 // One z-marching configuration entry.
 #define KL_ZC(T, DT, KERN, VX, BX, BY, KB, XCD)                                                   \
     Variant{"zc_v" KL_STR(VX) "_b" KL_STR(BX) "x" KL_STR(BY) "_k" KL_STR(KB) "_x" KL_STR(XCD), \
-            KERN, DT, FAMILY_ZC, VX, BX, BY, KB, XCD, &launch_zc<T, KERN, VX, BX, BY, KB, XCD>}
+            KERN, DT, FAMILY_ZC, VX, BX, BY, KB, XCD, &launch_zc<T, KERN, VX, BX, BY, KB, XCD>, nullptr, \
+            nullptr}
 
 #define KL_ZC_XCD(T, DT, KERN, VX, BX, BY, KB) \
     KL_ZC(T, DT, KERN, VX, BX, BY, KB, 0), KL_ZC(T, DT, KERN, VX, BX, BY, KB, 1)
@@ -110,7 +136,8 @@ hipError_t launch_zl(const HostArgs &h, hipStream_t s)
 // One LDS-staged z-marching configuration entry (block 64 x BY).
 #define KL_ZL(T, DT, KERN, VX, BY, KB, XCD)                                                   \
     Variant{"zl_v" KL_STR(VX) "_b64x" KL_STR(BY) "_k" KL_STR(KB) "_x" KL_STR(XCD), KERN, DT, \
-            FAMILY_ZL, VX, 64, BY, KB, XCD, &launch_zl<T, KERN, VX, BY, KB, XCD>}
+            FAMILY_ZL, VX, 64, BY, KB, XCD, &launch_zl<T, KERN, VX, BY, KB, XCD>,             \
+            &launch_zl_batch<T, KERN, VX, BY, KB>, &zl_batch_occupancy<T, KERN, VX, BY, KB>}
 
 #define KL_ZL_XCD(T, DT, KERN, VX, BY, KB) KL_ZL(T, DT, KERN, VX, BY, KB, 0), KL_ZL(T, DT, KERN, VX, BY, KB, 1)
 

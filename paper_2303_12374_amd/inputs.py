@@ -220,3 +220,25 @@ def analytic_padded(fn, field: int, itot: int, jtot: int, ktot: int, zg: dict,
     buf = np.full(alloc, np.nan)
     padded_view(buf, itot, jtot, ktot, off, js, ks)[...] = vals
     return buf
+
+
+# --------------------------------------------------------------------------
+# batched and served workloads
+# --------------------------------------------------------------------------
+
+BATCH_SIZES = (32, 64, 96, 128, 192)
+
+
+def batch_shapes(seed: int = 3, n_random: int = 48, n_aniso: int = 8):
+    """Grid shapes (itot, jtot, ktot) of the batched workload.
+
+    ``n_random`` grids draw each axis independently and uniformly from
+    {32, 64, 96, 128, 192} (counters of stream 7 of ``seed``), followed by
+    ``n_aniso`` anisotropic 256 x 256 x 32 grids.
+    """
+    with np.errstate(over="ignore"):
+        keys = field_key_base(seed, 7) + np.arange(3 * n_random, dtype=np.uint64)
+        r = uniform01(keys)
+    idx = np.minimum((r * len(BATCH_SIZES)).astype(np.int64), len(BATCH_SIZES) - 1)
+    shapes = [tuple(int(BATCH_SIZES[i]) for i in idx[3 * n:3 * n + 3]) for n in range(n_random)]
+    return shapes + [(256, 256, 32)] * n_aniso

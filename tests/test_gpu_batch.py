@@ -1,0 +1,124 @@
+"""Batched form: persistent tile-walking kernels in one HIP graph give the
+same bits as the single-grid launches, on every replay, and match the
+oracle."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2303_12374_amd import inputs
+from gpu_util import TOL, Case, outside_interior_mask, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def kl():
+    from paper_2303_12374_amd import kl as m
+    return m
+
+
+@pytest.fixture(autouse=True)
+def no_wisdom(tmp_path):
+    m = kl()
+    m.kl_set_wisdom_dir(str(tmp_path / "wisdom"))
+    yield
+    m.kl_set_wisdom_dir(None)
+
+
+def make_grids(shapes, dtypes, bcs, seed=0):
+    m = kl()
+    out = []
+    for n, (shape, dt, bc) in enumerate(zip(shapes, dtypes, bcs)):
+        g = m.Grid(*shape, dtype=dt, bc=bc)
+        f = [g.full() for _ in range(3)]
+        m.kl_generate_fields(g, seed + n, *f)
+        m.kl_fill_ghosts(g, *f)
+        t = [g.zeros_interior(fill=-3.0) for _ in range(3)]
+        out.append((g, f, t))
+    return out
+
+
+def plain(m, grids, visc):
+    res = []
+    for g, f, _ in grids:
+        t = [g.zeros_interior(fill=-3.0) for _ in range(3)]
+        m.kl_advec_u(g, t[0], *f)
+        m.kl_diff_uvw(g, *t, *f, visc)
+        res.append([x.cpu().numpy() for x in t])
+    return res
+
+
+SHAPES = [(64, 64, 64), (32, 96, 40), (192, 32, 17), (128, 128, 8), (96, 20, 33), (256, 8, 12),
+          (40, 24, 6), (33, 7, 5)]
+
+
+def test_batch_bitwise_equals_single_grid_launches():
+    m = kl()
+    dts = [0, 1, 0, 1, 0, 0, 1, 0]
+    bcs = [0, 2, 0, 0, 1, 2, 0, 2]
+    grids = make_grids(SHAPES, dts, bcs, seed=11)
+    visc = 1e-5
+    ref = plain(m, grids, visc)
+    b = m.kl_batch_create([g for g, _, _ in grids], [f + t for _, f, t in grids], visc, True)
+    try:
+        nk, nt = m.kl_batch_info(b)
+        assert nk >= 2 and nt >= len(grids)
+        for rep in range(3):
+            for g, _, t in grids:  # garbage in the interiors: the graph zeroes them
+                for x in t:
+                    g.interior(x).fill_(9.0)
+            m.kl_batch_run(b)
+            torch.cuda.synchronize()
+            # eager work between replays
+            torch.cuda.synchronize()
+            for (g, _, t), r in zip(grids, ref):
+                mask = outside_interior_mask(g)
+                for x, y in zip(t, r):
+                    got = x.cpu().numpy()
+                    assert np.array_equal(got, y), f"replay {rep}: batched result differs for {g.itot}x{g.jtot}x{g.ktot}"
+                    assert np.all(got[mask] == -3.0)
+    finally:
+        m.kl_batch_destroy(b)
+
+
+def test_batch_matches_oracle():
+    m = kl()
+    cases = [Case(48, 40, 24, 0, seed=5), Case(64, 16, 20, 1, bc=2, seed=6)]
+    grids = []
+    for c in cases:
+        t = [c.g.zeros_interior(fill=0.0) for _ in range(3)]
+        grids.append((c, t))
+    b = m.kl_batch_create([c.g for c, _ in grids], [c.dev + t for c, t in grids], cases[0].visc, True)
+    m.kl_batch_run(b)
+    torch.cuda.synchronize()
+    m.kl_batch_destroy(b)
+    for c, t in grids:
+        adv, du, dv, dw = c.oracle_tendencies()
+        for x, r in zip(t, (adv + du, dv, dw)):
+            assert rel_err(c.gpu_interior(x), r) <= TOL[c.g.dtype] * 2
+
+
+def test_batched_workload_shapes_and_equality():
+    """The 48 + 8 grid workload (FP32) in one graph equals per-grid launches."""
+    m = kl()
+    shapes = inputs.batch_shapes(3)
+    assert len(shapes) == 56 and shapes[-1] == (256, 256, 32)
+    assert all(s in inputs.BATCH_SIZES for sh in shapes[:48] for s in sh)
+    grids = make_grids(shapes, [0] * 56, [0] * 56, seed=300)
+    ref = plain(m, grids, 1e-5)
+    b = m.kl_batch_create([g for g, _, _ in grids], [f + t for _, f, t in grids], 1e-5, True)
+    m.kl_batch_run(b)
+    torch.cuda.synchronize()
+    nk, nt = m.kl_batch_info(b)
+    m.kl_batch_destroy(b)
+    assert nk <= 16
+    for (g, _, t), r in zip(grids, ref):
+        for x, y in zip(t, r):
+            assert np.array_equal(x.cpu().numpy(), y)
+
+
+def test_batch_rejects_bad_arguments():
+    m = kl()
+    g = m.Grid(16, 16, 16)
+    f = [g.full() for _ in range(6)]
+    with pytest.raises(m.KLError):
+        m.kl_batch_create([g], [f[:5] + [None]], 1e-5, True)
