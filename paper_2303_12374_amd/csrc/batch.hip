@@ -64,7 +64,10 @@ int batch_variant(const kl_grid_t *g, int kernel, void *const f[6])
     const void *ptrs[6] = {f[0], f[1], f[2], f[3], f[4], f[5]};
     const int nptr = kernel == KL_KERNEL_ADVEC_U ? 4 : 6;
     const int sel = select_variant(g, kernel);
-    if (vs[sel].batch && variant_eligible(vs[sel], g, ptrs, nptr)) return sel;
+    // a selected configuration whose wave segment (64 * vx points) is wider
+    // than the grid's rows would leave most lanes idle: size one to the grid
+    if (vs[sel].batch && variant_eligible(vs[sel], g, ptrs, nptr) && 64 * vs[sel].vx <= std::max(64, g->itot))
+        return sel;
     // fallback: widest vector that divides itot and does not exceed the row
     const int vmax = g->dtype == KL_F32 ? 4 : 2;
     for (int vx = vmax; vx >= 1; vx /= 2) {

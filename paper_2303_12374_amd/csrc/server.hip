@@ -165,7 +165,9 @@ struct Server {
     bool stop = false;
     std::thread th;
     int64_t ticks = 0, launches = 0, ndone = 0, point_steps = 0;
-    DevBuf tab;  // per-tick tables (descriptors, tiles, time steps)
+    DevBuf tab[2];        // per-tick tables (descriptors, tiles, time steps), one per tick in flight
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    std::map<const Variant *, int> occ;  // resident blocks per CU of batched kernels
 
     Server(void *arena_ptr, size_t ab, size_t bb) : base((char *)arena_ptr), arena_bytes(ab), budget(bb), arena(ab) {}
 };
@@ -229,8 +231,9 @@ int init_request(Server &S, Req &q)
     return e == hipSuccess ? KL_OK : hip_fail(e, "request init");
 }
 
-// One tick: every active request advances one step.
-int run_tick(Server &S)
+// Enqueue one tick on the server stream: every active request advances one
+// step.  Tables go through slot `slot`, which the previous use has released.
+int run_tick(Server &S, int slot)
 {
     const std::vector<Req *> &act = S.active;
     // per-dtype descriptor indices
@@ -291,10 +294,10 @@ int run_tick(Server &S)
     const size_t o_rf = place(rows[0].size() * sizeof(int4)), o_rd = place(rows[1].size() * sizeof(int4));
     std::vector<size_t> o_g;
     for (auto &kv : groups) o_g.push_back(place(kv.second.size() * sizeof(int4)));
-    hipError_t e = S.tab.ensure(off);
+    hipError_t e = S.tab[slot].ensure(off);
     if (e != hipSuccess) return hip_fail(e, "tick tables");
-    char *h = (char *)S.tab.h;
-    char *d = (char *)S.tab.d;
+    char *h = (char *)S.tab[slot].h;
+    char *d = (char *)S.tab[slot].d;
     memcpy(h + o_df, df.data(), df.size() * sizeof(df[0]));
     memcpy(h + o_dd, dd.data(), dd.size() * sizeof(dd[0]));
     memcpy(h + o_tf, dtf.data(), dtf.size() * 8);
@@ -322,7 +325,9 @@ int run_tick(Server &S)
             const int kernel = std::get<0>(kv.first), dt = std::get<1>(kv.first), vi = std::get<2>(kv.first);
             const Variant &v = variants(kernel, dt)[vi];
             const int nt = (int)kv.second.size();
-            const int nb = (int)std::min<int64_t>(nt, (int64_t)S.ncu * v.occupancy());
+            auto oc = S.occ.find(&v);
+            if (oc == S.occ.end()) oc = S.occ.emplace(&v, v.occupancy()).first;
+            const int nb = (int)std::min<int64_t>(nt, (int64_t)S.ncu * oc->second);
             if ((e = v.batch(d + o_desc[dt], d + o_g[gi], nt, nb, S.stream)) != hipSuccess) return hip_fail(e, v.name);
             ++S.launches;
             ++gi;
@@ -337,33 +342,69 @@ int run_tick(Server &S)
             return hip_fail(e, "euler");
         ++S.launches;
     }
-    if ((e = hipStreamSynchronize(S.stream)) != hipSuccess) return hip_fail(e, "tick");
     return KL_OK;
 }
 
-// Checksums of finished requests (FP64, on the server stream).
-int finish(Server &S, std::vector<Req *> &done)
+// Enqueue the FP64 checksums of requests whose last step was just enqueued.
+int enqueue_checksums(Server &S, const std::vector<Req *> &done)
 {
     if (done.empty()) return KL_OK;
     void *ws = workspace(reduce_scratch_bytes(), S.stream);
     if (!ws) return fail(KL_ERR_NOMEM, "server workspace");
     for (Req *q : done) {
-        hipError_t e = launch_reduce(make_args(&q->g), 1, q->f[0], q->f[1], q->f[2], q->d_sum, ws, S.stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(q->checksum, q->d_sum, 9 * sizeof(double), hipMemcpyDeviceToHost, S.stream);
+        const hipError_t e = launch_reduce(make_args(&q->g), 1, q->f[0], q->f[1], q->f[2], q->d_sum, ws, S.stream);
         if (e != hipSuccess) return hip_fail(e, "checksum");
         ++S.launches;
     }
-    const hipError_t e = hipStreamSynchronize(S.stream);
-    return e == hipSuccess ? KL_OK : hip_fail(e, "checksum sync");
+    return KL_OK;
+}
+
+// A tick whose work is on the stream but not known to be complete.
+struct InFlight {
+    int slot;
+    int rc;
+    int64_t pts;
+    std::vector<Req *> finishing;
+};
+
+// Wait for the oldest tick in flight and publish the requests it finished.
+void complete(Server &S, std::deque<InFlight> &inflight)
+{
+    InFlight t = inflight.front();
+    inflight.pop_front();
+    int rc = t.rc;
+    if (rc == KL_OK) {
+        const hipError_t e = hipEventSynchronize(S.ev[t.slot]);
+        if (e != hipSuccess) rc = hip_fail(e, "tick");
+    }
+    for (Req *q : t.finishing) {
+        if (rc == KL_OK) {
+            const hipError_t e = hipMemcpy(q->checksum, q->d_sum, 9 * sizeof(double), hipMemcpyDeviceToHost);
+            if (e != hipSuccess) rc = hip_fail(e, "checksum copy");
+        }
+    }
+    const int64_t now = now_ns();
+    std::lock_guard<std::mutex> lk(S.mu);
+    ++S.ticks;
+    if (rc == KL_OK) S.point_steps += t.pts;
+    for (Req *q : t.finishing) {
+        q->state = rc == KL_OK ? 2 : 3;
+        q->err = rc;
+        q->t_done = now;
+        ++S.ndone;
+    }
+    S.cv.notify_all();
 }
 
 void server_loop(Server *Sp)
 {
     Server &S = *Sp;
     (void)hipSetDevice(S.device);
+    std::deque<InFlight> inflight;  // at most one tick waits while the next is prepared
+    int64_t tick = 0;
     for (;;) {
         std::vector<Req *> fresh;
+        bool idle = false;
         {
             std::unique_lock<std::mutex> lk(S.mu);
             for (;;) {
@@ -384,6 +425,10 @@ void server_loop(Server *Sp)
                     fresh.push_back(q);
                 }
                 if (!S.active.empty()) break;
+                if (!inflight.empty()) {
+                    idle = true;  // nothing to enqueue: retire the tick in flight first
+                    break;
+                }
                 if (S.stop) {
                     // nothing runs and the head cannot be admitted now: fail what is left
                     for (Req *q : S.queue) {
@@ -397,33 +442,43 @@ void server_loop(Server *Sp)
                 S.cv.wait(lk);
             }
         }
+        if (idle) {
+            complete(S, inflight);
+            continue;
+        }
+        const int slot = (int)(tick & 1);
         int rc = KL_OK;
         for (Req *q : fresh)
             if (rc == KL_OK) rc = init_request(S, *q);
-        if (rc == KL_OK) rc = run_tick(S);
-        std::vector<Req *> done;
-        int64_t pts = 0;
+        if (rc == KL_OK) rc = run_tick(S, slot);
+        InFlight t{slot, rc, 0, {}};
+        std::vector<Req *> still;
         for (Req *q : S.active) {
             --q->steps_left;
-            pts += (int64_t)q->g.itot * q->g.jtot * q->g.ktot;
-            if (q->steps_left == 0 || rc != KL_OK) done.push_back(q);
+            t.pts += (int64_t)q->g.itot * q->g.jtot * q->g.ktot;
+            if (q->steps_left == 0 || rc != KL_OK)
+                t.finishing.push_back(q);
+            else
+                still.push_back(q);
         }
-        if (rc == KL_OK) rc = finish(S, done);
-        const int64_t t = now_ns();
-        std::lock_guard<std::mutex> lk(S.mu);
-        ++S.ticks;
-        if (rc == KL_OK) S.point_steps += pts;
-        for (Req *q : done) {
-            q->state = rc == KL_OK ? 2 : 3;
-            q->err = rc;
-            q->t_done = t;
-            ++S.ndone;
+        if (rc == KL_OK) rc = enqueue_checksums(S, t.finishing);
+        if (rc == KL_OK) {
+            const hipError_t e = hipEventRecord(S.ev[slot], S.stream);
+            if (e != hipSuccess) rc = hip_fail(e, "tick event");
         }
-        std::vector<Req *> still;
-        for (Req *q : S.active)
-            if (q->state == 1) still.push_back(q);
-        S.active.swap(still);
-        S.cv.notify_all();
+        t.rc = rc;
+        {
+            std::lock_guard<std::mutex> lk(S.mu);
+            if (rc != KL_OK) {  // a failed tick fails every request it carried
+                for (Req *q : still) t.finishing.push_back(q);
+                still.clear();
+            }
+            S.active.swap(still);
+        }
+        inflight.push_back(t);
+        ++tick;
+        // keep one tick queued on the GPU while the host prepares the next
+        while (inflight.size() > 1) complete(S, inflight);
     }
 }
 
@@ -447,6 +502,7 @@ int kl_server_create(void *arena, size_t arena_bytes, size_t budget_bytes, void 
     if (e == hipSuccess) e = hipGetDeviceProperties(&prop, S->device);
     if (e == hipSuccess) S->ncu = prop.multiProcessorCount;
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking);
+    for (int n = 0; n < 2 && e == hipSuccess; ++n) e = hipEventCreateWithFlags(&S->ev[n], hipEventDisableTiming);
     if (e != hipSuccess) {
         delete S;
         return hip_fail(e, "server create");
@@ -563,6 +619,8 @@ int kl_server_destroy(void *srv)
     }
     if (S->th.joinable()) S->th.join();
     for (auto &kv : S->reqs) delete kv.second;
+    for (int n = 0; n < 2; ++n)
+        if (S->ev[n]) (void)hipEventDestroy(S->ev[n]);
     if (S->stream) (void)hipStreamDestroy(S->stream);
     delete S;
     return KL_OK;

@@ -54,7 +54,8 @@ class Server:
             start = res.fields[n] - self.arena.data_ptr()
             nelem = res.off + res.kstride * (ktot + 2)
             flat = self.arena[start:start + nelem * s].view(tdt)
-            box = flat.as_strided((ktot + 2, jtot + 2, itot + 2), (res.kstride, res.jstride, 1), res.off)
+            box = flat.as_strided((ktot + 2, jtot + 2, itot + 2), (res.kstride, res.jstride, 1),
+                                  flat.storage_offset() + res.off)
             out.append(box.cpu().numpy().astype(np.float64))
         return out
 
