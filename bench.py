@@ -26,8 +26,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "grid-points/s & HBM GB/s (% peak), advec_u+diff_uvw 512^3 FP32; p99 latency"
 PEAK_HBM_GBPS = 8000.0  # MI355X HBM3E, published
-KERNEL_SOURCES = ["paper_2303_12374_amd/csrc/stencil.hpp", "paper_2303_12374_amd/csrc/variants.hpp",
-                  "paper_2303_12374_amd/csrc/variants_f32.hip", "paper_2303_12374_amd/csrc/variants_f64.hip"]
+KERNEL_SOURCES = ["paper_2303_12374_amd/csrc/stencil.hpp", "paper_2303_12374_amd/csrc/stencil_zl.hpp",
+                  "paper_2303_12374_amd/csrc/variants.hpp"]
 
 
 def log(msg):
@@ -281,6 +281,67 @@ def served_run(kl, torch, reqs, t_arr, budget_gib):
             "peak_bytes": stats[3]}
 
 
+def copy_probe(torch, nbytes=570425344, reps=5):
+    """A plain device copy of known size (torch's copy kernel), for scaling
+    the HBM byte counters: FETCH_SIZE and WRITE_SIZE of one dispatch should
+    read nbytes each."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": nbytes, "reps": reps}), flush=True)
+
+
+def summarize_counters(fetch_csv, write_csv, workload_key, out_json, out_txt, command):
+    """Per-dispatch HBM bytes of the tendency kernels from two rocprofv3 --pmc
+    runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what
+    the same counter reads for the copy probe of known size."""
+    import csv
+    import statistics
+
+    def per_kernel(path, counter):
+        acc = {}
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] != counter:
+                    continue
+                acc.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return acc
+
+    fetch = per_kernel(fetch_csv, "FETCH_SIZE")
+    write = per_kernel(write_csv, "WRITE_SIZE")
+    copy_name = [k for k in fetch if "copy" in k and "at::native" in k]
+    nbytes = 570425344
+    out = {}
+    lines = [f"# HBM byte counters, {workload_key}", "", f"command: {command}", ""]
+    if copy_name:
+        cf = statistics.median(fetch[copy_name[0]]) * 1024
+        cw = statistics.median(write[copy_name[0]]) * 1024
+        fs, ws = nbytes / cf, nbytes / cw
+        lines.append(f"copy probe ({nbytes} B): FETCH_SIZE reads {cf:.0f} B -> scale {fs:.3f}; "
+                     f"WRITE_SIZE reads {cw:.0f} B -> scale {ws:.3f}")
+    else:
+        fs = ws = 1.0
+        lines.append("copy probe not found: scale 1")
+    lines.append("")
+    lines.append("| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes (scaled) |")
+    lines.append("|---|---|---|---|---|")
+    for k in fetch:
+        if "kl::" not in k or k not in write:
+            continue
+        f_kib = statistics.median(fetch[k])
+        w_kib = statistics.median(write[k])
+        hbm = f_kib * 1024 * fs + w_kib * 1024 * ws
+        name = "advec_u" if "advec_u" in k else ("diff_uvw" if "diff_uvw" in k else None)
+        lines.append(f"| `{k[:90]}` | {len(fetch[k])} | {f_kib:.0f} | {w_kib:.0f} | {hbm:.4g} |")
+        if name:
+            out[f"{name}:{workload_key}"] = {"kernel_symbol": k, "fetch_kib": f_kib, "write_kib": w_kib,
+                                            "fetch_scale": fs, "write_scale": ws,
+                                            "hbm_bytes_per_launch": hbm}
+    return out, "\n".join(lines) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -298,7 +359,34 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--served-requests", type=int, default=2000)
+    ap.add_argument("--copy-probe", action="store_true", help="run only the copy probe used to scale counters")
+    ap.add_argument("--with-copy-probe", action="store_true", help="run the copy probe first")
+    ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_JSON"),
+                    help="write profiles/counters.json from two rocprofv3 --pmc runs of "
+                         "'bench.py --with-copy-probe' and that run's JSON line (no GPU work)")
     args = ap.parse_args()
+
+    if args.summarize_counters:
+        itot, jtot, ktot = (int(x) for x in args.size.split(","))
+        wkey = f"{itot}x{jtot}x{ktot}_{args.dtype}"
+        cmd = ("rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv -d <dir> -o bench -- python3 "
+               "bench.py --with-copy-probe --steps 3 --warmup 1 --no-cpu-baseline --no-untuned --no-batched "
+               "--no-served")
+        fetch_csv, write_csv, bench_json = args.summarize_counters
+        out, txt = summarize_counters(fetch_csv, write_csv, wkey, None, None, cmd)
+        with open(bench_json) as f:
+            sel = json.loads([ln for ln in f if ln.startswith("{")][-1])["config"]["configurations"]
+        path = os.path.join(ROOT, "profiles", "counters.json")
+        old = json.load(open(path)) if os.path.exists(path) else {}
+        for k, v in out.items():
+            v["source_hash"] = kernel_source_hash()
+            v["variant"] = sel[k.split(":")[0]]
+            old[k] = v
+        json.dump(old, open(path, "w"), indent=1)
+        with open(os.path.join(ROOT, "profiles", f"hbm_counters_{wkey}.md"), "w") as f:
+            f.write(txt)
+        print(txt)
+        return
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -308,6 +396,10 @@ def main():
     import numpy as np
     import torch
 
+    if args.copy_probe or args.with_copy_probe:
+        copy_probe(torch)
+        if args.copy_probe:
+            return
     from paper_2303_12374_amd import inputs, kl
 
     itot, jtot, ktot = (int(x) for x in args.size.split(","))

@@ -123,6 +123,47 @@ __device__ __forceinline__ void vstore(T *p, const T (&s)[N])
     }
 }
 
+// Streaming (non-temporal) variants for data touched exactly once.
+template <typename T, int N>
+__device__ __forceinline__ void vload_nt(T (&d)[N], const T *p)
+{
+    if constexpr (N == 1) {
+        d[0] = __builtin_nontemporal_load(p);
+    } else {
+        typedef typename VecOf<T, N>::type V;
+        const V x = __builtin_nontemporal_load(reinterpret_cast<const V *>(p));
+#pragma unroll
+        for (int n = 0; n < N; ++n) d[n] = x[n];
+    }
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void vstore_nt(T *p, const T (&s)[N])
+{
+    if constexpr (N == 1) {
+        __builtin_nontemporal_store(s[0], p);
+    } else {
+        typedef typename VecOf<T, N>::type V;
+        V x;
+#pragma unroll
+        for (int n = 0; n < N; ++n) x[n] = s[n];
+        __builtin_nontemporal_store(x, reinterpret_cast<V *>(p));
+    }
+}
+
+// Tendency load/store: cached, or streaming when NT is set.
+template <int NT, typename T, int N>
+__device__ __forceinline__ void tload(T (&d)[N], const T *p)
+{
+    if constexpr (NT) vload_nt<T, N>(d, p); else vload<T, N>(d, p);
+}
+
+template <int NT, typename T, int N>
+__device__ __forceinline__ void tstore(T *p, const T (&s)[N])
+{
+    if constexpr (NT) vstore_nt<T, N>(p, s); else vstore<T, N>(p, s);
+}
+
 // Map a hardware workgroup id to a logical tile id so that the tiles each of
 // the 8 XCDs receives (the dispatcher deals workgroups to XCDs round robin)
 // are contiguous in the logical x-fastest order: neighbouring tiles, which
@@ -193,19 +234,28 @@ __global__ __launch_bounds__(256) void diff_uvw_plain(StencilArgs<T> a)
 // XCD-contiguous tile order.
 // ---------------------------------------------------------------------------
 
+// Tile order.  XCD = 0: hardware order (x fastest, then y, then z);
+// XCD = 1: each XCD gets one contiguous range of the whole tile list;
+// XCD = 2: each XCD gets one contiguous range of every z slab of tiles (when
+// the slab holds a multiple of 8 tiles), so all XCDs sweep the same levels
+// together while neighbouring rows stay under one L2.
 template <int BX, int BY, int XCD>
 __device__ __forceinline__ void tile_of(int nbx, int nby, int nbz, int &tx, int &ty, int &tz)
 {
     unsigned b = blockIdx.x;
-    if (XCD) b = xcd_remap(b, (unsigned)(nbx * nby * nbz));
+    if (XCD == 1) b = xcd_remap(b, (unsigned)(nbx * nby * nbz));
+    if (XCD == 2) {
+        const unsigned S = (unsigned)(nbx * nby);
+        if ((S & 7u) == 0) b = (b / S) * S + xcd_remap(b % S, S);
+    }
     tx = (int)(b % (unsigned)nbx);
     b /= (unsigned)nbx;
     ty = (int)(b % (unsigned)nby);
     tz = (int)(b / (unsigned)nby);
 }
 
-template <typename T, int VX, int BX, int BY, int KB, int XCD>
-__global__ __launch_bounds__(BX *BY) void advec_u_zc(StencilArgs<T> a)
+template <typename T, int VX, int BX, int BY, int KB, int XCD, int NT = 0, int WPE = 1>
+__global__ __launch_bounds__(BX *BY, WPE) void advec_u_zc(StencilArgs<T> a)
 {
     int tx, ty, tz;
     tile_of<BX, BY, XCD>(a.nbx, a.nby, a.nbz, tx, ty, tz);
@@ -243,7 +293,7 @@ __global__ __launch_bounds__(BX *BY) void advec_u_zc(StencilArgs<T> a)
         vnw = pv[js - 1];
         vload<T, VX>(wt, pw + ks);
         wtw = pw[ks - 1];
-        vload<T, VX>(tt, put);
+        tload<NT, T, VX>(tt, put);
         const T dzik = a.dzi[k];
 #pragma unroll
         for (int n = 0; n < VX; ++n) {
@@ -257,7 +307,7 @@ __global__ __launch_bounds__(BX *BY) void advec_u_zc(StencilArgs<T> a)
                                              v_w, vc[n], v_nw, vn[n], w_w, wc[n], w_tw, wt[n],
                                              dxi, dyi, dzik);
         }
-        vstore<T, VX>(put, tt);
+        tstore<NT, T, VX>(put, tt);
 #pragma unroll
         for (int n = 0; n < VX; ++n) {
             ub[n] = uc[n];
@@ -274,8 +324,8 @@ __global__ __launch_bounds__(BX *BY) void advec_u_zc(StencilArgs<T> a)
     }
 }
 
-template <typename T, int VX, int BX, int BY, int KB, int XCD>
-__global__ __launch_bounds__(BX *BY) void diff_uvw_zc(StencilArgs<T> a)
+template <typename T, int VX, int BX, int BY, int KB, int XCD, int NT = 0, int WPE = 1>
+__global__ __launch_bounds__(BX *BY, WPE) void diff_uvw_zc(StencilArgs<T> a)
 {
     int tx, ty, tz;
     tile_of<BX, BY, XCD>(a.nbx, a.nby, a.nbz, tx, ty, tz);
@@ -315,7 +365,7 @@ __global__ __launch_bounds__(BX *BY) void diff_uvw_zc(StencilArgs<T> a)
             vload<T, VX>(fs, p - js);
             const bool active = f < 2 || k >= kw0;
             if (active) {
-                vload<T, VX>(tt, pt[f]);
+                tload<NT, T, VX>(tt, pt[f]);
 #pragma unroll
                 for (int n = 0; n < VX; ++n) {
                     const T w_ = n == 0 ? fw[f] : fc[f][n - 1];
@@ -326,7 +376,7 @@ __global__ __launch_bounds__(BX *BY) void diff_uvw_zc(StencilArgs<T> a)
                                                         dxi2, dyi2, dzik, dzikm1, dzhik, visc);
                     tt[n] = tt[n] + d;
                 }
-                vstore<T, VX>(pt[f], tt);
+                tstore<NT, T, VX>(pt[f], tt);
             }
         }
 #pragma unroll

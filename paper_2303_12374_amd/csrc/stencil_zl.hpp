@@ -70,7 +70,7 @@ struct ZlTile {
 // One tile (tx, ty, tz) of diff_uvw; called by the single-grid kernel and by
 // the persistent batched kernel.  Starts with a barrier so that a block can
 // run tiles back to back on the same LDS.
-template <typename T, int VX, int BY, int KB>
+template <typename T, int VX, int BY, int KB, int NT>
 __device__ __forceinline__ void diff_uvw_zl_tile(const StencilArgs<T> &a, int tx, int ty, int tz)
 {
     static_assert(BY >= 2, "two halo rows need two waves");
@@ -115,7 +115,7 @@ __device__ __forceinline__ void diff_uvw_zl_tile(const StencilArgs<T> &a, int tx
             vload<T, VX>(R[0][f], F[f] + c_own + (int64_t)k0 * ks);
             vload<T, VX>(R[1][f], F[f] + c_own + (int64_t)(k0 + 1) * ks);
             if (k0 + 2 <= k1) vload<T, VX>(R[2][f], F[f] + c_own + (int64_t)(k0 + 2) * ks);
-            if (f < 2 || k0 >= kw0) vload<T, VX>(Q[0][f], Tt[f] + c_own + (int64_t)k0 * ks);
+            if (f < 2 || k0 >= kw0) tload<NT, T, VX>(Q[0][f], Tt[f] + c_own + (int64_t)k0 * ks);
         }
         if (ld_x) vload<T, VX>(X[0][f], F[f] + c_x + (int64_t)k0 * ks);
         if (edge_l) EL[0][f] = F[f][c_own + (int64_t)k0 * ks - 1];
@@ -136,7 +136,7 @@ __device__ __forceinline__ void diff_uvw_zl_tile(const StencilArgs<T> &a, int tx
                 for (int f = 0; f < 3; ++f) {
                     if (k + 1 < k1) {
                         if (ld_own && (f < 2 || k + 1 >= kw0))
-                            vload<T, VX>(Q[q][f], Tt[f] + c_own + (int64_t)(k + 1) * ks);
+                            tload<NT, T, VX>(Q[q][f], Tt[f] + c_own + (int64_t)(k + 1) * ks);
                         if (ld_x) vload<T, VX>(X[q][f], F[f] + c_x + (int64_t)(k + 1) * ks);
                         if (edge_l) EL[q][f] = F[f][c_own + (int64_t)(k + 1) * ks - 1];
                         if (edge_r) ER[q][f] = F[f][c_own + (int64_t)(k + 1) * ks + VX];
@@ -170,7 +170,7 @@ __device__ __forceinline__ void diff_uvw_zl_tile(const StencilArgs<T> &a, int tx
                                                                 dxi2, dyi2, dzik, dzikm1, dzhik, visc);
                             Q[p][f][n] = Q[p][f][n] + d;
                         }
-                        vstore<T, VX>(Tt[f] + c_own + (int64_t)k * ks, Q[p][f]);
+                        tstore<NT, T, VX>(Tt[f] + c_own + (int64_t)k * ks, Q[p][f]);
                     }
                 }
                 // level k-1 is no longer needed: its slot takes the k+3 prefetch
@@ -185,7 +185,7 @@ __device__ __forceinline__ void diff_uvw_zl_tile(const StencilArgs<T> &a, int tx
 // ---------------------------------------------------------------------------
 // advec_u
 // ---------------------------------------------------------------------------
-template <typename T, int VX, int BY, int KB>
+template <typename T, int VX, int BY, int KB, int NT>
 __device__ __forceinline__ void advec_u_zl_tile(const StencilArgs<T> &a, int tx, int ty, int tz)
 {
     static_assert(BY >= 2, "two halo rows need two waves");
@@ -234,7 +234,7 @@ __device__ __forceinline__ void advec_u_zl_tile(const StencilArgs<T> &a, int tx,
         vload<T, VX>(RW[1], W + c_own + (int64_t)(k0 + 1) * ks);
         if (k0 + 2 <= k1) vload<T, VX>(RW[2], W + c_own + (int64_t)(k0 + 2) * ks);
         vload<T, VX>(RV[0], V + c_own + (int64_t)k0 * ks);
-        vload<T, VX>(Q[0], a.ut + c_own + (int64_t)k0 * ks);
+        tload<NT, T, VX>(Q[0], a.ut + c_own + (int64_t)k0 * ks);
     }
     if (ld_x) {
         vload<T, VX>(XU[0], U + c_x + (int64_t)k0 * ks);
@@ -267,7 +267,7 @@ __device__ __forceinline__ void advec_u_zl_tile(const StencilArgs<T> &a, int tx,
                 if (k + 1 < k1) {
                     if (ld_own) {
                         vload<T, VX>(RV[q], V + c_own + (int64_t)(k + 1) * ks);
-                        vload<T, VX>(Q[q], a.ut + c_own + (int64_t)(k + 1) * ks);
+                        tload<NT, T, VX>(Q[q], a.ut + c_own + (int64_t)(k + 1) * ks);
                     }
                     if (ld_x) {
                         vload<T, VX>(XU[q], U + c_x + (int64_t)(k + 1) * ks);
@@ -325,7 +325,7 @@ __device__ __forceinline__ void advec_u_zl_tile(const StencilArgs<T> &a, int tx,
                                                              RV[p][n], v_nw, vn[n], w_w, wc[n], w_tw, wt[n], dxi,
                                                              dyi, dzik);
                     }
-                    vstore<T, VX>(a.ut + c_own + (int64_t)k * ks, Q[p]);
+                    tstore<NT, T, VX>(a.ut + c_own + (int64_t)k * ks, Q[p]);
                 }
                 if (ld_own && k + 3 <= k1) vload<T, VX>(ub, U + c_own + (int64_t)(k + 3) * ks);
             }
@@ -333,45 +333,46 @@ __device__ __forceinline__ void advec_u_zl_tile(const StencilArgs<T> &a, int tx,
     }
 }
 
-// Single-grid kernels: one block per tile.
-template <typename T, int VX, int BY, int KB, int XCD>
-__global__ __launch_bounds__(64 * BY) void diff_uvw_zl(StencilArgs<T> a)
+// Single-grid kernels: one block per tile.  NT streams the tendency arrays;
+// WPE asks the compiler for at least that many waves per SIMD.
+template <typename T, int VX, int BY, int KB, int XCD, int NT = 0, int WPE = 1>
+__global__ __launch_bounds__(64 * BY, WPE) void diff_uvw_zl(StencilArgs<T> a)
 {
     int tx, ty, tz;
     tile_of<64, BY, XCD>(a.nbx, a.nby, a.nbz, tx, ty, tz);
-    diff_uvw_zl_tile<T, VX, BY, KB>(a, tx, ty, tz);
+    diff_uvw_zl_tile<T, VX, BY, KB, NT>(a, tx, ty, tz);
 }
 
-template <typename T, int VX, int BY, int KB, int XCD>
-__global__ __launch_bounds__(64 * BY) void advec_u_zl(StencilArgs<T> a)
+template <typename T, int VX, int BY, int KB, int XCD, int NT = 0, int WPE = 1>
+__global__ __launch_bounds__(64 * BY, WPE) void advec_u_zl(StencilArgs<T> a)
 {
     int tx, ty, tz;
     tile_of<64, BY, XCD>(a.nbx, a.nby, a.nbz, tx, ty, tz);
-    advec_u_zl_tile<T, VX, BY, KB>(a, tx, ty, tz);
+    advec_u_zl_tile<T, VX, BY, KB, NT>(a, tx, ty, tz);
 }
 
 // Persistent batched kernels: block b runs tiles b, b + gridDim.x, ... of a
 // static tile list; tile = (grid, tx, ty, tz) into a table of per-grid
 // arguments.  The assignment is fixed, so results do not depend on timing.
-template <typename T, int VX, int BY, int KB>
-__global__ __launch_bounds__(64 * BY) void diff_uvw_zl_batch(const StencilArgs<T> *__restrict__ grids,
-                                                            const int4 *__restrict__ tiles, int ntiles)
+template <typename T, int VX, int BY, int KB, int NT = 0, int WPE = 1>
+__global__ __launch_bounds__(64 * BY, WPE) void diff_uvw_zl_batch(const StencilArgs<T> *__restrict__ grids,
+                                                                 const int4 *__restrict__ tiles, int ntiles)
 {
     for (int n = blockIdx.x; n < ntiles; n += gridDim.x) {
         const int4 tl = tiles[n];
         const StencilArgs<T> a = grids[tl.x];
-        diff_uvw_zl_tile<T, VX, BY, KB>(a, tl.y, tl.z, tl.w);
+        diff_uvw_zl_tile<T, VX, BY, KB, NT>(a, tl.y, tl.z, tl.w);
     }
 }
 
-template <typename T, int VX, int BY, int KB>
-__global__ __launch_bounds__(64 * BY) void advec_u_zl_batch(const StencilArgs<T> *__restrict__ grids,
-                                                           const int4 *__restrict__ tiles, int ntiles)
+template <typename T, int VX, int BY, int KB, int NT = 0, int WPE = 1>
+__global__ __launch_bounds__(64 * BY, WPE) void advec_u_zl_batch(const StencilArgs<T> *__restrict__ grids,
+                                                                const int4 *__restrict__ tiles, int ntiles)
 {
     for (int n = blockIdx.x; n < ntiles; n += gridDim.x) {
         const int4 tl = tiles[n];
         const StencilArgs<T> a = grids[tl.x];
-        advec_u_zl_tile<T, VX, BY, KB>(a, tl.y, tl.z, tl.w);
+        advec_u_zl_tile<T, VX, BY, KB, NT>(a, tl.y, tl.z, tl.w);
     }
 }
 

@@ -56,7 +56,7 @@ hipError_t launch_plain(const HostArgs &h, hipStream_t s)
     return hipGetLastError();
 }
 
-template <typename T, int KERNEL, int VX, int BX, int BY, int KB, int XCD>
+template <typename T, int KERNEL, int VX, int BX, int BY, int KB, int XCD, int NT = 0, int WPE = 1>
 hipError_t launch_zc(const HostArgs &h, hipStream_t s)
 {
     StencilArgs<T> a = device_args<T>(h);
@@ -66,13 +66,13 @@ hipError_t launch_zc(const HostArgs &h, hipStream_t s)
     const uint64_t nb = (uint64_t)a.nbx * a.nby * a.nbz;
     if (!grid_fits(nb, BX * BY)) return hipErrorInvalidConfiguration;
     if (KERNEL == KL_KERNEL_ADVEC_U)
-        hipLaunchKernelGGL((advec_u_zc<T, VX, BX, BY, KB, XCD>), dim3((unsigned)nb), dim3(BX, BY), 0, s, a);
+        hipLaunchKernelGGL((advec_u_zc<T, VX, BX, BY, KB, XCD, NT, WPE>), dim3((unsigned)nb), dim3(BX, BY), 0, s, a);
     else
-        hipLaunchKernelGGL((diff_uvw_zc<T, VX, BX, BY, KB, XCD>), dim3((unsigned)nb), dim3(BX, BY), 0, s, a);
+        hipLaunchKernelGGL((diff_uvw_zc<T, VX, BX, BY, KB, XCD, NT, WPE>), dim3((unsigned)nb), dim3(BX, BY), 0, s, a);
     return hipGetLastError();
 }
 
-template <typename T, int KERNEL, int VX, int BY, int KB, int XCD>
+template <typename T, int KERNEL, int VX, int BY, int KB, int XCD, int NT = 0, int WPE = 1>
 hipError_t launch_zl(const HostArgs &h, hipStream_t s)
 {
     StencilArgs<T> a = device_args<T>(h);
@@ -82,33 +82,33 @@ hipError_t launch_zl(const HostArgs &h, hipStream_t s)
     const uint64_t nb = (uint64_t)a.nbx * a.nby * a.nbz;
     if (!grid_fits(nb, 64 * BY)) return hipErrorInvalidConfiguration;
     if (KERNEL == KL_KERNEL_ADVEC_U)
-        hipLaunchKernelGGL((advec_u_zl<T, VX, BY, KB, XCD>), dim3((unsigned)nb), dim3(64, BY), 0, s, a);
+        hipLaunchKernelGGL((advec_u_zl<T, VX, BY, KB, XCD, NT, WPE>), dim3((unsigned)nb), dim3(64, BY), 0, s, a);
     else
-        hipLaunchKernelGGL((diff_uvw_zl<T, VX, BY, KB, XCD>), dim3((unsigned)nb), dim3(64, BY), 0, s, a);
+        hipLaunchKernelGGL((diff_uvw_zl<T, VX, BY, KB, XCD, NT, WPE>), dim3((unsigned)nb), dim3(64, BY), 0, s, a);
     return hipGetLastError();
 }
 
-template <typename T, int KERNEL, int VX, int BY, int KB>
+template <typename T, int KERNEL, int VX, int BY, int KB, int NT = 0, int WPE = 1>
 hipError_t launch_zl_batch(const void *descs, const void *tiles, int ntiles, int nblocks, hipStream_t s)
 {
     if (KERNEL == KL_KERNEL_ADVEC_U)
-        hipLaunchKernelGGL((advec_u_zl_batch<T, VX, BY, KB>), dim3(nblocks), dim3(64, BY), 0, s,
+        hipLaunchKernelGGL((advec_u_zl_batch<T, VX, BY, KB, NT, WPE>), dim3(nblocks), dim3(64, BY), 0, s,
                            (const StencilArgs<T> *)descs, (const int4 *)tiles, ntiles);
     else
-        hipLaunchKernelGGL((diff_uvw_zl_batch<T, VX, BY, KB>), dim3(nblocks), dim3(64, BY), 0, s,
+        hipLaunchKernelGGL((diff_uvw_zl_batch<T, VX, BY, KB, NT, WPE>), dim3(nblocks), dim3(64, BY), 0, s,
                            (const StencilArgs<T> *)descs, (const int4 *)tiles, ntiles);
     return hipGetLastError();
 }
 
-template <typename T, int KERNEL, int VX, int BY, int KB>
+template <typename T, int KERNEL, int VX, int BY, int KB, int NT = 0, int WPE = 1>
 int zl_batch_occupancy()
 {
     int n = 0;
     hipError_t e;
     if (KERNEL == KL_KERNEL_ADVEC_U)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, advec_u_zl_batch<T, VX, BY, KB>, 64 * BY, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, advec_u_zl_batch<T, VX, BY, KB, NT, WPE>, 64 * BY, 0);
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, diff_uvw_zl_batch<T, VX, BY, KB>, 64 * BY, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, diff_uvw_zl_batch<T, VX, BY, KB, NT, WPE>, 64 * BY, 0);
     return e == hipSuccess && n > 0 ? n : 1;
 }
 
@@ -147,3 +147,28 @@ int zl_batch_occupancy()
 
 #define KL_ZL_BLOCKS(T, DT, KERN, VX) \
     KL_ZL_KB(T, DT, KERN, VX, 4), KL_ZL_KB(T, DT, KERN, VX, 8), KL_ZL_KB(T, DT, KERN, VX, 16)
+
+// Extra configurations: streaming tendencies (NT), slab-local XCD order and
+// a waves-per-SIMD floor (WPE), named ..._x<XCD>_nt<NT>_w<WPE>.
+#define KL_ZLX(T, DT, KERN, VX, BY, KB, XCD, NT, WPE)                                                 \
+    Variant{"zl_v" KL_STR(VX) "_b64x" KL_STR(BY) "_k" KL_STR(KB) "_x" KL_STR(XCD) "_nt" KL_STR(NT)     \
+            "_w" KL_STR(WPE),                                                                         \
+            KERN, DT, FAMILY_ZL, VX, 64, BY, KB, XCD, &launch_zl<T, KERN, VX, BY, KB, XCD, NT, WPE>,   \
+            &launch_zl_batch<T, KERN, VX, BY, KB, NT, WPE>, &zl_batch_occupancy<T, KERN, VX, BY, KB, NT, WPE>}
+
+#define KL_ZCX(T, DT, KERN, VX, BX, BY, KB, XCD, NT, WPE)                                              \
+    Variant{"zc_v" KL_STR(VX) "_b" KL_STR(BX) "x" KL_STR(BY) "_k" KL_STR(KB) "_x" KL_STR(XCD) "_nt"    \
+            KL_STR(NT) "_w" KL_STR(WPE),                                                              \
+            KERN, DT, FAMILY_ZC, VX, BX, BY, KB, XCD, &launch_zc<T, KERN, VX, BX, BY, KB, XCD, NT, WPE>, \
+            nullptr, nullptr}
+
+#define KL_ZLX_SET(T, DT, KERN, VX)                                                                     \
+    KL_ZLX(T, DT, KERN, VX, 8, 32, 2, 0, 1), KL_ZLX(T, DT, KERN, VX, 8, 32, 2, 1, 1),                  \
+        KL_ZLX(T, DT, KERN, VX, 8, 32, 0, 1, 1), KL_ZLX(T, DT, KERN, VX, 8, 128, 2, 0, 1),             \
+        KL_ZLX(T, DT, KERN, VX, 8, 128, 2, 1, 1), KL_ZLX(T, DT, KERN, VX, 8, 128, 0, 1, 1),            \
+        KL_ZLX(T, DT, KERN, VX, 8, 32, 0, 0, 4), KL_ZLX(T, DT, KERN, VX, 8, 32, 2, 1, 4),              \
+        KL_ZLX(T, DT, KERN, VX, 4, 64, 2, 1, 1), KL_ZLX(T, DT, KERN, VX, 16, 64, 2, 1, 1)
+
+#define KL_ZCX_SET(T, DT, KERN, VX)                                                                     \
+    KL_ZCX(T, DT, KERN, VX, 64, 4, 16, 2, 0, 1), KL_ZCX(T, DT, KERN, VX, 64, 4, 16, 2, 1, 1),          \
+        KL_ZCX(T, DT, KERN, VX, 64, 4, 16, 0, 1, 1), KL_ZCX(T, DT, KERN, VX, 64, 4, 32, 0, 1, 1)

@@ -1,18 +1,33 @@
-// Registry of FP32 tendency-kernel configurations.
+// Registry of F32 tendency-kernel configurations (index 0: the default).
 #include "variants.hpp"
 
 namespace kl {
 
+void add_variants_f32_zc(int kernel, std::vector<Variant> &out);
+void add_variants_f32_zl1(int kernel, std::vector<Variant> &out);
+void add_variants_f32_zl2(int kernel, std::vector<Variant> &out);
+void add_variants_f32_zl4(int kernel, std::vector<Variant> &out);
+void add_variants_f32_x(int kernel, std::vector<Variant> &out);
+
+static std::vector<Variant> build_f32(int kernel)
+{
+    std::vector<Variant> v;
+    v.push_back(Variant{"default", kernel, KL_F32, FAMILY_PLAIN, 1, 256, 1, 1, 0,
+                        kernel == KL_KERNEL_ADVEC_U ? &launch_plain<float, KL_KERNEL_ADVEC_U>
+                                                    : &launch_plain<float, KL_KERNEL_DIFF_UVW>,
+                        nullptr, nullptr});
+        add_variants_f32_zc(kernel, v);
+        add_variants_f32_zl1(kernel, v);
+        add_variants_f32_zl2(kernel, v);
+        add_variants_f32_zl4(kernel, v);
+        add_variants_f32_x(kernel, v);
+    return v;
+}
+
 const std::vector<Variant> &variants_f32(int kernel)
 {
-#define KL_LIST(KERN)                                                                       \
-    {Variant{"default", KERN, KL_F32, FAMILY_PLAIN, 1, 256, 1, 1, 0, &launch_plain<float, KERN>, nullptr, nullptr}, \
-     KL_ZC_BLOCKS(float, KL_F32, KERN, 1), KL_ZC_BLOCKS(float, KL_F32, KERN, 2),            \
-     KL_ZC_BLOCKS(float, KL_F32, KERN, 4), KL_ZL_BLOCKS(float, KL_F32, KERN, 1), KL_ZL_BLOCKS(float, KL_F32, KERN, 2), KL_ZL_BLOCKS(float, KL_F32, KERN, 4) \
-    }
-    static const std::vector<Variant> advec = KL_LIST(KL_KERNEL_ADVEC_U);
-    static const std::vector<Variant> diff = KL_LIST(KL_KERNEL_DIFF_UVW);
-#undef KL_LIST
+    static const std::vector<Variant> advec = build_f32(KL_KERNEL_ADVEC_U);
+    static const std::vector<Variant> diff = build_f32(KL_KERNEL_DIFF_UVW);
     return kernel == KL_KERNEL_ADVEC_U ? advec : diff;
 }
 

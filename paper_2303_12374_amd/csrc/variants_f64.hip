@@ -1,17 +1,31 @@
-// Registry of FP64 tendency-kernel configurations.
+// Registry of F64 tendency-kernel configurations (index 0: the default).
 #include "variants.hpp"
 
 namespace kl {
 
+void add_variants_f64_zc(int kernel, std::vector<Variant> &out);
+void add_variants_f64_zl1(int kernel, std::vector<Variant> &out);
+void add_variants_f64_zl2(int kernel, std::vector<Variant> &out);
+void add_variants_f64_x(int kernel, std::vector<Variant> &out);
+
+static std::vector<Variant> build_f64(int kernel)
+{
+    std::vector<Variant> v;
+    v.push_back(Variant{"default", kernel, KL_F64, FAMILY_PLAIN, 1, 256, 1, 1, 0,
+                        kernel == KL_KERNEL_ADVEC_U ? &launch_plain<double, KL_KERNEL_ADVEC_U>
+                                                    : &launch_plain<double, KL_KERNEL_DIFF_UVW>,
+                        nullptr, nullptr});
+        add_variants_f64_zc(kernel, v);
+        add_variants_f64_zl1(kernel, v);
+        add_variants_f64_zl2(kernel, v);
+        add_variants_f64_x(kernel, v);
+    return v;
+}
+
 const std::vector<Variant> &variants_f64(int kernel)
 {
-#define KL_LIST(KERN)                                                                         \
-    {Variant{"default", KERN, KL_F64, FAMILY_PLAIN, 1, 256, 1, 1, 0, &launch_plain<double, KERN>, nullptr, nullptr}, \
-     KL_ZC_BLOCKS(double, KL_F64, KERN, 1), KL_ZC_BLOCKS(double, KL_F64, KERN, 2), KL_ZL_BLOCKS(double, KL_F64, KERN, 1), KL_ZL_BLOCKS(double, KL_F64, KERN, 2) \
-    }
-    static const std::vector<Variant> advec = KL_LIST(KL_KERNEL_ADVEC_U);
-    static const std::vector<Variant> diff = KL_LIST(KL_KERNEL_DIFF_UVW);
-#undef KL_LIST
+    static const std::vector<Variant> advec = build_f64(KL_KERNEL_ADVEC_U);
+    static const std::vector<Variant> diff = build_f64(KL_KERNEL_DIFF_UVW);
     return kernel == KL_KERNEL_ADVEC_U ? advec : diff;
 }
 
