@@ -164,6 +164,13 @@ __device__ __forceinline__ void tstore(T *p, const T (&s)[N])
     if constexpr (NT) vstore_nt<T, N>(p, s); else vstore<T, N>(p, s);
 }
 
+// Field load: cached, or streaming when NT >= 2.
+template <int NT, typename T, int N>
+__device__ __forceinline__ void fload(T (&d)[N], const T *p)
+{
+    if constexpr (NT >= 2) vload_nt<T, N>(d, p); else vload<T, N>(d, p);
+}
+
 // Map a hardware workgroup id to a logical tile id so that the tiles each of
 // the 8 XCDs receives (the dispatcher deals workgroups to XCDs round robin)
 // are contiguous in the logical x-fastest order: neighbouring tiles, which
@@ -282,16 +289,16 @@ __global__ __launch_bounds__(BX *BY, WPE) void advec_u_zc(StencilArgs<T> a)
 
     for (int k = k0; k < k1; ++k) {
         T utp[VX], utw, ute, un[VX], us[VX], vc[VX], vcw, vn[VX], vnw, wt[VX], wtw, tt[VX];
-        vload<T, VX>(utp, pu + ks);
+        fload<NT, T, VX>(utp, pu + ks);
         utw = pu[ks - 1];
         ute = pu[ks + VX];
         vload<T, VX>(un, pu + js);
         vload<T, VX>(us, pu - js);
-        vload<T, VX>(vc, pv);
+        fload<NT, T, VX>(vc, pv);
         vcw = pv[-1];
         vload<T, VX>(vn, pv + js);
         vnw = pv[js - 1];
-        vload<T, VX>(wt, pw + ks);
+        fload<NT, T, VX>(wt, pw + ks);
         wtw = pw[ks - 1];
         tload<NT, T, VX>(tt, put);
         const T dzik = a.dzi[k];
@@ -357,7 +364,7 @@ __global__ __launch_bounds__(BX *BY, WPE) void diff_uvw_zc(StencilArgs<T> a)
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
             const T *p = pf[f];
-            vload<T, VX>(ft[f], p + ks);
+            fload<NT, T, VX>(ft[f], p + ks);
             ftw[f] = p[ks - 1];
             fte[f] = p[ks + VX];
             T fn[VX], fs[VX], tt[VX];

@@ -176,7 +176,7 @@ __device__ __forceinline__ void diff_uvw_zl_tile(const StencilArgs<T> &a, int tx
                 // level k-1 is no longer needed: its slot takes the k+3 prefetch
 #pragma unroll
                 for (int f = 0; f < 3; ++f)
-                    if (ld_own && k + 3 <= k1) vload<T, VX>(b[f], F[f] + c_own + (int64_t)(k + 3) * ks);
+                    if (ld_own && k + 3 <= k1) fload<NT, T, VX>(b[f], F[f] + c_own + (int64_t)(k + 3) * ks);
             }
         }
     }
@@ -262,11 +262,11 @@ __device__ __forceinline__ void advec_u_zl_tile(const StencilArgs<T> &a, int tx,
                 T(&wc)[VX] = RW[s & 3];
                 T(&wt)[VX] = RW[(s + 1) & 3];
                 T(&wnx)[VX] = RW[(s + 3) & 3];  // w of level k-1 is not needed: prefetch k+3
-                if (ld_own && k + 3 <= k1) vload<T, VX>(wnx, W + c_own + (int64_t)(k + 3) * ks);
+                if (ld_own && k + 3 <= k1) fload<NT, T, VX>(wnx, W + c_own + (int64_t)(k + 3) * ks);
                 if (edge_l && k + 3 <= k1) WLe[(s + 3) & 3] = W[c_own + (int64_t)(k + 3) * ks - 1];
                 if (k + 1 < k1) {
                     if (ld_own) {
-                        vload<T, VX>(RV[q], V + c_own + (int64_t)(k + 1) * ks);
+                        fload<NT, T, VX>(RV[q], V + c_own + (int64_t)(k + 1) * ks);
                         tload<NT, T, VX>(Q[q], a.ut + c_own + (int64_t)(k + 1) * ks);
                     }
                     if (ld_x) {
@@ -327,7 +327,7 @@ __device__ __forceinline__ void advec_u_zl_tile(const StencilArgs<T> &a, int tx,
                     }
                     tstore<NT, T, VX>(a.ut + c_own + (int64_t)k * ks, Q[p]);
                 }
-                if (ld_own && k + 3 <= k1) vload<T, VX>(ub, U + c_own + (int64_t)(k + 3) * ks);
+                if (ld_own && k + 3 <= k1) fload<NT, T, VX>(ub, U + c_own + (int64_t)(k + 3) * ks);
             }
         }
     }

@@ -169,6 +169,13 @@ int zl_batch_occupancy()
         KL_ZLX(T, DT, KERN, VX, 8, 32, 0, 0, 4), KL_ZLX(T, DT, KERN, VX, 8, 32, 2, 1, 4),              \
         KL_ZLX(T, DT, KERN, VX, 4, 64, 2, 1, 1), KL_ZLX(T, DT, KERN, VX, 16, 64, 2, 1, 1)
 
+#define KL_NT2_SET(T, DT, KERN, VX)                                                                     \
+    KL_ZLX(T, DT, KERN, VX, 4, 64, 2, 2, 1), KL_ZLX(T, DT, KERN, VX, 4, 128, 2, 1, 1),                 \
+        KL_ZLX(T, DT, KERN, VX, 4, 128, 2, 2, 1), KL_ZLX(T, DT, KERN, VX, 4, 256, 2, 1, 1),            \
+        KL_ZLX(T, DT, KERN, VX, 8, 64, 2, 1, 1), KL_ZLX(T, DT, KERN, VX, 8, 64, 2, 2, 1),              \
+        KL_ZLX(T, DT, KERN, VX, 4, 64, 0, 1, 1), KL_ZCX(T, DT, KERN, VX, 64, 4, 16, 2, 2, 1),          \
+        KL_ZCX(T, DT, KERN, VX, 64, 2, 16, 2, 1, 1), KL_ZCX(T, DT, KERN, VX, 64, 8, 16, 2, 1, 1)
+
 #define KL_ZCX_SET(T, DT, KERN, VX)                                                                     \
     KL_ZCX(T, DT, KERN, VX, 64, 4, 16, 2, 0, 1), KL_ZCX(T, DT, KERN, VX, 64, 4, 16, 2, 1, 1),          \
         KL_ZCX(T, DT, KERN, VX, 64, 4, 16, 0, 1, 1), KL_ZCX(T, DT, KERN, VX, 64, 4, 32, 0, 1, 1)

@@ -7,6 +7,7 @@ void add_variants_f64_zc(int kernel, std::vector<Variant> &out);
 void add_variants_f64_zl1(int kernel, std::vector<Variant> &out);
 void add_variants_f64_zl2(int kernel, std::vector<Variant> &out);
 void add_variants_f64_x(int kernel, std::vector<Variant> &out);
+void add_variants_f64_nt(int kernel, std::vector<Variant> &out);
 
 static std::vector<Variant> build_f64(int kernel)
 {
@@ -19,6 +20,7 @@ static std::vector<Variant> build_f64(int kernel)
         add_variants_f64_zl1(kernel, v);
         add_variants_f64_zl2(kernel, v);
         add_variants_f64_x(kernel, v);
+        add_variants_f64_nt(kernel, v);
     return v;
 }
 
