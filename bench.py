@@ -514,7 +514,31 @@ def main():
                      "algorithmic_bytes_per_launch": dom_bytes},
         "untuned": untuned,
     }
-    del dev, tend, u, v, w, ut, vt, wt
+    # one time step: separate kernels (kl_step) versus the fused step kernel
+    log("time step: kl_step (zero, advec_u, diff_uvw, Euler) vs kl_step_fused")
+    out = [g.full() for _ in range(3)]
+    dt_step = 1e-5
+
+    def time_fn(fn, k=10):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(k):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    fused_ms = time_fn(lambda: kl.kl_step_fused(g, visc, dt_step, u, v, w, *out, stream))
+    sep_ms = time_fn(lambda: kl.kl_step(g, visc, dt_step, u, v, w, ut, vt, wt, stream))
+    result["step"] = {"fused_ms": fused_ms, "separate_ms": sep_ms, "speedup": sep_ms / fused_ms,
+                      "fused_configuration": kl.kl_variant_name(kl.STEP, dtype, kl.kl_selected_variant(g, kl.STEP)),
+                      "fused_grid_points_per_s": npts / (fused_ms * 1e-3),
+                      "fused_hbm_gbps_6_values": 6 * s * npts / (fused_ms * 1e6),
+                      "separate_hbm_gbps_26_values": 26 * s * npts / (sep_ms * 1e6)}
+    del dev, tend, u, v, w, ut, vt, wt, out
     torch.cuda.empty_cache()
     if not args.no_batched:
         log("batched form: 56 grids in one graph vs 112 single-grid launches")

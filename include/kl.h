@@ -75,7 +75,9 @@ typedef enum {
     KL_ERR_IO = -7        /* wisdom file could not be written */
 } kl_status_t;
 
-enum { KL_KERNEL_ADVEC_U = 0, KL_KERNEL_DIFF_UVW = 1 };
+/* Kernels with tunable configurations.  KL_KERNEL_STEP is the fused time
+ * step of kl_step_fused. */
+enum { KL_KERNEL_ADVEC_U = 0, KL_KERNEL_DIFF_UVW = 1, KL_KERNEL_STEP = 2 };
 
 /* One grid.  Element (i, j, k) of every field is at index
  * off + i + j*jstride + k*kstride (elements of the field dtype), with
@@ -137,6 +139,16 @@ int kl_euler(const kl_grid_t *g, double dt, void *u, void *v, void *w,
 int kl_step(const kl_grid_t *g, double visc, double dt, void *u, void *v, void *w,
             void *ut, void *vt, void *wt, void *stream);
 
+/* One time step fused into a single kernel: reads u, v, w (ghost-filled, not
+ * modified) and writes the next state into u_out, v_out, w_out, ghost cells
+ * included.  The arithmetic and its order are those of kl_step (tendencies
+ * zeroed, advec_u, diff_uvw, forward Euler, ghost refill), so the result is
+ * bitwise identical to kl_step's, while the kernel moves 6 values per point
+ * instead of 26.  Inputs and outputs must not overlap; the outputs' padding
+ * cells are not written.  Configuration from the wisdom file step.wisdom. */
+int kl_step_fused(const kl_grid_t *g, double visc, double dt, const void *u, const void *v, const void *w,
+                  void *u_out, void *v_out, void *w_out, void *stream);
+
 /* FP64 reductions over the interior, accumulated in double for either field
  * dtype, in a fixed-shape two-pass tree (bitwise reproducible).
  *  what = 0 (conservation): f0, f1, f2 = ut, vt, wt; out[0] = sum ut*dz_k,
@@ -182,10 +194,14 @@ int kl_variant_eligible(const kl_grid_t *g, int32_t kernel, int32_t index,
                         const void *const fields[6]);
 
 /* Launch configuration `index` of `kernel` directly.  fields = {u, v, w, ut,
- * vt, wt}; advec_u uses u, v, w, ut.  Same semantics as kl_advec_u /
- * kl_diff_uvw.  KL_ERR_INVALID if the configuration is not eligible. */
+ * vt, wt}; advec_u uses u, v, w, ut; the fused step reads u, v, w and writes
+ * fields 3..5 (visc and the time step dt of kl_launch_variant_dt).  Same
+ * semantics as kl_advec_u / kl_diff_uvw / kl_step_fused.  KL_ERR_INVALID if
+ * the configuration is not eligible. */
 int kl_launch_variant(const kl_grid_t *g, int32_t kernel, int32_t index,
                       void *const fields[6], double visc, void *stream);
+int kl_launch_variant_dt(const kl_grid_t *g, int32_t kernel, int32_t index,
+                         void *const fields[6], double visc, double dt, void *stream);
 
 /* Index of the configuration kl_advec_u / kl_diff_uvw would run for this
  * grid on the current device (consults the wisdom files on first use per
@@ -217,7 +233,8 @@ int kl_wisdom_lookup(const char *wisdom_dir, int32_t kernel, int32_t dtype, cons
                      const char *arch, int32_t itot, int32_t jtot, int32_t ktot, char *variant,
                      size_t len, int32_t *level);
 
-/* Tune the kernels in kernel_mask (bit 0 advec_u, bit 1 diff_uvw) for this
+/* Tune the kernels in kernel_mask (bit 0 advec_u, bit 1 diff_uvw, bit 2 the
+ * fused step) for this
  * grid on the current device: every eligible configuration is checked for
  * bitwise-equal output against the default configuration, then timed (hip
  * events, median of repetitions after warm-up) until budget_s seconds are
@@ -277,8 +294,10 @@ typedef struct kl_result {
  * arena/arena_bytes: caller-owned device memory the server sub-allocates
  * all request fields from; budget_bytes (<= arena_bytes) caps the bytes held
  * by admitted requests.  Requests are admitted in arrival order while they
- * fit; every tick advances all admitted requests by one step in one batched
- * launch, so requests join and leave between ticks. */
+ * fit; every tick advances all admitted requests by one fused step (one
+ * persistent launch per configuration group, two field buffers per request
+ * used in turn), so requests join and leave between ticks.  The host
+ * prepares the next tick while the current one runs. */
 int kl_server_create(void *arena, size_t arena_bytes, size_t budget_bytes, void **srv);
 
 /* Enqueue a request; *ticket identifies it.  KL_ERR_BUDGET if the request's

@@ -160,7 +160,8 @@ int select_variant(const kl_grid_t *g, int kernel)
     return index;
 }
 
-int run_variant(const kl_grid_t *g, int kernel, int index, void *const fields[6], double visc, hipStream_t s)
+int run_variant(const kl_grid_t *g, int kernel, int index, void *const fields[6], double visc, hipStream_t s,
+                double dt)
 {
     const auto &vs = variants(kernel, g->dtype);
     if (index < 0 || index >= (int)vs.size()) return fail(KL_ERR_NOTFOUND, "variant index %d", index);
@@ -170,6 +171,7 @@ int run_variant(const kl_grid_t *g, int kernel, int index, void *const fields[6]
     if (!variant_eligible(v, g, ptrs, nptr))
         return fail(KL_ERR_INVALID, "configuration %s not eligible for this grid/alignment", v.name);
     HostArgs a = make_args(g);
+    a.dt = dt;
     a.u = fields[0];
     a.v = fields[1];
     a.w = fields[2];
@@ -197,13 +199,21 @@ int check_ptrs(const void *const *p, int n)
 
 // Launch `kernel` with the selected configuration, falling back to the
 // default when the selected one does not fit this call's alignment.
-int launch_selected(const kl_grid_t *g, int kernel, void *const fields[6], double visc, hipStream_t s)
+int launch_selected(const kl_grid_t *g, int kernel, void *const fields[6], double visc, hipStream_t s,
+                    double dt = 0.0)
 {
     int index = select_variant(g, kernel);
     const auto &vs = variants(kernel, g->dtype);
     const void *ptrs[6] = {fields[0], fields[1], fields[2], fields[3], fields[4], fields[5]};
     if (!variant_eligible(vs[index], g, ptrs, kernel == KL_KERNEL_ADVEC_U ? 4 : 6)) index = 0;
-    return run_variant(g, kernel, index, fields, visc, s);
+    if (!variant_eligible(vs[index], g, ptrs, kernel == KL_KERNEL_ADVEC_U ? 4 : 6))
+        return fail(KL_ERR_INVALID, "no configuration of %s fits this grid/alignment", kernel_name(kernel));
+    return run_variant(g, kernel, index, fields, visc, s, dt);
+}
+
+bool kernel_ok(int32_t kernel)
+{
+    return kernel == KL_KERNEL_ADVEC_U || kernel == KL_KERNEL_DIFF_UVW || kernel == KL_KERNEL_STEP;
 }
 
 }  // namespace
@@ -306,6 +316,21 @@ int kl_step(const kl_grid_t *g, double visc, double dt, void *u, void *v, void *
     return e == hipSuccess ? KL_OK : hip_fail(e, "euler");
 }
 
+int kl_step_fused(const kl_grid_t *g, double visc, double dt, const void *u, const void *v, const void *w,
+                  void *u_out, void *v_out, void *w_out, void *stream)
+{
+    clear_error();
+    int rc = check_grid(g);
+    if (rc) return rc;
+    const void *p[6] = {u, v, w, u_out, v_out, w_out};
+    if ((rc = check_ptrs(p, 6))) return rc;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 3; b < 6; ++b)
+            if (p[a] == p[b]) return fail(KL_ERR_INVALID, "fused step: input %d and output %d overlap", a, b - 3);
+    void *f[6] = {(void *)u, (void *)v, (void *)w, u_out, v_out, w_out};
+    return launch_selected(g, KL_KERNEL_STEP, f, visc, (hipStream_t)stream, dt);
+}
+
 int kl_reduce_fp64(const kl_grid_t *g, int32_t what, const void *f0, const void *f1, const void *f2, double *out,
                    void *stream)
 {
@@ -350,7 +375,7 @@ int kl_hash_interior(const kl_grid_t *g, const void *f, uint64_t *out, void *str
 int kl_num_variants(int32_t kernel, int32_t dtype)
 {
     clear_error();
-    if ((kernel != KL_KERNEL_ADVEC_U && kernel != KL_KERNEL_DIFF_UVW) || (dtype != KL_F32 && dtype != KL_F64))
+    if (!kernel_ok(kernel) || (dtype != KL_F32 && dtype != KL_F64))
         return fail(KL_ERR_INVALID, "kernel %d / dtype %d", kernel, dtype);
     return (int)variants(kernel, dtype).size();
 }
@@ -376,16 +401,22 @@ int kl_variant_eligible(const kl_grid_t *g, int32_t kernel, int32_t index, const
     return variant_eligible(variants(kernel, g->dtype)[index], g, fields, fields ? (kernel ? 6 : 4) : 0) ? 1 : 0;
 }
 
-int kl_launch_variant(const kl_grid_t *g, int32_t kernel, int32_t index, void *const fields[6], double visc,
-                      void *stream)
+int kl_launch_variant_dt(const kl_grid_t *g, int32_t kernel, int32_t index, void *const fields[6], double visc,
+                         double dt, void *stream)
 {
     clear_error();
     int rc = check_grid(g);
     if (rc) return rc;
-    if (kernel != KL_KERNEL_ADVEC_U && kernel != KL_KERNEL_DIFF_UVW) return fail(KL_ERR_INVALID, "kernel %d", kernel);
+    if (!kernel_ok(kernel)) return fail(KL_ERR_INVALID, "kernel %d", kernel);
     if (!fields) return fail(KL_ERR_INVALID, "fields is NULL");
     if ((rc = check_ptrs((const void *const *)fields, kernel == KL_KERNEL_ADVEC_U ? 4 : 6))) return rc;
-    return run_variant(g, kernel, index, fields, visc, (hipStream_t)stream);
+    return run_variant(g, kernel, index, fields, visc, (hipStream_t)stream, dt);
+}
+
+int kl_launch_variant(const kl_grid_t *g, int32_t kernel, int32_t index, void *const fields[6], double visc,
+                      void *stream)
+{
+    return kl_launch_variant_dt(g, kernel, index, fields, visc, 0.0, stream);
 }
 
 int kl_selected_variant(const kl_grid_t *g, int32_t kernel)
@@ -393,7 +424,7 @@ int kl_selected_variant(const kl_grid_t *g, int32_t kernel)
     clear_error();
     int rc = check_grid(g);
     if (rc) return rc;
-    if (kernel != KL_KERNEL_ADVEC_U && kernel != KL_KERNEL_DIFF_UVW) return fail(KL_ERR_INVALID, "kernel %d", kernel);
+    if (!kernel_ok(kernel)) return fail(KL_ERR_INVALID, "kernel %d", kernel);
     return select_variant(g, kernel);
 }
 

@@ -16,8 +16,9 @@ struct HostArgs {
     int itot, jtot, ktot, kw0, dtype, bc;
     int64_t off, js, ks;
     double dxi, dyi, visc;
+    double dt;  // fused step only
     const void *dzi, *dzhi;
-    void *ut, *vt, *wt;
+    void *ut, *vt, *wt;  // tendencies; for the fused step: the output fields
     const void *u, *v, *w;
 };
 
@@ -93,7 +94,7 @@ std::string provenance_json(const DeviceIdent &dev);
 // Plan cache (api.cpp).
 int select_variant(const kl_grid_t *g, int kernel);
 int run_variant(const kl_grid_t *g, int kernel, int index, void *const fields[6], double visc,
-                hipStream_t s);
+                hipStream_t s, double dt = 0.0);
 void clear_plans();
 
 }  // namespace kl

@@ -5,9 +5,9 @@
 // stay resident in the caller's arena until released.  A background thread
 // runs ticks: between ticks it admits queued requests in arrival order while
 // their footprint fits the memory budget (and the arena), and every tick
-// advances all admitted requests by one step with one batched launch per
-// phase (zero tendencies, advec_u groups, diff_uvw groups, Euler update with
-// ghost refill).  Requests therefore join and leave between ticks while
+// advances all admitted requests by one fused step (advec_u + diff_uvw +
+// forward Euler + ghost refill in one kernel, one persistent launch per
+// configuration group), each request ping-ponging between two field buffers.  Requests therefore join and leave between ticks while
 // others are running.  All per-point arithmetic is shared with the single-
 // grid path, so a request's result does not depend on what it ran beside.
 #include <hip/hip_runtime.h>
@@ -87,6 +87,7 @@ struct Req {
     int steps_left = 0;
     size_t off = 0, bytes = 0;
     bool fresh = false;
+    int cur = 0;  // the state is in f[3*cur .. 3*cur+2]; the other three take the next step
     double dt = 0;
     kl_grid_t g;
     void *f[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -232,57 +233,50 @@ int init_request(Server &S, Req &q)
 }
 
 // Enqueue one tick on the server stream: every active request advances one
-// step.  Tables go through slot `slot`, which the previous use has released.
+// fused step from its current buffer into the other.  Tables go through slot
+// `slot`, which the previous use has released.
 int run_tick(Server &S, int slot)
 {
     const std::vector<Req *> &act = S.active;
-    // per-dtype descriptor indices
     std::vector<StencilArgs<float>> df;
     std::vector<StencilArgs<double>> dd;
-    std::vector<double> dtf, dtd;
     std::vector<int> didx(act.size());
+    std::map<std::tuple<int, int>, std::vector<int4>> groups;  // (dtype, configuration) -> tiles
     for (size_t n = 0; n < act.size(); ++n) {
         Req &q = *act[n];
+        void *f[6];
+        for (int m = 0; m < 3; ++m) {
+            f[m] = q.f[3 * q.cur + m];
+            f[3 + m] = q.f[3 * (1 - q.cur) + m];
+        }
         HostArgs a = make_args(&q.g);
-        a.u = q.f[0];
-        a.v = q.f[1];
-        a.w = q.f[2];
-        a.ut = q.f[3];
-        a.vt = q.f[4];
-        a.wt = q.f[5];
+        a.u = f[0];
+        a.v = f[1];
+        a.w = f[2];
+        a.ut = f[3];
+        a.vt = f[4];
+        a.wt = f[5];
         a.visc = q.r.visc;
+        a.dt = q.dt;
         if (q.g.dtype == KL_F32) {
             didx[n] = (int)df.size();
             df.push_back(device_args<float>(a));
-            dtf.push_back(q.dt);
         } else {
             didx[n] = (int)dd.size();
             dd.push_back(device_args<double>(a));
-            dtd.push_back(q.dt);
         }
+        const int vi = batch_variant(&q.g, KL_KERNEL_STEP, f);
+        if (vi < 0)
+            return fail(KL_ERR_INVALID, "no step configuration for request %llu", (unsigned long long)q.ticket);
+        const Variant &v = variants(KL_KERNEL_STEP, q.g.dtype)[vi];
+        auto &tl = groups[std::make_tuple(q.g.dtype, vi)];
+        const int nbx = (int)cdivu(q.g.itot, 64 * v.vx), nby = (int)cdivu(q.g.jtot, v.by),
+                  nbz = (int)cdivu(q.g.ktot, v.kb);
+        for (int tz = 0; tz < nbz; ++tz)
+            for (int ty = 0; ty < nby; ++ty)
+                for (int tx = 0; tx < nbx; ++tx) tl.push_back(make_int4(didx[n], tx, ty, tz));
     }
-    // tiles
-    std::map<std::tuple<int, int, int>, std::vector<int4>> groups;
-    std::vector<int4> rows[2];
-    for (size_t n = 0; n < act.size(); ++n) {
-        Req &q = *act[n];
-        for (int kernel = 0; kernel < 2; ++kernel) {
-            const int vi = batch_variant(&q.g, kernel, q.f);
-            if (vi < 0) return fail(KL_ERR_INVALID, "no batched configuration for request %llu",
-                                    (unsigned long long)q.ticket);
-            const Variant &v = variants(kernel, q.g.dtype)[vi];
-            auto &tl = groups[std::make_tuple(kernel, q.g.dtype, vi)];
-            const int nbx = (int)cdivu(q.g.itot, 64 * v.vx), nby = (int)cdivu(q.g.jtot, v.by),
-                      nbz = (int)cdivu(q.g.ktot, v.kb);
-            for (int tz = 0; tz < nbz; ++tz)
-                for (int ty = 0; ty < nby; ++ty)
-                    for (int tx = 0; tx < nbx; ++tx) tl.push_back(make_int4(didx[n], tx, ty, tz));
-        }
-        const int nrows = q.g.jtot * q.g.ktot;
-        for (int r0 = 0; r0 < nrows; r0 += 32)
-            rows[q.g.dtype].push_back(make_int4(didx[n], r0, std::min(nrows, r0 + 32), 0));
-    }
-    // pack tables: [desc f32][desc f64][dt f32][dt f64][rows f32][rows f64][group tiles...]
+    // pack tables: [desc f32][desc f64][group tiles...]
     size_t off = 0;
     auto place = [&](size_t bytes) {
         const size_t o = off;
@@ -290,8 +284,6 @@ int run_tick(Server &S, int slot)
         return o;
     };
     const size_t o_df = place(df.size() * sizeof(df[0])), o_dd = place(dd.size() * sizeof(dd[0]));
-    const size_t o_tf = place(dtf.size() * 8), o_td = place(dtd.size() * 8);
-    const size_t o_rf = place(rows[0].size() * sizeof(int4)), o_rd = place(rows[1].size() * sizeof(int4));
     std::vector<size_t> o_g;
     for (auto &kv : groups) o_g.push_back(place(kv.second.size() * sizeof(int4)));
     hipError_t e = S.tab[slot].ensure(off);
@@ -300,48 +292,25 @@ int run_tick(Server &S, int slot)
     char *d = (char *)S.tab[slot].d;
     memcpy(h + o_df, df.data(), df.size() * sizeof(df[0]));
     memcpy(h + o_dd, dd.data(), dd.size() * sizeof(dd[0]));
-    memcpy(h + o_tf, dtf.data(), dtf.size() * 8);
-    memcpy(h + o_td, dtd.data(), dtd.size() * 8);
-    memcpy(h + o_rf, rows[0].data(), rows[0].size() * sizeof(int4));
-    memcpy(h + o_rd, rows[1].data(), rows[1].size() * sizeof(int4));
     {
         size_t gi = 0;
         for (auto &kv : groups) memcpy(h + o_g[gi++], kv.second.data(), kv.second.size() * sizeof(int4));
     }
     if ((e = hipMemcpyAsync(d, h, off, hipMemcpyHostToDevice, S.stream)) != hipSuccess) return hip_fail(e, "tables");
-    const size_t o_desc[2] = {o_df, o_dd}, o_dt[2] = {o_tf, o_td}, o_rows[2] = {o_rf, o_rd};
-    // zero tendencies
-    for (int dt = 0; dt < 2; ++dt) {
-        if (rows[dt].empty()) continue;
-        const int nt = (int)rows[dt].size(), nb = std::min(nt, S.ncu * 8);
-        if ((e = launch_zero_batch(dt, d + o_desc[dt], d + o_rows[dt], nt, nb, S.stream)) != hipSuccess)
-            return hip_fail(e, "zero");
+    const size_t o_desc[2] = {o_df, o_dd};
+    size_t gi = 0;
+    for (auto &kv : groups) {
+        const int dt = std::get<0>(kv.first), vi = std::get<1>(kv.first);
+        const Variant &v = variants(KL_KERNEL_STEP, dt)[vi];
+        const int nt = (int)kv.second.size();
+        auto oc = S.occ.find(&v);
+        if (oc == S.occ.end()) oc = S.occ.emplace(&v, v.occupancy()).first;
+        const int nb = (int)std::min<int64_t>(nt, (int64_t)S.ncu * oc->second);
+        if ((e = v.batch(d + o_desc[dt], d + o_g[gi], nt, nb, S.stream)) != hipSuccess) return hip_fail(e, v.name);
         ++S.launches;
+        ++gi;
     }
-    // advec_u groups, then diff_uvw groups (map order: kernel is the first key)
-    {
-        size_t gi = 0;
-        for (auto &kv : groups) {
-            const int kernel = std::get<0>(kv.first), dt = std::get<1>(kv.first), vi = std::get<2>(kv.first);
-            const Variant &v = variants(kernel, dt)[vi];
-            const int nt = (int)kv.second.size();
-            auto oc = S.occ.find(&v);
-            if (oc == S.occ.end()) oc = S.occ.emplace(&v, v.occupancy()).first;
-            const int nb = (int)std::min<int64_t>(nt, (int64_t)S.ncu * oc->second);
-            if ((e = v.batch(d + o_desc[dt], d + o_g[gi], nt, nb, S.stream)) != hipSuccess) return hip_fail(e, v.name);
-            ++S.launches;
-            ++gi;
-        }
-    }
-    // Euler update + ghost refill
-    for (int dt = 0; dt < 2; ++dt) {
-        if (rows[dt].empty()) continue;
-        const int nt = (int)rows[dt].size(), nb = std::min(nt, S.ncu * 8);
-        if ((e = launch_euler_batch(dt, d + o_desc[dt], d + o_rows[dt], nt, nb, (const double *)(d + o_dt[dt]),
-                                    S.stream)) != hipSuccess)
-            return hip_fail(e, "euler");
-        ++S.launches;
-    }
+    for (Req *q : act) q->cur ^= 1;
     return KL_OK;
 }
 
@@ -352,7 +321,8 @@ int enqueue_checksums(Server &S, const std::vector<Req *> &done)
     void *ws = workspace(reduce_scratch_bytes(), S.stream);
     if (!ws) return fail(KL_ERR_NOMEM, "server workspace");
     for (Req *q : done) {
-        const hipError_t e = launch_reduce(make_args(&q->g), 1, q->f[0], q->f[1], q->f[2], q->d_sum, ws, S.stream);
+        void *const *cur = q->f + 3 * q->cur;
+        const hipError_t e = launch_reduce(make_args(&q->g), 1, cur[0], cur[1], cur[2], q->d_sum, ws, S.stream);
         if (e != hipSuccess) return hip_fail(e, "checksum");
         ++S.launches;
     }
@@ -564,7 +534,7 @@ int kl_poll(void *srv, uint64_t ticket, kl_result_t *out)
     out->t_done_ns = q.t_done;
     if (q.state >= 2) {
         memcpy(out->checksum, q.checksum, sizeof q.checksum);
-        for (int n = 0; n < 3; ++n) out->fields[n] = q.f[n];
+        for (int n = 0; n < 3; ++n) out->fields[n] = q.f[3 * q.cur + n];
         out->off = q.g.off;
         out->jstride = q.g.jstride;
         out->kstride = q.g.kstride;

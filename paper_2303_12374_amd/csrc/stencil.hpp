@@ -21,6 +21,7 @@ struct StencilArgs {
     int bc;                  // KL_BC_* (used by the batched Euler update)
     int64_t off, js, ks;
     T dxi, dyi, visc;
+    T dt;                    // time step of the fused step kernels
     const T *__restrict__ dzi;
     const T *__restrict__ dzhi;
     T *ut, *vt, *wt;

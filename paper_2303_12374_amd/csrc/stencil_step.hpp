@@ -1,0 +1,235 @@
+// Fused time step: one kernel reads u, v, w (ghost-filled) once and writes
+// the next state into a second set of fields, ghost cells included:
+//   u' = u + dt * ((0 + advec_u) + diff_u),  v' = v + dt * (0 + diff_v),
+//   w' = w + dt * (0 + diff_w) on w's computed range,
+// then every updated value is also written to the ghost cells it is the
+// source of.  The operations and their order are those of the separate
+// path (tendencies zeroed, advec_u accumulated, diff_uvw accumulated,
+// forward Euler, ghost refill), so the result is bitwise identical to it
+// while HBM traffic drops from 26 to 6 values per point.
+//
+// Tile and data flow as the LDS-staged z-march (stencil_zl.hpp): a wave per
+// row, VX points per lane, a 4-slot register ring per field in z, LDS rows
+// for the y neighbours, shuffles for the x neighbours.  The x edge values
+// are prefetched three levels ahead like the field ring because the w
+// stencil of advec_u needs them at level k+1.
+#pragma once
+
+#include "stencil_zl.hpp"
+
+namespace kl {
+
+// Store a VX-vector of new values at (i0.., j, k) of field `fld` and at all
+// ghost cells whose source it is (periodic x and y; z by the boundary rule).
+template <typename T, int VX, int NT>
+__device__ __forceinline__ void put_with_images(T *f, const StencilArgs<T> &a, int fld, int i0, int j, int k,
+                                                const T (&val)[VX])
+{
+    int zk[4], zs[4], nz = 1;
+    zk[0] = k;
+    zs[0] = 1;
+    const int kt = a.ktot;
+    if (a.bc == KL_BC_ZPERIODIC) {
+        if (k == kt) { zk[nz] = 0; zs[nz++] = 1; }
+        if (k == 1) { zk[nz] = kt + 1; zs[nz++] = 1; }
+    } else if (fld < 2) {
+        if (k == 1) { zk[nz] = 0; zs[nz++] = 1; }
+        if (k == kt) { zk[nz] = kt + 1; zs[nz++] = 1; }
+    } else if (a.bc == KL_BC_ZWALL_ZEROGRAD) {
+        if (k == 2) { zk[nz] = 0; zs[nz++] = 1; zk[nz] = 1; zs[nz++] = 1; }
+        if (k == kt) { zk[nz] = kt + 1; zs[nz++] = 1; }
+    } else {
+        if (k == 2) { zk[nz] = 0; zs[nz++] = -1; zk[nz] = 1; zs[nz++] = 0; }
+        if (k == kt) { zk[nz] = kt + 1; zs[nz++] = 0; }
+    }
+    int yj[3], ny = 1;
+    yj[0] = j;
+    if (j == a.jtot) yj[ny++] = 0;
+    if (j == 1) yj[ny++] = a.jtot + 1;
+    const bool x_lo = i0 == 1, x_hi = i0 + VX - 1 == a.itot;
+    for (int z = 0; z < nz; ++z) {
+        T v[VX];
+#pragma unroll
+        for (int n = 0; n < VX; ++n) v[n] = zs[z] == 0 ? T(0) : (zs[z] < 0 ? -val[n] : val[n]);
+        for (int y = 0; y < ny; ++y) {
+            const int64_t base = a.off + (int64_t)yj[y] * a.js + (int64_t)zk[z] * a.ks;
+            if (z == 0 && y == 0)
+                tstore<NT, T, VX>(f + base + i0, v);
+            else
+                vstore<T, VX>(f + base + i0, v);
+            if (x_lo) f[base + a.itot + 1] = v[0];
+            if (x_hi) f[base] = v[VX - 1];
+        }
+    }
+}
+
+template <typename T, int VX, int BY, int KB, int NT>
+__device__ __forceinline__ void step_zl_tile(const StencilArgs<T> &a, int tx, int ty, int tz)
+{
+    static_assert(BY >= 2, "two halo rows need two waves");
+    constexpr int TX = 64 * VX;
+    typedef T RowT[TX];
+    __shared__ __align__(16) RowT sh[2][3][BY + 2];
+    __shared__ T shvl[2][BY + 2];  // v left of the segment, per LDS row
+    __syncthreads();
+
+    const ZlTile<VX, BY, KB> t(a.itot, a.jtot, a.ktot, tx, ty, tz);
+    const int64_t js = a.js, ks = a.ks;
+    const int64_t c_own = a.off + t.i0 + (int64_t)(t.j0 + t.r) * js;
+    const int64_t c_x = a.off + t.i0 + (int64_t)t.xrow_g * js;
+    const bool ld_own = t.own && t.lane_on;
+    const bool ld_x = t.xrow_g >= 0 && t.lane_on;
+    const bool x_is_top = t.xrow_g >= 0 && t.xrow_l > 0;
+    const bool edge_l = t.own && t.lane == 0;
+    const bool edge_r = t.own && t.lane == t.nlanes - 1;
+    const T *F[3] = {a.u, a.v, a.w};
+    T *O[3] = {a.ut, a.vt, a.wt};  // output fields
+    const T dxi = a.dxi, dyi = a.dyi, dxi2 = a.dxi * a.dxi, dyi2 = a.dyi * a.dyi, visc = a.visc, dt = a.dt;
+    const int kw0 = a.kw0;
+    const int j = t.j0 + t.r;
+
+    T R[4][3][VX];        // field ring: slot s%4 holds level kk+s
+    T EL[4][3], ER[4][3]; // x edge values, same ring
+    T X[2][3][VX];        // halo row, by level parity
+    T XVL[2];             // v left edge of the top halo row
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+#pragma unroll
+        for (int n = 0; n < VX; ++n) {
+            R[0][f][n] = R[1][f][n] = R[2][f][n] = R[3][f][n] = T(0);
+            X[0][f][n] = X[1][f][n] = T(0);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) EL[q][f] = ER[q][f] = T(0);
+    }
+    XVL[0] = XVL[1] = T(0);
+
+    const int k0 = t.k0, k1 = t.k1;
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        if (ld_own) {
+            vload<T, VX>(R[3][f], F[f] + c_own + (int64_t)(k0 - 1) * ks);
+            vload<T, VX>(R[0][f], F[f] + c_own + (int64_t)k0 * ks);
+            vload<T, VX>(R[1][f], F[f] + c_own + (int64_t)(k0 + 1) * ks);
+            if (k0 + 2 <= k1) vload<T, VX>(R[2][f], F[f] + c_own + (int64_t)(k0 + 2) * ks);
+        }
+        if (ld_x) vload<T, VX>(X[0][f], F[f] + c_x + (int64_t)k0 * ks);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            if (k0 + q <= k1) {
+                if (edge_l) EL[q][f] = F[f][c_own + (int64_t)(k0 + q) * ks - 1];
+                if (edge_r) ER[q][f] = F[f][c_own + (int64_t)(k0 + q) * ks + VX];
+            }
+        }
+    }
+    if (x_is_top && t.lane == 0) XVL[0] = a.v[c_x + (int64_t)k0 * ks - 1];
+
+    for (int kk = k0; kk < k1; kk += 4) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int k = kk + s;
+            if (k < k1) {
+                const int p = s & 1, q = p ^ 1;
+                T(&b)[3][VX] = R[(s + 3) & 3];  // level k-1; refilled with k+3 after use
+                T(&c)[3][VX] = R[s & 3];
+                T(&tp)[3][VX] = R[(s + 1) & 3];
+                // halo row of level k+1
+                if (k + 1 < k1) {
+#pragma unroll
+                    for (int f = 0; f < 3; ++f)
+                        if (ld_x) vload<T, VX>(X[q][f], F[f] + c_x + (int64_t)(k + 1) * ks);
+                    if (x_is_top && t.lane == 0) XVL[q] = a.v[c_x + (int64_t)(k + 1) * ks - 1];
+                }
+                // level-k rows into LDS
+#pragma unroll
+                for (int f = 0; f < 3; ++f) {
+                    if (t.own) vstore<T, VX>(&sh[p][f][t.r + 1][t.lane * VX], c[f]);
+                    if (t.xrow_l >= 0) vstore<T, VX>(&sh[p][f][t.xrow_l][t.lane * VX], X[p][f]);
+                }
+                if (t.own && t.lane == 0) shvl[p][t.r + 1] = EL[s & 3][1];
+                if (x_is_top && t.lane == 0) shvl[p][t.xrow_l] = XVL[p];
+                __syncthreads();
+                T nn[3][VX], ss[3][VX], left[3], right[3];
+#pragma unroll
+                for (int f = 0; f < 3; ++f) {
+                    vload<T, VX>(nn[f], &sh[p][f][t.r + 2][t.lane * VX]);
+                    vload<T, VX>(ss[f], &sh[p][f][t.r][t.lane * VX]);
+                    left[f] = shfl_up1<T>(c[f][VX - 1]);
+                    right[f] = shfl_down1<T>(c[f][0]);
+                    if (t.lane == 0) left[f] = EL[s & 3][f];
+                    if (t.lane == t.nlanes - 1) right[f] = ER[s & 3][f];
+                }
+                T vnleft = shfl_up1<T>(nn[1][VX - 1]);
+                T wtleft = shfl_up1<T>(tp[2][VX - 1]);
+                if (t.lane == 0) {
+                    vnleft = shvl[p][t.r + 2];
+                    wtleft = EL[(s + 1) & 3][2];
+                }
+                if (ld_own) {
+                    const T dzik = a.dzi[k], dzikm1 = a.dzi[k - 1], dzhik = a.dzhi[k], dzhik1 = a.dzhi[k + 1];
+                    T nu[VX], nv[VX], nw[VX];
+#pragma unroll
+                    for (int n = 0; n < VX; ++n) {
+                        const T uw = n == 0 ? left[0] : c[0][n - 1];
+                        const T ue = n == VX - 1 ? right[0] : c[0][n + 1];
+                        const T vw = n == 0 ? left[1] : c[1][n - 1];
+                        const T ve = n == VX - 1 ? right[1] : c[1][n + 1];
+                        const T ww = n == 0 ? left[2] : c[2][n - 1];
+                        const T we = n == VX - 1 ? right[2] : c[2][n + 1];
+                        const T v_nw = n == 0 ? vnleft : nn[1][n - 1];
+                        const T w_tw = n == 0 ? wtleft : tp[2][n - 1];
+                        const T adv = advec_u_point<T>(c[0][n], ue, uw, nn[0][n], ss[0][n], tp[0][n], b[0][n], vw,
+                                                       c[1][n], v_nw, nn[1][n], ww, c[2][n], w_tw, tp[2][n], dxi,
+                                                       dyi, dzik);
+                        const T du = diff_c_point<T>(c[0][n], ue, uw, nn[0][n], ss[0][n], tp[0][n], b[0][n], dxi2,
+                                                     dyi2, dzik, dzhik1, dzhik, visc);
+                        const T dv = diff_c_point<T>(c[1][n], ve, vw, nn[1][n], ss[1][n], tp[1][n], b[1][n], dxi2,
+                                                     dyi2, dzik, dzhik1, dzhik, visc);
+                        const T tu = (T(0) + adv) + du;
+                        const T tv = T(0) + dv;
+                        nu[n] = c[0][n] + dt * tu;
+                        nv[n] = c[1][n] + dt * tv;
+                        if (k >= kw0) {
+                            const T dw = diff_w_point<T>(c[2][n], we, ww, nn[2][n], ss[2][n], tp[2][n], b[2][n],
+                                                         dxi2, dyi2, dzik, dzikm1, dzhik, visc);
+                            nw[n] = c[2][n] + dt * (T(0) + dw);
+                        }
+                    }
+                    put_with_images<T, VX, NT>(O[0], a, 0, t.i0, j, k, nu);
+                    put_with_images<T, VX, NT>(O[1], a, 1, t.i0, j, k, nv);
+                    if (k >= kw0) put_with_images<T, VX, NT>(O[2], a, 2, t.i0, j, k, nw);
+                }
+                // level k-1 is no longer needed: its slot takes level k+3
+                if (k + 3 <= k1) {
+#pragma unroll
+                    for (int f = 0; f < 3; ++f) {
+                        if (ld_own) fload<NT, T, VX>(b[f], F[f] + c_own + (int64_t)(k + 3) * ks);
+                        if (edge_l) EL[(s + 3) & 3][f] = F[f][c_own + (int64_t)(k + 3) * ks - 1];
+                        if (edge_r) ER[(s + 3) & 3][f] = F[f][c_own + (int64_t)(k + 3) * ks + VX];
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <typename T, int VX, int BY, int KB, int XCD, int NT = 0, int WPE = 1>
+__global__ __launch_bounds__(64 * BY, WPE) void step_zl(StencilArgs<T> a)
+{
+    int tx, ty, tz;
+    tile_of<64, BY, XCD>(a.nbx, a.nby, a.nbz, tx, ty, tz);
+    step_zl_tile<T, VX, BY, KB, NT>(a, tx, ty, tz);
+}
+
+template <typename T, int VX, int BY, int KB, int NT = 0, int WPE = 1>
+__global__ __launch_bounds__(64 * BY, WPE) void step_zl_batch(const StencilArgs<T> *__restrict__ grids,
+                                                             const int4 *__restrict__ tiles, int ntiles)
+{
+    for (int n = blockIdx.x; n < ntiles; n += gridDim.x) {
+        const int4 tl = tiles[n];
+        const StencilArgs<T> a = grids[tl.x];
+        step_zl_tile<T, VX, BY, KB, NT>(a, tl.y, tl.z, tl.w);
+    }
+}
+
+}  // namespace kl

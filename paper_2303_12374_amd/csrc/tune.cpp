@@ -70,13 +70,13 @@ int tune_one(const kl_grid_t *g, int kernel, void *const f[6], const std::string
     const auto &vs = variants(kernel, g->dtype);
     const void *ptrs[6] = {f[0], f[1], f[2], f[3], f[4], f[5]};
     const int nptr = kernel == KL_KERNEL_ADVEC_U ? 4 : 6;
-    const double visc = 1e-5;
+    const double visc = 1e-5, dt = 1e-4;
     int rc;
 
     // reference output of the default configuration
     uint64_t ref[3];
     if ((rc = zero_tendencies(g, f, s))) return rc;
-    if ((rc = run_variant(g, kernel, 0, f, visc, s))) return rc;
+    if ((rc = run_variant(g, kernel, 0, f, visc, s, dt))) return rc;
     if ((rc = output_hashes(g, kernel, f, gd.dhash, ref, s))) return rc;
 
     const int reps = 15, warm = 3;
@@ -94,14 +94,14 @@ int tune_one(const kl_grid_t *g, int kernel, void *const f[6], const std::string
         double ms = -1.0;
         uint64_t h[3];
         if ((rc = zero_tendencies(g, f, s))) return rc;
-        if ((rc = run_variant(g, kernel, idx, f, visc, s))) return rc;
+        if ((rc = run_variant(g, kernel, idx, f, visc, s, dt))) return rc;
         if ((rc = output_hashes(g, kernel, f, gd.dhash, h, s))) return rc;
         if (h[0] == ref[0] && h[1] == ref[1] && h[2] == ref[2]) {
             for (int r = 0; r < warm; ++r)
-                if ((rc = run_variant(g, kernel, idx, f, visc, s))) return rc;
+                if ((rc = run_variant(g, kernel, idx, f, visc, s, dt))) return rc;
             for (int r = 0; r < reps; ++r) {
                 (void)hipEventRecord(gd.ev[2 * r], s);
-                if ((rc = run_variant(g, kernel, idx, f, visc, s))) return rc;
+                if ((rc = run_variant(g, kernel, idx, f, visc, s, dt))) return rc;
                 (void)hipEventRecord(gd.ev[2 * r + 1], s);
             }
             if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "tune sync");
@@ -126,7 +126,8 @@ int tune_one(const kl_grid_t *g, int kernel, void *const f[6], const std::string
     DeviceIdent id;
     if ((rc = current_device_ident(&id))) return rc;
     const double npts = (double)g->itot * g->jtot * g->ktot;
-    const double bytes = npts * (kernel == KL_KERNEL_ADVEC_U ? 5 : 9) * (g->dtype == KL_F32 ? 4 : 8);
+    const int values = kernel == KL_KERNEL_ADVEC_U ? 5 : (kernel == KL_KERNEL_DIFF_UVW ? 9 : 6);
+    const double bytes = npts * values * (g->dtype == KL_F32 ? 4 : 8);
     const Variant &v = vs[best];
     std::ostringstream o;
     o.precision(6);
@@ -151,11 +152,11 @@ extern "C" int kl_tune(const kl_grid_t *g, void *const fields[6], uint32_t kerne
     if (!fields) return fail(KL_ERR_INVALID, "fields is NULL");
     for (int n = 0; n < 6; ++n)
         if (!fields[n]) return fail(KL_ERR_INVALID, "field %d is NULL", n);
-    if (kernel_mask == 0 || kernel_mask > 3) return fail(KL_ERR_INVALID, "kernel_mask %u", kernel_mask);
+    if (kernel_mask == 0 || kernel_mask > 7) return fail(KL_ERR_INVALID, "kernel_mask %u", kernel_mask);
     if (n_timings) *n_timings = 0;
     const std::string dir = wisdom_dir_ && *wisdom_dir_ ? std::string(wisdom_dir_) : wisdom_dir();
     bool first = true;
-    for (int kernel = 0; kernel < 2; ++kernel) {
+    for (int kernel = 0; kernel < 3; ++kernel) {
         if (!(kernel_mask & (1u << kernel))) continue;
         rc = tune_one(g, kernel, fields, dir, budget_s, (hipStream_t)stream, first ? timings_out : nullptr,
                       max_timings, first ? n_timings : nullptr);

@@ -5,6 +5,7 @@
 #include "kl_internal.hpp"
 #include "stencil.hpp"
 #include "stencil_zl.hpp"
+#include "stencil_step.hpp"
 
 namespace kl {
 
@@ -25,6 +26,7 @@ StencilArgs<T> device_args(const HostArgs &h)
     a.dxi = (T)h.dxi;
     a.dyi = (T)h.dyi;
     a.visc = (T)h.visc;
+    a.dt = (T)h.dt;
     a.dzi = (const T *)h.dzi;
     a.dzhi = (const T *)h.dzhi;
     a.ut = (T *)h.ut;
@@ -112,6 +114,36 @@ int zl_batch_occupancy()
     return e == hipSuccess && n > 0 ? n : 1;
 }
 
+template <typename T, int VX, int BY, int KB, int XCD, int NT = 0, int WPE = 1>
+hipError_t launch_step(const HostArgs &h, hipStream_t s)
+{
+    StencilArgs<T> a = device_args<T>(h);
+    a.nbx = (int)cdivu(h.itot, (int64_t)64 * VX);
+    a.nby = (int)cdivu(h.jtot, BY);
+    a.nbz = (int)cdivu(h.ktot, KB);
+    const uint64_t nb = (uint64_t)a.nbx * a.nby * a.nbz;
+    if (!grid_fits(nb, 64 * BY)) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((step_zl<T, VX, BY, KB, XCD, NT, WPE>), dim3((unsigned)nb), dim3(64, BY), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, int VX, int BY, int KB, int NT = 0, int WPE = 1>
+hipError_t launch_step_batch(const void *descs, const void *tiles, int ntiles, int nblocks, hipStream_t s)
+{
+    hipLaunchKernelGGL((step_zl_batch<T, VX, BY, KB, NT, WPE>), dim3(nblocks), dim3(64, BY), 0, s,
+                       (const StencilArgs<T> *)descs, (const int4 *)tiles, ntiles);
+    return hipGetLastError();
+}
+
+template <typename T, int VX, int BY, int KB, int NT = 0, int WPE = 1>
+int step_batch_occupancy()
+{
+    int n = 0;
+    const hipError_t e =
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_zl_batch<T, VX, BY, KB, NT, WPE>, 64 * BY, 0);
+    return e == hipSuccess && n > 0 ? n : 1;
+}
+
 }  // namespace kl
 
 #define KL_STR2(x) #x
@@ -179,3 +211,13 @@ int zl_batch_occupancy()
 #define KL_ZCX_SET(T, DT, KERN, VX)                                                                     \
     KL_ZCX(T, DT, KERN, VX, 64, 4, 16, 2, 0, 1), KL_ZCX(T, DT, KERN, VX, 64, 4, 16, 2, 1, 1),          \
         KL_ZCX(T, DT, KERN, VX, 64, 4, 16, 0, 1, 1), KL_ZCX(T, DT, KERN, VX, 64, 4, 32, 0, 1, 1)
+
+// Fused-step configurations (kernel KL_KERNEL_STEP).
+#define KL_ST(T, DT, VX, BY, KB, XCD, NT)                                                                  \
+    Variant{"step_v" KL_STR(VX) "_b64x" KL_STR(BY) "_k" KL_STR(KB) "_x" KL_STR(XCD) "_nt" KL_STR(NT),    \
+            KL_KERNEL_STEP, DT, FAMILY_ZL, VX, 64, BY, KB, XCD, &launch_step<T, VX, BY, KB, XCD, NT>,     \
+            &launch_step_batch<T, VX, BY, KB, NT>, &step_batch_occupancy<T, VX, BY, KB, NT>}
+
+#define KL_ST_SET(T, DT, VX)                                                                             \
+    KL_ST(T, DT, VX, 8, 32, 0, 0), KL_ST(T, DT, VX, 4, 64, 2, 1), KL_ST(T, DT, VX, 8, 32, 2, 1),         \
+        KL_ST(T, DT, VX, 4, 128, 2, 1), KL_ST(T, DT, VX, 8, 64, 0, 1), KL_ST(T, DT, VX, 4, 32, 0, 0)

@@ -9,10 +9,15 @@ void add_variants_f32_zl2(int kernel, std::vector<Variant> &out);
 void add_variants_f32_zl4(int kernel, std::vector<Variant> &out);
 void add_variants_f32_x(int kernel, std::vector<Variant> &out);
 void add_variants_f32_nt(int kernel, std::vector<Variant> &out);
+void add_variants_f32_step(std::vector<Variant> &out);
 
 static std::vector<Variant> build_f32(int kernel)
 {
     std::vector<Variant> v;
+    if (kernel == KL_KERNEL_STEP) {  // index 0: a fused step with scalar lanes (fits any itot)
+        add_variants_f32_step(v);
+        return v;
+    }
     v.push_back(Variant{"default", kernel, KL_F32, FAMILY_PLAIN, 1, 256, 1, 1, 0,
                         kernel == KL_KERNEL_ADVEC_U ? &launch_plain<float, KL_KERNEL_ADVEC_U>
                                                     : &launch_plain<float, KL_KERNEL_DIFF_UVW>,
@@ -30,7 +35,8 @@ const std::vector<Variant> &variants_f32(int kernel)
 {
     static const std::vector<Variant> advec = build_f32(KL_KERNEL_ADVEC_U);
     static const std::vector<Variant> diff = build_f32(KL_KERNEL_DIFF_UVW);
-    return kernel == KL_KERNEL_ADVEC_U ? advec : diff;
+    static const std::vector<Variant> step = build_f32(KL_KERNEL_STEP);
+    return kernel == KL_KERNEL_ADVEC_U ? advec : (kernel == KL_KERNEL_DIFF_UVW ? diff : step);
 }
 
 }  // namespace kl

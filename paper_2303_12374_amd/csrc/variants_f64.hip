@@ -8,10 +8,15 @@ void add_variants_f64_zl1(int kernel, std::vector<Variant> &out);
 void add_variants_f64_zl2(int kernel, std::vector<Variant> &out);
 void add_variants_f64_x(int kernel, std::vector<Variant> &out);
 void add_variants_f64_nt(int kernel, std::vector<Variant> &out);
+void add_variants_f64_step(std::vector<Variant> &out);
 
 static std::vector<Variant> build_f64(int kernel)
 {
     std::vector<Variant> v;
+    if (kernel == KL_KERNEL_STEP) {  // index 0: a fused step with scalar lanes (fits any itot)
+        add_variants_f64_step(v);
+        return v;
+    }
     v.push_back(Variant{"default", kernel, KL_F64, FAMILY_PLAIN, 1, 256, 1, 1, 0,
                         kernel == KL_KERNEL_ADVEC_U ? &launch_plain<double, KL_KERNEL_ADVEC_U>
                                                     : &launch_plain<double, KL_KERNEL_DIFF_UVW>,
@@ -28,7 +33,8 @@ const std::vector<Variant> &variants_f64(int kernel)
 {
     static const std::vector<Variant> advec = build_f64(KL_KERNEL_ADVEC_U);
     static const std::vector<Variant> diff = build_f64(KL_KERNEL_DIFF_UVW);
-    return kernel == KL_KERNEL_ADVEC_U ? advec : diff;
+    static const std::vector<Variant> step = build_f64(KL_KERNEL_STEP);
+    return kernel == KL_KERNEL_ADVEC_U ? advec : (kernel == KL_KERNEL_DIFF_UVW ? diff : step);
 }
 
 }  // namespace kl

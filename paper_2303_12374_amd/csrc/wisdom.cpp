@@ -248,7 +248,10 @@ std::string g_dir;  // empty: default
 
 }  // namespace
 
-const char *kernel_name(int kernel) { return kernel == KL_KERNEL_ADVEC_U ? "advec_u" : "diff_uvw"; }
+const char *kernel_name(int kernel)
+{
+    return kernel == KL_KERNEL_ADVEC_U ? "advec_u" : (kernel == KL_KERNEL_DIFF_UVW ? "diff_uvw" : "step");
+}
 
 std::string wisdom_dir()
 {
@@ -388,7 +391,7 @@ int kl_wisdom_lookup(const char *wisdom_dir_, int32_t kernel, int32_t dtype, con
                      int32_t *level)
 {
     clear_error();
-    if (kernel != KL_KERNEL_ADVEC_U && kernel != KL_KERNEL_DIFF_UVW) return fail(KL_ERR_INVALID, "kernel %d", kernel);
+    if (kernel < KL_KERNEL_ADVEC_U || kernel > KL_KERNEL_STEP) return fail(KL_ERR_INVALID, "kernel %d", kernel);
     if (dtype != KL_F32 && dtype != KL_F64) return fail(KL_ERR_INVALID, "dtype %d", dtype);
     if (!device_name || !arch || !variant || !level || len == 0) return fail(KL_ERR_INVALID, "NULL argument");
     DeviceIdent id{device_name, arch, 0};

@@ -24,7 +24,7 @@ LIB_PATH = os.path.join(HERE, "libkl.so")
 
 F32, F64 = 0, 1
 BC_ZWALL_ZEROGRAD, BC_ZWALL_NOPEN, BC_ZPERIODIC = 0, 1, 2
-ADVEC_U, DIFF_UVW = 0, 1
+ADVEC_U, DIFF_UVW, STEP = 0, 1, 2
 OK, ERR_INVALID, ERR_DEVICE, ERR_NOMEM, ERR_BUDGET, ERR_AGAIN, ERR_NOTFOUND, ERR_IO = 0, -1, -2, -3, -4, -5, -6, -7
 
 TORCH_DTYPE = {F32: torch.float32, F64: torch.float64}
@@ -75,6 +75,8 @@ _sig = {
                          c_void_p]),
     "kl_step": (c_int, [_G, c_double, c_double, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                         c_void_p, c_void_p]),
+    "kl_step_fused": (c_int, [_G, c_double, c_double, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                              c_void_p, c_void_p]),
     "kl_reduce_fp64": (c_int, [_G, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "kl_generate_fields": (c_int, [_G, c_uint64, c_void_p, c_void_p, c_void_p, c_void_p]),
     "kl_hash_interior": (c_int, [_G, c_void_p, c_void_p, c_void_p]),
@@ -82,6 +84,7 @@ _sig = {
     "kl_variant_name": (c_int, [c_int32, c_int32, c_int32, c_char_p, c_size_t]),
     "kl_variant_eligible": (c_int, [_G, c_int32, c_int32, POINTER(c_void_p)]),
     "kl_launch_variant": (c_int, [_G, c_int32, c_int32, POINTER(c_void_p), c_double, c_void_p]),
+    "kl_launch_variant_dt": (c_int, [_G, c_int32, c_int32, POINTER(c_void_p), c_double, c_double, c_void_p]),
     "kl_selected_variant": (c_int, [_G, c_int32]),
     "kl_set_wisdom_dir": (c_int, [c_char_p]),
     "kl_clear_plan_cache": (c_int, []),
@@ -177,6 +180,11 @@ def kl_step(g, visc, dt, u, v, w, ut, vt, wt, stream=None):
                         _ptr(vt), _ptr(wt), _stream(stream)))
 
 
+def kl_step_fused(g, visc, dt, u, v, w, u_out, v_out, w_out, stream=None):
+    _check(_lib.kl_step_fused(byref(_cg(g)), float(visc), float(dt), _ptr(u), _ptr(v), _ptr(w), _ptr(u_out),
+                              _ptr(v_out), _ptr(w_out), _stream(stream)))
+
+
 def kl_reduce_fp64(g, what, f0, f1, f2, out, stream=None):
     _check(_lib.kl_reduce_fp64(byref(_cg(g)), what, _ptr(f0), _ptr(f1), _ptr(f2), _ptr(out),
                                _stream(stream)))
@@ -208,6 +216,11 @@ def kl_variant_eligible(g, kernel, index, fields) -> bool:
 def kl_launch_variant(g, kernel, index, fields, visc=0.0, stream=None):
     _check(_lib.kl_launch_variant(byref(_cg(g)), kernel, index, _fields6(fields), float(visc),
                                   _stream(stream)))
+
+
+def kl_launch_variant_dt(g, kernel, index, fields, visc=0.0, dt=0.0, stream=None):
+    _check(_lib.kl_launch_variant_dt(byref(_cg(g)), kernel, index, _fields6(fields), float(visc), float(dt),
+                                     _stream(stream)))
 
 
 def kl_selected_variant(g, kernel) -> int:

@@ -31,7 +31,7 @@ def tune_shape(kl, shape, dtype, wisdom, budget, bc=0, log=None):
     kl.kl_generate_fields(g, 12345, *f[:3])
     kl.kl_fill_ghosts(g, *f[:3])
     out = {}
-    for kern, name in ((kl.ADVEC_U, "advec_u"), (kl.DIFF_UVW, "diff_uvw")):
+    for kern, name in ((kl.ADVEC_U, "advec_u"), (kl.DIFF_UVW, "diff_uvw"), (kl.STEP, "step")):
         t0 = time.time()
         res = kl.kl_tune(g, f, 1 << kern, wisdom, budget)
         ok = [(ms, i) for i, ms in res if ms > 0]
