@@ -1,0 +1,88 @@
+"""Parity at the benchmark's full sizes, in the configuration bench.py times
+(selected from the committed wisdom files): the CPU oracle evaluates sampled
+interior points one by one (``ora_point``), boundary points included, and the
+selected configuration must equal the default one bitwise on the whole grid."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2303_12374_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+TOL = {0: 1e-5, 1: 1e-12}
+
+
+def kl():
+    from paper_2303_12374_amd import kl as m
+    return m
+
+
+def sample_points(itot, jtot, ktot, n, rng):
+    pts = set()
+    for i in (1, 2, itot - 1, itot):
+        for j in (1, jtot):
+            for k in (1, 2, ktot - 1, ktot):
+                pts.add((i, j, k))
+    while len(pts) < n:
+        pts.add((int(rng.integers(1, itot + 1)), int(rng.integers(1, jtot + 1)), int(rng.integers(1, ktot + 1))))
+    return sorted(pts)
+
+
+@pytest.mark.parametrize("shape,dtype", [((512, 512, 512), 0), ((1024, 1024, 128), 0), ((512, 512, 512), 1)],
+                         ids=["512cube-f32", "1024x1024x128-f32", "512cube-f64"])
+def test_full_size_sampled_parity(shape, dtype):
+    m = kl()
+    m.kl_set_wisdom_dir(os.path.join(ROOT, "wisdom"))
+    try:
+        itot, jtot, ktot = shape
+        g = m.Grid(itot, jtot, ktot, dtype=dtype, bc=0)
+        npd = m.NP_DTYPE[dtype]
+        visc = 1e-5
+        dev, host = [], []
+        for f in inputs.random_fields(2, itot, jtot, ktot):
+            fr = f.astype(npd)
+            del f
+            dev.append(g.upload(fr))
+            host.append(inputs.embed(fr.astype(np.float64), g.off, g.js, g.ks, g.alloc))
+            del fr
+        m.kl_fill_ghosts(g, *dev)
+        og = oracle.Grid(itot, jtot, ktot, g.off, g.js, g.ks, g.alloc, g.dxi, g.dyi,
+                         g.dzi_h.astype(np.float64), g.dzhi_h.astype(np.float64), 0)
+        oracle.fill_ghosts(og, *host)
+        sel = [m.kl_selected_variant(g, k) for k in (m.ADVEC_U, m.DIFF_UVW)]
+        t = [g.zeros_interior(fill=0.0) for _ in range(4)]
+        m.kl_advec_u(g, t[0], *dev)
+        m.kl_diff_uvw(g, t[1], t[2], t[3], *dev, visc)
+        torch.cuda.synchronize()
+        rng = np.random.default_rng(5)
+        pts = sample_points(itot, jtot, ktot, 3000, rng)
+        idx = torch.tensor([g.off + i + j * g.js + k * g.ks for i, j, k in pts], device="cuda")
+        got = np.stack([x[idx].cpu().numpy().astype(np.float64) for x in t], axis=1)
+        ref = np.stack([oracle.point(og, float(npd(visc)), *host, i, j, k) for i, j, k in pts])
+        wall = np.array([k for _, _, k in pts]) >= 2
+        for n in range(4):
+            r, gt = ref[:, n], got[:, n]
+            if n == 3:
+                r, gt = r[wall], gt[wall]
+            err = np.max(np.abs(gt - r)) / np.max(np.abs(r))
+            assert err <= TOL[dtype], f"output {n}: sampled rel err {err:.3e}"
+        # the selected configurations equal the default ones bitwise on the whole grid
+        h = torch.zeros(8, dtype=torch.int64, device="cuda")
+        for kern, outs, base in ((m.ADVEC_U, [0], 0), (m.DIFF_UVW, [1, 2, 3], 1)):
+            if sel[kern] == 0:
+                continue
+            d = [g.zeros_interior(fill=0.0) for _ in range(3)]
+            m.kl_launch_variant(g, kern, 0, dev + d, visc)
+            for q, o in enumerate(outs):
+                m.kl_hash_interior(g, t[o], h[2 * q:2 * q + 1])
+                m.kl_hash_interior(g, d[q], h[2 * q + 1:2 * q + 2])
+            hh = h.cpu().numpy()
+            for q in range(len(outs)):
+                assert hh[2 * q] == hh[2 * q + 1], f"selected configuration differs from the default (kernel {kern})"
+    finally:
+        m.kl_set_wisdom_dir(None)
