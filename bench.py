@@ -281,16 +281,17 @@ def served_run(kl, torch, reqs, t_arr, budget_gib):
             "peak_bytes": stats[3]}
 
 
-def copy_probe(torch, nbytes=570425344, reps=5):
-    """A plain device copy of known size (torch's copy kernel), for scaling
-    the HBM byte counters: FETCH_SIZE and WRITE_SIZE of one dispatch should
-    read nbytes each."""
-    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+def copy_probe(torch, nelem=1 << 27, reps=5):
+    """A plain elementwise copy of known size (torch's multiply-by-one
+    kernel: reads and writes nelem FP32 values), for scaling the HBM byte
+    counters: FETCH_SIZE and WRITE_SIZE of one dispatch should each read
+    4 * nelem bytes."""
+    src = torch.ones(nelem, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(reps):
-        dst.copy_(src)
+        torch.mul(src, 1.0, out=dst)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_probe_bytes": nbytes, "reps": reps}), flush=True)
+    print(json.dumps({"copy_probe_bytes": 4 * nelem, "reps": reps}), flush=True)
 
 
 def summarize_counters(fetch_csv, write_csv, workload_key, out_json, out_txt, command):
@@ -311,8 +312,8 @@ def summarize_counters(fetch_csv, write_csv, workload_key, out_json, out_txt, co
 
     fetch = per_kernel(fetch_csv, "FETCH_SIZE")
     write = per_kernel(write_csv, "WRITE_SIZE")
-    copy_name = [k for k in fetch if "copy" in k and "at::native" in k]
-    nbytes = 570425344
+    copy_name = [k for k in fetch if "MulFunctor" in k and len(fetch[k]) >= 5]
+    nbytes = 4 << 27
     out = {}
     lines = [f"# HBM byte counters, {workload_key}", "", f"command: {command}", ""]
     if copy_name:

@@ -100,7 +100,7 @@ bool variant_eligible(const Variant &v, const kl_grid_t *g, const void *const *p
 namespace {
 std::mutex g_ws_mu;
 std::map<std::pair<int, hipStream_t>, void *> g_ws;
-constexpr size_t WS_BYTES = 128 * 1024;
+constexpr size_t WS_BYTES = 512 * 1024;
 }  // namespace
 
 void *workspace(size_t bytes, hipStream_t s)

@@ -199,7 +199,7 @@ __global__ __launch_bounds__(256) void zero_interior_kernel(Dims d, T *f, int nb
 // the RB partials in one block the same way.  No atomics, so the result is
 // bitwise reproducible.
 // ---------------------------------------------------------------------------
-constexpr int RB = 1024;   // pass-1 blocks
+constexpr int RB = 4096;   // pass-1 blocks
 constexpr int RT = 256;    // threads per block
 constexpr int RQ = 9;      // values per partial
 

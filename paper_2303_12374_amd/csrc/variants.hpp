@@ -220,4 +220,11 @@ int step_batch_occupancy()
 
 #define KL_ST_SET(T, DT, VX)                                                                             \
     KL_ST(T, DT, VX, 8, 32, 0, 0), KL_ST(T, DT, VX, 4, 64, 2, 1), KL_ST(T, DT, VX, 8, 32, 2, 1),         \
-        KL_ST(T, DT, VX, 4, 128, 2, 1), KL_ST(T, DT, VX, 8, 64, 0, 1), KL_ST(T, DT, VX, 4, 32, 0, 0)
+        KL_ST(T, DT, VX, 4, 128, 2, 1), KL_ST(T, DT, VX, 8, 64, 0, 1), KL_ST(T, DT, VX, 4, 32, 0, 0),    \
+        KL_ST(T, DT, VX, 4, 8, 0, 0), KL_ST(T, DT, VX, 4, 16, 0, 0), KL_ST(T, DT, VX, 8, 8, 0, 0),       \
+        KL_ST(T, DT, VX, 2, 16, 0, 0)
+
+// Short z-marches for small grids (more tiles, shorter chains).
+#define KL_SMALL_SET(T, DT, KERN, VX)                                                                   \
+    KL_ZLX(T, DT, KERN, VX, 4, 8, 0, 0, 1), KL_ZLX(T, DT, KERN, VX, 4, 16, 0, 0, 1),                   \
+        KL_ZLX(T, DT, KERN, VX, 8, 8, 0, 0, 1), KL_ZLX(T, DT, KERN, VX, 8, 16, 0, 1, 1)

@@ -10,6 +10,7 @@ void add_variants_f32_zl4(int kernel, std::vector<Variant> &out);
 void add_variants_f32_x(int kernel, std::vector<Variant> &out);
 void add_variants_f32_nt(int kernel, std::vector<Variant> &out);
 void add_variants_f32_step(std::vector<Variant> &out);
+void add_variants_f32_small(int kernel, std::vector<Variant> &out);
 
 static std::vector<Variant> build_f32(int kernel)
 {
@@ -28,6 +29,7 @@ static std::vector<Variant> build_f32(int kernel)
         add_variants_f32_zl4(kernel, v);
         add_variants_f32_x(kernel, v);
         add_variants_f32_nt(kernel, v);
+        add_variants_f32_small(kernel, v);
     return v;
 }
 
