@@ -234,7 +234,8 @@ int kl_wisdom_lookup(const char *wisdom_dir, int32_t kernel, int32_t dtype, cons
                      size_t len, int32_t *level);
 
 /* Tune the kernels in kernel_mask (bit 0 advec_u, bit 1 diff_uvw, bit 2 the
- * fused step) for this
+ * fused step; bit 3: time diff_uvw right after the selected advec_u, as in a
+ * time step, so that the cache state it starts from is realistic) for this
  * grid on the current device: every eligible configuration is checked for
  * bitwise-equal output against the default configuration, then timed (hip
  * events, median of repetitions after warm-up) until budget_s seconds are

@@ -246,13 +246,15 @@ __global__ __launch_bounds__(256) void diff_uvw_plain(StencilArgs<T> a)
 // XCD = 1: each XCD gets one contiguous range of the whole tile list;
 // XCD = 2: each XCD gets one contiguous range of every z slab of tiles (when
 // the slab holds a multiple of 8 tiles), so all XCDs sweep the same levels
-// together while neighbouring rows stay under one L2.
+// together while neighbouring rows stay under one L2; XCD = 3: as 2 with the
+// slabs taken from the top down, so a kernel that follows one sweeping
+// upward starts on the levels still held in the memory-side cache.
 template <int BX, int BY, int XCD>
 __device__ __forceinline__ void tile_of(int nbx, int nby, int nbz, int &tx, int &ty, int &tz)
 {
     unsigned b = blockIdx.x;
     if (XCD == 1) b = xcd_remap(b, (unsigned)(nbx * nby * nbz));
-    if (XCD == 2) {
+    if (XCD >= 2) {
         const unsigned S = (unsigned)(nbx * nby);
         if ((S & 7u) == 0) b = (b / S) * S + xcd_remap(b % S, S);
     }
@@ -260,6 +262,7 @@ __device__ __forceinline__ void tile_of(int nbx, int nby, int nbz, int &tx, int 
     b /= (unsigned)nbx;
     ty = (int)(b % (unsigned)nby);
     tz = (int)(b / (unsigned)nby);
+    if (XCD == 3) tz = nbz - 1 - tz;  // top slab first
 }
 
 template <typename T, int VX, int BX, int BY, int KB, int XCD, int NT = 0, int WPE = 1>

@@ -224,6 +224,12 @@ int step_batch_occupancy()
         KL_ST(T, DT, VX, 4, 8, 0, 0), KL_ST(T, DT, VX, 4, 16, 0, 0), KL_ST(T, DT, VX, 8, 8, 0, 0),       \
         KL_ST(T, DT, VX, 2, 16, 0, 0)
 
+// Top-down slab order (XCD = 3) for a kernel that follows another sweep.
+#define KL_REV_SET(T, DT, KERN, VX)                                                                     \
+    KL_ZLX(T, DT, KERN, VX, 4, 64, 3, 1, 1), KL_ZLX(T, DT, KERN, VX, 4, 128, 3, 1, 1),                 \
+        KL_ZLX(T, DT, KERN, VX, 4, 256, 3, 1, 1), KL_ZLX(T, DT, KERN, VX, 8, 32, 3, 1, 1),             \
+        KL_ZLX(T, DT, KERN, VX, 8, 128, 3, 1, 1), KL_ZLX(T, DT, KERN, VX, 4, 128, 3, 0, 1)
+
 // Short z-marches for small grids (more tiles, shorter chains).
 #define KL_SMALL_SET(T, DT, KERN, VX)                                                                   \
     KL_ZLX(T, DT, KERN, VX, 4, 8, 0, 0, 1), KL_ZLX(T, DT, KERN, VX, 4, 16, 0, 0, 1),                   \

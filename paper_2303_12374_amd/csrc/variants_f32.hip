@@ -11,6 +11,7 @@ void add_variants_f32_x(int kernel, std::vector<Variant> &out);
 void add_variants_f32_nt(int kernel, std::vector<Variant> &out);
 void add_variants_f32_step(std::vector<Variant> &out);
 void add_variants_f32_small(int kernel, std::vector<Variant> &out);
+void add_variants_f32_rev(int kernel, std::vector<Variant> &out);
 
 static std::vector<Variant> build_f32(int kernel)
 {
@@ -30,6 +31,7 @@ static std::vector<Variant> build_f32(int kernel)
         add_variants_f32_x(kernel, v);
         add_variants_f32_nt(kernel, v);
         add_variants_f32_small(kernel, v);
+        add_variants_f32_rev(kernel, v);
     return v;
 }
 

@@ -10,6 +10,7 @@ void add_variants_f64_x(int kernel, std::vector<Variant> &out);
 void add_variants_f64_nt(int kernel, std::vector<Variant> &out);
 void add_variants_f64_step(std::vector<Variant> &out);
 void add_variants_f64_small(int kernel, std::vector<Variant> &out);
+void add_variants_f64_rev(int kernel, std::vector<Variant> &out);
 
 static std::vector<Variant> build_f64(int kernel)
 {
@@ -28,6 +29,7 @@ static std::vector<Variant> build_f64(int kernel)
         add_variants_f64_x(kernel, v);
         add_variants_f64_nt(kernel, v);
         add_variants_f64_small(kernel, v);
+        add_variants_f64_rev(kernel, v);
     return v;
 }
 

@@ -1,0 +1,16 @@
+// Registry part: F64 top-down slab order configurations.
+#include "variants.hpp"
+
+namespace kl {
+
+void add_variants_f64_rev(int kernel, std::vector<Variant> &out)
+{
+#define KL_LIST(KERN) {KL_REV_SET(double, KL_F64, KERN, 1), KL_REV_SET(double, KL_F64, KERN, 2)}
+    static const std::vector<Variant> advec = KL_LIST(KL_KERNEL_ADVEC_U);
+    static const std::vector<Variant> diff = KL_LIST(KL_KERNEL_DIFF_UVW);
+#undef KL_LIST
+    const auto &v = kernel == KL_KERNEL_ADVEC_U ? advec : diff;
+    out.insert(out.end(), v.begin(), v.end());
+}
+
+}  // namespace kl
