@@ -294,7 +294,42 @@ def copy_probe(torch, nelem=1 << 27, reps=5):
     print(json.dumps({"copy_probe_bytes": 4 * nelem, "reps": reps}), flush=True)
 
 
-def summarize_counters(fetch_csv, write_csv, workload_key, out_json, out_txt, command):
+def other_dtype_leg(kl, torch, np, shape, dtype, host_fields, visc, steps):
+    """The advec_u + diff_uvw pair on the same grid and fields in the other
+    precision, configurations selected from the wisdom files."""
+    g = kl.Grid(*shape, dtype=dtype, bc=kl.BC_ZWALL_ZEROGRAD)
+    s = 4 if dtype == kl.F32 else 8
+    dev = [g.upload(f.astype(kl.NP_DTYPE[dtype])) for f in host_fields]
+    kl.kl_fill_ghosts(g, *dev)
+    tend = [g.zeros_interior(fill=0.0) for _ in range(3)]
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        kl.kl_advec_u(g, tend[0], *dev, stream)
+        kl.kl_diff_uvw(g, *tend, *dev, visc, stream)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    for e in ev:
+        e[0].record(stream)
+        kl.kl_advec_u(g, tend[0], *dev, stream)
+        e[1].record(stream)
+        kl.kl_diff_uvw(g, *tend, *dev, visc, stream)
+        e[2].record(stream)
+    torch.cuda.synchronize()
+    adv = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    dif = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+    pair = float(np.mean([e[0].elapsed_time(e[2]) for e in ev]))
+    npts = shape[0] * shape[1] * shape[2]
+    names = {n: kl.kl_variant_name(k, dtype, kl.kl_selected_variant(g, k))
+             for n, k in (("advec_u", kl.ADVEC_U), ("diff_uvw", kl.DIFF_UVW))}
+    del dev, tend
+    torch.cuda.empty_cache()
+    return {"dtype": "f64" if dtype == kl.F64 else "f32", "ms_per_pair": pair, "advec_u_ms": adv, "diff_uvw_ms": dif,
+            "grid_points_per_s": npts / (pair * 1e-3), "hbm_gbps": 14 * s * npts / (pair * 1e6),
+            "hbm_frac_of_peak": 14 * s * npts / (pair * 1e6) / PEAK_HBM_GBPS, "configurations": names,
+            "steps": steps}
+
+
+def summarize_counters(fetch_csv, write_csv, workload_key, out_json, out_txt, command, elem="float"):
     """Per-dispatch HBM bytes of the tendency kernels from two rocprofv3 --pmc
     runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what
     the same counter reads for the copy probe of known size."""
@@ -335,6 +370,8 @@ def summarize_counters(fetch_csv, write_csv, workload_key, out_json, out_txt, co
         w_kib = statistics.median(write[k])
         hbm = f_kib * 1024 * fs + w_kib * 1024 * ws
         name = "advec_u" if "advec_u" in k else ("diff_uvw" if "diff_uvw" in k else None)
+        if name and f"<{elem}," not in k:
+            name = None
         lines.append(f"| `{k[:90]}` | {len(fetch[k])} | {f_kib:.0f} | {w_kib:.0f} | {hbm:.4g} |")
         if name:
             out[f"{name}:{workload_key}"] = {"kernel_symbol": k, "fetch_kib": f_kib, "write_kib": w_kib,
@@ -357,6 +394,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-k", type=int, default=128)
     ap.add_argument("--no-untuned", action="store_true")
+    ap.add_argument("--no-other-dtype", action="store_true", help="skip the pair in the other precision")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--served-requests", type=int, default=2000)
@@ -372,9 +410,10 @@ def main():
         wkey = f"{itot}x{jtot}x{ktot}_{args.dtype}"
         cmd = ("rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv -d <dir> -o bench -- python3 "
                "bench.py --with-copy-probe --steps 3 --warmup 1 --no-cpu-baseline --no-untuned --no-batched "
-               "--no-served")
+               "--no-served --no-other-dtype")
         fetch_csv, write_csv, bench_json = args.summarize_counters
-        out, txt = summarize_counters(fetch_csv, write_csv, wkey, None, None, cmd)
+        out, txt = summarize_counters(fetch_csv, write_csv, wkey, None, None, cmd,
+                                      "float" if args.dtype == "f32" else "double")
         with open(bench_json) as f:
             sel = json.loads([ln for ln in f if ln.startswith("{")][-1])["config"]["configurations"]
         path = os.path.join(ROOT, "profiles", "counters.json")
@@ -419,7 +458,8 @@ def main():
     dev = []
     for f in fs:
         dev.append(g.upload(f.astype(kl.NP_DTYPE[dtype])))
-    del fs
+    if args.no_other_dtype:
+        del fs
     kl.kl_fill_ghosts(g, *dev)
     tend = [g.zeros_interior(fill=0.0) for _ in range(3)]
     u, v, w = dev
@@ -515,6 +555,12 @@ def main():
                      "algorithmic_bytes_per_launch": dom_bytes},
         "untuned": untuned,
     }
+    if not args.no_other_dtype:
+        other = kl.F64 if dtype == kl.F32 else kl.F32
+        log(f"the same pair in {'FP64' if other == kl.F64 else 'FP32'}")
+        result["other_dtype"] = other_dtype_leg(kl, torch, np, (itot, jtot, ktot), other, fs, visc,
+                                                max(5, args.steps // 2))
+        del fs
     # one time step: separate kernels (kl_step) versus the fused step kernel
     log("time step: kl_step (zero, advec_u, diff_uvw, Euler) vs kl_step_fused")
     out = [g.full() for _ in range(3)]

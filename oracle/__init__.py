@@ -67,10 +67,16 @@ def _declare(lib):
     lib.ora_conservation.argtypes = dims + [_I, _P, _P, _P, _P, _P, _P]
     lib.ora_checksums.argtypes = dims + [_P, _P]
     lib.ora_point.argtypes = dims + [_I, _D, _D, _P, _P, _D, _P, _P, _P, _I, _I, _I, _P]
+    lib.ora_fill_ghosts_gc.argtypes = dims + [_I, _I, _P, _P, _P]
+    lib.ora_fill_scalar.argtypes = dims + [_I, _I, _P]
+    lib.ora_advec_u_2i5.argtypes = dims + [_D, _D, _P, _P, _P, _P, _P]
+    lib.ora_diff_smag.argtypes = dims + [_D, _D, _P, _P, _I, _P, _P, _P, _P, _P, _P, _P]
+    lib.ora_point_les.argtypes = dims + [_I, _D, _D, _P, _P, _P, _P, _P, _P, _I, _I, _I, _P]
     lib.ora_threads.argtypes = []
     lib.ora_threads.restype = ctypes.c_int
     for f in ("ora_fill_ghosts", "ora_advec_u", "ora_diff_uvw", "ora_euler", "ora_step",
-              "ora_conservation", "ora_checksums", "ora_point"):
+              "ora_conservation", "ora_checksums", "ora_point", "ora_fill_ghosts_gc",
+              "ora_fill_scalar", "ora_advec_u_2i5", "ora_diff_smag", "ora_point_les"):
         getattr(lib, f).restype = None
 
 
@@ -80,16 +86,18 @@ def _p(a: np.ndarray):
 
 
 class Grid:
-    """Interior sizes, padded layout and metrics of one grid (host, FP64)."""
+    """Interior sizes, padded layout and metrics of one grid (host, FP64);
+    ``gc`` ghost cells per side in x and y (1, or 3 for advec_u_2i5)."""
 
     def __init__(self, itot, jtot, ktot, off, js, ks, alloc, dxi, dyi, dzi, dzhi,
-                 bc=BC_ZWALL_ZEROGRAD):
+                 bc=BC_ZWALL_ZEROGRAD, gc=1):
         self.itot, self.jtot, self.ktot = int(itot), int(jtot), int(ktot)
         self.off, self.js, self.ks, self.alloc = int(off), int(js), int(ks), int(alloc)
         self.dxi, self.dyi = float(dxi), float(dyi)
         self.dzi = np.ascontiguousarray(dzi, dtype=np.float64)
         self.dzhi = np.ascontiguousarray(dzhi, dtype=np.float64)
         self.bc = int(bc)
+        self.gc = int(gc)
 
     @property
     def dims(self):
@@ -97,7 +105,37 @@ class Grid:
 
 
 def fill_ghosts(g: Grid, u, v, w, lib=None):
-    (lib or load()).ora_fill_ghosts(*g.dims, g.bc, _p(u), _p(v), _p(w))
+    """Ghost cells of u, v, w (gc per side in x and y, one in z)."""
+    if g.gc == 1:
+        (lib or load()).ora_fill_ghosts(*g.dims, g.bc, _p(u), _p(v), _p(w))
+    else:
+        (lib or load()).ora_fill_ghosts_gc(*g.dims, g.gc, g.bc, _p(u), _p(v), _p(w))
+
+
+def fill_scalar(g: Grid, f, lib=None):
+    """Ghost cells of a cell-center scalar (the eddy viscosity)."""
+    (lib or load()).ora_fill_scalar(*g.dims, g.gc, g.bc, _p(f))
+
+
+def advec_u_2i5(g: Grid, ut, u, v, w, lib=None):
+    """ut += advection of u with fifth-order interpolation (needs gc >= 3)."""
+    assert g.gc >= 3, "advec_u_2i5 needs three ghost cells in x and y"
+    (lib or load()).ora_advec_u_2i5(*g.dims, g.dxi, g.dyi, _p(g.dzi), _p(ut), _p(u), _p(v), _p(w))
+
+
+def diff_smag(g: Grid, ut, vt, wt, u, v, w, evisc, lib=None):
+    """(ut, vt, wt) += divergence of the viscous stress with eddy viscosity evisc."""
+    (lib or load()).ora_diff_smag(*g.dims, g.dxi, g.dyi, _p(g.dzi), _p(g.dzhi), g.bc,
+                                  _p(ut), _p(vt), _p(wt), _p(u), _p(v), _p(w), _p(evisc))
+
+
+def point_les(g: Grid, u, v, w, evisc, i, j, k, lib=None) -> np.ndarray:
+    """[advec_u_2i5, diff_smag u, v, w] at one interior point (needs gc >= 3)."""
+    assert g.gc >= 3
+    out = np.zeros(4)
+    (lib or load()).ora_point_les(*g.dims, g.bc, g.dxi, g.dyi, _p(g.dzi), _p(g.dzhi),
+                                  _p(u), _p(v), _p(w), _p(evisc), int(i), int(j), int(k), _p(out))
+    return out
 
 
 def advec_u(g: Grid, ut, u, v, w, lib=None):

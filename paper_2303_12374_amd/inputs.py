@@ -9,9 +9,11 @@ Grid conventions (the paper states the problem as fields on a 3-D grid with
 grid dimensions, spacings, viscosity and precision; Section "Application" and
 "Tunable Parameters").  The readings below are this library's:
 
-* interior sizes ``itot, jtot, ktot``; one ghost cell per side;
+* interior sizes ``itot, jtot, ktot``; ``gh`` ghost cells per side in x and
+  y (1, or 3 for the fifth-order advection scheme), one in z;
 * index ``idx(i, j, k) = off + i + j*jstride + k*kstride`` with
-  ``i in [0, itot+1]`` etc., interior ``i in [1, itot]``;
+  ``i in [1-gh, itot+gh]``, ``j in [1-gh, jtot+gh]``, ``k in [0, ktot+1]``,
+  interior ``i in [1, itot]`` etc.;
 * Arakawa-C staggering: u at (xh_i, y_j, z_k), v at (x_i, yh_j, z_k),
   w at (x_i, y_j, zh_k) with ``xh_i = (i-1) dx`` and ``x_i = (i-1/2) dx``;
 * ``Lx = Ly = 1`` so ``dx = 1/itot``, ``dy = 1/jtot``;
@@ -126,18 +128,19 @@ def zgrid(ktot: int, Lz: float, gamma: float = 1.5) -> dict:
     return dict(z=z, zh=zh, dz=dz, dzh=dzh, dzi=1.0 / dz, dzhi=1.0 / dzh, Lz=Lz, gamma=gamma)
 
 
-def coords(itot: int, jtot: int, zg: dict) -> dict:
-    """Cell-center and face coordinates, ghost cells included (length n+2)."""
+def coords(itot: int, jtot: int, zg: dict, gh: int = 1) -> dict:
+    """Cell-center and face coordinates, ghost cells included (length n+2*gh,
+    entry 0 is index 1-gh)."""
     dx, dy = 1.0 / itot, 1.0 / jtot
-    i = np.arange(itot + 2, dtype=np.float64)
-    j = np.arange(jtot + 2, dtype=np.float64)
+    i = np.arange(1 - gh, itot + gh + 1, dtype=np.float64)
+    j = np.arange(1 - gh, jtot + gh + 1, dtype=np.float64)
     return dict(x=(i - 0.5) * dx, xh=(i - 1.0) * dx, y=(j - 0.5) * dy, yh=(j - 1.0) * dy,
                 z=zg["z"], zh=zg["zh"])
 
 
-def staggered_positions(field: int, itot: int, jtot: int, zg: dict):
+def staggered_positions(field: int, itot: int, jtot: int, zg: dict, gh: int = 1):
     """Broadcastable (Z, Y, X) coordinate arrays of one field, ghosts included."""
-    c = coords(itot, jtot, zg)
+    c = coords(itot, jtot, zg, gh)
     X = c["xh"] if field == FIELD_U else c["x"]
     Y = c["yh"] if field == FIELD_V else c["y"]
     Z = c["zh"] if field == FIELD_W else c["z"]
@@ -151,6 +154,15 @@ def staggered_positions(field: int, itot: int, jtot: int, zg: dict):
 def random_fields(seed: int, itot: int, jtot: int, ktot: int, mean=MEAN_FLOW):
     """u, v, w interior = U[-1, 1) noise + mean flow (1.0, 0.5, 0)."""
     return [uniform_field(seed, f, itot, jtot, ktot) + mean[f] for f in range(3)]
+
+
+FIELD_EVISC = 3
+
+
+def evisc_field(seed: int, itot: int, jtot: int, ktot: int, mean: float = 1e-3, amp: float = 0.5):
+    """A positive eddy-viscosity field at cell centers:
+    ``mean * (1 + amp * U[-1, 1))`` from stream 3 of ``seed``."""
+    return mean * (1.0 + amp * uniform_field(seed, FIELD_EVISC, itot, jtot, ktot))
 
 
 def sinusoid_fields(seed: int, itot: int, jtot: int, ktot: int, zg: dict,
@@ -185,22 +197,33 @@ def sinusoid_fields(seed: int, itot: int, jtot: int, ktot: int, zg: dict,
 # padded layout
 # --------------------------------------------------------------------------
 
-def plain_layout(itot: int, jtot: int, ktot: int):
-    """Unpadded layout: off = 0, jstride = itot+2, kstride = jstride*(jtot+2)."""
-    js = itot + 2
-    ks = js * (jtot + 2)
-    return 0, js, ks, ks * (ktot + 2)
+def plain_layout(itot: int, jtot: int, ktot: int, gh: int = 1):
+    """Unpadded layout: jstride = itot+2*gh, kstride = jstride*(jtot+2*gh),
+    and off such that idx(1-gh, 1-gh, 0) = 0."""
+    js = itot + 2 * gh
+    ks = js * (jtot + 2 * gh)
+    off = (gh - 1) * (js + 1)
+    return off, js, ks, ks * (ktot + 2)
 
 
-def padded_view(buf: np.ndarray, itot: int, jtot: int, ktot: int, off: int, js: int, ks: int):
-    """Strided (kcells, jcells, icells) view of a flat buffer in the index layout."""
+def padded_view(buf: np.ndarray, itot: int, jtot: int, ktot: int, off: int, js: int, ks: int,
+                gh: int = 1):
+    """Strided (ktot+2, jtot+2*gh, itot+2*gh) view of a flat buffer in the
+    index layout; view[k, j, i] is element (i+1-gh, j+1-gh, k)."""
     item = buf.itemsize
+    start = off - (gh - 1) * (js + 1)
     return np.lib.stride_tricks.as_strided(
-        buf[off:], shape=(ktot + 2, jtot + 2, itot + 2), strides=(ks * item, js * item, item))
+        buf[start:], shape=(ktot + 2, jtot + 2 * gh, itot + 2 * gh), strides=(ks * item, js * item, item))
+
+
+def interior_view(buf: np.ndarray, itot: int, jtot: int, ktot: int, off: int, js: int, ks: int,
+                  gh: int = 1):
+    """The (ktot, jtot, itot) interior of a flat buffer in the index layout."""
+    return padded_view(buf, itot, jtot, ktot, off, js, ks, gh)[1:ktot + 1, gh:jtot + gh, gh:itot + gh]
 
 
 def embed(interior: np.ndarray, off: int, js: int, ks: int, alloc: int,
-          dtype=np.float64, fill=np.nan) -> np.ndarray:
+          dtype=np.float64, fill=np.nan, gh: int = 1) -> np.ndarray:
     """Flat buffer of ``alloc`` elements holding ``interior`` at [1..n] in each axis.
 
     Ghost and padding cells hold ``fill`` (NaN by default) so that a read of
@@ -208,17 +231,18 @@ def embed(interior: np.ndarray, off: int, js: int, ks: int, alloc: int,
     """
     ktot, jtot, itot = interior.shape
     buf = np.full(alloc, fill, dtype=dtype)
-    padded_view(buf, itot, jtot, ktot, off, js, ks)[1:ktot + 1, 1:jtot + 1, 1:itot + 1] = interior
+    interior_view(buf, itot, jtot, ktot, off, js, ks, gh)[...] = interior
     return buf
 
 
 def analytic_padded(fn, field: int, itot: int, jtot: int, ktot: int, zg: dict,
-                    off: int, js: int, ks: int, alloc: int) -> np.ndarray:
-    """Flat FP64 buffer with ``fn(x, y, z)`` at every cell, ghosts included."""
-    Z, Y, X = staggered_positions(field, itot, jtot, zg)
-    vals = np.broadcast_to(fn(X, Y, Z), (ktot + 2, jtot + 2, itot + 2))
+                    off: int, js: int, ks: int, alloc: int, gh: int = 1) -> np.ndarray:
+    """Flat FP64 buffer with ``fn(x, y, z)`` at every cell, ghosts included.
+    ``field`` 3 is a cell-center scalar (the position of v's x, u's y and z)."""
+    Z, Y, X = staggered_positions(field, itot, jtot, zg, gh)
+    vals = np.broadcast_to(fn(X, Y, Z), (ktot + 2, jtot + 2 * gh, itot + 2 * gh))
     buf = np.full(alloc, np.nan)
-    padded_view(buf, itot, jtot, ktot, off, js, ks)[...] = vals
+    padded_view(buf, itot, jtot, ktot, off, js, ks, gh)[...] = vals
     return buf
 
 

@@ -139,6 +139,37 @@ def test_alone_and_in_a_mix_are_bitwise_equal():
         S.close()
 
 
+def test_sixty_request_mix_equals_each_request_alone():
+    """Every request of a 60-request mix (both precisions, all boundary
+    modes, ragged shapes, 1-6 steps) equals, bitwise, the same request served
+    on its own; the FP64 checksums agree bitwise too."""
+    S = Server(arena_bytes=3 << 30)
+    try:
+        rng = np.random.default_rng(11)
+        mix = []
+        for n in range(60):
+            shape = [int(x) for x in rng.choice([8, 16, 24, 33, 48, 64, 72], 3)]
+            shape[2] = max(shape[2], 2)
+            mix.append((*shape, int(rng.integers(0, 2)), int(rng.integers(0, 3)), int(rng.integers(1, 7)),
+                        1e-3, 1e-5, 500 + n))
+        tickets = [S.m.kl_submit(S.h, *r) for r in mix]
+        in_mix = {}
+        for tk, r in zip(tickets, mix):
+            res = S.wait(tk)
+            in_mix[tk] = (S.fields(res, r), list(res.checksum))
+            S.m.kl_release(S.h, tk)
+        for tk, r in zip(tickets, mix):
+            t = S.m.kl_submit(S.h, *r)
+            res = S.wait(t)
+            alone = S.fields(res, r)
+            for a, b in zip(in_mix[tk][0], alone):
+                assert np.array_equal(a, b), f"request {r} differs alone and in the mix"
+            assert list(res.checksum) == in_mix[tk][1], f"request {r}: checksums differ"
+            S.m.kl_release(S.h, t)
+    finally:
+        S.close()
+
+
 def test_served_equals_single_grid_steps():
     """A served request equals the same steps run with kl_step on its own grid."""
     m = kl()

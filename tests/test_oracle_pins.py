@@ -3,6 +3,7 @@ import pytest
 
 import oracle
 import pins
+import pins_les
 
 
 @pytest.fixture(scope="module")
@@ -10,7 +11,7 @@ def lib():
     return oracle.load()
 
 
-@pytest.mark.parametrize("pin", pins.PINS, ids=lambda p: p.__name__)
+@pytest.mark.parametrize("pin", pins.PINS + pins_les.PINS, ids=lambda p: p.__name__)
 def test_pin(pin, lib):
     pin(lib)
 
