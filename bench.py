@@ -329,6 +329,55 @@ def other_dtype_leg(kl, torch, np, shape, dtype, host_fields, visc, steps):
             "steps": steps}
 
 
+def les_leg(kl, torch, np, inputs, shape, host_fields, seed, steps):
+    """The paper's own schemes on the same grid and fields: advec_u_2i5
+    (fifth-order interpolated advection, three ghost cells in x and y) and
+    diff_smag (stress divergence with a cell-center eddy viscosity), FP32,
+    configurations selected from the wisdom files.  Algorithmic values per
+    point: 5 (advection) and 10 (diffusion: u, v, w, evisc, ut, vt, wt read;
+    ut, vt, wt written)."""
+    g = kl.Grid(*shape, dtype=kl.F32, bc=kl.BC_ZWALL_ZEROGRAD, gc=3)
+    dev = [g.upload(f.astype(np.float32)) for f in host_fields]
+    dev.append(g.upload(inputs.evisc_field(seed, *shape).astype(np.float32)))
+    kl.kl_fill_ghosts(g, *dev[:3])
+    kl.kl_fill_scalar(g, dev[3])
+    tend = [g.zeros_interior(fill=0.0) for _ in range(3)]
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        kl.kl_advec_u_2i5(g, tend[0], *dev[:3], stream)
+        kl.kl_diff_smag(g, *tend, *dev, stream)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    for e in ev:
+        e[0].record(stream)
+        kl.kl_advec_u_2i5(g, tend[0], *dev[:3], stream)
+        e[1].record(stream)
+        kl.kl_diff_smag(g, *tend, *dev, stream)
+        e[2].record(stream)
+    torch.cuda.synchronize()
+    adv = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    dif = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+    pair = float(np.mean([e[0].elapsed_time(e[2]) for e in ev]))
+    npts = shape[0] * shape[1] * shape[2]
+    names = {n: kl.kl_variant_name(k, kl.F32, kl.kl_selected_variant(g, k))
+             for n, k in (("advec_u_2i5", kl.ADVEC_U_2I5), ("diff_smag", kl.DIFF_SMAG))}
+    b_adv, b_dif = 5 * 4 * npts, 10 * 4 * npts
+    del dev, tend
+    torch.cuda.empty_cache()
+    return {"workload": f"advec_u_2i5+diff_smag {shape[0]}x{shape[1]}x{shape[2]} F32, same fields, "
+                        f"eddy viscosity 1e-3 (1 +- 0.5 noise), 3 ghost cells in x and y",
+            "ms_per_pair": pair, "grid_points_per_s": npts / (pair * 1e-3),
+            "hbm_gbps": (b_adv + b_dif) / (pair * 1e6),
+            "hbm_frac_of_peak": (b_adv + b_dif) / (pair * 1e6) / PEAK_HBM_GBPS,
+            "kernels": {"advec_u_2i5": {"ms": adv, "gbps": b_adv / (adv * 1e6),
+                                        "frac": b_adv / (adv * 1e6) / PEAK_HBM_GBPS,
+                                        "algorithmic_bytes_per_launch": b_adv},
+                        "diff_smag": {"ms": dif, "gbps": b_dif / (dif * 1e6),
+                                      "frac": b_dif / (dif * 1e6) / PEAK_HBM_GBPS,
+                                      "algorithmic_bytes_per_launch": b_dif}},
+            "configurations": names, "steps": steps}
+
+
 def summarize_counters(fetch_csv, write_csv, workload_key, out_json, out_txt, command, elem="float"):
     """Per-dispatch HBM bytes of the tendency kernels from two rocprofv3 --pmc
     runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what
@@ -395,6 +444,7 @@ def main():
     ap.add_argument("--cpu-sample-k", type=int, default=128)
     ap.add_argument("--no-untuned", action="store_true")
     ap.add_argument("--no-other-dtype", action="store_true", help="skip the pair in the other precision")
+    ap.add_argument("--no-les", action="store_true", help="skip the fifth-order advection + Smagorinsky pair")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--served-requests", type=int, default=2000)
@@ -410,7 +460,7 @@ def main():
         wkey = f"{itot}x{jtot}x{ktot}_{args.dtype}"
         cmd = ("rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv -d <dir> -o bench -- python3 "
                "bench.py --with-copy-probe --steps 3 --warmup 1 --no-cpu-baseline --no-untuned --no-batched "
-               "--no-served --no-other-dtype")
+               "--no-served --no-other-dtype --no-les")
         fetch_csv, write_csv, bench_json = args.summarize_counters
         out, txt = summarize_counters(fetch_csv, write_csv, wkey, None, None, cmd,
                                       "float" if args.dtype == "f32" else "double")
@@ -458,7 +508,7 @@ def main():
     dev = []
     for f in fs:
         dev.append(g.upload(f.astype(kl.NP_DTYPE[dtype])))
-    if args.no_other_dtype:
+    if args.no_other_dtype and args.no_les:
         del fs
     kl.kl_fill_ghosts(g, *dev)
     tend = [g.zeros_interior(fill=0.0) for _ in range(3)]
@@ -560,6 +610,10 @@ def main():
         log(f"the same pair in {'FP64' if other == kl.F64 else 'FP32'}")
         result["other_dtype"] = other_dtype_leg(kl, torch, np, (itot, jtot, ktot), other, fs, visc,
                                                 max(5, args.steps // 2))
+    if not args.no_les:
+        log("the paper's schemes: advec_u_2i5 + diff_smag")
+        result["les"] = les_leg(kl, torch, np, inputs, (itot, jtot, ktot), fs, seed, max(5, args.steps // 2))
+    if not (args.no_other_dtype and args.no_les):
         del fs
     # one time step: separate kernels (kl_step) versus the fused step kernel
     log("time step: kl_step (zero, advec_u, diff_uvw, Euler) vs kl_step_fused")

@@ -30,6 +30,25 @@
  *     for w.  u and v are advanced on k in [1, ktot]; w on k in [2, ktot]
  *     with z walls and on [1, ktot] when z is periodic.
  *
+ * The schemes the paper names for its two kernels (Section "Tunable
+ * Parameters": advection of u "second order with fifth order
+ * interpolation", diffusion as part of "second order Smagorinsky
+ * diffusion") are also provided:
+ *   advec_u_2i5: the flux form above with the advected u interpolated to
+ *     each face by the fifth-order upwind-biased formula of Wicker and
+ *     Skamarock (2002): face(U; a_-2..a_3) = U c6 - |U| d5 with
+ *     c6 = (37(a0+a1) - 8(a_-1+a2) + (a_-2+a3))/60,
+ *     d5 = (10(a1-a0) - 5(a2-a_-1) + (a3-a_-2))/60 (face between a0, a1;
+ *     U the midpoint-interpolated advecting velocity).  In z the order drops
+ *     to third, U c4 - |U| d3 with c4 = (7(a0+a1) - (a_-1+a2))/12,
+ *     d3 = (3(a1-a0) - (a2-a_-1))/12, on faces 2 and ktot, and to the
+ *     midpoint U (a0+a1)/2 on faces 1 and ktot+1.  Needs gc = 3.
+ *   diff_smag: (ut, vt, wt) += div(nu (grad u + grad u^T)) with nu = evisc
+ *     given at cell centers: normal stresses 2 nu d_i u_i at cell centers,
+ *     shear stresses on cell edges with nu the mean of the four surrounding
+ *     centers, z widths dz_k for u, v and dzh_k for w.  w is advanced on the
+ *     same range as in diff_uvw.
+ *
  * Conventions shared by every entry point:
  *  - Return value: KL_OK (0) or a negative kl_status_t.  The message of the
  *    last failure on the calling thread is kl_last_error().  No C++
@@ -77,18 +96,35 @@ typedef enum {
 
 /* Kernels with tunable configurations.  KL_KERNEL_STEP is the fused time
  * step of kl_step_fused. */
-enum { KL_KERNEL_ADVEC_U = 0, KL_KERNEL_DIFF_UVW = 1, KL_KERNEL_STEP = 2 };
+enum {
+    KL_KERNEL_ADVEC_U = 0,
+    KL_KERNEL_DIFF_UVW = 1,
+    KL_KERNEL_STEP = 2,
+    KL_KERNEL_ADVEC_U_2I5 = 3,
+    KL_KERNEL_DIFF_SMAG = 4
+};
+
+/* kl_tune kernel_mask bits. */
+enum {
+    KL_TUNE_ADVEC_U = 1u,
+    KL_TUNE_DIFF_UVW = 2u,
+    KL_TUNE_STEP = 4u,
+    KL_TUNE_PAIR = 8u, /* time each diffusion kernel right after its advection kernel */
+    KL_TUNE_ADVEC_U_2I5 = 16u,
+    KL_TUNE_DIFF_SMAG = 32u
+};
 
 /* One grid.  Element (i, j, k) of every field is at index
  * off + i + j*jstride + k*kstride (elements of the field dtype), with
- * i in [0, itot+1] (interior [1, itot]) and likewise for j and k.  The same
- * layout holds for u, v, w and the tendencies ut, vt, wt.
+ * i in [1-gc, itot+gc] (interior [1, itot]), likewise j, and k in
+ * [0, ktot+1] (one ghost level in z).  The same layout holds for u, v, w,
+ * the tendencies ut, vt, wt and the eddy viscosity.
  * dzi[k] = 1/(zh_{k+1} - zh_k) and dzhi[k] = 1/(z_k - z_{k-1}) are device
  * arrays of ktot+2 entries in the field dtype; dxi = 1/dx and dyi = 1/dy are
  * rounded to the field dtype inside the kernels. */
 typedef struct kl_grid {
     int32_t itot, jtot, ktot; /* interior points per axis, >= 1 (ktot >= 2 with z walls) */
-    int32_t gc;               /* ghost width, must be 1 */
+    int32_t gc;               /* ghost cells per side in x and y: 1, or 3 (advec_u_2i5) */
     int64_t off, jstride, kstride;
     double dxi, dyi;
     const void *dzi, *dzhi;
@@ -111,10 +147,23 @@ const char *kl_last_error(void);
 int kl_layout(int32_t itot, int32_t jtot, int32_t ktot, int32_t dtype,
               int64_t *off, int64_t *jstride, int64_t *kstride, int64_t *alloc_elems);
 
+/* kl_layout for gc ghost cells per side in x and y (gc = 1 or 3): rows of
+ * itot + 2 gc cells padded to whole 128-byte lines, interior rows starting
+ * on a line boundary, off = (gc-1) jstride + (line - 1) (line = 128 bytes in
+ * elements) so that the first ghost cell (1-gc, 1-gc, 0) has a non-negative
+ * index.  gc = 1 is kl_layout. */
+int kl_layout_gc(int32_t itot, int32_t jtot, int32_t ktot, int32_t dtype, int32_t gc,
+                 int64_t *off, int64_t *jstride, int64_t *kstride, int64_t *alloc_elems);
+
 /* Fill the ghost cells of u, v and w from the interior by the boundary rules
  * of g->bc (and, in wall modes, the wall faces w_1 and w_{ktot+1}).  Reads
  * interior cells only, so all ghosts are filled in one pass. */
 int kl_fill_ghosts(const kl_grid_t *g, void *u, void *v, void *w, void *stream);
+
+/* Fill the ghost cells of one cell-center scalar (the eddy viscosity):
+ * periodic in x and y, in z periodic (KL_BC_ZPERIODIC) or zero gradient
+ * across the walls, as u and v. */
+int kl_fill_scalar(const kl_grid_t *g, void *f, void *stream);
 
 /* ut += advec_u(u, v, w) on the interior (formula above).  u, v, w must be
  * ghost-filled.  Runs the configuration selected for (dtype, itot, jtot,
@@ -126,6 +175,19 @@ int kl_advec_u(const kl_grid_t *g, void *ut, const void *u, const void *v, const
  * (formula above).  u, v, w must be ghost-filled.  Selection as kl_advec_u. */
 int kl_diff_uvw(const kl_grid_t *g, void *ut, void *vt, void *wt,
                 const void *u, const void *v, const void *w, double visc, void *stream);
+
+/* ut += advec_u_2i5(u, v, w) on the interior (scheme above).  Requires
+ * g->gc >= 3; u, v, w ghost-filled.  Selection as kl_advec_u (wisdom file
+ * advec_u_2i5.wisdom). */
+int kl_advec_u_2i5(const kl_grid_t *g, void *ut, const void *u, const void *v, const void *w,
+                   void *stream);
+
+/* (ut, vt, wt) += div(evisc (grad u + grad u^T)) on each field's computed
+ * range (scheme above).  u, v, w and evisc must be ghost-filled
+ * (kl_fill_ghosts, kl_fill_scalar).  Selection as kl_advec_u (wisdom file
+ * diff_smag.wisdom). */
+int kl_diff_smag(const kl_grid_t *g, void *ut, void *vt, void *wt, const void *u, const void *v,
+                 const void *w, const void *evisc, void *stream);
 
 /* Forward-Euler update f += dt * ft on each field's computed range, fused
  * with the ghost refill of the updated fields (every ghost cell is written
@@ -189,15 +251,18 @@ int kl_num_variants(int32_t kernel, int32_t dtype);
 int kl_variant_name(int32_t kernel, int32_t dtype, int32_t index, char *buf, size_t len);
 
 /* 1 if configuration `index` can run on this grid and these pointers
- * (vector width divides itot and the layout/pointer alignment), else 0. */
+ * (vector width divides itot and the layout/pointer alignment), else 0.
+ * `fields` as in kl_launch_variant (may be NULL: layout checks only). */
 int kl_variant_eligible(const kl_grid_t *g, int32_t kernel, int32_t index,
                         const void *const fields[6]);
 
 /* Launch configuration `index` of `kernel` directly.  fields = {u, v, w, ut,
- * vt, wt}; advec_u uses u, v, w, ut; the fused step reads u, v, w and writes
+ * vt, wt} and, for KL_KERNEL_DIFF_SMAG, a seventh entry evisc; the
+ * advection kernels use u, v, w, ut; the fused step reads u, v, w and writes
  * fields 3..5 (visc and the time step dt of kl_launch_variant_dt).  Same
- * semantics as kl_advec_u / kl_diff_uvw / kl_step_fused.  KL_ERR_INVALID if
- * the configuration is not eligible. */
+ * semantics as the corresponding kl_advec_u / kl_diff_uvw / kl_step_fused /
+ * kl_advec_u_2i5 / kl_diff_smag entry point.  KL_ERR_INVALID if the
+ * configuration is not eligible. */
 int kl_launch_variant(const kl_grid_t *g, int32_t kernel, int32_t index,
                       void *const fields[6], double visc, void *stream);
 int kl_launch_variant_dt(const kl_grid_t *g, int32_t kernel, int32_t index,
@@ -233,8 +298,9 @@ int kl_wisdom_lookup(const char *wisdom_dir, int32_t kernel, int32_t dtype, cons
                      const char *arch, int32_t itot, int32_t jtot, int32_t ktot, char *variant,
                      size_t len, int32_t *level);
 
-/* Tune the kernels in kernel_mask (bit 0 advec_u, bit 1 diff_uvw, bit 2 the
- * fused step; bit 3: time diff_uvw right after the selected advec_u, as in a
+/* Tune the kernels in kernel_mask (KL_TUNE_* bits: advec_u, diff_uvw, the
+ * fused step, advec_u_2i5, diff_smag; KL_TUNE_PAIR: time each diffusion
+ * kernel right after the selected advection kernel of its scheme, as in a
  * time step, so that the cache state it starts from is realistic) for this
  * grid on the current device: every eligible configuration is checked for
  * bitwise-equal output against the default configuration, then timed (hip
@@ -243,7 +309,8 @@ int kl_wisdom_lookup(const char *wisdom_dir, int32_t kernel, int32_t dtype, cons
  * appended as a record (kernel, dtype, problem size, device, architecture,
  * configuration, time, provenance) to the kernel's wisdom file in
  * wisdom_dir (NULL = current wisdom directory), and the selection cache is
- * cleared.  fields = {u, v, w, ut, vt, wt}: u, v, w must be ghost-filled;
+ * cleared.  fields = {u, v, w, ut, vt, wt} (plus evisc as a seventh entry
+ * when diff_smag is tuned): u, v, w (and evisc) must be ghost-filled;
  * ut, vt, wt are clobbered.  Synchronous (returns after the file is written).
  * If timings_out is not NULL it receives up to max_timings entries of
  * (configuration index, median ms) for kernel_mask's lowest kernel, or -1 ms

@@ -46,18 +46,21 @@ const std::vector<Variant> &variants(int kernel, int dtype)
 int check_grid(const kl_grid_t *g)
 {
     if (!g) return fail(KL_ERR_INVALID, "grid is NULL");
-    if (g->gc != 1) return fail(KL_ERR_INVALID, "ghost width gc=%d, must be 1", g->gc);
+    if (g->gc != 1 && g->gc != 3) return fail(KL_ERR_INVALID, "ghost width gc=%d, must be 1 or 3", g->gc);
     if (g->dtype != KL_F32 && g->dtype != KL_F64) return fail(KL_ERR_INVALID, "dtype %d", g->dtype);
     if (g->bc < KL_BC_ZWALL_ZEROGRAD || g->bc > KL_BC_ZPERIODIC) return fail(KL_ERR_INVALID, "bc %d", g->bc);
     if (g->itot < 1 || g->jtot < 1 || g->ktot < 1)
         return fail(KL_ERR_INVALID, "interior sizes %d x %d x %d must be >= 1", g->itot, g->jtot, g->ktot);
     if (g->bc != KL_BC_ZPERIODIC && g->ktot < 2)
         return fail(KL_ERR_INVALID, "z walls need ktot >= 2 (got %d)", g->ktot);
-    if (g->off < 0) return fail(KL_ERR_INVALID, "off %lld < 0", (long long)g->off);
-    if (g->jstride < (int64_t)g->itot + 2)
-        return fail(KL_ERR_INVALID, "jstride %lld < itot+2", (long long)g->jstride);
-    if (g->kstride < g->jstride * ((int64_t)g->jtot + 2))
-        return fail(KL_ERR_INVALID, "kstride %lld < jstride*(jtot+2)", (long long)g->kstride);
+    const int64_t gc = g->gc;
+    if (g->jstride < (int64_t)g->itot + 2 * gc)
+        return fail(KL_ERR_INVALID, "jstride %lld < itot+2*gc", (long long)g->jstride);
+    if (g->kstride < g->jstride * ((int64_t)g->jtot + 2 * gc))
+        return fail(KL_ERR_INVALID, "kstride %lld < jstride*(jtot+2*gc)", (long long)g->kstride);
+    if (g->off < (gc - 1) * (g->jstride + 1))
+        return fail(KL_ERR_INVALID, "off %lld < (gc-1)*(jstride+1): ghost cells before the buffer",
+                    (long long)g->off);
     if (!g->dzi || !g->dzhi) return fail(KL_ERR_INVALID, "dzi/dzhi is NULL");
     return KL_OK;
 }
@@ -70,6 +73,7 @@ HostArgs make_args(const kl_grid_t *g)
     a.jtot = g->jtot;
     a.ktot = g->ktot;
     a.kw0 = g->bc == KL_BC_ZPERIODIC ? 1 : 2;
+    a.gc = g->gc;
     a.dtype = g->dtype;
     a.bc = g->bc;
     a.off = g->off;
@@ -160,15 +164,16 @@ int select_variant(const kl_grid_t *g, int kernel)
     return index;
 }
 
-int run_variant(const kl_grid_t *g, int kernel, int index, void *const fields[6], double visc, hipStream_t s,
+int run_variant(const kl_grid_t *g, int kernel, int index, void *const *fields, double visc, hipStream_t s,
                 double dt)
 {
     const auto &vs = variants(kernel, g->dtype);
     if (index < 0 || index >= (int)vs.size()) return fail(KL_ERR_NOTFOUND, "variant index %d", index);
+    if (kernel == KL_KERNEL_ADVEC_U_2I5 && g->gc < 3)
+        return fail(KL_ERR_INVALID, "advec_u_2i5 needs gc = 3 ghost cells in x and y (grid has %d)", g->gc);
     const Variant &v = vs[index];
-    const void *ptrs[6] = {fields[0], fields[1], fields[2], fields[3], fields[4], fields[5]};
-    const int nptr = kernel == KL_KERNEL_ADVEC_U ? 4 : 6;
-    if (!variant_eligible(v, g, ptrs, nptr))
+    const int nptr = kernel_nptr(kernel);
+    if (!variant_eligible(v, g, (const void *const *)fields, nptr))
         return fail(KL_ERR_INVALID, "configuration %s not eligible for this grid/alignment", v.name);
     HostArgs a = make_args(g);
     a.dt = dt;
@@ -178,6 +183,7 @@ int run_variant(const kl_grid_t *g, int kernel, int index, void *const fields[6]
     a.ut = fields[3];
     a.vt = fields[4];
     a.wt = fields[5];
+    a.evisc = nptr > 6 ? fields[6] : nullptr;
     a.visc = visc;
     const hipError_t e = v.launch(a, s);
     if (e != hipSuccess) return hip_fail(e, v.name);
@@ -199,22 +205,20 @@ int check_ptrs(const void *const *p, int n)
 
 // Launch `kernel` with the selected configuration, falling back to the
 // default when the selected one does not fit this call's alignment.
-int launch_selected(const kl_grid_t *g, int kernel, void *const fields[6], double visc, hipStream_t s,
+int launch_selected(const kl_grid_t *g, int kernel, void *const *fields, double visc, hipStream_t s,
                     double dt = 0.0)
 {
     int index = select_variant(g, kernel);
     const auto &vs = variants(kernel, g->dtype);
-    const void *ptrs[6] = {fields[0], fields[1], fields[2], fields[3], fields[4], fields[5]};
-    if (!variant_eligible(vs[index], g, ptrs, kernel == KL_KERNEL_ADVEC_U ? 4 : 6)) index = 0;
-    if (!variant_eligible(vs[index], g, ptrs, kernel == KL_KERNEL_ADVEC_U ? 4 : 6))
+    const void *const *ptrs = (const void *const *)fields;
+    const int nptr = kernel_nptr(kernel);
+    if (!variant_eligible(vs[index], g, ptrs, nptr)) index = 0;
+    if (!variant_eligible(vs[index], g, ptrs, nptr))
         return fail(KL_ERR_INVALID, "no configuration of %s fits this grid/alignment", kernel_name(kernel));
     return run_variant(g, kernel, index, fields, visc, s, dt);
 }
 
-bool kernel_ok(int32_t kernel)
-{
-    return kernel == KL_KERNEL_ADVEC_U || kernel == KL_KERNEL_DIFF_UVW || kernel == KL_KERNEL_STEP;
-}
+bool kernel_ok(int32_t kernel) { return kernel >= 0 && kernel < KL_NUM_KERNELS; }
 
 }  // namespace
 
@@ -224,22 +228,29 @@ const char *kl_version(void) { return KL_VERSION_STRING; }
 
 const char *kl_last_error(void) { return g_last_error.c_str(); }
 
-int kl_layout(int32_t itot, int32_t jtot, int32_t ktot, int32_t dtype, int64_t *off, int64_t *jstride,
-              int64_t *kstride, int64_t *alloc_elems)
+int kl_layout_gc(int32_t itot, int32_t jtot, int32_t ktot, int32_t dtype, int32_t gc, int64_t *off,
+                 int64_t *jstride, int64_t *kstride, int64_t *alloc_elems)
 {
     clear_error();
     if (itot < 1 || jtot < 1 || ktot < 1) return fail(KL_ERR_INVALID, "sizes must be >= 1");
     if (dtype != KL_F32 && dtype != KL_F64) return fail(KL_ERR_INVALID, "dtype %d", dtype);
+    if (gc != 1 && gc != 3) return fail(KL_ERR_INVALID, "gc %d must be 1 or 3", gc);
     if (!off || !jstride || !kstride || !alloc_elems) return fail(KL_ERR_INVALID, "NULL output");
     const int64_t line = 128 / (dtype == KL_F32 ? 4 : 8);  // elements per 128-byte line
-    const int64_t o = line - 1;                            // idx(1, 0, 0) on a line boundary
-    const int64_t js = ((int64_t)itot + 2 + line - 1) / line * line;
-    const int64_t ks = js * ((int64_t)jtot + 2);
+    const int64_t js = ((int64_t)itot + 2 * gc + line - 1) / line * line;
+    const int64_t o = (gc - 1) * js + line - 1;  // idx(1, j, k) on a line boundary
+    const int64_t ks = js * ((int64_t)jtot + 2 * gc);
     *off = o;
     *jstride = js;
     *kstride = ks;
     *alloc_elems = o + ks * ((int64_t)ktot + 2) + 2 * line;
     return KL_OK;
+}
+
+int kl_layout(int32_t itot, int32_t jtot, int32_t ktot, int32_t dtype, int64_t *off, int64_t *jstride,
+              int64_t *kstride, int64_t *alloc_elems)
+{
+    return kl_layout_gc(itot, jtot, ktot, dtype, 1, off, jstride, kstride, alloc_elems);
 }
 
 int kl_fill_ghosts(const kl_grid_t *g, void *u, void *v, void *w, void *stream)
@@ -251,6 +262,40 @@ int kl_fill_ghosts(const kl_grid_t *g, void *u, void *v, void *w, void *stream)
     if ((rc = check_ptrs(p, 3))) return rc;
     const hipError_t e = launch_fill_ghosts(make_args(g), u, v, w, (hipStream_t)stream);
     return e == hipSuccess ? KL_OK : hip_fail(e, "fill_ghosts");
+}
+
+int kl_fill_scalar(const kl_grid_t *g, void *f, void *stream)
+{
+    clear_error();
+    int rc = check_grid(g);
+    if (rc) return rc;
+    if (!f) return fail(KL_ERR_INVALID, "field pointer is NULL");
+    const hipError_t e = launch_fill_scalar(make_args(g), f, (hipStream_t)stream);
+    return e == hipSuccess ? KL_OK : hip_fail(e, "fill_scalar");
+}
+
+int kl_advec_u_2i5(const kl_grid_t *g, void *ut, const void *u, const void *v, const void *w, void *stream)
+{
+    clear_error();
+    int rc = check_grid(g);
+    if (rc) return rc;
+    if (g->gc < 3) return fail(KL_ERR_INVALID, "advec_u_2i5 needs gc = 3 ghost cells in x and y (grid has %d)", g->gc);
+    const void *p[4] = {u, v, w, ut};
+    if ((rc = check_ptrs(p, 4))) return rc;
+    void *f[6] = {(void *)u, (void *)v, (void *)w, ut, nullptr, nullptr};
+    return launch_selected(g, KL_KERNEL_ADVEC_U_2I5, f, 0.0, (hipStream_t)stream);
+}
+
+int kl_diff_smag(const kl_grid_t *g, void *ut, void *vt, void *wt, const void *u, const void *v, const void *w,
+                 const void *evisc, void *stream)
+{
+    clear_error();
+    int rc = check_grid(g);
+    if (rc) return rc;
+    const void *p[7] = {u, v, w, ut, vt, wt, evisc};
+    if ((rc = check_ptrs(p, 7))) return rc;
+    void *f[7] = {(void *)u, (void *)v, (void *)w, ut, vt, wt, (void *)evisc};
+    return launch_selected(g, KL_KERNEL_DIFF_SMAG, f, 0.0, (hipStream_t)stream);
 }
 
 int kl_advec_u(const kl_grid_t *g, void *ut, const void *u, const void *v, const void *w, void *stream)
@@ -288,7 +333,9 @@ int kl_euler(const kl_grid_t *g, double dt, void *u, void *v, void *w, const voi
     a.ut = (void *)ut;
     a.vt = (void *)vt;
     a.wt = (void *)wt;
-    const hipError_t e = launch_euler(a, dt, u, v, w, (hipStream_t)stream);
+    hipError_t e = launch_euler(a, dt, u, v, w, (hipStream_t)stream);
+    // the fused refill covers one ghost layer; wider halos are refilled whole
+    if (e == hipSuccess && g->gc != 1) e = launch_fill_ghosts(a, u, v, w, (hipStream_t)stream);
     return e == hipSuccess ? KL_OK : hip_fail(e, "euler");
 }
 
@@ -312,7 +359,8 @@ int kl_step(const kl_grid_t *g, double visc, double dt, void *u, void *v, void *
     a.ut = ut;
     a.vt = vt;
     a.wt = wt;
-    const hipError_t e = launch_euler(a, dt, u, v, w, s);
+    hipError_t e = launch_euler(a, dt, u, v, w, s);
+    if (e == hipSuccess && g->gc != 1) e = launch_fill_ghosts(a, u, v, w, s);
     return e == hipSuccess ? KL_OK : hip_fail(e, "euler");
 }
 
@@ -328,7 +376,12 @@ int kl_step_fused(const kl_grid_t *g, double visc, double dt, const void *u, con
         for (int b = 3; b < 6; ++b)
             if (p[a] == p[b]) return fail(KL_ERR_INVALID, "fused step: input %d and output %d overlap", a, b - 3);
     void *f[6] = {(void *)u, (void *)v, (void *)w, u_out, v_out, w_out};
-    return launch_selected(g, KL_KERNEL_STEP, f, visc, (hipStream_t)stream, dt);
+    if ((rc = launch_selected(g, KL_KERNEL_STEP, f, visc, (hipStream_t)stream, dt))) return rc;
+    if (g->gc != 1) {  // the kernel writes one ghost layer; refill wider halos whole
+        const hipError_t e = launch_fill_ghosts(make_args(g), u_out, v_out, w_out, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, "fill_ghosts");
+    }
+    return KL_OK;
 }
 
 int kl_reduce_fp64(const kl_grid_t *g, int32_t what, const void *f0, const void *f1, const void *f2, double *out,
@@ -398,7 +451,7 @@ int kl_variant_eligible(const kl_grid_t *g, int32_t kernel, int32_t index, const
     const int n = kl_num_variants(kernel, g->dtype);
     if (n < 0) return n;
     if (index < 0 || index >= n) return fail(KL_ERR_NOTFOUND, "variant index %d", index);
-    return variant_eligible(variants(kernel, g->dtype)[index], g, fields, fields ? (kernel ? 6 : 4) : 0) ? 1 : 0;
+    return variant_eligible(variants(kernel, g->dtype)[index], g, fields, fields ? kernel_nptr(kernel) : 0) ? 1 : 0;
 }
 
 int kl_launch_variant_dt(const kl_grid_t *g, int32_t kernel, int32_t index, void *const fields[6], double visc,
@@ -409,7 +462,7 @@ int kl_launch_variant_dt(const kl_grid_t *g, int32_t kernel, int32_t index, void
     if (rc) return rc;
     if (!kernel_ok(kernel)) return fail(KL_ERR_INVALID, "kernel %d", kernel);
     if (!fields) return fail(KL_ERR_INVALID, "fields is NULL");
-    if ((rc = check_ptrs((const void *const *)fields, kernel == KL_KERNEL_ADVEC_U ? 4 : 6))) return rc;
+    if ((rc = check_ptrs((const void *const *)fields, kernel_nptr(kernel)))) return rc;
     return run_variant(g, kernel, index, fields, visc, (hipStream_t)stream, dt);
 }
 

@@ -12,17 +12,25 @@ namespace {
 struct Dims {
     int itot, jtot, ktot, bc;
     int64_t off, js, ks;
+    int gc;  // ghost cells per side in x and y
 };
 
-inline Dims dims_of(const HostArgs &a) { return Dims{a.itot, a.jtot, a.ktot, a.bc, a.off, a.js, a.ks}; }
+inline Dims dims_of(const HostArgs &a) { return Dims{a.itot, a.jtot, a.ktot, a.bc, a.off, a.js, a.ks, a.gc}; }
 
 __device__ __forceinline__ int64_t at(const Dims &d, int i, int j, int k)
 {
     return d.off + i + (int64_t)j * d.js + (int64_t)k * d.ks;
 }
 
-__device__ __forceinline__ int wrap_i(const Dims &d, int i) { return i == 0 ? d.itot : (i == d.itot + 1 ? 1 : i); }
-__device__ __forceinline__ int wrap_j(const Dims &d, int j) { return j == 0 ? d.jtot : (j == d.jtot + 1 ? 1 : j); }
+// Interior index of which periodic index p (p >= 1 - gc) is the image.
+__device__ __forceinline__ int wrap_n(int p, int n)
+{
+    int q = (p - 1) % n;
+    if (q < 0) q += n;
+    return q + 1;
+}
+__device__ __forceinline__ int wrap_i(const Dims &d, int i) { return wrap_n(i, d.itot); }
+__device__ __forceinline__ int wrap_j(const Dims &d, int j) { return wrap_n(j, d.jtot); }
 
 // Source level and factor of level k of field f (0 u, 1 v, 2 w) under the
 // boundary rule; factor 0 means the cell is set to zero.
@@ -45,36 +53,40 @@ __device__ __forceinline__ int src_k(const Dims &d, int f, int k, int &sign)
     return k;
 }
 
-// One thread per ghost cell (region R0: planes k = 0 and ktot+1; R1: rows
-// j = 0, jtot+1 of levels 1..ktot; R2: columns i = 0, itot+1 of interior
-// rows; R3: the interior of plane k = 1, for w in wall modes).  Every
-// source cell is an interior cell that no thread writes, so the cells can
-// be filled in any order.
+// One thread per ghost cell (region R0: the whole planes k = 0 and ktot+1;
+// R1: the 2 gc ghost rows of levels 1..ktot; R2: the 2 gc ghost columns of
+// the interior rows of levels 1..ktot; R3: the interior of plane k = 1, for
+// w in wall modes).  Every source cell is an interior cell that no thread
+// writes, so the cells can be filled in any order.  kind[f] is the z rule
+// of field f (0 and 1: the u/v rule, 2: the w rule); a NULL field is skipped.
 template <typename T>
-__global__ __launch_bounds__(256) void fill_ghosts_kernel(Dims d, T *u, T *v, T *w, int64_t n0,
-                                                         int64_t n1, int64_t n2, int64_t n3)
+__global__ __launch_bounds__(256) void fill_ghosts_kernel(Dims d, T *u, T *v, T *w, int k0, int k1, int k2,
+                                                         int64_t n0, int64_t n1, int64_t n2, int64_t n3)
 {
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int ic = d.itot + 2, jc = d.jtot + 2;
+    const int gc = d.gc;
+    const int ic = d.itot + 2 * gc, jc = d.jtot + 2 * gc;
     int i, j, k;
     bool w_only = false;
     if (t < n0) {
         const int64_t p = t % ((int64_t)ic * jc);
         k = t < (int64_t)ic * jc ? 0 : d.ktot + 1;
-        j = (int)(p / ic);
-        i = (int)(p % ic);
+        j = (int)(p / ic) + 1 - gc;
+        i = (int)(p % ic) + 1 - gc;
     } else if (t < n0 + n1) {
         const int64_t q = t - n0;
-        const int64_t p = q % ((int64_t)ic * d.ktot);
-        j = q < (int64_t)ic * d.ktot ? 0 : d.jtot + 1;
-        k = 1 + (int)(p / ic);
-        i = (int)(p % ic);
+        const int64_t r = q / ic;  // ghost row index over (level, row)
+        i = (int)(q % ic) + 1 - gc;
+        k = 1 + (int)(r / (2 * gc));
+        const int jr = (int)(r % (2 * gc));
+        j = jr < gc ? 1 - gc + jr : d.jtot + 1 + (jr - gc);
     } else if (t < n0 + n1 + n2) {
         const int64_t q = t - n0 - n1;
-        const int64_t p = q % ((int64_t)d.jtot * d.ktot);
-        i = q < (int64_t)d.jtot * d.ktot ? 0 : d.itot + 1;
-        k = 1 + (int)(p / d.jtot);
-        j = 1 + (int)(p % d.jtot);
+        const int c = (int)(q % (2 * gc));
+        const int64_t rest = q / (2 * gc);
+        j = 1 + (int)(rest % d.jtot);
+        k = 1 + (int)(rest / d.jtot);
+        i = c < gc ? 1 - gc + c : d.itot + 1 + (c - gc);
     } else if (t < n0 + n1 + n2 + n3) {
         const int64_t q = t - n0 - n1 - n2;
         k = 1;
@@ -87,12 +99,13 @@ __global__ __launch_bounds__(256) void fill_ghosts_kernel(Dims d, T *u, T *v, T 
     const int si = wrap_i(d, i), sj = wrap_j(d, j);
     const int64_t dst = at(d, i, j, k);
     T *f3[3] = {u, v, w};
+    const int kind[3] = {k0, k1, k2};
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
-        if (w_only && f < 2) continue;
-        int sign;
-        const int sk = src_k(d, f, k, sign);
         T *p = f3[f];
+        if (!p || (w_only && kind[f] != 2)) continue;
+        int sign;
+        const int sk = src_k(d, kind[f], k, sign);
         p[dst] = sign == 0 ? T(0) : (sign < 0 ? -p[at(d, si, sj, sk)] : p[at(d, si, sj, sk)]);
     }
 }
@@ -379,20 +392,34 @@ inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b);
 
 size_t reduce_scratch_bytes() { return (size_t)RB * RQ * sizeof(double); }
 
-hipError_t launch_fill_ghosts(const HostArgs &a, void *u, void *v, void *w, hipStream_t s)
+namespace {
+hipError_t fill_launch(const HostArgs &a, void *u, void *v, void *w, int k0, int k1, int k2, bool w_faces,
+                       hipStream_t s)
 {
     const Dims d = dims_of(a);
-    const int64_t ic = a.itot + 2, jc = a.jtot + 2;
-    const int64_t n0 = 2 * ic * jc, n1 = 2 * ic * a.ktot, n2 = 2 * (int64_t)a.jtot * a.ktot;
-    const int64_t n3 = a.bc == KL_BC_ZPERIODIC ? 0 : (int64_t)a.itot * a.jtot;
+    const int64_t gc = a.gc;
+    const int64_t ic = a.itot + 2 * gc, jc = a.jtot + 2 * gc;
+    const int64_t n0 = 2 * ic * jc, n1 = 2 * gc * ic * a.ktot, n2 = 2 * gc * (int64_t)a.jtot * a.ktot;
+    const int64_t n3 = (w_faces && a.bc != KL_BC_ZPERIODIC) ? (int64_t)a.itot * a.jtot : 0;
     const unsigned nb = cdiv(n0 + n1 + n2 + n3, 256);
     if (a.dtype == KL_F32)
         hipLaunchKernelGGL(fill_ghosts_kernel<float>, dim3(nb), dim3(256), 0, s, d, (float *)u, (float *)v,
-                           (float *)w, n0, n1, n2, n3);
+                           (float *)w, k0, k1, k2, n0, n1, n2, n3);
     else
         hipLaunchKernelGGL(fill_ghosts_kernel<double>, dim3(nb), dim3(256), 0, s, d, (double *)u,
-                           (double *)v, (double *)w, n0, n1, n2, n3);
+                           (double *)v, (double *)w, k0, k1, k2, n0, n1, n2, n3);
     return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_fill_ghosts(const HostArgs &a, void *u, void *v, void *w, hipStream_t s)
+{
+    return fill_launch(a, u, v, w, 0, 1, 2, true, s);
+}
+
+hipError_t launch_fill_scalar(const HostArgs &a, void *f, hipStream_t s)
+{
+    return fill_launch(a, f, nullptr, nullptr, 0, 0, 0, false, s);
 }
 
 hipError_t launch_euler(const HostArgs &a, double dt, void *u, void *v, void *w, hipStream_t s)

@@ -14,13 +14,25 @@ namespace kl {
 // dtype-agnostic launch arguments; launchers convert metrics to the field type.
 struct HostArgs {
     int itot, jtot, ktot, kw0, dtype, bc;
+    int gc;  // ghost cells per side in x and y
     int64_t off, js, ks;
     double dxi, dyi, visc;
     double dt;  // fused step only
     const void *dzi, *dzhi;
     void *ut, *vt, *wt;  // tendencies; for the fused step: the output fields
     const void *u, *v, *w;
+    const void *evisc;  // diff_smag only
 };
+
+// Number of leading entries of a fields[] array a kernel reads:
+// u, v, w, ut (advection); u, v, w, ut, vt, wt (diffusion, step); and evisc
+// as the seventh for diff_smag.
+inline int kernel_nptr(int kernel)
+{
+    return (kernel == KL_KERNEL_ADVEC_U || kernel == KL_KERNEL_ADVEC_U_2I5) ? 4
+           : (kernel == KL_KERNEL_DIFF_SMAG ? 7 : 6);
+}
+constexpr int KL_NUM_KERNELS = 5;
 
 typedef hipError_t (*LaunchFn)(const HostArgs &, hipStream_t);
 // Persistent batched launch: descriptor table (StencilArgs<T>[]), tile table
@@ -60,6 +72,7 @@ void *workspace(size_t bytes, hipStream_t s);
 
 // Auxiliary kernels (aux.hip).
 hipError_t launch_fill_ghosts(const HostArgs &a, void *u, void *v, void *w, hipStream_t s);
+hipError_t launch_fill_scalar(const HostArgs &a, void *f, hipStream_t s);
 hipError_t launch_euler(const HostArgs &a, double dt, void *u, void *v, void *w, hipStream_t s);
 hipError_t launch_zero_interior(const HostArgs &a, void *f, hipStream_t s);
 hipError_t launch_reduce(const HostArgs &a, int what, const void *f0, const void *f1,
@@ -93,7 +106,7 @@ std::string provenance_json(const DeviceIdent &dev);
 
 // Plan cache (api.cpp).
 int select_variant(const kl_grid_t *g, int kernel);
-int run_variant(const kl_grid_t *g, int kernel, int index, void *const fields[6], double visc,
+int run_variant(const kl_grid_t *g, int kernel, int index, void *const *fields, double visc,
                 hipStream_t s, double dt = 0.0);
 void clear_plans();
 

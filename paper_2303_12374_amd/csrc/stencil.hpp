@@ -5,7 +5,7 @@
 // served) produces bitwise-identical tendencies.
 //
 // Index layout: element (i, j, k) at off + i + j*js + k*ks, interior
-// [1, itot] x [1, jtot] x [1, ktot], one ghost cell per side.
+// [1, itot] x [1, jtot] x [1, ktot], at least one ghost cell per side.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -27,6 +27,7 @@ struct StencilArgs {
     T *ut, *vt, *wt;
     const T *u, *v, *w;
     int nbx, nby, nbz;       // tiles per axis (1-D grid unravelled x fastest)
+    const T *evisc;          // eddy viscosity at cell centers (diff_smag only)
 };
 
 // ---------------------------------------------------------------------------

@@ -1,0 +1,483 @@
+// LDS-staged z-marching configuration of advec_u_2i5.
+//
+// Workgroup = 64 x BY threads: wave r owns row j0 + r of a tile 64*VX wide
+// in x and BY rows in y, each lane VX consecutive points; the tile walks the
+// levels [k0, k0 + KB).  Per level k:
+//   * every wave writes its row of u (level k, from its register window) and
+//     of v into double-buffered LDS planes: u with three halo rows and
+//     columns on each side ((BY+6) x (TX+6)), v with one halo row above and
+//     one column to the left ((BY+1) x (TX+1)); the six u halo rows and the
+//     v halo row are loaded by the waves in turn, the halo columns by the
+//     edge lanes; one barrier per level;
+//   * x faces: each lane reads VX+6 values of its LDS row and evaluates the
+//     VX+1 faces around its points once (a face is shared by two points);
+//   * y faces: two per point, from the seven LDS rows of its column;
+//   * z faces: the u column lives in a seven-level register window (levels
+//     k-2 .. k+4); the lower face's flux is the upper face's flux of the
+//     level below, carried over; the advecting w of the left neighbour comes
+//     from the neighbouring lane by a shuffle.
+// Every global load is issued one level ahead.  The per-face and per-point
+// arithmetic is the shared one of stencil_les.hpp with the same operands, so
+// results equal the default configuration's bitwise.
+#pragma once
+
+#include "stencil_les.hpp"
+#include "stencil_zl.hpp"
+
+namespace kl {
+
+// Level l of a column at address p + l*ks into d (VX values), or zeros
+// outside [0, ktot+1].
+template <typename T, int VX>
+__device__ __forceinline__ void col_load(T (&d)[VX], const T *p, int64_t ks, int l, int ktot, bool on)
+{
+    if (on && l >= 0 && l <= ktot + 1) {
+        vload<T, VX>(d, p + (int64_t)l * ks);
+    } else {
+#pragma unroll
+        for (int n = 0; n < VX; ++n) d[n] = T(0);
+    }
+}
+
+template <typename T, int VX, int BY, int KB, int XCD, int NT, int WPE>
+__global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zl(StencilArgs<T> a)
+{
+    constexpr int TX = 64 * VX;
+    constexpr int SW = TX + 6;               // u row in LDS: columns i0w-3 .. i0w+TX+2
+    constexpr int VW = TX + 1;               // v row in LDS: columns i0w-1 .. i0w+TX-1
+    constexpr int NH = (6 + BY - 1) / BY;    // u halo rows per wave (upper bound)
+    __shared__ __align__(16) T su[2][BY + 6][SW];
+    __shared__ __align__(16) T sv[2][BY + 1][VW];
+
+    int tx, ty, tz;
+    tile_of<64, BY, XCD>(a.nbx, a.nby, a.nbz, tx, ty, tz);
+    const int lane = (int)threadIdx.x, r = (int)threadIdx.y;
+    const int i0w = 1 + tx * TX;
+    const int nlanes = min(64, (a.itot - i0w + 1) / VX);
+    const bool lane_on = lane < nlanes;
+    const int xo = lane * VX;
+    const bool edge_l = lane == 0, edge_r = lane == nlanes - 1;
+    const int j0 = 1 + ty * BY;
+    const int nv = min(BY, a.jtot - j0 + 1);
+    const bool own = r < nv;
+    const int k0 = 1 + tz * KB, k1 = min(k0 + KB, a.ktot + 1);
+    const int kt = a.ktot;
+    const int64_t js = a.js, ks = a.ks;
+    const T *u = a.u, *v = a.v, *w = a.w;
+    T *ut = a.ut;
+    const T dxi = a.dxi, dyi = a.dyi;
+
+    // level-0 addresses of this lane's points in the own row and the halo rows
+    const int64_t row0 = a.off + i0w + xo;
+    const int64_t c_own = row0 + (int64_t)(j0 + r) * js;
+    const int64_t e_own = a.off + i0w + (int64_t)(j0 + r) * js;           // (i0w, j0 + r, 0)
+    const int iend = i0w + nlanes * VX - 1;                               // last point of the tile
+    int hrho[NH];   // LDS rows of this wave's u halo rows, -1 if none
+    int64_t hc[NH], he[NH];
+#pragma unroll
+    for (int m = 0; m < NH; ++m) {
+        const int h = r + m * BY;
+        hrho[m] = h < 6 ? (h < 3 ? h : nv + h) : -1;
+        const int jg = j0 - 3 + (hrho[m] < 0 ? 3 : hrho[m]);
+        hc[m] = row0 + (int64_t)jg * js;
+        he[m] = a.off + i0w + (int64_t)jg * js;
+    }
+    const bool vhalo = r == BY - 1;                                       // loads v row j0 + nv
+    const int64_t c_vh = row0 + (int64_t)(j0 + nv) * js;
+    const int64_t e_vh = a.off + i0w + (int64_t)(j0 + nv) * js;
+
+    // registers: current (level k) and next (level k+1) copies of what the
+    // LDS planes receive, the w row at k+1 (next: k+2), ut at k (next: k+1)
+    T S[7][VX];                              // u(k-2) .. u(k+4) of the own column
+    T HU[2][NH][VX], HUL[2][NH][3], HUR[2][NH][3];
+    T OUL[2][3], OUR[2][3];                  // x halo of the own u row
+    T VO[2][VX], VOL[2];                     // own v row and its left halo cell
+    T VH[2][VX], VHL[2];                     // v halo row and its left halo cell
+    T WR[2][VX], WL[2];                      // w at k+1 (and k+2), left neighbour cell (lane 0)
+    T UT[2][VX];
+
+    auto load_level = [&](int q, int k) {    // everything level k needs, into slot q
+#pragma unroll
+        for (int m = 0; m < NH; ++m) {
+            const bool on = hrho[m] >= 0;
+            if (on && lane_on) vload<T, VX>(HU[q][m], u + hc[m] + (int64_t)k * ks);
+            if (on && edge_l) {
+#pragma unroll
+                for (int e = 0; e < 3; ++e) HUL[q][m][e] = u[he[m] + (int64_t)k * ks - 3 + e];
+            }
+            if (on && edge_r) {
+#pragma unroll
+                for (int e = 0; e < 3; ++e) HUR[q][m][e] = u[he[m] + (iend - i0w) + (int64_t)k * ks + 1 + e];
+            }
+        }
+        if (own) {
+            if (edge_l) {
+#pragma unroll
+                for (int e = 0; e < 3; ++e) OUL[q][e] = u[e_own + (int64_t)k * ks - 3 + e];
+                VOL[q] = v[e_own + (int64_t)k * ks - 1];
+            }
+            if (edge_r) {
+#pragma unroll
+                for (int e = 0; e < 3; ++e) OUR[q][e] = u[e_own + (iend - i0w) + (int64_t)k * ks + 1 + e];
+            }
+            if (lane_on) {
+                vload<T, VX>(VO[q], v + c_own + (int64_t)k * ks);
+                vload<T, VX>(WR[q], w + c_own + (int64_t)(k + 1) * ks);
+                tload<NT, T, VX>(UT[q], ut + c_own + (int64_t)k * ks);
+            }
+            if (edge_l) WL[q] = w[e_own + (int64_t)(k + 1) * ks - 1];
+        }
+        if (vhalo) {
+            if (lane_on) vload<T, VX>(VH[q], v + c_vh + (int64_t)k * ks);
+            if (edge_l) VHL[q] = v[e_vh + (int64_t)k * ks - 1];
+        }
+    };
+
+    // prologue: the u window, the flux through face k0, level k0's data
+#pragma unroll
+    for (int m = 0; m < 7; ++m) col_load<T, VX>(S[m], u + c_own, ks, k0 - 2 + m, kt, own && lane_on);
+    T FB[VX];
+    {
+        T ub3[VX], w0[VX];
+        col_load<T, VX>(ub3, u + c_own, ks, k0 - 3, kt, own && lane_on);
+        col_load<T, VX>(w0, w + c_own, ks, k0, kt, own && lane_on);
+        T wl0 = (own && edge_l) ? w[e_own + (int64_t)k0 * ks - 1] : T(0);
+        const T sh = shfl_up1(w0[VX - 1]);
+        if (!edge_l) wl0 = sh;
+#pragma unroll
+        for (int n = 0; n < VX; ++n) {
+            const T wm = n == 0 ? wl0 : w0[n - 1];
+            FB[n] = flux_z_2i5(mid(wm, w0[n]), ub3[n], S[0][n], S[1][n], S[2][n], S[3][n], S[4][n], k0, kt);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+#pragma unroll
+        for (int n = 0; n < VX; ++n) VO[q][n] = VH[q][n] = WR[q][n] = UT[q][n] = T(0);
+#pragma unroll
+        for (int m = 0; m < NH; ++m)
+#pragma unroll
+            for (int n = 0; n < VX; ++n) HU[q][m][n] = T(0);
+    }
+    load_level(0, k0);
+
+    for (int k = k0; k < k1; ++k) {
+        const int p = k & 1;
+        // 1. level k into LDS plane p
+        if (own && lane_on) {
+#pragma unroll
+            for (int n = 0; n < VX; ++n) {
+                su[p][r + 3][3 + xo + n] = S[2][n];
+                sv[p][r][1 + xo + n] = VO[0][n];
+            }
+        }
+        if (own && edge_l) {
+#pragma unroll
+            for (int e = 0; e < 3; ++e) su[p][r + 3][e] = OUL[0][e];
+            sv[p][r][0] = VOL[0];
+        }
+        if (own && edge_r) {
+#pragma unroll
+            for (int e = 0; e < 3; ++e) su[p][r + 3][3 + nlanes * VX + e] = OUR[0][e];
+        }
+#pragma unroll
+        for (int m = 0; m < NH; ++m) {
+            const int rho = hrho[m];
+            if (rho >= 0) {
+                if (lane_on) {
+#pragma unroll
+                    for (int n = 0; n < VX; ++n) su[p][rho][3 + xo + n] = HU[0][m][n];
+                }
+                if (edge_l) {
+#pragma unroll
+                    for (int e = 0; e < 3; ++e) su[p][rho][e] = HUL[0][m][e];
+                }
+                if (edge_r) {
+#pragma unroll
+                    for (int e = 0; e < 3; ++e) su[p][rho][3 + nlanes * VX + e] = HUR[0][m][e];
+                }
+            }
+        }
+        if (vhalo) {
+            if (lane_on) {
+#pragma unroll
+                for (int n = 0; n < VX; ++n) sv[p][nv][1 + xo + n] = VH[0][n];
+            }
+            if (edge_l) sv[p][nv][0] = VHL[0];
+        }
+        // 2. prefetch level k+1 and the u window's next level
+        if (k + 1 < k1) load_level(1, k + 1);
+        T unext[VX];
+        col_load<T, VX>(unext, u + c_own, ks, k + 5, kt, own && lane_on && k + 1 < k1);
+        __syncthreads();
+
+        // 3. compute level k
+        const T sh = shfl_up1(WR[0][VX - 1]);
+        const T wl = edge_l ? WL[0] : sh;
+        if (own && lane_on) {
+            T uxr[VX + 6];
+#pragma unroll
+            for (int m = 0; m < VX + 6; ++m) uxr[m] = su[p][r + 3][xo + m];
+            T FX[VX + 1];
+#pragma unroll
+            for (int f = 0; f <= VX; ++f)
+                FX[f] = flux5(mid(uxr[f + 2], uxr[f + 3]), uxr[f], uxr[f + 1], uxr[f + 2], uxr[f + 3],
+                              uxr[f + 4], uxr[f + 5]);
+            const T dzik = a.dzi[k];
+            T res[VX];
+#pragma unroll
+            for (int n = 0; n < VX; ++n) {
+                const int x = 3 + xo + n;
+                T col[7];
+#pragma unroll
+                for (int m = 0; m < 7; ++m) col[m] = su[p][r + m][x];
+                const T vn = mid(sv[p][r + 1][xo + n], sv[p][r + 1][xo + n + 1]);
+                const T vs = mid(sv[p][r][xo + n], sv[p][r][xo + n + 1]);
+                const T fn = flux5(vn, col[1], col[2], col[3], col[4], col[5], col[6]);
+                const T fs = flux5(vs, col[0], col[1], col[2], col[3], col[4], col[5]);
+                const T wm = n == 0 ? wl : WR[0][n - 1];
+                const T ft = flux_z_2i5(mid(wm, WR[0][n]), S[0][n], S[1][n], S[2][n], S[3][n], S[4][n], S[5][n],
+                                        k + 1, kt);
+                res[n] = UT[0][n] + advec_2i5_combine(FX[n + 1], FX[n], fn, fs, ft, FB[n], dxi, dyi, dzik);
+                FB[n] = ft;
+            }
+            tstore<NT, T, VX>(ut + c_own + (int64_t)k * ks, res);
+        }
+
+        // 4. advance the window and the register slots
+#pragma unroll
+        for (int m = 0; m < 6; ++m)
+#pragma unroll
+            for (int n = 0; n < VX; ++n) S[m][n] = S[m + 1][n];
+#pragma unroll
+        for (int n = 0; n < VX; ++n) {
+            S[6][n] = unext[n];
+            VO[0][n] = VO[1][n];
+            VH[0][n] = VH[1][n];
+            WR[0][n] = WR[1][n];
+            UT[0][n] = UT[1][n];
+        }
+        VOL[0] = VOL[1];
+        VHL[0] = VHL[1];
+        WL[0] = WL[1];
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            OUL[0][e] = OUL[1][e];
+            OUR[0][e] = OUR[1][e];
+        }
+#pragma unroll
+        for (int m = 0; m < NH; ++m) {
+#pragma unroll
+            for (int n = 0; n < VX; ++n) HU[0][m][n] = HU[1][m][n];
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+                HUL[0][m][e] = HUL[1][m][e];
+                HUR[0][m][e] = HUR[1][m][e];
+            }
+        }
+    }
+}
+
+}  // namespace kl
+
+namespace kl {
+
+// ---------------------------------------------------------------------------
+// LDS-staged z-marching configuration of diff_smag.
+//
+// Workgroup = 64 x BY threads (wave r owns row j0 + r, each lane VX points),
+// tile 64*VX x BY, levels [k0, k0 + KB).  The stencil of a point reaches one
+// cell in every direction, in all four inputs (u, v, w, evisc), on levels
+// k-1, k and k+1.  Each input lives in LDS as a ring of four planes of
+// (BY+2) x (TX+2) cells (one halo cell on each side); at level k every
+// wave writes level k+1 of its own row (and its share of the halo rows,
+// the edge lanes the halo columns), while levels k-1 .. k+1 are read.  A
+// plane is rewritten only four levels later, after every wave has passed two
+// barriers since its last reader, so one barrier per level suffices.
+// Global loads of level k+2 are issued one level ahead.  Every point calls
+// the shared per-component functions with the default configuration's
+// operands, so results are bitwise identical.
+// ---------------------------------------------------------------------------
+
+template <typename T, int VX, int BY, int KB, int XCD, int NT, int WPE>
+__global__ __launch_bounds__(64 * BY, WPE) void diff_smag_zl(StencilArgs<T> a)
+{
+    constexpr int TX = 64 * VX;
+    constexpr int PW = TX + 2;              // plane row: columns i0w-1 .. i0w+TX
+    constexpr int PH = BY + 2;              // plane rows: j0-1 .. j0+BY
+    constexpr int NH = (8 + BY - 1) / BY;   // halo rows per wave (8 = 2 rows x 4 fields)
+    __shared__ __align__(16) T pl[4][4][PH][PW];  // [field][level & 3][row][column]
+
+    int tx, ty, tz;
+    tile_of<64, BY, XCD>(a.nbx, a.nby, a.nbz, tx, ty, tz);
+    const int lane = (int)threadIdx.x, r = (int)threadIdx.y;
+    const int i0w = 1 + tx * TX;
+    const int nlanes = min(64, (a.itot - i0w + 1) / VX);
+    const bool lane_on = lane < nlanes;
+    const int xo = lane * VX;
+    const bool edge_l = lane == 0, edge_r = lane == nlanes - 1;
+    const int j0 = 1 + ty * BY;
+    const int nv = min(BY, a.jtot - j0 + 1);
+    const bool own = r < nv;
+    const int k0 = 1 + tz * KB, k1 = min(k0 + KB, a.ktot + 1);
+    const int64_t js = a.js, ks = a.ks;
+    const T *F[4] = {a.u, a.v, a.w, a.evisc};
+    const int xr = 1 + nlanes * VX;         // LDS column of the right halo cell
+
+    // rows this wave stages: its own (LDS row r+1) and halo rows h = r, r+BY,
+    // ... of the 8 (field h/2; LDS row 0 for even h, nv+1 for odd h)
+    const int64_t c_own = a.off + i0w + xo + (int64_t)(j0 + r) * js;
+    const int64_t e_own = a.off + i0w + (int64_t)(j0 + r) * js;
+    int hf[NH], hrow[NH];
+    int64_t hc[NH], he[NH];
+#pragma unroll
+    for (int m = 0; m < NH; ++m) {
+        const int h = r + m * BY;
+        hf[m] = h < 8 ? h >> 1 : -1;
+        hrow[m] = (h & 1) ? nv + 1 : 0;
+        const int jg = j0 - 1 + hrow[m];
+        hc[m] = a.off + i0w + xo + (int64_t)jg * js;
+        he[m] = a.off + i0w + (int64_t)jg * js;
+    }
+
+    T O[2][4][VX], OL[2][4], OR_[2][4];     // own row of the 4 inputs at one level, halo columns
+    T H[2][NH][VX], HL[2][NH], HR[2][NH];   // halo rows
+    T TT[2][3][VX];                          // ut, vt, wt at level k (next: k+1)
+
+    auto load_plane = [&](int q, int l) {    // level l of everything staged, into slot q
+        if (own) {
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                if (lane_on) vload<T, VX>(O[q][f], F[f] + c_own + (int64_t)l * ks);
+                if (edge_l) OL[q][f] = F[f][e_own + (int64_t)l * ks - 1];
+                if (edge_r) OR_[q][f] = F[f][e_own + (int64_t)l * ks + nlanes * VX];
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < NH; ++m) {
+            if (hf[m] < 0) continue;
+            const T *p = F[hf[m]];
+            if (lane_on) vload<T, VX>(H[q][m], p + hc[m] + (int64_t)l * ks);
+            if (edge_l) HL[q][m] = p[he[m] + (int64_t)l * ks - 1];
+            if (edge_r) HR[q][m] = p[he[m] + (int64_t)l * ks + nlanes * VX];
+        }
+    };
+    auto store_plane = [&](int q, int l) {   // slot q into the LDS planes of level l
+        const int b = l & 3;
+        if (own) {
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                if (lane_on) {
+#pragma unroll
+                    for (int n = 0; n < VX; ++n) pl[f][b][r + 1][1 + xo + n] = O[q][f][n];
+                }
+                if (edge_l) pl[f][b][r + 1][0] = OL[q][f];
+                if (edge_r) pl[f][b][r + 1][xr] = OR_[q][f];
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < NH; ++m) {
+            if (hf[m] < 0) continue;
+            if (lane_on) {
+#pragma unroll
+                for (int n = 0; n < VX; ++n) pl[hf[m]][b][hrow[m]][1 + xo + n] = H[q][m][n];
+            }
+            if (edge_l) pl[hf[m]][b][hrow[m]][0] = HL[q][m];
+            if (edge_r) pl[hf[m]][b][hrow[m]][xr] = HR[q][m];
+        }
+    };
+    auto load_tend = [&](int q, int k) {
+        if (own && lane_on) {
+#pragma unroll
+            for (int f = 0; f < 3; ++f)
+                if (f < 2 || k >= a.kw0) tload<NT, T, VX>(TT[q][f], (f == 0 ? a.ut : (f == 1 ? a.vt : a.wt)) + c_own + (int64_t)k * ks);
+        }
+    };
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+            for (int n = 0; n < VX; ++n) TT[q][f][n] = T(0);
+
+    // prologue: planes k0-1 and k0 into LDS, level k0+1 and tendencies of k0 in flight
+    load_plane(0, k0 - 1);
+    store_plane(0, k0 - 1);
+    load_plane(0, k0);
+    store_plane(0, k0);
+    load_plane(0, k0 + 1);
+    load_tend(0, k0);
+
+    const T dxi = a.dxi, dyi = a.dyi;
+    for (int k = k0; k < k1; ++k) {
+        // level k+1 into the ring; prefetch level k+2 and the next tendencies
+        store_plane(0, k + 1);
+        if (k + 1 < k1) {
+            load_plane(1, k + 2);
+            load_tend(1, k + 1);
+        }
+        __syncthreads();
+
+        if (own && lane_on) {
+            const int bm = (k - 1) & 3, bc = k & 3, bp = (k + 1) & 3;
+            const T dzik = a.dzi[k], dzikm1 = a.dzi[k - 1], dzhik = a.dzhi[k], dzhik1 = a.dzhi[k + 1];
+            const int rr = r + 1;
+            T o0[VX], o1[VX], o2[VX];
+#pragma unroll
+            for (int n = 0; n < VX; ++n) {
+                const int x = 1 + xo + n;
+                // operand names: <field><offset>; offsets e/w (x), n/s (y), t/b (z)
+#define P(f, b, dj, di) pl[f][b][rr + (dj)][x + (di)]
+                const T uc = P(0, bc, 0, 0), ue = P(0, bc, 0, 1), uw = P(0, bc, 0, -1), un = P(0, bc, 1, 0),
+                        us = P(0, bc, -1, 0), ut_ = P(0, bp, 0, 0), ub = P(0, bm, 0, 0), use = P(0, bc, -1, 1),
+                        ube = P(0, bm, 0, 1);
+                const T vc = P(1, bc, 0, 0), ve = P(1, bc, 0, 1), vw = P(1, bc, 0, -1), vn = P(1, bc, 1, 0),
+                        vs = P(1, bc, -1, 0), vt_ = P(1, bp, 0, 0), vb = P(1, bm, 0, 0), vnw = P(1, bc, 1, -1),
+                        vbn = P(1, bm, 1, 0);
+                const T wc = P(2, bc, 0, 0), we = P(2, bc, 0, 1), ww = P(2, bc, 0, -1), wn = P(2, bc, 1, 0),
+                        ws = P(2, bc, -1, 0), wt_ = P(2, bp, 0, 0), wb = P(2, bm, 0, 0), wtw = P(2, bp, 0, -1),
+                        wts = P(2, bp, -1, 0);
+                const T ec = P(3, bc, 0, 0), ee = P(3, bc, 0, 1), ew = P(3, bc, 0, -1), en = P(3, bc, 1, 0),
+                        es = P(3, bc, -1, 0), et = P(3, bp, 0, 0), eb = P(3, bm, 0, 0), enw = P(3, bc, 1, -1),
+                        esw = P(3, bc, -1, -1), ese = P(3, bc, -1, 1), etw = P(3, bp, 0, -1),
+                        ebw = P(3, bm, 0, -1), ebe = P(3, bm, 0, 1), ets = P(3, bp, -1, 0), ebs = P(3, bm, -1, 0),
+                        ebn = P(3, bm, 1, 0);
+#undef P
+                o0[n] = TT[0][0][n] + smag_u<T>(uc, ue, uw, un, us, ut_, ub, vn, vnw, vc, vw, wt_, wtw, wc, ww,
+                                                ec, ew, en, enw, es, esw, et, etw, eb, ebw, dxi, dyi, dzik, dzhik,
+                                                dzhik1);
+                o1[n] = TT[0][1][n] + smag_v<T>(vc, ve, vw, vn, vs, vt_, vb, ue, use, uc, us, wt_, wts, wc, ws,
+                                                ec, es, ee, ese, ew, esw, et, ets, eb, ebs, dxi, dyi, dzik, dzhik,
+                                                dzhik1);
+                o2[n] = TT[0][2][n] + smag_w<T>(wc, we, ww, wn, ws, wt_, wb, ue, ube, uc, ub, vn, vbn, vc, vb,
+                                                ec, eb, ee, ebe, ew, ebw, en, ebn, es, ebs, dxi, dyi, dzik, dzikm1,
+                                                dzhik);
+            }
+            tstore<NT, T, VX>(a.ut + c_own + (int64_t)k * ks, o0);
+            tstore<NT, T, VX>(a.vt + c_own + (int64_t)k * ks, o1);
+            if (k >= a.kw0) tstore<NT, T, VX>(a.wt + c_own + (int64_t)k * ks, o2);
+        }
+
+        // advance the register slots
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+#pragma unroll
+            for (int n = 0; n < VX; ++n) O[0][f][n] = O[1][f][n];
+            OL[0][f] = OL[1][f];
+            OR_[0][f] = OR_[1][f];
+        }
+#pragma unroll
+        for (int m = 0; m < NH; ++m) {
+#pragma unroll
+            for (int n = 0; n < VX; ++n) H[0][m][n] = H[1][m][n];
+            HL[0][m] = HL[1][m];
+            HR[0][m] = HR[1][m];
+        }
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+            for (int n = 0; n < VX; ++n) TT[0][f][n] = TT[1][f][n];
+    }
+}
+
+}  // namespace kl

@@ -28,7 +28,7 @@ struct Guard {
     }
 };
 
-int zero_tendencies(const kl_grid_t *g, void *const f[6], hipStream_t s)
+int zero_tendencies(const kl_grid_t *g, void *const *f, hipStream_t s)
 {
     const HostArgs a = make_args(g);
     for (int n = 3; n < 6; ++n) {
@@ -39,12 +39,12 @@ int zero_tendencies(const kl_grid_t *g, void *const f[6], hipStream_t s)
 }
 
 // Hashes of the outputs of `kernel` (ut; or ut, vt, wt) into host h[3].
-int output_hashes(const kl_grid_t *g, int kernel, void *const f[6], uint64_t *dhash, uint64_t h[3], hipStream_t s)
+int output_hashes(const kl_grid_t *g, int kernel, void *const *f, uint64_t *dhash, uint64_t h[3], hipStream_t s)
 {
     void *ws = workspace(reduce_scratch_bytes(), s);
     if (!ws) return fail(KL_ERR_NOMEM, "tune workspace");
     const HostArgs a = make_args(g);
-    const int nout = kernel == KL_KERNEL_ADVEC_U ? 1 : 3;
+    const int nout = kernel_nptr(kernel) == 4 ? 1 : 3;
     for (int n = 0; n < nout; ++n) {
         hipError_t e = launch_hash(a, f[3 + n], dhash + n, ws, s);
         if (e != hipSuccess) return hip_fail(e, "hash");
@@ -61,15 +61,33 @@ double now_s()
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-int tune_one(const kl_grid_t *g, int kernel, void *const f[6], const std::string &dir, double budget_s,
+// Advection kernel a diffusion kernel follows in a time step of its scheme.
+int partner_of(int kernel)
+{
+    return kernel == KL_KERNEL_DIFF_UVW ? KL_KERNEL_ADVEC_U : (kernel == KL_KERNEL_DIFF_SMAG ? KL_KERNEL_ADVEC_U_2I5 : -1);
+}
+
+// Algorithmic values moved per grid point (read + written).
+int values_per_point(int kernel)
+{
+    switch (kernel) {
+    case KL_KERNEL_ADVEC_U:
+    case KL_KERNEL_ADVEC_U_2I5: return 5;
+    case KL_KERNEL_DIFF_UVW: return 9;
+    case KL_KERNEL_DIFF_SMAG: return 10;
+    default: return 6;
+    }
+}
+
+int tune_one(const kl_grid_t *g, int kernel, void *const *f, const std::string &dir, double budget_s,
              hipStream_t s, double *timings_out, int max_timings, int *n_timings, bool after_advec)
 {
     Guard gd;
     hipError_t e = hipMalloc(&gd.dhash, 3 * sizeof(uint64_t));
     if (e != hipSuccess) return hip_fail(e, "hipMalloc");
     const auto &vs = variants(kernel, g->dtype);
-    const void *ptrs[6] = {f[0], f[1], f[2], f[3], f[4], f[5]};
-    const int nptr = kernel == KL_KERNEL_ADVEC_U ? 4 : 6;
+    const void *const *ptrs = (const void *const *)f;
+    const int nptr = kernel_nptr(kernel);
     const double visc = 1e-5, dt = 1e-4;
     int rc;
 
@@ -79,12 +97,13 @@ int tune_one(const kl_grid_t *g, int kernel, void *const f[6], const std::string
     if ((rc = run_variant(g, kernel, 0, f, visc, s, dt))) return rc;
     if ((rc = output_hashes(g, kernel, f, gd.dhash, ref, s))) return rc;
 
-    // In pair mode diff_uvw is timed right after the selected advec_u, as it
-    // runs in a time step, so the memory-side cache state it starts from is
-    // the one advec_u leaves behind.
-    int adv = after_advec ? select_variant(g, KL_KERNEL_ADVEC_U) : -1;
-    if (adv > 0 && !variant_eligible(variants(KL_KERNEL_ADVEC_U, g->dtype)[adv], g, ptrs, 4)) adv = 0;
-    auto before = [&]() { return adv >= 0 ? run_variant(g, KL_KERNEL_ADVEC_U, adv, f, visc, s, dt) : KL_OK; };
+    // In pair mode a diffusion kernel is timed right after the selected
+    // advection kernel of its scheme, as it runs in a time step, so the
+    // memory-side cache state it starts from is the one advection leaves.
+    const int pk = after_advec ? partner_of(kernel) : -1;
+    int adv = pk >= 0 ? select_variant(g, pk) : -1;
+    if (adv > 0 && !variant_eligible(variants(pk, g->dtype)[adv], g, ptrs, 4)) adv = 0;
+    auto before = [&]() { return adv >= 0 ? run_variant(g, pk, adv, f, visc, s, dt) : KL_OK; };
     const int reps = 15, warm = 3;
     gd.ev.resize(2 * reps);
     for (auto &ev : gd.ev)
@@ -135,7 +154,7 @@ int tune_one(const kl_grid_t *g, int kernel, void *const f[6], const std::string
     DeviceIdent id;
     if ((rc = current_device_ident(&id))) return rc;
     const double npts = (double)g->itot * g->jtot * g->ktot;
-    const int values = kernel == KL_KERNEL_ADVEC_U ? 5 : (kernel == KL_KERNEL_DIFF_UVW ? 9 : 6);
+    const int values = values_per_point(kernel);
     const double bytes = npts * values * (g->dtype == KL_F32 ? 4 : 8);
     const Variant &v = vs[best];
     std::ostringstream o;
@@ -153,6 +172,14 @@ int tune_one(const kl_grid_t *g, int kernel, void *const f[6], const std::string
 
 }  // namespace
 
+// kl_tune mask bit of each kernel.
+uint32_t tune_bit(int kernel)
+{
+    static const uint32_t bits[KL_NUM_KERNELS] = {KL_TUNE_ADVEC_U, KL_TUNE_DIFF_UVW, KL_TUNE_STEP,
+                                                  KL_TUNE_ADVEC_U_2I5, KL_TUNE_DIFF_SMAG};
+    return bits[kernel];
+}
+
 extern "C" int kl_tune(const kl_grid_t *g, void *const fields[6], uint32_t kernel_mask, const char *wisdom_dir_,
                        double budget_s, void *stream, double *timings_out, int32_t max_timings, int32_t *n_timings)
 {
@@ -160,17 +187,22 @@ extern "C" int kl_tune(const kl_grid_t *g, void *const fields[6], uint32_t kerne
     int rc = check_grid(g);
     if (rc) return rc;
     if (!fields) return fail(KL_ERR_INVALID, "fields is NULL");
-    for (int n = 0; n < 6; ++n)
+    const uint32_t kernels = KL_TUNE_ADVEC_U | KL_TUNE_DIFF_UVW | KL_TUNE_STEP | KL_TUNE_ADVEC_U_2I5 | KL_TUNE_DIFF_SMAG;
+    if ((kernel_mask & kernels) == 0 || (kernel_mask & ~(kernels | KL_TUNE_PAIR)))
+        return fail(KL_ERR_INVALID, "kernel_mask %u", kernel_mask);
+    const int nf = (kernel_mask & KL_TUNE_DIFF_SMAG) ? 7 : 6;
+    for (int n = 0; n < nf; ++n)
         if (!fields[n]) return fail(KL_ERR_INVALID, "field %d is NULL", n);
-    if ((kernel_mask & 7u) == 0 || kernel_mask > 15) return fail(KL_ERR_INVALID, "kernel_mask %u", kernel_mask);
-    const bool pair = (kernel_mask & 8u) != 0;
+    const bool pair = (kernel_mask & KL_TUNE_PAIR) != 0;
     if (n_timings) *n_timings = 0;
     const std::string dir = wisdom_dir_ && *wisdom_dir_ ? std::string(wisdom_dir_) : wisdom_dir();
     bool first = true;
-    for (int kernel = 0; kernel < 3; ++kernel) {
-        if (!(kernel_mask & (1u << kernel))) continue;
+    for (int kernel = 0; kernel < KL_NUM_KERNELS; ++kernel) {
+        if (!(kernel_mask & tune_bit(kernel))) continue;
+        if (kernel == KL_KERNEL_ADVEC_U_2I5 && g->gc < 3)
+            return fail(KL_ERR_INVALID, "advec_u_2i5 needs gc = 3 ghost cells in x and y");
         rc = tune_one(g, kernel, fields, dir, budget_s, (hipStream_t)stream, first ? timings_out : nullptr,
-                      max_timings, first ? n_timings : nullptr, pair && kernel == KL_KERNEL_DIFF_UVW);
+                      max_timings, first ? n_timings : nullptr, pair && partner_of(kernel) >= 0);
         clear_plans();  // a kernel tuned above is selected for the ones that follow
         if (rc) return rc;
         first = false;

@@ -6,6 +6,8 @@
 #include "stencil.hpp"
 #include "stencil_zl.hpp"
 #include "stencil_step.hpp"
+#include "stencil_les.hpp"
+#include "stencil_les_zl.hpp"
 
 namespace kl {
 
@@ -36,6 +38,7 @@ StencilArgs<T> device_args(const HostArgs &h)
     a.v = (const T *)h.v;
     a.w = (const T *)h.w;
     a.nbx = a.nby = a.nbz = 1;
+    a.evisc = (const T *)h.evisc;
     return a;
 }
 
@@ -53,8 +56,12 @@ hipError_t launch_plain(const HostArgs &h, hipStream_t s)
     if (!grid_fits(nb, 256)) return hipErrorInvalidConfiguration;
     if (KERNEL == KL_KERNEL_ADVEC_U)
         hipLaunchKernelGGL(advec_u_plain<T>, dim3((unsigned)nb), dim3(256), 0, s, a);
-    else
+    else if (KERNEL == KL_KERNEL_DIFF_UVW)
         hipLaunchKernelGGL(diff_uvw_plain<T>, dim3((unsigned)nb), dim3(256), 0, s, a);
+    else if (KERNEL == KL_KERNEL_ADVEC_U_2I5)
+        hipLaunchKernelGGL(advec_u_2i5_plain<T>, dim3((unsigned)nb), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(diff_smag_plain<T>, dim3((unsigned)nb), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -142,6 +149,32 @@ int step_batch_occupancy()
     const hipError_t e =
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_zl_batch<T, VX, BY, KB, NT, WPE>, 64 * BY, 0);
     return e == hipSuccess && n > 0 ? n : 1;
+}
+
+template <typename T, int VX, int BY, int KB, int XCD, int NT = 0, int WPE = 1>
+hipError_t launch_advec5_zl(const HostArgs &h, hipStream_t s)
+{
+    StencilArgs<T> a = device_args<T>(h);
+    a.nbx = (int)cdivu(h.itot, (int64_t)64 * VX);
+    a.nby = (int)cdivu(h.jtot, BY);
+    a.nbz = (int)cdivu(h.ktot, KB);
+    const uint64_t nb = (uint64_t)a.nbx * a.nby * a.nbz;
+    if (!grid_fits(nb, 64 * BY)) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((advec_u_2i5_zl<T, VX, BY, KB, XCD, NT, WPE>), dim3((unsigned)nb), dim3(64, BY), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, int VX, int BY, int KB, int XCD, int NT = 0, int WPE = 1>
+hipError_t launch_smag_zl(const HostArgs &h, hipStream_t s)
+{
+    StencilArgs<T> a = device_args<T>(h);
+    a.nbx = (int)cdivu(h.itot, (int64_t)64 * VX);
+    a.nby = (int)cdivu(h.jtot, BY);
+    a.nbz = (int)cdivu(h.ktot, KB);
+    const uint64_t nb = (uint64_t)a.nbx * a.nby * a.nbz;
+    if (!grid_fits(nb, 64 * BY)) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((diff_smag_zl<T, VX, BY, KB, XCD, NT, WPE>), dim3((unsigned)nb), dim3(64, BY), 0, s, a);
+    return hipGetLastError();
 }
 
 }  // namespace kl
@@ -234,3 +267,15 @@ int step_batch_occupancy()
 #define KL_SMALL_SET(T, DT, KERN, VX)                                                                   \
     KL_ZLX(T, DT, KERN, VX, 4, 8, 0, 0, 1), KL_ZLX(T, DT, KERN, VX, 4, 16, 0, 0, 1),                   \
         KL_ZLX(T, DT, KERN, VX, 8, 8, 0, 0, 1), KL_ZLX(T, DT, KERN, VX, 8, 16, 0, 1, 1)
+
+// advec_u_2i5 LDS z-march configurations, named a5_v<VX>_b64x<BY>_k<KB>_x<XCD>_nt<NT>.
+#define KL_A5(T, DT, VX, BY, KB, XCD, NT)                                                                   \
+    Variant{"a5_v" KL_STR(VX) "_b64x" KL_STR(BY) "_k" KL_STR(KB) "_x" KL_STR(XCD) "_nt" KL_STR(NT),        \
+            KL_KERNEL_ADVEC_U_2I5, DT, FAMILY_ZL, VX, 64, BY, KB, XCD,                                     \
+            &launch_advec5_zl<T, VX, BY, KB, XCD, NT>, nullptr, nullptr}
+
+// diff_smag LDS z-march configurations, named s2_v<VX>_b64x<BY>_k<KB>_x<XCD>_nt<NT>.
+#define KL_S2(T, DT, VX, BY, KB, XCD, NT)                                                                   \
+    Variant{"s2_v" KL_STR(VX) "_b64x" KL_STR(BY) "_k" KL_STR(KB) "_x" KL_STR(XCD) "_nt" KL_STR(NT),        \
+            KL_KERNEL_DIFF_SMAG, DT, FAMILY_ZL, VX, 64, BY, KB, XCD,                                       \
+            &launch_smag_zl<T, VX, BY, KB, XCD, NT>, nullptr, nullptr}

@@ -12,12 +12,21 @@ void add_variants_f32_nt(int kernel, std::vector<Variant> &out);
 void add_variants_f32_step(std::vector<Variant> &out);
 void add_variants_f32_small(int kernel, std::vector<Variant> &out);
 void add_variants_f32_rev(int kernel, std::vector<Variant> &out);
+void add_variants_f32_les(int kernel, std::vector<Variant> &out);
 
 static std::vector<Variant> build_f32(int kernel)
 {
     std::vector<Variant> v;
     if (kernel == KL_KERNEL_STEP) {  // index 0: a fused step with scalar lanes (fits any itot)
         add_variants_f32_step(v);
+        return v;
+    }
+    if (kernel == KL_KERNEL_ADVEC_U_2I5 || kernel == KL_KERNEL_DIFF_SMAG) {
+        v.push_back(Variant{"default", kernel, KL_F32, FAMILY_PLAIN, 1, 256, 1, 1, 0,
+                            kernel == KL_KERNEL_ADVEC_U_2I5 ? &launch_plain<float, KL_KERNEL_ADVEC_U_2I5>
+                                                            : &launch_plain<float, KL_KERNEL_DIFF_SMAG>,
+                            nullptr, nullptr});
+        add_variants_f32_les(kernel, v);
         return v;
     }
     v.push_back(Variant{"default", kernel, KL_F32, FAMILY_PLAIN, 1, 256, 1, 1, 0,
@@ -40,7 +49,15 @@ const std::vector<Variant> &variants_f32(int kernel)
     static const std::vector<Variant> advec = build_f32(KL_KERNEL_ADVEC_U);
     static const std::vector<Variant> diff = build_f32(KL_KERNEL_DIFF_UVW);
     static const std::vector<Variant> step = build_f32(KL_KERNEL_STEP);
-    return kernel == KL_KERNEL_ADVEC_U ? advec : (kernel == KL_KERNEL_DIFF_UVW ? diff : step);
+    static const std::vector<Variant> advec5 = build_f32(KL_KERNEL_ADVEC_U_2I5);
+    static const std::vector<Variant> smag = build_f32(KL_KERNEL_DIFF_SMAG);
+    switch (kernel) {
+    case KL_KERNEL_ADVEC_U: return advec;
+    case KL_KERNEL_DIFF_UVW: return diff;
+    case KL_KERNEL_STEP: return step;
+    case KL_KERNEL_ADVEC_U_2I5: return advec5;
+    default: return smag;
+    }
 }
 
 }  // namespace kl

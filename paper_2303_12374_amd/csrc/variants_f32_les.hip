@@ -1,0 +1,43 @@
+// Registry part: F32 configurations of advec_u_2i5 and diff_smag.
+#include "variants.hpp"
+
+namespace kl {
+
+void add_variants_f32_les(int kernel, std::vector<Variant> &out)
+{
+    if (kernel == KL_KERNEL_ADVEC_U_2I5) {
+        static const std::vector<Variant> v = {
+        KL_A5(float, KL_F32, 4, 4, 64, 2, 1),
+        KL_A5(float, KL_F32, 4, 4, 128, 2, 1),
+        KL_A5(float, KL_F32, 4, 8, 64, 2, 1),
+        KL_A5(float, KL_F32, 4, 2, 64, 2, 1),
+        KL_A5(float, KL_F32, 2, 4, 64, 2, 1),
+        KL_A5(float, KL_F32, 2, 8, 64, 2, 1),
+        KL_A5(float, KL_F32, 2, 8, 128, 2, 1),
+        KL_A5(float, KL_F32, 1, 8, 64, 2, 1),
+        KL_A5(float, KL_F32, 1, 16, 64, 2, 1),
+        KL_A5(float, KL_F32, 4, 4, 32, 0, 0),
+        KL_A5(float, KL_F32, 2, 4, 32, 0, 0),
+        KL_A5(float, KL_F32, 4, 4, 256, 3, 1),
+        KL_A5(float, KL_F32, 4, 4, 64, 0, 1),
+        KL_A5(float, KL_F32, 2, 4, 16, 0, 0),
+        KL_A5(float, KL_F32, 1, 8, 16, 0, 0)};
+        out.insert(out.end(), v.begin(), v.end());
+    } else if (kernel == KL_KERNEL_DIFF_SMAG) {
+        static const std::vector<Variant> v = {
+        KL_S2(float, KL_F32, 1, 8, 64, 2, 1),
+        KL_S2(float, KL_F32, 1, 16, 64, 2, 1),
+        KL_S2(float, KL_F32, 2, 4, 64, 2, 1),
+        KL_S2(float, KL_F32, 2, 8, 64, 2, 1),
+        KL_S2(float, KL_F32, 4, 4, 64, 2, 1),
+        KL_S2(float, KL_F32, 1, 8, 32, 0, 0),
+        KL_S2(float, KL_F32, 2, 4, 32, 0, 0),
+        KL_S2(float, KL_F32, 1, 4, 64, 2, 1),
+        KL_S2(float, KL_F32, 2, 4, 128, 2, 1),
+        KL_S2(float, KL_F32, 1, 8, 16, 0, 0),
+        KL_S2(float, KL_F32, 2, 2, 64, 2, 1)};
+        out.insert(out.end(), v.begin(), v.end());
+    }
+}
+
+}  // namespace kl

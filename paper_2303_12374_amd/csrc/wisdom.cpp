@@ -250,7 +250,13 @@ std::string g_dir;  // empty: default
 
 const char *kernel_name(int kernel)
 {
-    return kernel == KL_KERNEL_ADVEC_U ? "advec_u" : (kernel == KL_KERNEL_DIFF_UVW ? "diff_uvw" : "step");
+    switch (kernel) {
+    case KL_KERNEL_ADVEC_U: return "advec_u";
+    case KL_KERNEL_DIFF_UVW: return "diff_uvw";
+    case KL_KERNEL_STEP: return "step";
+    case KL_KERNEL_ADVEC_U_2I5: return "advec_u_2i5";
+    default: return "diff_smag";
+    }
 }
 
 std::string wisdom_dir()
@@ -391,7 +397,7 @@ int kl_wisdom_lookup(const char *wisdom_dir_, int32_t kernel, int32_t dtype, con
                      int32_t *level)
 {
     clear_error();
-    if (kernel < KL_KERNEL_ADVEC_U || kernel > KL_KERNEL_STEP) return fail(KL_ERR_INVALID, "kernel %d", kernel);
+    if (kernel < 0 || kernel >= KL_NUM_KERNELS) return fail(KL_ERR_INVALID, "kernel %d", kernel);
     if (dtype != KL_F32 && dtype != KL_F64) return fail(KL_ERR_INVALID, "dtype %d", dtype);
     if (!device_name || !arch || !variant || !level || len == 0) return fail(KL_ERR_INVALID, "NULL argument");
     DeviceIdent id{device_name, arch, 0};

@@ -24,7 +24,10 @@ LIB_PATH = os.path.join(HERE, "libkl.so")
 
 F32, F64 = 0, 1
 BC_ZWALL_ZEROGRAD, BC_ZWALL_NOPEN, BC_ZPERIODIC = 0, 1, 2
-ADVEC_U, DIFF_UVW, STEP = 0, 1, 2
+ADVEC_U, DIFF_UVW, STEP, ADVEC_U_2I5, DIFF_SMAG = 0, 1, 2, 3, 4
+TUNE_ADVEC_U, TUNE_DIFF_UVW, TUNE_STEP, TUNE_PAIR, TUNE_ADVEC_U_2I5, TUNE_DIFF_SMAG = 1, 2, 4, 8, 16, 32
+KERNEL_NAMES = {ADVEC_U: "advec_u", DIFF_UVW: "diff_uvw", STEP: "step", ADVEC_U_2I5: "advec_u_2i5",
+                DIFF_SMAG: "diff_smag"}
 OK, ERR_INVALID, ERR_DEVICE, ERR_NOMEM, ERR_BUDGET, ERR_AGAIN, ERR_NOTFOUND, ERR_IO = 0, -1, -2, -3, -4, -5, -6, -7
 
 TORCH_DTYPE = {F32: torch.float32, F64: torch.float64}
@@ -67,7 +70,13 @@ _sig = {
     "kl_last_error": (c_char_p, []),
     "kl_layout": (c_int, [c_int32, c_int32, c_int32, c_int32, POINTER(c_int64), POINTER(c_int64),
                           POINTER(c_int64), POINTER(c_int64)]),
+    "kl_layout_gc": (c_int, [c_int32, c_int32, c_int32, c_int32, c_int32, POINTER(c_int64), POINTER(c_int64),
+                             POINTER(c_int64), POINTER(c_int64)]),
     "kl_fill_ghosts": (c_int, [_G, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "kl_fill_scalar": (c_int, [_G, c_void_p, c_void_p]),
+    "kl_advec_u_2i5": (c_int, [_G, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "kl_diff_smag": (c_int, [_G, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                             c_void_p]),
     "kl_advec_u": (c_int, [_G, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "kl_diff_uvw": (c_int, [_G, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                             c_double, c_void_p]),
@@ -135,8 +144,10 @@ def _stream(stream):
 
 
 def _fields6(fields):
-    arr = (c_void_p * 6)(*[_ptr(f) for f in fields])
-    return arr
+    """C array of the field pointers (6, or 7 with the eddy viscosity)."""
+    ptrs = [_ptr(f) for f in fields]
+    ptrs += [None] * (max(6, len(ptrs)) - len(ptrs))
+    return (c_void_p * len(ptrs))(*ptrs)
 
 
 # ---------------------------------------------------------------------------
@@ -157,8 +168,27 @@ def kl_layout(itot, jtot, ktot, dtype):
     return off.value, js.value, ks.value, alloc.value
 
 
+def kl_layout_gc(itot, jtot, ktot, dtype, gc):
+    off, js, ks, alloc = c_int64(), c_int64(), c_int64(), c_int64()
+    _check(_lib.kl_layout_gc(itot, jtot, ktot, dtype, gc, byref(off), byref(js), byref(ks), byref(alloc)))
+    return off.value, js.value, ks.value, alloc.value
+
+
 def kl_fill_ghosts(g, u, v, w, stream=None):
     _check(_lib.kl_fill_ghosts(byref(_cg(g)), _ptr(u), _ptr(v), _ptr(w), _stream(stream)))
+
+
+def kl_fill_scalar(g, f, stream=None):
+    _check(_lib.kl_fill_scalar(byref(_cg(g)), _ptr(f), _stream(stream)))
+
+
+def kl_advec_u_2i5(g, ut, u, v, w, stream=None):
+    _check(_lib.kl_advec_u_2i5(byref(_cg(g)), _ptr(ut), _ptr(u), _ptr(v), _ptr(w), _stream(stream)))
+
+
+def kl_diff_smag(g, ut, vt, wt, u, v, w, evisc, stream=None):
+    _check(_lib.kl_diff_smag(byref(_cg(g)), _ptr(ut), _ptr(vt), _ptr(wt), _ptr(u), _ptr(v), _ptr(w),
+                             _ptr(evisc), _stream(stream)))
 
 
 def kl_advec_u(g, ut, u, v, w, stream=None):
@@ -326,16 +356,18 @@ class Grid:
 
     The vertical grid is the centers-primary tanh stretch of
     :func:`inputs.zgrid` (uniform when ``bc == BC_ZPERIODIC`` or
-    ``gamma == 0``); ``dx = 1/itot``, ``dy = 1/jtot``.  ``layout`` defaults to
-    :func:`kl_layout`.
+    ``gamma == 0``); ``dx = 1/itot``, ``dy = 1/jtot``.  ``gc`` ghost cells per
+    side in x and y (1, or 3 for advec_u_2i5).  ``layout`` defaults to
+    :func:`kl_layout_gc`.
     """
 
     def __init__(self, itot, jtot, ktot, dtype=F32, bc=BC_ZWALL_ZEROGRAD, gamma=1.5, layout=None,
-                 device="cuda"):
+                 device="cuda", gc=1):
         self.itot, self.jtot, self.ktot, self.dtype, self.bc = itot, jtot, ktot, dtype, bc
+        self.gc = gc
         self.device = torch.device(device)
         if layout is None:
-            layout = kl_layout(itot, jtot, ktot, dtype)
+            layout = kl_layout_gc(itot, jtot, ktot, dtype, gc)
         self.off, self.js, self.ks, self.alloc = (int(x) for x in layout)
         Lz = inputs.domain_height(itot, jtot, ktot)
         self.zg = inputs.zgrid(ktot, Lz, 0.0 if bc == BC_ZPERIODIC else gamma)
@@ -347,7 +379,7 @@ class Grid:
         self.dyi = float(npd(jtot))
         self.dzi = torch.from_numpy(self.dzi_h.copy()).to(self.device)
         self.dzhi = torch.from_numpy(self.dzhi_h.copy()).to(self.device)
-        self.c = kl_grid_t(itot, jtot, ktot, 1, self.off, self.js, self.ks, self.dxi, self.dyi,
+        self.c = kl_grid_t(itot, jtot, ktot, gc, self.off, self.js, self.ks, self.dxi, self.dyi,
                            self.dzi.data_ptr(), self.dzhi.data_ptr(), dtype, bc)
 
     @property
@@ -362,12 +394,15 @@ class Grid:
         return torch.full((self.alloc,), value, dtype=self.tdtype, device=self.device)
 
     def box(self, t):
-        """(kcells, jcells, icells) strided view of a flat field tensor."""
-        return t.as_strided((self.ktot + 2, self.jtot + 2, self.itot + 2), (self.ks, self.js, 1),
-                            self.off)
+        """(ktot+2, jtot+2*gc, itot+2*gc) strided view of a flat field tensor;
+        box[k, j, i] is element (i+1-gc, j+1-gc, k)."""
+        g = self.gc
+        return t.as_strided((self.ktot + 2, self.jtot + 2 * g, self.itot + 2 * g), (self.ks, self.js, 1),
+                            t.storage_offset() + self.off - (g - 1) * (self.js + 1))
 
     def interior(self, t):
-        return self.box(t)[1:self.ktot + 1, 1:self.jtot + 1, 1:self.itot + 1]
+        g = self.gc
+        return self.box(t)[1:self.ktot + 1, g:self.jtot + g, g:self.itot + g]
 
     def upload(self, interior_np, fill=math.nan):
         """Device field holding ``interior_np`` (rounded to the dtype); ghosts = fill."""

@@ -1,13 +1,15 @@
-"""Tuning command line: measure every compiled configuration of advec_u and
-diff_uvw for a list of grid shapes and dtypes on this GPU and append the
-best ones to the wisdom files (the tune step of the capture -> tune ->
+"""Tuning command line: measure every compiled configuration of the
+tendency kernels for a list of grid shapes and dtypes on this GPU and append
+the best ones to the wisdom files (the tune step of the capture -> tune ->
 wisdom -> select flow; Section "Kernel Tuning").
 
-Fields are the library's seeded initial state (kl_generate_fields): stencil
-timings do not depend on the field values.
+Fields are the library's seeded initial state (kl_generate_fields; the eddy
+viscosity of diff_smag is a constant 1e-3): stencil timings do not depend on
+the field values.
 
     python -m paper_2303_12374_amd.tune --wisdom wisdom \\
-        --shapes 512x512x512,256x256x256 --dtypes f32,f64 --budget 60
+        --shapes 512x512x512,256x256x256 --dtypes f32,f64 --budget 60 \\
+        --kernels advec_u,diff_uvw,step,advec_u_2i5,diff_smag
 """
 from __future__ import annotations
 
@@ -24,19 +26,31 @@ def parse_shape(s: str):
     return tuple(parts)
 
 
-def tune_shape(kl, shape, dtype, wisdom, budget, bc=0, log=None):
+KERNELS = ("advec_u", "diff_uvw", "step", "advec_u_2i5", "diff_smag")
+
+
+def tune_shape(kl, shape, dtype, wisdom, budget, bc=0, log=None, kernels=KERNELS[:3]):
     import torch
-    g = kl.Grid(*shape, dtype=dtype, bc=bc)
-    f = [g.full(0.0) for _ in range(6)]
-    kl.kl_generate_fields(g, 12345, *f[:3])
-    kl.kl_fill_ghosts(g, *f[:3])
     out = {}
     kl.kl_set_wisdom_dir(wisdom)
-    for kern, name in ((kl.ADVEC_U, "advec_u"), (kl.DIFF_UVW, "diff_uvw"), (kl.STEP, "step")):
+    bits = {kl.ADVEC_U: kl.TUNE_ADVEC_U, kl.DIFF_UVW: kl.TUNE_DIFF_UVW | kl.TUNE_PAIR, kl.STEP: kl.TUNE_STEP,
+            kl.ADVEC_U_2I5: kl.TUNE_ADVEC_U_2I5, kl.DIFF_SMAG: kl.TUNE_DIFF_SMAG | kl.TUNE_PAIR}
+    grids = {}
+    for name in kernels:
+        kern = KERNELS.index(name)
+        gc = 3 if kern in (kl.ADVEC_U_2I5, kl.DIFF_SMAG) else 1
+        if gc not in grids:
+            g = kl.Grid(*shape, dtype=dtype, bc=bc, gc=gc)
+            f = [g.full(0.0) for _ in range(7)]
+            kl.kl_generate_fields(g, 12345, *f[:3])
+            kl.kl_fill_ghosts(g, *f[:3])
+            f[6].fill_(1e-3)
+            grids[gc] = (g, f)
+        g, f = grids[gc]
         t0 = time.time()
-        # diff_uvw is timed after the advec_u just tuned (it follows it in a step)
-        mask = (1 << kern) | (8 if kern == kl.DIFF_UVW else 0)
-        res = kl.kl_tune(g, f, mask, wisdom, budget)
+        # a diffusion kernel is timed after the advection kernel just tuned
+        # (it follows it in a step)
+        res = kl.kl_tune(g, f, bits[kern], wisdom, budget)
         ok = [(ms, i) for i, ms in res if ms > 0]
         best_ms, best = min(ok)
         default_ms = dict((i, ms) for i, ms in res).get(0, float("nan"))
@@ -46,7 +60,7 @@ def tune_shape(kl, shape, dtype, wisdom, budget, bc=0, log=None):
             log(f"{name} {'x'.join(map(str, shape))} {'f32' if dtype == kl.F32 else 'f64'}: "
                 f"{out[name]['best']} {best_ms:.4f} ms (default {default_ms:.4f} ms, "
                 f"{len(res)} configurations)")
-    del f
+    grids.clear()
     torch.cuda.synchronize()
     return out
 
@@ -58,6 +72,7 @@ def main(argv=None):
     ap.add_argument("--dtypes", default="f32,f64")
     ap.add_argument("--budget", type=float, default=60.0, help="seconds per kernel and shape")
     ap.add_argument("--json", default="", help="write a summary here")
+    ap.add_argument("--kernels", default="advec_u,diff_uvw,step", help="comma-separated, from " + ",".join(KERNELS))
     a = ap.parse_args(argv)
     from paper_2303_12374_amd import kl
     log = lambda m: print(f"[tune] {m}", flush=True)
@@ -66,7 +81,9 @@ def main(argv=None):
         shape = parse_shape(s)
         for d in a.dtypes.split(","):
             dtype = kl.F32 if d == "f32" else kl.F64
-            summary.append({"shape": shape, "dtype": d, **tune_shape(kl, shape, dtype, a.wisdom, a.budget, log=log)})
+            summary.append({"shape": shape, "dtype": d,
+                            **tune_shape(kl, shape, dtype, a.wisdom, a.budget, log=log,
+                                         kernels=tuple(a.kernels.split(",")))})
     if a.json:
         with open(a.json, "w") as f:
             json.dump(summary, f, indent=1)

@@ -86,3 +86,63 @@ def test_full_size_sampled_parity(shape, dtype):
                 assert hh[2 * q] == hh[2 * q + 1], f"selected configuration differs from the default (kernel {kern})"
     finally:
         m.kl_set_wisdom_dir(None)
+
+
+@pytest.mark.parametrize("dtype", [0, 1], ids=["f32", "f64"])
+def test_full_size_les_sampled_parity(dtype):
+    """advec_u_2i5 and diff_smag at 512^3 (three ghost cells in x and y), in
+    the configurations the wisdom files select: sampled points against the
+    oracle's single-point evaluation, and the selected configurations equal
+    the default ones bitwise on the whole grid."""
+    m = kl()
+    m.kl_set_wisdom_dir(os.path.join(ROOT, "wisdom"))
+    try:
+        itot = jtot = ktot = 512
+        g = m.Grid(itot, jtot, ktot, dtype=dtype, bc=0, gc=3)
+        npd = m.NP_DTYPE[dtype]
+        fs = inputs.random_fields(6, itot, jtot, ktot)
+        fs.append(inputs.evisc_field(6, itot, jtot, ktot, mean=2e-3))
+        dev, host = [], []
+        for f in fs:
+            fr = f.astype(npd)
+            dev.append(g.upload(fr))
+            host.append(inputs.embed(fr.astype(np.float64), g.off, g.js, g.ks, g.alloc, gh=3))
+            del fr
+        del fs
+        m.kl_fill_ghosts(g, *dev[:3])
+        m.kl_fill_scalar(g, dev[3])
+        og = oracle.Grid(itot, jtot, ktot, g.off, g.js, g.ks, g.alloc, g.dxi, g.dyi,
+                         g.dzi_h.astype(np.float64), g.dzhi_h.astype(np.float64), 0, 3)
+        oracle.fill_ghosts(og, *host[:3])
+        oracle.fill_scalar(og, host[3])
+        t = [g.zeros_interior(fill=0.0) for _ in range(4)]
+        m.kl_advec_u_2i5(g, t[0], *dev[:3])
+        m.kl_diff_smag(g, t[1], t[2], t[3], *dev)
+        torch.cuda.synchronize()
+        rng = np.random.default_rng(9)
+        pts = sample_points(itot, jtot, ktot, 3000, rng)
+        idx = torch.tensor([g.off + i + j * g.js + k * g.ks for i, j, k in pts], device="cuda")
+        got = np.stack([x[idx].cpu().numpy().astype(np.float64) for x in t], axis=1)
+        ref = np.stack([oracle.point_les(og, *host, i, j, k) for i, j, k in pts])
+        wall = np.array([k for _, _, k in pts]) >= 2
+        for n in range(4):
+            r, gt = ref[:, n], got[:, n]
+            if n == 3:
+                r, gt = r[wall], gt[wall]
+            err = np.max(np.abs(gt - r)) / np.max(np.abs(r))
+            assert err <= TOL[dtype], f"output {n}: sampled rel err {err:.3e}"
+        h = torch.zeros(8, dtype=torch.int64, device="cuda")
+        for kern, outs in ((m.ADVEC_U_2I5, [0]), (m.DIFF_SMAG, [1, 2, 3])):
+            if m.kl_selected_variant(g, kern) == 0:
+                continue
+            d = [g.zeros_interior(fill=0.0) for _ in range(3)]
+            fields = dev[:3] + d + ([dev[3]] if kern == m.DIFF_SMAG else [])
+            m.kl_launch_variant(g, kern, 0, fields)
+            for q, o in enumerate(outs):
+                m.kl_hash_interior(g, t[o], h[2 * q:2 * q + 1])
+                m.kl_hash_interior(g, d[q], h[2 * q + 1:2 * q + 2])
+            hh = h.cpu().numpy()
+            for q in range(len(outs)):
+                assert hh[2 * q] == hh[2 * q + 1], f"selected configuration differs from the default (kernel {kern})"
+    finally:
+        m.kl_set_wisdom_dir(None)

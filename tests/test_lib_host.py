@@ -44,6 +44,22 @@ def test_layout_alignment(dtype, s, shape):
     assert (last_ghost * s) // 128 == (next_first * s) // 128
 
 
+@pytest.mark.parametrize("dtype,s", [(kl.F32, 4), (kl.F64, 8)])
+@pytest.mark.parametrize("shape", [(512, 512, 512), (37, 23, 19), (1, 1, 2), (2, 3, 4)])
+def test_layout_three_ghost_cells(dtype, s, shape):
+    """gc = 3: interior rows start on a 128-byte line, the first ghost cell
+    (1-3, 1-3, 0) has a non-negative index, the last one fits the allocation,
+    and rows / planes hold itot+6 / jtot+6 cells."""
+    itot, jtot, ktot = shape
+    off, js, ks, alloc = kl.kl_layout_gc(itot, jtot, ktot, dtype, 3)
+    assert ((off + 1) * s) % 128 == 0
+    assert (js * s) % 128 == 0 and js >= itot + 6
+    assert ks == js * (jtot + 6)
+    assert off + (1 - 3) + (1 - 3) * js >= 0
+    assert off + (itot + 3) + (jtot + 3) * js + (ktot + 1) * ks < alloc
+    assert kl.kl_layout_gc(itot, jtot, ktot, dtype, 1) == kl.kl_layout(itot, jtot, ktot, dtype)
+
+
 def test_layout_rejects_bad_sizes():
     with pytest.raises(kl.KLError) as e:
         kl.kl_layout(0, 4, 4, kl.F32)
@@ -66,6 +82,27 @@ def test_argument_checks_need_no_device():
         kl.kl_advec_u(g, None, 1, 1, 1, stream=0)
     with pytest.raises(kl.KLError):
         kl.kl_reduce_fp64(g, 5, 1, 1, 1, 1, stream=0)
+
+
+def test_new_scheme_argument_checks_need_no_device():
+    """advec_u_2i5 refuses a grid with one ghost cell; diff_smag refuses a
+    NULL eddy viscosity; gc must be 1 or 3 (all before any device work)."""
+    off, js, ks, _ = kl.kl_layout(8, 8, 8, kl.F32)
+    g1 = kl.kl_grid_t(8, 8, 8, 1, off, js, ks, 8.0, 8.0, 16, 16, kl.F32, 0)
+    with pytest.raises(kl.KLError) as e:
+        kl.kl_advec_u_2i5(g1, 64, 64, 64, 64, stream=0)
+    assert e.value.code == kl.ERR_INVALID and "gc" in str(e.value)
+    with pytest.raises(kl.KLError) as e:
+        kl.kl_diff_smag(g1, 64, 64, 64, 64, 64, 64, None, stream=0)
+    assert e.value.code == kl.ERR_INVALID
+    off3, js3, ks3, _ = kl.kl_layout_gc(8, 8, 8, kl.F32, 3)
+    g3 = kl.kl_grid_t(8, 8, 8, 3, off3, js3, ks3, 8.0, 8.0, 16, 16, kl.F32, 0)
+    bad = kl.kl_grid_t.from_buffer_copy(g3)
+    bad.off = 10  # first ghost cells would lie before the buffer
+    with pytest.raises(kl.KLError):
+        kl.kl_fill_ghosts(bad, 64, 64, 64, stream=0)
+    with pytest.raises(kl.KLError):
+        kl.kl_layout_gc(8, 8, 8, kl.F32, 2)
 
 
 def test_variant_registry():
