@@ -378,6 +378,35 @@ def les_leg(kl, torch, np, inputs, shape, host_fields, seed, steps):
             "configurations": names, "steps": steps}
 
 
+def launch_overhead_leg(kl, torch, np, shape=(256, 256, 256), calls=200):
+    """Host time of one kl_advec_u call: the first call for a problem size
+    (reads the wisdom file, runs the selection heuristic, launches) and the
+    mean of later calls (cached selection; launch only), as in the paper's
+    measurement of its first and subsequent launches.  No runtime compilation
+    is involved: every configuration is compiled ahead of time."""
+    import time as _t
+    g = kl.Grid(*shape, dtype=kl.F32)
+    f = [g.full(0.0) for _ in range(4)]
+    kl.kl_fill_ghosts(g, *f[:3])
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    firsts = []
+    for _ in range(5):
+        kl.kl_clear_plan_cache()
+        t0 = _t.perf_counter()
+        kl.kl_advec_u(g, f[3], *f[:3], stream)
+        firsts.append(_t.perf_counter() - t0)
+        torch.cuda.synchronize()
+    t0 = _t.perf_counter()
+    for _ in range(calls):
+        kl.kl_advec_u(g, f[3], *f[:3], stream)
+    later = (_t.perf_counter() - t0) / calls
+    torch.cuda.synchronize()
+    return {"grid": list(shape), "first_call_ms": 1e3 * float(np.median(firsts)),
+            "later_call_us": 1e6 * later, "calls": calls,
+            "note": "host time per call through the Python binding; the first call reads advec_u.wisdom"}
+
+
 def summarize_counters(fetch_csv, write_csv, workload_key, out_json, out_txt, command, elem="float"):
     """Per-dispatch HBM bytes of the tendency kernels from two rocprofv3 --pmc
     runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what
@@ -445,6 +474,7 @@ def main():
     ap.add_argument("--no-untuned", action="store_true")
     ap.add_argument("--no-other-dtype", action="store_true", help="skip the pair in the other precision")
     ap.add_argument("--no-les", action="store_true", help="skip the fifth-order advection + Smagorinsky pair")
+    ap.add_argument("--no-overhead", action="store_true", help="skip the first-launch overhead measurement")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--served-requests", type=int, default=2000)
@@ -460,7 +490,7 @@ def main():
         wkey = f"{itot}x{jtot}x{ktot}_{args.dtype}"
         cmd = ("rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv -d <dir> -o bench -- python3 "
                "bench.py --with-copy-probe --steps 3 --warmup 1 --no-cpu-baseline --no-untuned --no-batched "
-               "--no-served --no-other-dtype --no-les")
+               "--no-served --no-other-dtype --no-les --no-overhead")
         fetch_csv, write_csv, bench_json = args.summarize_counters
         out, txt = summarize_counters(fetch_csv, write_csv, wkey, None, None, cmd,
                                       "float" if args.dtype == "f32" else "double")
@@ -641,6 +671,9 @@ def main():
                       "separate_hbm_gbps_26_values": 26 * s * npts / (sep_ms * 1e6)}
     del dev, tend, u, v, w, ut, vt, wt, out
     torch.cuda.empty_cache()
+    if not args.no_overhead:
+        log("launch overhead: first call per problem size vs later calls")
+        result["launch_overhead"] = launch_overhead_leg(kl, torch, np)
     if not args.no_batched:
         log("batched form: 56 grids in one graph vs 112 single-grid launches")
         result["batched"] = batched_leg(kl, inputs, torch)

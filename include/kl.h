@@ -319,6 +319,42 @@ int kl_tune(const kl_grid_t *g, void *const fields[6], uint32_t kernel_mask,
             const char *wisdom_dir, double budget_s, void *stream,
             double *timings_out, int32_t max_timings, int32_t *n_timings);
 
+/* ---- capture and replay (Section "Kernel Capturing") --------------------- */
+
+/* Capture launches: the first launch per problem size of each kernel named
+ * in the comma-separated list `kernels` ("advec_u", "diff_uvw", "step",
+ * "advec_u_2i5", "diff_smag"; NULL or "" switches capturing off) is written,
+ * before it runs, to <dir>/<kernel>_<dtype>_<itot>x<jtot>x<ktot>.klcap
+ * (dir NULL = "captures").  Without this call the environment variables
+ * KL_CAPTURE (the list) and KL_CAPTURE_DIR are read on the first launch.
+ * Capturing copies the launch's fields to the host and blocks the calling
+ * thread until the copy is done; it is meant for tuning runs. */
+int kl_set_capture(const char *kernels, const char *dir);
+
+/* Write one capture of `kernel` with these fields (as in kl_launch_variant),
+ * viscosity and time step to `path`.  File format: line 1 "KLCAP 1"; line 2
+ * a JSON header (kernel, kernel_id, dtype, problem_size, gc, off, jstride,
+ * kstride, dxi, dyi, bc, visc, dt, arrays = [{name, elems}], device
+ * provenance); then the arrays dzi, dzhi and the kernel's fields as raw
+ * elements of the field dtype.  Field arrays cover the cells from the first
+ * ghost cell (rounded down to a 128-byte line) to the last; "off" is
+ * relative to that base.  Synchronises `stream`. */
+int kl_capture(const kl_grid_t *g, int32_t kernel, void *const fields[6], double visc, double dt,
+               const char *path, void *stream);
+
+/* Host-only: copy the JSON header of a capture file into header
+ * (NUL-terminated, truncated to len).  KL_ERR_IO if unreadable,
+ * KL_ERR_INVALID if it is not a capture. */
+int kl_capture_info(const char *path, char *header, size_t len);
+
+/* Replay a capture for tuning: upload its metrics and fields to library-
+ * allocated device buffers, run kl_tune for its kernel on them (each
+ * configuration checked bitwise against the default, timed, the fastest
+ * appended to the wisdom file in wisdom_dir), free the buffers.  timings_out
+ * / max_timings / n_timings as in kl_tune.  Synchronous. */
+int kl_tune_capture(const char *path, const char *wisdom_dir, double budget_s, void *stream,
+                    double *timings_out, int32_t max_timings, int32_t *n_timings);
+
 /* ---- batched form: many independent grids in one captured graph ---------- */
 
 /* Build a batch of n grids (fields[6*g + f] = {u, v, w, ut, vt, wt} of grid

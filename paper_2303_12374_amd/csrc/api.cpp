@@ -215,6 +215,8 @@ int launch_selected(const kl_grid_t *g, int kernel, void *const *fields, double 
     if (!variant_eligible(vs[index], g, ptrs, nptr)) index = 0;
     if (!variant_eligible(vs[index], g, ptrs, nptr))
         return fail(KL_ERR_INVALID, "no configuration of %s fits this grid/alignment", kernel_name(kernel));
+    const int rc = maybe_capture(g, kernel, fields, visc, dt, s);
+    if (rc) return rc;
     return run_variant(g, kernel, index, fields, visc, s, dt);
 }
 

@@ -110,4 +110,8 @@ int run_variant(const kl_grid_t *g, int kernel, int index, void *const *fields, 
                 hipStream_t s, double dt = 0.0);
 void clear_plans();
 
+// Capture (capture.cpp): write the launch to a capture file if its kernel is
+// named in KL_CAPTURE / kl_set_capture and its problem size is new.
+int maybe_capture(const kl_grid_t *g, int kernel, void *const *fields, double visc, double dt, hipStream_t s);
+
 }  // namespace kl

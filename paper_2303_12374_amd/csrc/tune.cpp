@@ -28,10 +28,12 @@ struct Guard {
     }
 };
 
-int zero_tendencies(const kl_grid_t *g, void *const *f, hipStream_t s)
+// Zero the interiors of the outputs `kernel` accumulates into (ut; or ut, vt, wt).
+int zero_tendencies(const kl_grid_t *g, int kernel, void *const *f, hipStream_t s)
 {
     const HostArgs a = make_args(g);
-    for (int n = 3; n < 6; ++n) {
+    const int nout = kernel_nptr(kernel) == 4 ? 1 : 3;
+    for (int n = 3; n < 3 + nout; ++n) {
         const hipError_t e = launch_zero_interior(a, f[n], s);
         if (e != hipSuccess) return hip_fail(e, "zero tendencies");
     }
@@ -93,7 +95,7 @@ int tune_one(const kl_grid_t *g, int kernel, void *const *f, const std::string &
 
     // reference output of the default configuration
     uint64_t ref[3];
-    if ((rc = zero_tendencies(g, f, s))) return rc;
+    if ((rc = zero_tendencies(g, kernel, f, s))) return rc;
     if ((rc = run_variant(g, kernel, 0, f, visc, s, dt))) return rc;
     if ((rc = output_hashes(g, kernel, f, gd.dhash, ref, s))) return rc;
 
@@ -118,7 +120,7 @@ int tune_one(const kl_grid_t *g, int kernel, void *const *f, const std::string &
         if (!variant_eligible(vs[idx], g, ptrs, nptr)) continue;
         double ms = -1.0;
         uint64_t h[3];
-        if ((rc = zero_tendencies(g, f, s))) return rc;
+        if ((rc = zero_tendencies(g, kernel, f, s))) return rc;
         if ((rc = run_variant(g, kernel, idx, f, visc, s, dt))) return rc;
         if ((rc = output_hashes(g, kernel, f, gd.dhash, h, s))) return rc;
         if (h[0] == ref[0] && h[1] == ref[1] && h[2] == ref[2]) {

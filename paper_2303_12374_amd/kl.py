@@ -101,6 +101,11 @@ _sig = {
                                  c_int32, c_char_p, c_size_t, POINTER(c_int32)]),
     "kl_tune": (c_int, [_G, POINTER(c_void_p), c_uint32, c_char_p, c_double, c_void_p,
                         POINTER(c_double), c_int32, POINTER(c_int32)]),
+    "kl_set_capture": (c_int, [c_char_p, c_char_p]),
+    "kl_capture": (c_int, [_G, c_int32, POINTER(c_void_p), c_double, c_double, c_char_p, c_void_p]),
+    "kl_capture_info": (c_int, [c_char_p, c_char_p, c_size_t]),
+    "kl_tune_capture": (c_int, [c_char_p, c_char_p, c_double, c_void_p, POINTER(c_double), c_int32,
+                                POINTER(c_int32)]),
     "kl_batch_create": (c_int, [_G, POINTER(c_void_p), c_int32, c_double, c_int32, c_void_p,
                                 POINTER(c_void_p)]),
     "kl_batch_run": (c_int, [c_void_p, c_void_p]),
@@ -281,6 +286,45 @@ def kl_tune(g, fields, kernel_mask, wisdom_dir=None, budget_s=60.0, stream=None,
                         None if wisdom_dir is None else str(wisdom_dir).encode(), float(budget_s),
                         _stream(stream), out, max_timings, byref(n)))
     return [(int(out[2 * i]), out[2 * i + 1]) for i in range(n.value)]
+
+
+def kl_set_capture(kernels, directory=None):
+    """kernels: comma-separated kernel names, or None / "" to stop capturing."""
+    _check(_lib.kl_set_capture(None if not kernels else kernels.encode(),
+                               None if directory is None else str(directory).encode()))
+
+
+def kl_capture(g, kernel, fields, visc, dt, path, stream=None):
+    _check(_lib.kl_capture(byref(_cg(g)), kernel, _fields6(fields), float(visc), float(dt), str(path).encode(),
+                           _stream(stream)))
+
+
+def kl_capture_info(path) -> dict:
+    import json
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(_lib.kl_capture_info(str(path).encode(), buf, 1 << 16))
+    return json.loads(buf.value.decode())
+
+
+def kl_tune_capture(path, wisdom_dir=None, budget_s=60.0, stream=None, max_timings=512):
+    out = (c_double * (2 * max_timings))()
+    n = c_int32()
+    _check(_lib.kl_tune_capture(str(path).encode(), None if wisdom_dir is None else str(wisdom_dir).encode(),
+                                float(budget_s), _stream(stream), out, max_timings, byref(n)))
+    return [(int(out[2 * i]), out[2 * i + 1]) for i in range(n.value)]
+
+
+def read_capture(path):
+    """(header dict, {array name: numpy array}) of a capture file, read on the host."""
+    import json
+    with open(path, "rb") as f:
+        magic = f.readline()
+        if magic != b"KLCAP 1\n":
+            raise ValueError(f"{path} is not a KLCAP 1 file")
+        hdr = json.loads(f.readline().decode())
+        dt = np.float32 if hdr["dtype"] == "f32" else np.float64
+        arrays = {a["name"]: np.fromfile(f, dtype=dt, count=int(a["elems"])) for a in hdr["arrays"]}
+    return hdr, arrays
 
 
 def kl_batch_create(grids, fields, visc, zero_tendencies=True, stream=None):
