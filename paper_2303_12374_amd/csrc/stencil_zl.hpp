@@ -67,16 +67,25 @@ struct ZlTile {
 // ---------------------------------------------------------------------------
 // diff_uvw
 // ---------------------------------------------------------------------------
+// Field mask FM (bit f: field f of u, v, w is computed) and the LDS slot of a
+// computed field; FM = 7 is the whole kernel, single bits are the
+// per-component passes of the split configurations.
+__host__ __device__ constexpr int fslot(int fm, int f)
+{
+    return (f > 0 ? (fm & 1) : 0) + (f > 1 ? ((fm >> 1) & 1) : 0);
+}
+
 // One tile (tx, ty, tz) of diff_uvw; called by the single-grid kernel and by
 // the persistent batched kernel.  Starts with a barrier so that a block can
 // run tiles back to back on the same LDS.
-template <typename T, int VX, int BY, int KB, int NT>
+template <typename T, int VX, int BY, int KB, int NT, int FM = 7>
 __device__ __forceinline__ void diff_uvw_zl_tile(const StencilArgs<T> &a, int tx, int ty, int tz)
 {
     static_assert(BY >= 2, "two halo rows need two waves");
     constexpr int TX = 64 * VX;
     typedef T RowT[TX];
-    __shared__ __align__(16) RowT sh[2][3][BY + 2];
+    constexpr int NFL = (FM & 1) + ((FM >> 1) & 1) + ((FM >> 2) & 1);  // fields computed
+    __shared__ __align__(16) RowT sh[2][NFL][BY + 2];
     __syncthreads();
 
     const ZlTile<VX, BY, KB> t(a.itot, a.jtot, a.ktot, tx, ty, tz);
@@ -98,6 +107,7 @@ __device__ __forceinline__ void diff_uvw_zl_tile(const StencilArgs<T> &a, int tx
     T EL[2][3], ER[2][3]; // x edge values, by level parity
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
+        if (!((FM >> f) & 1)) continue;
 #pragma unroll
         for (int n = 0; n < VX; ++n) {
             R[0][f][n] = R[1][f][n] = R[2][f][n] = R[3][f][n] = T(0);
@@ -110,6 +120,7 @@ __device__ __forceinline__ void diff_uvw_zl_tile(const StencilArgs<T> &a, int tx
     // prologue: levels k0-1, k0, k0+1 (and the k0+2 prefetch) of the own row
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
+        if (!((FM >> f) & 1)) continue;
         if (ld_own) {
             vload<T, VX>(R[3][f], F[f] + c_own + (int64_t)(k0 - 1) * ks);
             vload<T, VX>(R[0][f], F[f] + c_own + (int64_t)k0 * ks);
@@ -134,6 +145,7 @@ __device__ __forceinline__ void diff_uvw_zl_tile(const StencilArgs<T> &a, int tx
                 // prefetch level k+1 of tendencies, halo row and edges
 #pragma unroll
                 for (int f = 0; f < 3; ++f) {
+        if (!((FM >> f) & 1)) continue;
                     if (k + 1 < k1) {
                         if (ld_own && (f < 2 || k + 1 >= kw0))
                             tload<NT, T, VX>(Q[q][f], Tt[f] + c_own + (int64_t)(k + 1) * ks);
@@ -145,16 +157,18 @@ __device__ __forceinline__ void diff_uvw_zl_tile(const StencilArgs<T> &a, int tx
                 // level k rows into LDS
 #pragma unroll
                 for (int f = 0; f < 3; ++f) {
-                    if (t.own) vstore<T, VX>(&sh[p][f][t.r + 1][t.lane * VX], c[f]);
-                    if (t.xrow_l >= 0) vstore<T, VX>(&sh[p][f][t.xrow_l][t.lane * VX], X[p][f]);
+        if (!((FM >> f) & 1)) continue;
+                    if (t.own) vstore<T, VX>(&sh[p][fslot(FM, f)][t.r + 1][t.lane * VX], c[f]);
+                    if (t.xrow_l >= 0) vstore<T, VX>(&sh[p][fslot(FM, f)][t.xrow_l][t.lane * VX], X[p][f]);
                 }
                 __syncthreads();
                 const T dzik = a.dzi[k], dzikm1 = a.dzi[k - 1], dzhik = a.dzhi[k], dzhik1 = a.dzhi[k + 1];
 #pragma unroll
                 for (int f = 0; f < 3; ++f) {
+        if (!((FM >> f) & 1)) continue;
                     T nn[VX], ss[VX];
-                    vload<T, VX>(nn, &sh[p][f][t.r + 2][t.lane * VX]);
-                    vload<T, VX>(ss, &sh[p][f][t.r][t.lane * VX]);
+                    vload<T, VX>(nn, &sh[p][fslot(FM, f)][t.r + 2][t.lane * VX]);
+                    vload<T, VX>(ss, &sh[p][fslot(FM, f)][t.r][t.lane * VX]);
                     T left = shfl_up1<T>(c[f][VX - 1]);
                     T right = shfl_down1<T>(c[f][0]);
                     if (t.lane == 0) left = EL[p][f];
@@ -176,7 +190,8 @@ __device__ __forceinline__ void diff_uvw_zl_tile(const StencilArgs<T> &a, int tx
                 // level k-1 is no longer needed: its slot takes the k+3 prefetch
 #pragma unroll
                 for (int f = 0; f < 3; ++f)
-                    if (ld_own && k + 3 <= k1) fload<NT, T, VX>(b[f], F[f] + c_own + (int64_t)(k + 3) * ks);
+                    if (((FM >> f) & 1) && ld_own && k + 3 <= k1)
+                        fload<NT, T, VX>(b[f], F[f] + c_own + (int64_t)(k + 3) * ks);
             }
         }
     }
@@ -335,12 +350,12 @@ __device__ __forceinline__ void advec_u_zl_tile(const StencilArgs<T> &a, int tx,
 
 // Single-grid kernels: one block per tile.  NT streams the tendency arrays;
 // WPE asks the compiler for at least that many waves per SIMD.
-template <typename T, int VX, int BY, int KB, int XCD, int NT = 0, int WPE = 1>
+template <typename T, int VX, int BY, int KB, int XCD, int NT = 0, int WPE = 1, int FM = 7>
 __global__ __launch_bounds__(64 * BY, WPE) void diff_uvw_zl(StencilArgs<T> a)
 {
     int tx, ty, tz;
     tile_of<64, BY, XCD>(a.nbx, a.nby, a.nbz, tx, ty, tz);
-    diff_uvw_zl_tile<T, VX, BY, KB, NT>(a, tx, ty, tz);
+    diff_uvw_zl_tile<T, VX, BY, KB, NT, FM>(a, tx, ty, tz);
 }
 
 template <typename T, int VX, int BY, int KB, int XCD, int NT = 0, int WPE = 1>

@@ -151,6 +151,24 @@ int step_batch_occupancy()
     return e == hipSuccess && n > 0 ? n : 1;
 }
 
+// diff_uvw as three single-component passes (u, then v, then w) of the LDS
+// z-march: the same values and arithmetic, three read/write streams in
+// flight at a time instead of nine.
+template <typename T, int VX, int BY, int KB, int XCD, int NT = 0>
+hipError_t launch_zl_split(const HostArgs &h, hipStream_t s)
+{
+    StencilArgs<T> a = device_args<T>(h);
+    a.nbx = (int)cdivu(h.itot, (int64_t)64 * VX);
+    a.nby = (int)cdivu(h.jtot, BY);
+    a.nbz = (int)cdivu(h.ktot, KB);
+    const uint64_t nb = (uint64_t)a.nbx * a.nby * a.nbz;
+    if (!grid_fits(nb, 64 * BY)) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((diff_uvw_zl<T, VX, BY, KB, XCD, NT, 1, 1>), dim3((unsigned)nb), dim3(64, BY), 0, s, a);
+    hipLaunchKernelGGL((diff_uvw_zl<T, VX, BY, KB, XCD, NT, 1, 2>), dim3((unsigned)nb), dim3(64, BY), 0, s, a);
+    hipLaunchKernelGGL((diff_uvw_zl<T, VX, BY, KB, XCD, NT, 1, 4>), dim3((unsigned)nb), dim3(64, BY), 0, s, a);
+    return hipGetLastError();
+}
+
 template <typename T, int VX, int BY, int KB, int XCD, int NT = 0, int WPE = 1>
 hipError_t launch_advec5_zl(const HostArgs &h, hipStream_t s)
 {
@@ -279,3 +297,9 @@ hipError_t launch_smag_zl(const HostArgs &h, hipStream_t s)
     Variant{"s2_v" KL_STR(VX) "_b64x" KL_STR(BY) "_k" KL_STR(KB) "_x" KL_STR(XCD) "_nt" KL_STR(NT),        \
             KL_KERNEL_DIFF_SMAG, DT, FAMILY_ZL, VX, 64, BY, KB, XCD,                                       \
             &launch_smag_zl<T, VX, BY, KB, XCD, NT>, nullptr, nullptr}
+
+// diff_uvw split into per-component passes, named zl3_v<VX>_b64x<BY>_k<KB>_x<XCD>_nt<NT>.
+#define KL_ZL3(T, DT, VX, BY, KB, XCD, NT)                                                                  \
+    Variant{"zl3_v" KL_STR(VX) "_b64x" KL_STR(BY) "_k" KL_STR(KB) "_x" KL_STR(XCD) "_nt" KL_STR(NT),       \
+            KL_KERNEL_DIFF_UVW, DT, FAMILY_ZL, VX, 64, BY, KB, XCD, &launch_zl_split<T, VX, BY, KB, XCD, NT>, \
+            nullptr, nullptr}

@@ -13,6 +13,7 @@ void add_variants_f32_step(std::vector<Variant> &out);
 void add_variants_f32_small(int kernel, std::vector<Variant> &out);
 void add_variants_f32_rev(int kernel, std::vector<Variant> &out);
 void add_variants_f32_les(int kernel, std::vector<Variant> &out);
+void add_variants_f32_split(std::vector<Variant> &out);
 
 static std::vector<Variant> build_f32(int kernel)
 {
@@ -41,6 +42,7 @@ static std::vector<Variant> build_f32(int kernel)
         add_variants_f32_nt(kernel, v);
         add_variants_f32_small(kernel, v);
         add_variants_f32_rev(kernel, v);
+        if (kernel == KL_KERNEL_DIFF_UVW) add_variants_f32_split(v);
     return v;
 }
 

@@ -3,6 +3,20 @@
 
 namespace kl {
 
+void add_variants_f32_split(std::vector<Variant> &out)
+{
+    static const std::vector<Variant> v = {
+        KL_ZL3(float, KL_F32, 4, 4, 128, 2, 1),
+        KL_ZL3(float, KL_F32, 4, 4, 256, 3, 1),
+        KL_ZL3(float, KL_F32, 4, 8, 64, 2, 1),
+        KL_ZL3(float, KL_F32, 4, 4, 64, 2, 1),
+        KL_ZL3(float, KL_F32, 2, 4, 128, 2, 1),
+        KL_ZL3(float, KL_F32, 2, 4, 256, 3, 1),
+        KL_ZL3(float, KL_F32, 2, 8, 64, 2, 1),
+        KL_ZL3(float, KL_F32, 2, 4, 64, 2, 1)};
+    out.insert(out.end(), v.begin(), v.end());
+}
+
 void add_variants_f32_les(int kernel, std::vector<Variant> &out)
 {
     if (kernel == KL_KERNEL_ADVEC_U_2I5) {

@@ -12,6 +12,7 @@ void add_variants_f64_step(std::vector<Variant> &out);
 void add_variants_f64_small(int kernel, std::vector<Variant> &out);
 void add_variants_f64_rev(int kernel, std::vector<Variant> &out);
 void add_variants_f64_les(int kernel, std::vector<Variant> &out);
+void add_variants_f64_split(std::vector<Variant> &out);
 
 static std::vector<Variant> build_f64(int kernel)
 {
@@ -39,6 +40,7 @@ static std::vector<Variant> build_f64(int kernel)
         add_variants_f64_nt(kernel, v);
         add_variants_f64_small(kernel, v);
         add_variants_f64_rev(kernel, v);
+        if (kernel == KL_KERNEL_DIFF_UVW) add_variants_f64_split(v);
     return v;
 }
 
