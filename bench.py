@@ -166,9 +166,11 @@ def served_trace(n=2000, seed=4, rate=None):
     return reqs
 
 
-def served_leg(kl, torch, wisdom, n_req=2000, budget_gib=8.0, load=0.8):
+def served_leg(kl, torch, wisdom, n_req=2000, budget_gib=8.0, load=0.8, sweep=(0.5, 1.0, 1.2)):
     """Continuous batching server on the Poisson trace versus serial plain
-    execution of the same trace; p50/p99 latency of (done - arrival)."""
+    execution of the same trace; p50/p99 latency of (done - arrival), at the
+    main offered load and at the loads of `sweep` (fractions of the served
+    capacity)."""
     import threading
     import numpy as np
     reqs = served_trace(n_req)
@@ -200,18 +202,28 @@ def served_leg(kl, torch, wisdom, n_req=2000, budget_gib=8.0, load=0.8):
     served_capacity = served_run(kl, torch, reqs[:400], np.zeros(400), budget_gib)["requests_per_s"]
     rate = load * served_capacity
     t_arr = np.cumsum([r["gap"] for r in reqs]) / rate
-    # serial plain execution of the trace (measured per request)
-    t_free, lat_serial, t0 = 0.0, [], None
-    for r, ta in zip(reqs, t_arr):
-        sh, dt = r["shape"], r["dtype"]
-        s = cost[(sh, dt)] * r["steps"]
-        start = max(ta, t_free)
-        t_free = start + s
-        lat_serial.append(t_free - ta)
-    serial_makespan = t_free
-    run = served_run(kl, torch, reqs, t_arr, budget_gib)
-    ls = np.array(lat_serial) * 1e3
     pts_steps = sum(r["shape"][0] * r["shape"][1] * r["shape"][2] * r["steps"] for r in reqs)
+
+    def serial(t_arr):
+        """Serial plain execution of the trace (measured per-request costs)."""
+        t_free, lat = 0.0, []
+        for r, ta in zip(reqs, t_arr):
+            start = max(ta, t_free)
+            t_free = start + cost[(r["shape"], r["dtype"])] * r["steps"]
+            lat.append(t_free - ta)
+        return np.array(lat) * 1e3, t_free
+
+    ls, serial_makespan = serial(t_arr)
+    run = served_run(kl, torch, reqs, t_arr, budget_gib)
+    sweep_out = []
+    for ld in sweep:
+        ta = np.cumsum([r["gap"] for r in reqs]) / (ld * served_capacity)
+        rr = served_run(kl, torch, reqs, ta, budget_gib)
+        sl, _ = serial(ta)
+        sweep_out.append({"load": ld, "p50_ms": rr["p50_ms"], "p99_ms": rr["p99_ms"],
+                          "grid_point_steps_per_s": rr["grid_point_steps_per_s"],
+                          "serial_plain_p50_ms": float(np.percentile(sl, 50)),
+                          "serial_plain_p99_ms": float(np.percentile(sl, 99))})
     return {"workload": f"{n_req} requests, Poisson (seed 4) at {load:.1f} x the served capacity, grids "
                         "{64^3,128^3,256^3,512x512x128}, 75% FP32, 1-10 steps, budget "
                         f"{budget_gib:g} GiB",
@@ -224,7 +236,8 @@ def served_leg(kl, torch, wisdom, n_req=2000, budget_gib=8.0, load=0.8):
                              "grid_point_steps_per_s": pts_steps / serial_makespan,
                              "makespan_s": serial_makespan,
                              "method": "each request's measured plain kl_step time x steps, queued serially "
-                                       "on the same arrival times"}}
+                                       "on the same arrival times"},
+            "load_sweep": sweep_out}
 
 
 def served_run(kl, torch, reqs, t_arr, budget_gib):
