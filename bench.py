@@ -26,17 +26,25 @@ sys.path.insert(0, ROOT)
 
 METRIC = "grid-points/s & HBM GB/s (% peak), advec_u+diff_uvw 512^3 FP32; p99 latency"
 PEAK_HBM_GBPS = 8000.0  # MI355X HBM3E, published
-KERNEL_SOURCES = ["paper_2303_12374_amd/csrc/stencil.hpp", "paper_2303_12374_amd/csrc/stencil_zl.hpp",
-                  "paper_2303_12374_amd/csrc/variants.hpp"]
+_CSRC = "paper_2303_12374_amd/csrc/"
+# device sources whose change invalidates a kernel's recorded counters
+KERNEL_SOURCES = {
+    "advec_u": [_CSRC + "stencil.hpp", _CSRC + "stencil_zl.hpp"],
+    "diff_uvw": [_CSRC + "stencil.hpp", _CSRC + "stencil_zl.hpp"],
+    "advec_u_2i5": [_CSRC + "stencil.hpp", _CSRC + "stencil_zl.hpp", _CSRC + "stencil_les.hpp",
+                    _CSRC + "stencil_les_zl.hpp"],
+    "diff_smag": [_CSRC + "stencil.hpp", _CSRC + "stencil_zl.hpp", _CSRC + "stencil_les.hpp",
+                  _CSRC + "stencil_les_zl.hpp"],
+}
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
+def kernel_source_hash(kernel_name):
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in KERNEL_SOURCES[kernel_name]:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -52,7 +60,7 @@ def load_traffic(kernel_name, workload_key, variant):
         with open(path) as f:
             data = json.load(f)
         rec = data.get(f"{kernel_name}:{workload_key}")
-        if not rec or rec.get("source_hash") != kernel_source_hash() or rec.get("variant") != variant:
+        if not rec or rec.get("source_hash") != kernel_source_hash(kernel_name) or rec.get("variant") != variant:
             return None
         return float(rec["hbm_bytes_per_launch"])
     except (OSError, ValueError, KeyError):
@@ -375,6 +383,7 @@ def les_leg(kl, torch, np, inputs, shape, host_fields, seed, steps):
     names = {n: kl.kl_variant_name(k, kl.F32, kl.kl_selected_variant(g, k))
              for n, k in (("advec_u_2i5", kl.ADVEC_U_2I5), ("diff_smag", kl.DIFF_SMAG))}
     b_adv, b_dif = 5 * 4 * npts, 10 * 4 * npts
+    wkey = f"{shape[0]}x{shape[1]}x{shape[2]}_f32"
     del dev, tend
     torch.cuda.empty_cache()
     return {"workload": f"advec_u_2i5+diff_smag {shape[0]}x{shape[1]}x{shape[2]} F32, same fields, "
@@ -384,10 +393,12 @@ def les_leg(kl, torch, np, inputs, shape, host_fields, seed, steps):
             "hbm_frac_of_peak": (b_adv + b_dif) / (pair * 1e6) / PEAK_HBM_GBPS,
             "kernels": {"advec_u_2i5": {"ms": adv, "gbps": b_adv / (adv * 1e6),
                                         "frac": b_adv / (adv * 1e6) / PEAK_HBM_GBPS,
-                                        "algorithmic_bytes_per_launch": b_adv},
+                                        "algorithmic_bytes_per_launch": b_adv,
+                                        "traffic": load_traffic("advec_u_2i5", wkey, names["advec_u_2i5"])},
                         "diff_smag": {"ms": dif, "gbps": b_dif / (dif * 1e6),
                                       "frac": b_dif / (dif * 1e6) / PEAK_HBM_GBPS,
-                                      "algorithmic_bytes_per_launch": b_dif}},
+                                      "algorithmic_bytes_per_launch": b_dif,
+                                      "traffic": load_traffic("diff_smag", wkey, names["diff_smag"])}},
             "configurations": names, "steps": steps}
 
 
@@ -460,7 +471,11 @@ def summarize_counters(fetch_csv, write_csv, workload_key, out_json, out_txt, co
         f_kib = statistics.median(fetch[k])
         w_kib = statistics.median(write[k])
         hbm = f_kib * 1024 * fs + w_kib * 1024 * ws
-        name = "advec_u" if "advec_u" in k else ("diff_uvw" if "diff_uvw" in k else None)
+        name = None
+        for cand in ("advec_u_2i5", "diff_smag", "advec_u", "diff_uvw"):   # longest names first
+            if f"kl::{cand}_" in k:
+                name = cand
+                break
         if name and f"<{elem}," not in k:
             name = None
         lines.append(f"| `{k[:90]}` | {len(fetch[k])} | {f_kib:.0f} | {w_kib:.0f} | {hbm:.4g} |")
@@ -508,11 +523,15 @@ def main():
         out, txt = summarize_counters(fetch_csv, write_csv, wkey, None, None, cmd,
                                       "float" if args.dtype == "f32" else "double")
         with open(bench_json) as f:
-            sel = json.loads([ln for ln in f if ln.startswith("{")][-1])["config"]["configurations"]
+            line = json.loads([ln for ln in f if ln.startswith("{")][-1])
+        sel = dict(line["config"]["configurations"])
+        sel.update((line.get("les") or {}).get("configurations", {}))
         path = os.path.join(ROOT, "profiles", "counters.json")
         old = json.load(open(path)) if os.path.exists(path) else {}
         for k, v in out.items():
-            v["source_hash"] = kernel_source_hash()
+            if k.split(":")[0] not in sel:
+                continue
+            v["source_hash"] = kernel_source_hash(k.split(":")[0])
             v["variant"] = sel[k.split(":")[0]]
             old[k] = v
         json.dump(old, open(path, "w"), indent=1)

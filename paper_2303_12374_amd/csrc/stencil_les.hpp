@@ -6,9 +6,10 @@
 //                 with a cell-center eddy viscosity nu (Smagorinsky-type
 //                 diffusion), second order on the staggered grid.
 //
-// The per-point arithmetic is written once, as functions of values, and
-// every configuration calls it with the same operands in the same order
-// (-ffp-contract=off), so all configurations agree bitwise.
+// The per-point arithmetic is written once, as functions of values (with
+// explicit fused multiply-adds), and every configuration calls it with the
+// same operands in the same order (-ffp-contract=off elsewhere), so all
+// configurations agree bitwise.
 #pragma once
 
 #include "stencil.hpp"
@@ -19,43 +20,38 @@ namespace kl {
 // fifth-order advection: face fluxes
 // ---------------------------------------------------------------------------
 
+// Fused multiply-add of the field type.  The face and stress functions below
+// are written with explicit fused operations (fewer instructions on a path
+// that is close to the ALU limit); every configuration calls the same
+// functions, so configurations still agree bitwise.
+__device__ __forceinline__ float tfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double tfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float tabs(float a) { return __builtin_fabsf(a); }
+__device__ __forceinline__ double tabs(double a) { return __builtin_fabs(a); }
+
 // Face between a0 and a1, advecting velocity U: U * c6 - |U| * d5 with the
-// sixth-order centered value c6 and the fifth-difference dissipation d5.
+// sixth-order centered value c6 and the fifth-difference dissipation d5,
+// c6 = (37 (a0+a1) - 8 (a-1+a2) + (a-2+a3)) / 60,
+// d5 = (10 (a1-a0) - 5 (a2-a-1) + (a3-a-2)) / 60.
 template <typename T>
 __device__ __forceinline__ T flux5(T U, T am2, T am1, T a0, T a1, T a2, T a3)
 {
-    const T r60 = T(1.0 / 60.0);
-    const T c6 = (T(37) * (a0 + a1) - T(8) * (am1 + a2) + (am2 + a3)) * r60;
-    const T d5 = (T(10) * (a1 - a0) - T(5) * (a2 - am1) + (a3 - am2)) * r60;
-    return U * c6 - __builtin_fabs(U) * d5;
+    const T c37 = T(37.0 / 60.0), c8 = T(-8.0 / 60.0), c1 = T(1.0 / 60.0);
+    const T c10 = T(10.0 / 60.0), c5 = T(-5.0 / 60.0);
+    const T c6 = tfma(c37, a0 + a1, tfma(c8, am1 + a2, c1 * (am2 + a3)));
+    const T d5 = tfma(c10, a1 - a0, tfma(c5, a2 - am1, c1 * (a3 - am2)));
+    return tfma(U, c6, -(tabs(U) * d5));
 }
 
-template <>
-__device__ __forceinline__ float flux5<float>(float U, float am2, float am1, float a0, float a1, float a2, float a3)
-{
-    const float r60 = 1.0f / 60.0f;
-    const float c6 = (37.0f * (a0 + a1) - 8.0f * (am1 + a2) + (am2 + a3)) * r60;
-    const float d5 = (10.0f * (a1 - a0) - 5.0f * (a2 - am1) + (a3 - am2)) * r60;
-    return U * c6 - __builtin_fabsf(U) * d5;
-}
-
-// Third-order upwind-biased face value times U.
+// Third-order upwind-biased face value times U:
+// c4 = (7 (a0+a1) - (a-1+a2)) / 12, d3 = (3 (a1-a0) - (a2-a-1)) / 12.
 template <typename T>
 __device__ __forceinline__ T flux3(T U, T am1, T a0, T a1, T a2)
 {
-    const T r12 = T(1.0 / 12.0);
-    const T c4 = (T(7) * (a0 + a1) - (am1 + a2)) * r12;
-    const T d3 = (T(3) * (a1 - a0) - (a2 - am1)) * r12;
-    return U * c4 - __builtin_fabs(U) * d3;
-}
-
-template <>
-__device__ __forceinline__ float flux3<float>(float U, float am1, float a0, float a1, float a2)
-{
-    const float r12 = 1.0f / 12.0f;
-    const float c4 = (7.0f * (a0 + a1) - (am1 + a2)) * r12;
-    const float d3 = (3.0f * (a1 - a0) - (a2 - am1)) * r12;
-    return U * c4 - __builtin_fabsf(U) * d3;
+    const T c7 = T(7.0 / 12.0), cm1 = T(-1.0 / 12.0), c3 = T(3.0 / 12.0);
+    const T c4 = tfma(c7, a0 + a1, cm1 * (am1 + a2));
+    const T d3 = tfma(c3, a1 - a0, cm1 * (a2 - am1));
+    return tfma(U, c4, -(tabs(U) * d3));
 }
 
 // Midpoint interpolation (also the advecting velocity at a face).
@@ -81,10 +77,8 @@ __device__ __forceinline__ T flux_z_2i5(T W, T a0, T a1, T a2, T a3, T a4, T a5,
 template <typename T>
 __device__ __forceinline__ T advec_2i5_combine(T fe, T fw, T fn, T fs, T ft, T fb, T dxi, T dyi, T dzik)
 {
-    const T adv_x = (fe - fw) * dxi;
-    const T adv_y = (fn - fs) * dyi;
-    const T adv_z = (ft - fb) * dzik;
-    return -(adv_x + adv_y + adv_z);
+    const T adv_xy = tfma(fe - fw, dxi, (fn - fs) * dyi);
+    return -tfma(ft - fb, dzik, adv_xy);
 }
 
 // ---------------------------------------------------------------------------
@@ -96,7 +90,7 @@ __device__ __forceinline__ T advec_2i5_combine(T fe, T fw, T fn, T fs, T ft, T f
 template <typename T>
 __device__ __forceinline__ T mean4(T a, T b, T c, T d)
 {
-    return T(0.25) * (a + b + c + d);
+    return T(0.25) * ((a + b) + (c + d));
 }
 
 // u at (xh_i, y_j, z_k).  v_n/v_nw: v(i, j+1), v(i-1, j+1); v_c/v_w: v(i, j),
@@ -108,13 +102,15 @@ __device__ __forceinline__ T smag_u(T uc, T ue, T uw, T un, T us, T ut, T ub,
                                     T e_c, T e_w, T e_n, T e_nw, T e_s, T e_sw, T e_t, T e_tw, T e_b, T e_bw,
                                     T dxi, T dyi, T dzik, T dzhik, T dzhik1)
 {
-    const T tx = (e_c * (ue - uc) - e_w * (uc - uw)) * (T(2) * dxi * dxi);
+    const T tx = tfma(e_c, ue - uc, -(e_w * (uc - uw))) * (T(2) * dxi * dxi);
     const T en = mean4(e_w, e_c, e_nw, e_n);
     const T es = mean4(e_sw, e_s, e_w, e_c);
-    const T ty = (en * ((un - uc) * dyi + (v_n - v_nw) * dxi) - es * ((uc - us) * dyi + (v_c - v_w) * dxi)) * dyi;
+    const T gn = tfma(un - uc, dyi, (v_n - v_nw) * dxi), gs = tfma(uc - us, dyi, (v_c - v_w) * dxi);
+    const T ty = tfma(en, gn, -(es * gs)) * dyi;
     const T et = mean4(e_w, e_c, e_tw, e_t);
     const T eb = mean4(e_bw, e_b, e_w, e_c);
-    const T tz = (et * ((ut - uc) * dzhik1 + (w_t - w_tw) * dxi) - eb * ((uc - ub) * dzhik + (w_c - w_w) * dxi)) * dzik;
+    const T gt = tfma(ut - uc, dzhik1, (w_t - w_tw) * dxi), gb = tfma(uc - ub, dzhik, (w_c - w_w) * dxi);
+    const T tz = tfma(et, gt, -(eb * gb)) * dzik;
     return tx + ty + tz;
 }
 
@@ -129,11 +125,13 @@ __device__ __forceinline__ T smag_v(T vc, T ve, T vw, T vn, T vs, T vt, T vb,
 {
     const T ee = mean4(e_s, e_se, e_c, e_e);
     const T ew = mean4(e_sw, e_s, e_w, e_c);
-    const T tx = (ee * ((ve - vc) * dxi + (u_e - u_se) * dyi) - ew * ((vc - vw) * dxi + (u_c - u_s) * dyi)) * dxi;
-    const T ty = (e_c * (vn - vc) - e_s * (vc - vs)) * (T(2) * dyi * dyi);
+    const T ge = tfma(ve - vc, dxi, (u_e - u_se) * dyi), gw = tfma(vc - vw, dxi, (u_c - u_s) * dyi);
+    const T tx = tfma(ee, ge, -(ew * gw)) * dxi;
+    const T ty = tfma(e_c, vn - vc, -(e_s * (vc - vs))) * (T(2) * dyi * dyi);
     const T et = mean4(e_s, e_c, e_ts, e_t);
     const T eb = mean4(e_bs, e_b, e_s, e_c);
-    const T tz = (et * ((vt - vc) * dzhik1 + (w_t - w_ts) * dyi) - eb * ((vc - vb) * dzhik + (w_c - w_s) * dyi)) * dzik;
+    const T gt = tfma(vt - vc, dzhik1, (w_t - w_ts) * dyi), gb = tfma(vc - vb, dzhik, (w_c - w_s) * dyi);
+    const T tz = tfma(et, gt, -(eb * gb)) * dzik;
     return tx + ty + tz;
 }
 
@@ -148,11 +146,13 @@ __device__ __forceinline__ T smag_w(T wc, T we, T ww, T wn, T ws, T wt, T wb,
 {
     const T ee = mean4(e_b, e_be, e_c, e_e);
     const T ew = mean4(e_bw, e_b, e_w, e_c);
-    const T tx = (ee * ((we - wc) * dxi + (u_e - u_be) * dzhik) - ew * ((wc - ww) * dxi + (u_c - u_b) * dzhik)) * dxi;
+    const T ge = tfma(we - wc, dxi, (u_e - u_be) * dzhik), gw = tfma(wc - ww, dxi, (u_c - u_b) * dzhik);
+    const T tx = tfma(ee, ge, -(ew * gw)) * dxi;
     const T en = mean4(e_b, e_bn, e_c, e_n);
     const T es = mean4(e_bs, e_b, e_s, e_c);
-    const T ty = (en * ((wn - wc) * dyi + (v_n - v_bn) * dzhik) - es * ((wc - ws) * dyi + (v_c - v_b) * dzhik)) * dyi;
-    const T tz = (e_c * (wt - wc) * dzik - e_b * (wc - wb) * dzikm1) * (T(2) * dzhik);
+    const T gn = tfma(wn - wc, dyi, (v_n - v_bn) * dzhik), gs = tfma(wc - ws, dyi, (v_c - v_b) * dzhik);
+    const T ty = tfma(en, gn, -(es * gs)) * dyi;
+    const T tz = tfma(e_c * (wt - wc), dzik, -(e_b * (wc - wb) * dzikm1)) * (T(2) * dzhik);
     return tx + ty + tz;
 }
 
