@@ -21,6 +21,8 @@
 // results equal the default configuration's bitwise.
 #pragma once
 
+#include <type_traits>
+
 #include "stencil_les.hpp"
 #include "stencil_zl.hpp"
 
@@ -278,6 +280,238 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zl(StencilArgs<T> a)
     }
 }
 
+// The same tile with the z-march unrolled by pairs of levels: the two
+// register slots and the two LDS planes alternate with compile-time indices
+// and the u window moves two levels at a time, so no per-level register
+// copies remain (more live registers, fewer instructions).
+template <typename T, int VX, int BY, int KB, int XCD, int NT, int WPE>
+__global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zlp(StencilArgs<T> a)
+{
+    constexpr int TX = 64 * VX;
+    constexpr int SW = TX + 6;               // u row in LDS: columns i0w-3 .. i0w+TX+2
+    constexpr int VW = TX + 1;               // v row in LDS: columns i0w-1 .. i0w+TX-1
+    constexpr int NH = (6 + BY - 1) / BY;    // u halo rows per wave (upper bound)
+    __shared__ __align__(16) T su[2][BY + 6][SW];
+    __shared__ __align__(16) T sv[2][BY + 1][VW];
+
+    int tx, ty, tz;
+    tile_of<64, BY, XCD>(a.nbx, a.nby, a.nbz, tx, ty, tz);
+    const int lane = (int)threadIdx.x, r = (int)threadIdx.y;
+    const int i0w = 1 + tx * TX;
+    const int nlanes = min(64, (a.itot - i0w + 1) / VX);
+    const bool lane_on = lane < nlanes;
+    const int xo = lane * VX;
+    const bool edge_l = lane == 0, edge_r = lane == nlanes - 1;
+    const int j0 = 1 + ty * BY;
+    const int nv = min(BY, a.jtot - j0 + 1);
+    const bool own = r < nv;
+    const int k0 = 1 + tz * KB, k1 = min(k0 + KB, a.ktot + 1);
+    const int kt = a.ktot;
+    const int64_t js = a.js, ks = a.ks;
+    const T *u = a.u, *v = a.v, *w = a.w;
+    T *ut = a.ut;
+    const T dxi = a.dxi, dyi = a.dyi;
+
+    // level-0 addresses of this lane's points in the own row and the halo rows
+    const int64_t row0 = a.off + i0w + xo;
+    const int64_t c_own = row0 + (int64_t)(j0 + r) * js;
+    const int64_t e_own = a.off + i0w + (int64_t)(j0 + r) * js;           // (i0w, j0 + r, 0)
+    const int iend = i0w + nlanes * VX - 1;                               // last point of the tile
+    int hrho[NH];   // LDS rows of this wave's u halo rows, -1 if none
+    int64_t hc[NH], he[NH];
+#pragma unroll
+    for (int m = 0; m < NH; ++m) {
+        const int h = r + m * BY;
+        hrho[m] = h < 6 ? (h < 3 ? h : nv + h) : -1;
+        const int jg = j0 - 3 + (hrho[m] < 0 ? 3 : hrho[m]);
+        hc[m] = row0 + (int64_t)jg * js;
+        he[m] = a.off + i0w + (int64_t)jg * js;
+    }
+    const bool vhalo = r == BY - 1;                                       // loads v row j0 + nv
+    const int64_t c_vh = row0 + (int64_t)(j0 + nv) * js;
+    const int64_t e_vh = a.off + i0w + (int64_t)(j0 + nv) * js;
+
+    // registers, in two slots used in turn by the two levels of a pair: what
+    // the LDS planes receive, the w row at k+1, ut at k
+    T S[9][VX];                              // u(k-2) .. u(k+6) of the own column, k = even level of a pair
+    T HU[2][NH][VX], HUL[2][NH][3], HUR[2][NH][3];
+    T OUL[2][3], OUR[2][3];                  // x halo of the own u row
+    T VO[2][VX], VOL[2];                     // own v row and its left halo cell
+    T VH[2][VX], VHL[2];                     // v halo row and its left halo cell
+    T WR[2][VX], WL[2];                      // w at k+1, left neighbour cell (lane 0)
+    T UT[2][VX];
+
+    auto load_level = [&](auto qc, int k) {  // everything level k needs, into slot q
+        constexpr int q = decltype(qc)::value;
+#pragma unroll
+        for (int m = 0; m < NH; ++m) {
+            const bool on = hrho[m] >= 0;
+            if (on && lane_on) vload<T, VX>(HU[q][m], u + hc[m] + (int64_t)k * ks);
+            if (on && edge_l) {
+#pragma unroll
+                for (int e = 0; e < 3; ++e) HUL[q][m][e] = u[he[m] + (int64_t)k * ks - 3 + e];
+            }
+            if (on && edge_r) {
+#pragma unroll
+                for (int e = 0; e < 3; ++e) HUR[q][m][e] = u[he[m] + (iend - i0w) + (int64_t)k * ks + 1 + e];
+            }
+        }
+        if (own) {
+            if (edge_l) {
+#pragma unroll
+                for (int e = 0; e < 3; ++e) OUL[q][e] = u[e_own + (int64_t)k * ks - 3 + e];
+                VOL[q] = v[e_own + (int64_t)k * ks - 1];
+            }
+            if (edge_r) {
+#pragma unroll
+                for (int e = 0; e < 3; ++e) OUR[q][e] = u[e_own + (iend - i0w) + (int64_t)k * ks + 1 + e];
+            }
+            if (lane_on) {
+                vload<T, VX>(VO[q], v + c_own + (int64_t)k * ks);
+                vload<T, VX>(WR[q], w + c_own + (int64_t)(k + 1) * ks);
+                tload<NT, T, VX>(UT[q], ut + c_own + (int64_t)k * ks);
+            }
+            if (edge_l) WL[q] = w[e_own + (int64_t)(k + 1) * ks - 1];
+        }
+        if (vhalo) {
+            if (lane_on) vload<T, VX>(VH[q], v + c_vh + (int64_t)k * ks);
+            if (edge_l) VHL[q] = v[e_vh + (int64_t)k * ks - 1];
+        }
+    };
+
+    // prologue: the u window, the flux through face k0, level k0's data
+#pragma unroll
+    for (int m = 0; m < 7; ++m) col_load<T, VX>(S[m], u + c_own, ks, k0 - 2 + m, kt, own && lane_on);
+#pragma unroll
+    for (int n = 0; n < VX; ++n) S[7][n] = S[8][n] = T(0);
+    T FB[VX];
+    {
+        T ub3[VX], w0[VX];
+        col_load<T, VX>(ub3, u + c_own, ks, k0 - 3, kt, own && lane_on);
+        col_load<T, VX>(w0, w + c_own, ks, k0, kt, own && lane_on);
+        T wl0 = (own && edge_l) ? w[e_own + (int64_t)k0 * ks - 1] : T(0);
+        const T sh = shfl_up1(w0[VX - 1]);
+        if (!edge_l) wl0 = sh;
+#pragma unroll
+        for (int n = 0; n < VX; ++n) {
+            const T wm = n == 0 ? wl0 : w0[n - 1];
+            FB[n] = flux_z_2i5(mid(wm, w0[n]), ub3[n], S[0][n], S[1][n], S[2][n], S[3][n], S[4][n], k0, kt);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+#pragma unroll
+        for (int n = 0; n < VX; ++n) VO[q][n] = VH[q][n] = WR[q][n] = UT[q][n] = T(0);
+#pragma unroll
+        for (int m = 0; m < NH; ++m) {
+#pragma unroll
+            for (int n = 0; n < VX; ++n) HU[q][m][n] = T(0);
+#pragma unroll
+            for (int e = 0; e < 3; ++e) HUL[q][m][e] = HUR[q][m][e] = T(0);
+        }
+#pragma unroll
+        for (int e = 0; e < 3; ++e) OUL[q][e] = OUR[q][e] = T(0);
+        VOL[q] = VHL[q] = WL[q] = T(0);
+    }
+    load_level(std::integral_constant<int, 0>(), k0);
+
+    // One level; P is its position in the pair (LDS plane P, register slot
+    // P, u window offset P).
+    auto level = [&](auto pc, int k) {
+        constexpr int P = decltype(pc)::value;
+        constexpr int Q = P ^ 1;
+        // 1. level k into LDS plane P
+        if (own && lane_on) {
+#pragma unroll
+            for (int n = 0; n < VX; ++n) {
+                su[P][r + 3][3 + xo + n] = S[2 + P][n];
+                sv[P][r][1 + xo + n] = VO[P][n];
+            }
+        }
+        if (own && edge_l) {
+#pragma unroll
+            for (int e = 0; e < 3; ++e) su[P][r + 3][e] = OUL[P][e];
+            sv[P][r][0] = VOL[P];
+        }
+        if (own && edge_r) {
+#pragma unroll
+            for (int e = 0; e < 3; ++e) su[P][r + 3][3 + nlanes * VX + e] = OUR[P][e];
+        }
+#pragma unroll
+        for (int m = 0; m < NH; ++m) {
+            const int rho = hrho[m];
+            if (rho >= 0) {
+                if (lane_on) {
+#pragma unroll
+                    for (int n = 0; n < VX; ++n) su[P][rho][3 + xo + n] = HU[P][m][n];
+                }
+                if (edge_l) {
+#pragma unroll
+                    for (int e = 0; e < 3; ++e) su[P][rho][e] = HUL[P][m][e];
+                }
+                if (edge_r) {
+#pragma unroll
+                    for (int e = 0; e < 3; ++e) su[P][rho][3 + nlanes * VX + e] = HUR[P][m][e];
+                }
+            }
+        }
+        if (vhalo) {
+            if (lane_on) {
+#pragma unroll
+                for (int n = 0; n < VX; ++n) sv[P][nv][1 + xo + n] = VH[P][n];
+            }
+            if (edge_l) sv[P][nv][0] = VHL[P];
+        }
+        // 2. prefetch level k+1 into the other slot and the u window's k+5
+        if (k + 1 < k1) load_level(std::integral_constant<int, Q>(), k + 1);
+        col_load<T, VX>(S[7 + P], u + c_own, ks, k + 5, kt, own && lane_on && k + 1 < k1);
+        __syncthreads();
+
+        // 3. compute level k from plane P and the window S[P .. P+5]
+        const T sh = shfl_up1(WR[P][VX - 1]);
+        const T wl = edge_l ? WL[P] : sh;
+        if (own && lane_on) {
+            T uxr[VX + 6];
+#pragma unroll
+            for (int m = 0; m < VX + 6; ++m) uxr[m] = su[P][r + 3][xo + m];
+            T FX[VX + 1];
+#pragma unroll
+            for (int f = 0; f <= VX; ++f)
+                FX[f] = flux5(mid(uxr[f + 2], uxr[f + 3]), uxr[f], uxr[f + 1], uxr[f + 2], uxr[f + 3],
+                              uxr[f + 4], uxr[f + 5]);
+            const T dzik = a.dzi[k];
+            T res[VX];
+#pragma unroll
+            for (int n = 0; n < VX; ++n) {
+                const int x = 3 + xo + n;
+                T col[7];
+#pragma unroll
+                for (int m = 0; m < 7; ++m) col[m] = su[P][r + m][x];
+                const T vn = mid(sv[P][r + 1][xo + n], sv[P][r + 1][xo + n + 1]);
+                const T vs = mid(sv[P][r][xo + n], sv[P][r][xo + n + 1]);
+                const T fn = flux5(vn, col[1], col[2], col[3], col[4], col[5], col[6]);
+                const T fs = flux5(vs, col[0], col[1], col[2], col[3], col[4], col[5]);
+                const T wm = n == 0 ? wl : WR[P][n - 1];
+                const T ft = flux_z_2i5(mid(wm, WR[P][n]), S[P][n], S[P + 1][n], S[P + 2][n], S[P + 3][n],
+                                        S[P + 4][n], S[P + 5][n], k + 1, kt);
+                res[n] = UT[P][n] + advec_2i5_combine(FX[n + 1], FX[n], fn, fs, ft, FB[n], dxi, dyi, dzik);
+                FB[n] = ft;
+            }
+            tstore<NT, T, VX>(ut + c_own + (int64_t)k * ks, res);
+        }
+    };
+
+    for (int k = k0; k < k1; k += 2) {
+        level(std::integral_constant<int, 0>(), k);
+        if (k + 1 < k1) level(std::integral_constant<int, 1>(), k + 1);
+        // the window moves two levels
+#pragma unroll
+        for (int m = 0; m < 7; ++m)
+#pragma unroll
+            for (int n = 0; n < VX; ++n) S[m][n] = S[m + 2][n];
+    }
+}
+
 }  // namespace kl
 
 namespace kl {
@@ -356,7 +590,8 @@ __global__ __launch_bounds__(64 * BY, WPE) void diff_smag_zl(StencilArgs<T> a)
 #pragma unroll
         for (int m = 0; m < NH; ++m) {
             if (hf[m] < 0) continue;
-            const T *p = F[hf[m]];
+            // a select, not an indexed pointer array, keeps these global loads
+            const T *p = hf[m] == 0 ? a.u : (hf[m] == 1 ? a.v : (hf[m] == 2 ? a.w : a.evisc));
             if (lane_on) vload<T, VX>(H[q][m], p + hc[m] + (int64_t)l * ks);
             if (edge_l) HL[q][m] = p[he[m] + (int64_t)l * ks - 1];
             if (edge_r) HR[q][m] = p[he[m] + (int64_t)l * ks + nlanes * VX];

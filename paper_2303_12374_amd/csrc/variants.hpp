@@ -169,7 +169,7 @@ hipError_t launch_zl_split(const HostArgs &h, hipStream_t s)
     return hipGetLastError();
 }
 
-template <typename T, int VX, int BY, int KB, int XCD, int NT = 0, int WPE = 1>
+template <typename T, int VX, int BY, int KB, int XCD, int NT = 0, int WPE = 1, int PAIR = 0>
 hipError_t launch_advec5_zl(const HostArgs &h, hipStream_t s)
 {
     StencilArgs<T> a = device_args<T>(h);
@@ -178,7 +178,10 @@ hipError_t launch_advec5_zl(const HostArgs &h, hipStream_t s)
     a.nbz = (int)cdivu(h.ktot, KB);
     const uint64_t nb = (uint64_t)a.nbx * a.nby * a.nbz;
     if (!grid_fits(nb, 64 * BY)) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((advec_u_2i5_zl<T, VX, BY, KB, XCD, NT, WPE>), dim3((unsigned)nb), dim3(64, BY), 0, s, a);
+    if (PAIR)
+        hipLaunchKernelGGL((advec_u_2i5_zlp<T, VX, BY, KB, XCD, NT, WPE>), dim3((unsigned)nb), dim3(64, BY), 0, s, a);
+    else
+        hipLaunchKernelGGL((advec_u_2i5_zl<T, VX, BY, KB, XCD, NT, WPE>), dim3((unsigned)nb), dim3(64, BY), 0, s, a);
     return hipGetLastError();
 }
 
@@ -287,6 +290,12 @@ hipError_t launch_smag_zl(const HostArgs &h, hipStream_t s)
         KL_ZLX(T, DT, KERN, VX, 8, 8, 0, 0, 1), KL_ZLX(T, DT, KERN, VX, 8, 16, 0, 1, 1)
 
 // advec_u_2i5 LDS z-march configurations, named a5_v<VX>_b64x<BY>_k<KB>_x<XCD>_nt<NT>.
+// The pair-unrolled march, named a5p_...
+#define KL_A5P(T, DT, VX, BY, KB, XCD, NT)                                                                  \
+    Variant{"a5p_v" KL_STR(VX) "_b64x" KL_STR(BY) "_k" KL_STR(KB) "_x" KL_STR(XCD) "_nt" KL_STR(NT),       \
+            KL_KERNEL_ADVEC_U_2I5, DT, FAMILY_ZL, VX, 64, BY, KB, XCD,                                     \
+            &launch_advec5_zl<T, VX, BY, KB, XCD, NT, 1, 1>, nullptr, nullptr}
+
 #define KL_A5(T, DT, VX, BY, KB, XCD, NT)                                                                   \
     Variant{"a5_v" KL_STR(VX) "_b64x" KL_STR(BY) "_k" KL_STR(KB) "_x" KL_STR(XCD) "_nt" KL_STR(NT),        \
             KL_KERNEL_ADVEC_U_2I5, DT, FAMILY_ZL, VX, 64, BY, KB, XCD,                                     \

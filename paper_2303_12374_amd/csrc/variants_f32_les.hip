@@ -21,6 +21,12 @@ void add_variants_f32_les(int kernel, std::vector<Variant> &out)
 {
     if (kernel == KL_KERNEL_ADVEC_U_2I5) {
         static const std::vector<Variant> v = {
+        KL_A5P(float, KL_F32, 2, 8, 64, 2, 1),
+        KL_A5P(float, KL_F32, 2, 4, 64, 2, 1),
+        KL_A5P(float, KL_F32, 1, 8, 64, 2, 1),
+        KL_A5P(float, KL_F32, 1, 16, 64, 2, 1),
+        KL_A5P(float, KL_F32, 2, 8, 128, 2, 1),
+        KL_A5P(float, KL_F32, 4, 4, 64, 2, 1),
         KL_A5(float, KL_F32, 4, 4, 64, 2, 1),
         KL_A5(float, KL_F32, 4, 4, 128, 2, 1),
         KL_A5(float, KL_F32, 4, 8, 64, 2, 1),
