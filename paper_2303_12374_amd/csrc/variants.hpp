@@ -284,6 +284,12 @@ hipError_t launch_smag_zl(const HostArgs &h, hipStream_t s)
         KL_ZLX(T, DT, KERN, VX, 4, 256, 3, 1, 1), KL_ZLX(T, DT, KERN, VX, 8, 32, 3, 1, 1),             \
         KL_ZLX(T, DT, KERN, VX, 8, 128, 3, 1, 1), KL_ZLX(T, DT, KERN, VX, 4, 128, 3, 0, 1)
 
+// Waves-per-SIMD floors of 3 and 4 on the top-down slab configurations
+// (fewer registers, more waves in flight).
+#define KL_OCC_SET(T, DT, KERN, VX)                                                                     \
+    KL_ZLX(T, DT, KERN, VX, 4, 256, 3, 1, 3), KL_ZLX(T, DT, KERN, VX, 4, 256, 3, 1, 4),                \
+        KL_ZLX(T, DT, KERN, VX, 4, 128, 3, 1, 3), KL_ZLX(T, DT, KERN, VX, 4, 64, 3, 1, 4)
+
 // Short z-marches for small grids (more tiles, shorter chains).
 #define KL_SMALL_SET(T, DT, KERN, VX)                                                                   \
     KL_ZLX(T, DT, KERN, VX, 4, 8, 0, 0, 1), KL_ZLX(T, DT, KERN, VX, 4, 16, 0, 0, 1),                   \

@@ -55,7 +55,8 @@ def tune_shape(kl, shape, dtype, wisdom, budget, bc=0, log=None, kernels=KERNELS
         best_ms, best = min(ok)
         default_ms = dict((i, ms) for i, ms in res).get(0, float("nan"))
         out[name] = {"best": kl.kl_variant_name(kern, dtype, best), "ms": best_ms, "default_ms": default_ms,
-                     "evaluated": len(res), "bitwise_failures": len(res) - len(ok), "seconds": time.time() - t0}
+                     "evaluated": len(res), "bitwise_failures": len(res) - len(ok), "seconds": time.time() - t0,
+                     "times_ms": {kl.kl_variant_name(kern, dtype, i): ms for i, ms in res}}
         if log:
             log(f"{name} {'x'.join(map(str, shape))} {'f32' if dtype == kl.F32 else 'f64'}: "
                 f"{out[name]['best']} {best_ms:.4f} ms (default {default_ms:.4f} ms, "
