@@ -117,6 +117,30 @@ def test_les_tendencies_match_oracle(dtype, bc, shape):
         assert np.all(t.cpu().numpy()[mask] == sentinel), f"{name}: wrote outside the interior"
 
 
+@pytest.mark.parametrize("shape", [(37, 23, 19), (64, 16, 8)], ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("dtype", [0, 1], ids=["f32", "f64"])
+def test_les_unpadded_layout(dtype, shape):
+    """The schemes on an unpadded layout (rows of itot+6 cells, no line
+    alignment): every configuration that is eligible there (the default one
+    at least) matches the oracle."""
+    m = kl()
+    lay = inputs.plain_layout(*shape, gh=3)
+    c = LesCase(*shape, dtype, bc=0, seed=41, layout=lay)
+    g = c.g
+    ref = [c.oracle_advec()] + c.oracle_smag()
+    for kernel, nout in ((m.ADVEC_U_2I5, 1), (m.DIFF_SMAG, 3)):
+        for idx in range(m.kl_num_variants(kernel, dtype)):
+            outs = [g.zeros_interior(fill=0.0) for _ in range(3)]
+            fields = c.dev[:3] + outs + ([c.dev[3]] if kernel == m.DIFF_SMAG else [])
+            if not m.kl_variant_eligible(g, kernel, idx, fields):
+                continue
+            m.kl_launch_variant(g, kernel, idx, fields)
+            r = ref[:1] if nout == 1 else ref[1:]
+            for q in range(nout):
+                err = rel_err(c.gpu_interior(outs[q]), r[q])
+                assert err <= TOL[dtype], f"{m.kl_variant_name(kernel, dtype, idx)} output {q}: {err:.3e}"
+
+
 @pytest.mark.parametrize("dtype", [0, 1], ids=["f32", "f64"])
 def test_les_tendencies_accumulate(dtype):
     m = kl()
