@@ -166,6 +166,29 @@ __device__ __forceinline__ void tstore(T *p, const T (&s)[N])
     if constexpr (NT) vstore_nt<T, N>(p, s); else vstore<T, N>(p, s);
 }
 
+// A read of a vertical metric (dzi, dzhi) at a wave-uniform level k.  The
+// metrics are never written while a kernel runs, so they are read through the
+// constant address space: the load is a scalar-memory read, counted apart
+// from the vector loads of the fields, and waiting for it does not also wait
+// for the prefetched levels in flight.
+template <typename T>
+__device__ __forceinline__ T kload(const T *p, int k)
+{
+    typedef __attribute__((address_space(4))) const T CT;
+    return reinterpret_cast<CT *>(reinterpret_cast<uintptr_t>(p))[k];
+}
+
+// Wait for every outstanding vector-memory load of this wave (s_waitcnt with
+// vmcnt = 0 and the export and LDS counters left at their maxima; GFX9
+// encoding: vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8).  Called
+// once at the end of a z-march prologue: the loop is then entered with no
+// load in flight, so the compiler's wait placement inside the loop need not
+// allow for the prologue's loads still being outstanding on the first pass.
+__device__ __forceinline__ void vm_drain()
+{
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+}
+
 // Field load: cached, or streaming when NT >= 2.
 template <int NT, typename T, int N>
 __device__ __forceinline__ void fload(T (&d)[N], const T *p)

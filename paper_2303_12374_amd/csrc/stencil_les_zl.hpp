@@ -163,6 +163,7 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zl(StencilArgs<T> a)
     }
     load_level(0, k0);
 
+    vm_drain();
     for (int k = k0; k < k1; ++k) {
         const int p = k & 1;
         // 1. level k into LDS plane p
@@ -225,7 +226,7 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zl(StencilArgs<T> a)
             for (int f = 0; f <= VX; ++f)
                 FX[f] = flux5(mid(uxr[f + 2], uxr[f + 3]), uxr[f], uxr[f + 1], uxr[f + 2], uxr[f + 3],
                               uxr[f + 4], uxr[f + 5]);
-            const T dzik = a.dzi[k];
+            const T dzik = kload(a.dzi, k);
             T res[VX];
 #pragma unroll
             for (int n = 0; n < VX; ++n) {
@@ -479,7 +480,7 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zlp(StencilArgs<T> a
             for (int f = 0; f <= VX; ++f)
                 FX[f] = flux5(mid(uxr[f + 2], uxr[f + 3]), uxr[f], uxr[f + 1], uxr[f + 2], uxr[f + 3],
                               uxr[f + 4], uxr[f + 5]);
-            const T dzik = a.dzi[k];
+            const T dzik = kload(a.dzi, k);
             T res[VX];
 #pragma unroll
             for (int n = 0; n < VX; ++n) {
@@ -501,6 +502,7 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zlp(StencilArgs<T> a
         }
     };
 
+    vm_drain();
     for (int k = k0; k < k1; k += 2) {
         level(std::integral_constant<int, 0>(), k);
         if (k + 1 < k1) level(std::integral_constant<int, 1>(), k + 1);
@@ -644,6 +646,7 @@ __global__ __launch_bounds__(64 * BY, WPE) void diff_smag_zl(StencilArgs<T> a)
     load_tend(0, k0);
 
     const T dxi = a.dxi, dyi = a.dyi;
+    vm_drain();
     for (int k = k0; k < k1; ++k) {
         // level k+1 into the ring; prefetch level k+2 and the next tendencies
         store_plane(0, k + 1);
@@ -655,7 +658,7 @@ __global__ __launch_bounds__(64 * BY, WPE) void diff_smag_zl(StencilArgs<T> a)
 
         if (own && lane_on) {
             const int bm = (k - 1) & 3, bc = k & 3, bp = (k + 1) & 3;
-            const T dzik = a.dzi[k], dzikm1 = a.dzi[k - 1], dzhik = a.dzhi[k], dzhik1 = a.dzhi[k + 1];
+            const T dzik = kload(a.dzi, k), dzikm1 = kload(a.dzi, k - 1), dzhik = kload(a.dzhi, k), dzhik1 = kload(a.dzhi, k + 1);
             const int rr = r + 1;
             T o0[VX], o1[VX], o2[VX];
 #pragma unroll

@@ -124,6 +124,7 @@ __device__ __forceinline__ void step_zl_tile(const StencilArgs<T> &a, int tx, in
     }
     if (x_is_top && t.lane == 0) XVL[0] = a.v[c_x + (int64_t)k0 * ks - 1];
 
+    vm_drain();
     for (int kk = k0; kk < k1; kk += 4) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -166,7 +167,7 @@ __device__ __forceinline__ void step_zl_tile(const StencilArgs<T> &a, int tx, in
                     wtleft = EL[(s + 1) & 3][2];
                 }
                 if (ld_own) {
-                    const T dzik = a.dzi[k], dzikm1 = a.dzi[k - 1], dzhik = a.dzhi[k], dzhik1 = a.dzhi[k + 1];
+                    const T dzik = kload(a.dzi, k), dzikm1 = kload(a.dzi, k - 1), dzhik = kload(a.dzhi, k), dzhik1 = kload(a.dzhi, k + 1);
                     T nu[VX], nv[VX], nw[VX];
 #pragma unroll
                     for (int n = 0; n < VX; ++n) {

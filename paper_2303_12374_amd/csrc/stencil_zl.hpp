@@ -133,6 +133,7 @@ __device__ __forceinline__ void diff_uvw_zl_tile(const StencilArgs<T> &a, int tx
         if (edge_r) ER[0][f] = F[f][c_own + (int64_t)k0 * ks + VX];
     }
 
+    vm_drain();
     for (int kk = k0; kk < k1; kk += 4) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -162,7 +163,7 @@ __device__ __forceinline__ void diff_uvw_zl_tile(const StencilArgs<T> &a, int tx
                     if (t.xrow_l >= 0) vstore<T, VX>(&sh[p][fslot(FM, f)][t.xrow_l][t.lane * VX], X[p][f]);
                 }
                 __syncthreads();
-                const T dzik = a.dzi[k], dzikm1 = a.dzi[k - 1], dzhik = a.dzhi[k], dzhik1 = a.dzhi[k + 1];
+                const T dzik = kload(a.dzi, k), dzikm1 = kload(a.dzi, k - 1), dzhik = kload(a.dzhi, k), dzhik1 = kload(a.dzhi, k + 1);
 #pragma unroll
                 for (int f = 0; f < 3; ++f) {
         if (!((FM >> f) & 1)) continue;
@@ -265,6 +266,7 @@ __device__ __forceinline__ void advec_u_zl_tile(const StencilArgs<T> &a, int tx,
     }
     if (edge_r) URe[0] = U[c_own + (int64_t)k0 * ks + VX];
 
+    vm_drain();
     for (int kk = k0; kk < k1; kk += 4) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -327,7 +329,7 @@ __device__ __forceinline__ void advec_u_zl_tile(const StencilArgs<T> &a, int tx,
                 }
                 if (t.lane == t.nlanes - 1) uright = URe[p];
                 if (ld_own) {
-                    const T dzik = a.dzi[k];
+                    const T dzik = kload(a.dzi, k);
 #pragma unroll
                     for (int n = 0; n < VX; ++n) {
                         const T uw = n == 0 ? uleft : uc[n - 1];
