@@ -551,7 +551,6 @@ __global__ __launch_bounds__(64 * BY, WPE) void diff_smag_zl(StencilArgs<T> a)
     const int nlanes = min(64, (a.itot - i0w + 1) / VX);
     const bool lane_on = lane < nlanes;
     const int xo = lane * VX;
-    const bool edge_l = lane == 0, edge_r = lane == nlanes - 1;
     const int j0 = 1 + ty * BY;
     const int nv = min(BY, a.jtot - j0 + 1);
     const bool own = r < nv;
@@ -560,10 +559,21 @@ __global__ __launch_bounds__(64 * BY, WPE) void diff_smag_zl(StencilArgs<T> a)
     const T *F[4] = {a.u, a.v, a.w, a.evisc};
     const int xr = 1 + nlanes * VX;         // LDS column of the right halo cell
 
+    // Every global load below is unconditional, from an address inside the
+    // field: lanes beyond the grid re-read the last active lane's points,
+    // waves beyond the last row re-read the last row, waves without a halo
+    // row re-read their own row, and one scalar load per row carries both
+    // halo columns (the left one in lane 0, the right one in lane le).  No
+    // load sits behind a branch, so the compiler counts the loads in flight
+    // exactly and does not drain the prefetch of level k+2 before it is due.
+    const int lane_c = min(lane, nlanes - 1);
+    const int le = max(nlanes - 1, 1);      // lane loading the right halo cell
+    const int64_t row_c = a.off + i0w + (int64_t)min(j0 + r, a.jtot) * js;
+    const int64_t c_own = row_c + lane_c * VX;
+    const int64_t e_own = lane == 0 ? row_c - 1 : (lane == le ? row_c + nlanes * VX : c_own);
+
     // rows this wave stages: its own (LDS row r+1) and halo rows h = r, r+BY,
     // ... of the 8 (field h/2; LDS row 0 for even h, nv+1 for odd h)
-    const int64_t c_own = a.off + i0w + xo + (int64_t)(j0 + r) * js;
-    const int64_t e_own = a.off + i0w + (int64_t)(j0 + r) * js;
     int hf[NH], hrow[NH];
     int64_t hc[NH], he[NH];
 #pragma unroll
@@ -571,32 +581,27 @@ __global__ __launch_bounds__(64 * BY, WPE) void diff_smag_zl(StencilArgs<T> a)
         const int h = r + m * BY;
         hf[m] = h < 8 ? h >> 1 : -1;
         hrow[m] = (h & 1) ? nv + 1 : 0;
-        const int jg = j0 - 1 + hrow[m];
-        hc[m] = a.off + i0w + xo + (int64_t)jg * js;
-        he[m] = a.off + i0w + (int64_t)jg * js;
+        const int64_t hrow0 = a.off + i0w + (int64_t)(j0 - 1 + hrow[m]) * js;
+        hc[m] = hf[m] < 0 ? c_own : hrow0 + lane_c * VX;
+        he[m] = hf[m] < 0 ? c_own : (lane == 0 ? hrow0 - 1 : (lane == le ? hrow0 + nlanes * VX : hrow0 + lane_c * VX));
     }
 
-    T O[2][4][VX], OL[2][4], OR_[2][4];     // own row of the 4 inputs at one level, halo columns
-    T H[2][NH][VX], HL[2][NH], HR[2][NH];   // halo rows
+    T O[2][4][VX], OE[2][4];                // own row of the 4 inputs at one level, halo columns
+    T H[2][NH][VX], HE[2][NH];              // halo rows
     T TT[2][3][VX];                          // ut, vt, wt at level k (next: k+1)
 
     auto load_plane = [&](int q, int l) {    // level l of everything staged, into slot q
-        if (own) {
 #pragma unroll
-            for (int f = 0; f < 4; ++f) {
-                if (lane_on) vload<T, VX>(O[q][f], F[f] + c_own + (int64_t)l * ks);
-                if (edge_l) OL[q][f] = F[f][e_own + (int64_t)l * ks - 1];
-                if (edge_r) OR_[q][f] = F[f][e_own + (int64_t)l * ks + nlanes * VX];
-            }
+        for (int f = 0; f < 4; ++f) {
+            vload<T, VX>(O[q][f], F[f] + c_own + (int64_t)l * ks);
+            OE[q][f] = F[f][e_own + (int64_t)l * ks];
         }
 #pragma unroll
         for (int m = 0; m < NH; ++m) {
-            if (hf[m] < 0) continue;
             // a select, not an indexed pointer array, keeps these global loads
-            const T *p = hf[m] == 0 ? a.u : (hf[m] == 1 ? a.v : (hf[m] == 2 ? a.w : a.evisc));
-            if (lane_on) vload<T, VX>(H[q][m], p + hc[m] + (int64_t)l * ks);
-            if (edge_l) HL[q][m] = p[he[m] + (int64_t)l * ks - 1];
-            if (edge_r) HR[q][m] = p[he[m] + (int64_t)l * ks + nlanes * VX];
+            const T *p = hf[m] == 1 ? a.v : (hf[m] == 2 ? a.w : (hf[m] == 3 ? a.evisc : a.u));
+            vload<T, VX>(H[q][m], p + hc[m] + (int64_t)l * ks);
+            HE[q][m] = p[he[m] + (int64_t)l * ks];
         }
     };
     auto store_plane = [&](int q, int l) {   // slot q into the LDS planes of level l
@@ -608,8 +613,8 @@ __global__ __launch_bounds__(64 * BY, WPE) void diff_smag_zl(StencilArgs<T> a)
 #pragma unroll
                     for (int n = 0; n < VX; ++n) pl[f][b][r + 1][1 + xo + n] = O[q][f][n];
                 }
-                if (edge_l) pl[f][b][r + 1][0] = OL[q][f];
-                if (edge_r) pl[f][b][r + 1][xr] = OR_[q][f];
+                if (lane == 0) pl[f][b][r + 1][0] = OE[q][f];
+                if (lane == le) pl[f][b][r + 1][xr] = OE[q][f];
             }
         }
 #pragma unroll
@@ -619,23 +624,15 @@ __global__ __launch_bounds__(64 * BY, WPE) void diff_smag_zl(StencilArgs<T> a)
 #pragma unroll
                 for (int n = 0; n < VX; ++n) pl[hf[m]][b][hrow[m]][1 + xo + n] = H[q][m][n];
             }
-            if (edge_l) pl[hf[m]][b][hrow[m]][0] = HL[q][m];
-            if (edge_r) pl[hf[m]][b][hrow[m]][xr] = HR[q][m];
+            if (lane == 0) pl[hf[m]][b][hrow[m]][0] = HE[q][m];
+            if (lane == le) pl[hf[m]][b][hrow[m]][xr] = HE[q][m];
         }
     };
-    auto load_tend = [&](int q, int k) {
-        if (own && lane_on) {
-#pragma unroll
-            for (int f = 0; f < 3; ++f)
-                if (f < 2 || k >= a.kw0) tload<NT, T, VX>(TT[q][f], (f == 0 ? a.ut : (f == 1 ? a.vt : a.wt)) + c_own + (int64_t)k * ks);
-        }
-    };
-#pragma unroll
-    for (int q = 0; q < 2; ++q)
+    auto load_tend = [&](int q, int k) {     // k <= k1 <= ktot+1
 #pragma unroll
         for (int f = 0; f < 3; ++f)
-#pragma unroll
-            for (int n = 0; n < VX; ++n) TT[q][f][n] = T(0);
+            tload<NT, T, VX>(TT[q][f], (f == 0 ? a.ut : (f == 1 ? a.vt : a.wt)) + c_own + (int64_t)k * ks);
+    };
 
     // prologue: planes k0-1 and k0 into LDS, level k0+1 and tendencies of k0 in flight
     load_plane(0, k0 - 1);
@@ -650,10 +647,8 @@ __global__ __launch_bounds__(64 * BY, WPE) void diff_smag_zl(StencilArgs<T> a)
     for (int k = k0; k < k1; ++k) {
         // level k+1 into the ring; prefetch level k+2 and the next tendencies
         store_plane(0, k + 1);
-        if (k + 1 < k1) {
-            load_plane(1, k + 2);
-            load_tend(1, k + 1);
-        }
+        load_plane(1, min(k + 2, k1));       // clamped at the end of the tile, where it is unused
+        load_tend(1, k + 1);
         __syncthreads();
 
         if (own && lane_on) {
@@ -701,15 +696,13 @@ __global__ __launch_bounds__(64 * BY, WPE) void diff_smag_zl(StencilArgs<T> a)
         for (int f = 0; f < 4; ++f) {
 #pragma unroll
             for (int n = 0; n < VX; ++n) O[0][f][n] = O[1][f][n];
-            OL[0][f] = OL[1][f];
-            OR_[0][f] = OR_[1][f];
+            OE[0][f] = OE[1][f];
         }
 #pragma unroll
         for (int m = 0; m < NH; ++m) {
 #pragma unroll
             for (int n = 0; n < VX; ++n) H[0][m][n] = H[1][m][n];
-            HL[0][m] = HL[1][m];
-            HR[0][m] = HR[1][m];
+            HE[0][m] = HE[1][m];
         }
 #pragma unroll
         for (int f = 0; f < 3; ++f)

@@ -78,6 +78,15 @@ __host__ __device__ constexpr int fslot(int fm, int f)
 // One tile (tx, ty, tz) of diff_uvw; called by the single-grid kernel and by
 // the persistent batched kernel.  Starts with a barrier so that a block can
 // run tiles back to back on the same LDS.
+//
+// Every global load of the level loop is unconditional, from an address
+// inside the field: lanes beyond the grid and waves beyond the last row
+// re-read a point of their clamped own row, waves without a halo row re-read
+// their own row, and one scalar load per field carries both x-edge values
+// (the left one in lane 0, the right one in the last active lane, or in lane 1
+// when only lane 0 is active).  No load then sits behind a branch, so the
+// compiler counts the loads in flight exactly and a level waits only for the
+// data it uses, not for the prefetch of the levels after it.
 template <typename T, int VX, int BY, int KB, int NT, int FM = 7>
 __device__ __forceinline__ void diff_uvw_zl_tile(const StencilArgs<T> &a, int tx, int ty, int tz)
 {
@@ -90,110 +99,96 @@ __device__ __forceinline__ void diff_uvw_zl_tile(const StencilArgs<T> &a, int tx
 
     const ZlTile<VX, BY, KB> t(a.itot, a.jtot, a.ktot, tx, ty, tz);
     const int64_t js = a.js, ks = a.ks;
-    const int64_t c_own = a.off + t.i0 + (int64_t)(t.j0 + t.r) * js;
-    const int64_t c_x = a.off + t.i0 + (int64_t)t.xrow_g * js;
+    const int lane_c = min(t.lane, t.nlanes - 1);                      // clamped lane
+    const int64_t row_c = a.off + t.i0w + (int64_t)min(t.j0 + t.r, a.jtot) * js;  // (i0w, clamped row, 0)
+    const int64_t c_own = row_c + lane_c * VX;                         // own point (clamped)
+    const int64_t c_x = t.xrow_g >= 0 ? a.off + t.i0w + lane_c * VX + (int64_t)t.xrow_g * js : c_own;
+    const int le = max(t.nlanes - 1, 1);                               // lane loading the right edge
+    const int64_t c_e = t.lane == 0 ? row_c - 1 : (t.lane == le ? row_c + t.nlanes * VX : c_own);
     const bool ld_own = t.own && t.lane_on;
-    const bool ld_x = t.xrow_g >= 0 && t.lane_on;
-    const bool edge_l = t.own && t.lane == 0;
-    const bool edge_r = t.own && t.lane == t.nlanes - 1;
     const T *F[3] = {a.u, a.v, a.w};
     T *Tt[3] = {a.ut, a.vt, a.wt};
     const T dxi2 = a.dxi * a.dxi, dyi2 = a.dyi * a.dyi, visc = a.visc;
     const int kw0 = a.kw0;
 
     T R[4][3][VX];        // field ring: slot s%4 holds level kk+s
-    T X[2][3][VX];        // extra row, by level parity
+    T X[2][3][VX];        // halo row (or a re-read of the own row), by level parity
     T Q[2][3][VX];        // tendencies, by level parity
-    T EL[2][3], ER[2][3]; // x edge values, by level parity
-#pragma unroll
-    for (int f = 0; f < 3; ++f) {
-        if (!((FM >> f) & 1)) continue;
-#pragma unroll
-        for (int n = 0; n < VX; ++n) {
-            R[0][f][n] = R[1][f][n] = R[2][f][n] = R[3][f][n] = T(0);
-            X[0][f][n] = X[1][f][n] = Q[0][f][n] = Q[1][f][n] = T(0);
-        }
-        EL[0][f] = EL[1][f] = ER[0][f] = ER[1][f] = T(0);
-    }
+    T E[2][3];            // x edge values, by level parity
 
     const int k0 = t.k0, k1 = t.k1;
-    // prologue: levels k0-1, k0, k0+1 (and the k0+2 prefetch) of the own row
+    // prologue: levels k0-1, k0, k0+1 and k0+2 of the own row (k0+2 <= ktot+1)
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
         if (!((FM >> f) & 1)) continue;
-        if (ld_own) {
-            vload<T, VX>(R[3][f], F[f] + c_own + (int64_t)(k0 - 1) * ks);
-            vload<T, VX>(R[0][f], F[f] + c_own + (int64_t)k0 * ks);
-            vload<T, VX>(R[1][f], F[f] + c_own + (int64_t)(k0 + 1) * ks);
-            if (k0 + 2 <= k1) vload<T, VX>(R[2][f], F[f] + c_own + (int64_t)(k0 + 2) * ks);
-            if (f < 2 || k0 >= kw0) tload<NT, T, VX>(Q[0][f], Tt[f] + c_own + (int64_t)k0 * ks);
-        }
-        if (ld_x) vload<T, VX>(X[0][f], F[f] + c_x + (int64_t)k0 * ks);
-        if (edge_l) EL[0][f] = F[f][c_own + (int64_t)k0 * ks - 1];
-        if (edge_r) ER[0][f] = F[f][c_own + (int64_t)k0 * ks + VX];
+        vload<T, VX>(R[3][f], F[f] + c_own + (int64_t)(k0 - 1) * ks);
+        vload<T, VX>(R[0][f], F[f] + c_own + (int64_t)k0 * ks);
+        vload<T, VX>(R[1][f], F[f] + c_own + (int64_t)(k0 + 1) * ks);
+        vload<T, VX>(R[2][f], F[f] + c_own + (int64_t)min(k0 + 2, k1) * ks);
+        tload<NT, T, VX>(Q[0][f], Tt[f] + c_own + (int64_t)k0 * ks);
+        vload<T, VX>(X[0][f], F[f] + c_x + (int64_t)k0 * ks);
+        E[0][f] = F[f][c_e + (int64_t)k0 * ks];
     }
 
     vm_drain();
-    for (int kk = k0; kk < k1; kk += 4) {
+    for (int kk = k0;; kk += 4) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const int k = kk + s;
-            if (k < k1) {
-                const int p = s & 1, q = p ^ 1;
-                T(&b)[3][VX] = R[(s + 3) & 3];  // level k-1; refilled with k+3 after use
-                T(&c)[3][VX] = R[s & 3];
-                T(&tp)[3][VX] = R[(s + 1) & 3];  // R[(s+2)&3] already holds level k+2
-                // prefetch level k+1 of tendencies, halo row and edges
+            if (k >= k1) return;
+            const int p = s & 1, q = p ^ 1;
+            T(&b)[3][VX] = R[(s + 3) & 3];  // level k-1; refilled with k+3 after use
+            T(&c)[3][VX] = R[s & 3];
+            T(&tp)[3][VX] = R[(s + 1) & 3];  // R[(s+2)&3] already holds level k+2
+            // prefetch level k+1 (<= k1 <= ktot+1) of tendencies, halo row and edges
 #pragma unroll
-                for (int f = 0; f < 3; ++f) {
-        if (!((FM >> f) & 1)) continue;
-                    if (k + 1 < k1) {
-                        if (ld_own && (f < 2 || k + 1 >= kw0))
-                            tload<NT, T, VX>(Q[q][f], Tt[f] + c_own + (int64_t)(k + 1) * ks);
-                        if (ld_x) vload<T, VX>(X[q][f], F[f] + c_x + (int64_t)(k + 1) * ks);
-                        if (edge_l) EL[q][f] = F[f][c_own + (int64_t)(k + 1) * ks - 1];
-                        if (edge_r) ER[q][f] = F[f][c_own + (int64_t)(k + 1) * ks + VX];
-                    }
-                }
-                // level k rows into LDS
-#pragma unroll
-                for (int f = 0; f < 3; ++f) {
-        if (!((FM >> f) & 1)) continue;
-                    if (t.own) vstore<T, VX>(&sh[p][fslot(FM, f)][t.r + 1][t.lane * VX], c[f]);
-                    if (t.xrow_l >= 0) vstore<T, VX>(&sh[p][fslot(FM, f)][t.xrow_l][t.lane * VX], X[p][f]);
-                }
-                __syncthreads();
-                const T dzik = kload(a.dzi, k), dzikm1 = kload(a.dzi, k - 1), dzhik = kload(a.dzhi, k), dzhik1 = kload(a.dzhi, k + 1);
-#pragma unroll
-                for (int f = 0; f < 3; ++f) {
-        if (!((FM >> f) & 1)) continue;
-                    T nn[VX], ss[VX];
-                    vload<T, VX>(nn, &sh[p][fslot(FM, f)][t.r + 2][t.lane * VX]);
-                    vload<T, VX>(ss, &sh[p][fslot(FM, f)][t.r][t.lane * VX]);
-                    T left = shfl_up1<T>(c[f][VX - 1]);
-                    T right = shfl_down1<T>(c[f][0]);
-                    if (t.lane == 0) left = EL[p][f];
-                    if (t.lane == t.nlanes - 1) right = ER[p][f];
-                    if (ld_own && (f < 2 || k >= kw0)) {
-#pragma unroll
-                        for (int n = 0; n < VX; ++n) {
-                            const T w_ = n == 0 ? left : c[f][n - 1];
-                            const T e_ = n == VX - 1 ? right : c[f][n + 1];
-                            const T d = f < 2 ? diff_c_point<T>(c[f][n], e_, w_, nn[n], ss[n], tp[f][n], b[f][n],
-                                                                dxi2, dyi2, dzik, dzhik1, dzhik, visc)
-                                              : diff_w_point<T>(c[f][n], e_, w_, nn[n], ss[n], tp[f][n], b[f][n],
-                                                                dxi2, dyi2, dzik, dzikm1, dzhik, visc);
-                            Q[p][f][n] = Q[p][f][n] + d;
-                        }
-                        tstore<NT, T, VX>(Tt[f] + c_own + (int64_t)k * ks, Q[p][f]);
-                    }
-                }
-                // level k-1 is no longer needed: its slot takes the k+3 prefetch
-#pragma unroll
-                for (int f = 0; f < 3; ++f)
-                    if (((FM >> f) & 1) && ld_own && k + 3 <= k1)
-                        fload<NT, T, VX>(b[f], F[f] + c_own + (int64_t)(k + 3) * ks);
+            for (int f = 0; f < 3; ++f) {
+                if (!((FM >> f) & 1)) continue;
+                tload<NT, T, VX>(Q[q][f], Tt[f] + c_own + (int64_t)(k + 1) * ks);
+                vload<T, VX>(X[q][f], F[f] + c_x + (int64_t)(k + 1) * ks);
+                E[q][f] = F[f][c_e + (int64_t)(k + 1) * ks];
             }
+            // level k rows into LDS
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                if (!((FM >> f) & 1)) continue;
+                if (t.own) vstore<T, VX>(&sh[p][fslot(FM, f)][t.r + 1][t.lane * VX], c[f]);
+                if (t.xrow_l >= 0) vstore<T, VX>(&sh[p][fslot(FM, f)][t.xrow_l][t.lane * VX], X[p][f]);
+            }
+            __syncthreads();
+            const T dzik = kload(a.dzi, k), dzikm1 = kload(a.dzi, k - 1), dzhik = kload(a.dzhi, k),
+                    dzhik1 = kload(a.dzhi, k + 1);
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                if (!((FM >> f) & 1)) continue;
+                T nn[VX], ss[VX];
+                vload<T, VX>(nn, &sh[p][fslot(FM, f)][t.r + 2][t.lane * VX]);
+                vload<T, VX>(ss, &sh[p][fslot(FM, f)][t.r][t.lane * VX]);
+                T left = shfl_up1<T>(c[f][VX - 1]);
+                T right = shfl_down1<T>(c[f][0]);
+                T er = E[p][f];
+                if (t.nlanes == 1) er = __shfl(er, 1, 64);
+                if (t.lane == 0) left = E[p][f];
+                if (t.lane == t.nlanes - 1) right = er;
+                if (ld_own && (f < 2 || k >= kw0)) {
+#pragma unroll
+                    for (int n = 0; n < VX; ++n) {
+                        const T w_ = n == 0 ? left : c[f][n - 1];
+                        const T e_ = n == VX - 1 ? right : c[f][n + 1];
+                        const T d = f < 2 ? diff_c_point<T>(c[f][n], e_, w_, nn[n], ss[n], tp[f][n], b[f][n],
+                                                            dxi2, dyi2, dzik, dzhik1, dzhik, visc)
+                                          : diff_w_point<T>(c[f][n], e_, w_, nn[n], ss[n], tp[f][n], b[f][n],
+                                                            dxi2, dyi2, dzik, dzikm1, dzhik, visc);
+                        Q[p][f][n] = Q[p][f][n] + d;
+                    }
+                    tstore<NT, T, VX>(Tt[f] + c_own + (int64_t)k * ks, Q[p][f]);
+                }
+            }
+            // level k-1 is no longer needed: its slot takes the k+3 prefetch
+            // (clamped to k1 near the end of the tile, where it is not used)
+#pragma unroll
+            for (int f = 0; f < 3; ++f)
+                if ((FM >> f) & 1) fload<NT, T, VX>(b[f], F[f] + c_own + (int64_t)min(k + 3, k1) * ks);
         }
     }
 }
@@ -201,6 +196,10 @@ __device__ __forceinline__ void diff_uvw_zl_tile(const StencilArgs<T> &a, int tx
 // ---------------------------------------------------------------------------
 // advec_u
 // ---------------------------------------------------------------------------
+// The loads of the level loop are unconditional, as in diff_uvw_zl_tile:
+// per field one scalar load carries the x-edge values (u: left in lane 0,
+// right in the last active lane or lane 1; v: the own row's left value in
+// lane 0, the top halo row's in lane 1; w: left in lane 0).
 template <typename T, int VX, int BY, int KB, int NT>
 __device__ __forceinline__ void advec_u_zl_tile(const StencilArgs<T> &a, int tx, int ty, int tz)
 {
@@ -214,138 +213,119 @@ __device__ __forceinline__ void advec_u_zl_tile(const StencilArgs<T> &a, int tx,
 
     const ZlTile<VX, BY, KB> t(a.itot, a.jtot, a.ktot, tx, ty, tz);
     const int64_t js = a.js, ks = a.ks;
-    const int64_t c_own = a.off + t.i0 + (int64_t)(t.j0 + t.r) * js;
-    const int64_t c_x = a.off + t.i0 + (int64_t)t.xrow_g * js;
+    const int lane_c = min(t.lane, t.nlanes - 1);                      // clamped lane
+    const int64_t row_c = a.off + t.i0w + (int64_t)min(t.j0 + t.r, a.jtot) * js;  // (i0w, clamped row, 0)
+    const int64_t c_own = row_c + lane_c * VX;                         // own point (clamped)
+    const bool x_is_top = t.xrow_g >= 0 && t.xrow_l > 0;              // the top halo row also needs v
+    const int64_t xrow0 = a.off + t.i0w + (int64_t)max(t.xrow_g, 0) * js;   // (i0w, halo row, 0)
+    const int64_t c_x = t.xrow_g >= 0 ? xrow0 + lane_c * VX : c_own;
+    const int le = max(t.nlanes - 1, 1);                               // lane loading the right u edge
+    const int64_t c_eu = t.lane == 0 ? row_c - 1 : (t.lane == le ? row_c + t.nlanes * VX : c_own);
+    const int64_t c_ev = t.lane == 0 ? row_c - 1 : (t.lane == 1 && x_is_top ? xrow0 - 1 : c_own);
+    const int64_t c_ew = t.lane == 0 ? row_c - 1 : c_own;
     const bool ld_own = t.own && t.lane_on;
-    const bool ld_x = t.xrow_g >= 0 && t.lane_on;
-    const bool x_is_top = t.xrow_g >= 0 && t.xrow_l > 0;   // the top halo row also needs v
-    const bool edge_l = t.own && t.lane == 0;
-    const bool edge_r = t.own && t.lane == t.nlanes - 1;
     const T dxi = a.dxi, dyi = a.dyi;
     const T *U = a.u, *V = a.v, *W = a.w;
 
     T RU[4][VX], RW[4][VX];   // u and w rings (u: k-1..k+2, w: k..k+2)
     T RV[2][VX];              // v at level k, k+1
-    T XU[2][VX], XV[2][VX];   // extra row u (and v for the top halo)
-    T XVL[2];                 // v left edge of the top halo row
+    T XU[2][VX], XV[2][VX];   // extra row u and v (a re-read of the own row where there is none)
     T Q[2][VX];               // ut
-    T ULe[2], URe[2], VLe[2]; // own-row edges by level parity
-    T WLe[4];                 // w left edge, ring like RW
-#pragma unroll
-    for (int n = 0; n < VX; ++n) {
-        RU[0][n] = RU[1][n] = RU[2][n] = RU[3][n] = T(0);
-        RW[0][n] = RW[1][n] = RW[2][n] = RW[3][n] = T(0);
-        RV[0][n] = RV[1][n] = XU[0][n] = XU[1][n] = XV[0][n] = XV[1][n] = Q[0][n] = Q[1][n] = T(0);
-    }
-    ULe[0] = ULe[1] = URe[0] = URe[1] = VLe[0] = VLe[1] = XVL[0] = XVL[1] = T(0);
-    WLe[0] = WLe[1] = WLe[2] = WLe[3] = T(0);
+    T EU[2], EV[2];           // u and v edge values by level parity
+    T EW[4];                  // w left edge, ring like RW
 
     const int k0 = t.k0, k1 = t.k1;
-    if (ld_own) {
-        vload<T, VX>(RU[3], U + c_own + (int64_t)(k0 - 1) * ks);
-        vload<T, VX>(RU[0], U + c_own + (int64_t)k0 * ks);
-        vload<T, VX>(RU[1], U + c_own + (int64_t)(k0 + 1) * ks);
-        if (k0 + 2 <= k1) vload<T, VX>(RU[2], U + c_own + (int64_t)(k0 + 2) * ks);
-        vload<T, VX>(RW[0], W + c_own + (int64_t)k0 * ks);
-        vload<T, VX>(RW[1], W + c_own + (int64_t)(k0 + 1) * ks);
-        if (k0 + 2 <= k1) vload<T, VX>(RW[2], W + c_own + (int64_t)(k0 + 2) * ks);
-        vload<T, VX>(RV[0], V + c_own + (int64_t)k0 * ks);
-        tload<NT, T, VX>(Q[0], a.ut + c_own + (int64_t)k0 * ks);
-    }
-    if (ld_x) {
-        vload<T, VX>(XU[0], U + c_x + (int64_t)k0 * ks);
-        if (x_is_top) vload<T, VX>(XV[0], V + c_x + (int64_t)k0 * ks);
-    }
-    if (x_is_top && t.lane == 0) XVL[0] = V[c_x + (int64_t)k0 * ks - 1];
-    if (edge_l) {
-        ULe[0] = U[c_own + (int64_t)k0 * ks - 1];
-        VLe[0] = V[c_own + (int64_t)k0 * ks - 1];
-        WLe[0] = W[c_own + (int64_t)k0 * ks - 1];
-        WLe[1] = W[c_own + (int64_t)(k0 + 1) * ks - 1];
-        if (k0 + 2 <= k1) WLe[2] = W[c_own + (int64_t)(k0 + 2) * ks - 1];
-    }
-    if (edge_r) URe[0] = U[c_own + (int64_t)k0 * ks + VX];
+    const int k2 = min(k0 + 2, k1);
+    vload<T, VX>(RU[3], U + c_own + (int64_t)(k0 - 1) * ks);
+    vload<T, VX>(RU[0], U + c_own + (int64_t)k0 * ks);
+    vload<T, VX>(RU[1], U + c_own + (int64_t)(k0 + 1) * ks);
+    vload<T, VX>(RU[2], U + c_own + (int64_t)k2 * ks);
+    vload<T, VX>(RW[0], W + c_own + (int64_t)k0 * ks);
+    vload<T, VX>(RW[1], W + c_own + (int64_t)(k0 + 1) * ks);
+    vload<T, VX>(RW[2], W + c_own + (int64_t)k2 * ks);
+    vload<T, VX>(RV[0], V + c_own + (int64_t)k0 * ks);
+    tload<NT, T, VX>(Q[0], a.ut + c_own + (int64_t)k0 * ks);
+    vload<T, VX>(XU[0], U + c_x + (int64_t)k0 * ks);
+    vload<T, VX>(XV[0], V + c_x + (int64_t)k0 * ks);
+    EU[0] = U[c_eu + (int64_t)k0 * ks];
+    EV[0] = V[c_ev + (int64_t)k0 * ks];
+    EW[0] = W[c_ew + (int64_t)k0 * ks];
+    EW[1] = W[c_ew + (int64_t)(k0 + 1) * ks];
+    EW[2] = W[c_ew + (int64_t)k2 * ks];
 
     vm_drain();
-    for (int kk = k0; kk < k1; kk += 4) {
+    for (int kk = k0;; kk += 4) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const int k = kk + s;
-            if (k < k1) {
-                const int p = s & 1, q = p ^ 1;
-                T(&ub)[VX] = RU[(s + 3) & 3];  // level k-1; refilled with k+3 after use
-                T(&uc)[VX] = RU[s & 3];
-                T(&ut_)[VX] = RU[(s + 1) & 3];
-                T(&wc)[VX] = RW[s & 3];
-                T(&wt)[VX] = RW[(s + 1) & 3];
-                T(&wnx)[VX] = RW[(s + 3) & 3];  // w of level k-1 is not needed: prefetch k+3
-                if (ld_own && k + 3 <= k1) fload<NT, T, VX>(wnx, W + c_own + (int64_t)(k + 3) * ks);
-                if (edge_l && k + 3 <= k1) WLe[(s + 3) & 3] = W[c_own + (int64_t)(k + 3) * ks - 1];
-                if (k + 1 < k1) {
-                    if (ld_own) {
-                        fload<NT, T, VX>(RV[q], V + c_own + (int64_t)(k + 1) * ks);
-                        tload<NT, T, VX>(Q[q], a.ut + c_own + (int64_t)(k + 1) * ks);
-                    }
-                    if (ld_x) {
-                        vload<T, VX>(XU[q], U + c_x + (int64_t)(k + 1) * ks);
-                        if (x_is_top) vload<T, VX>(XV[q], V + c_x + (int64_t)(k + 1) * ks);
-                    }
-                    if (x_is_top && t.lane == 0) XVL[q] = V[c_x + (int64_t)(k + 1) * ks - 1];
-                    if (edge_l) {
-                        ULe[q] = U[c_own + (int64_t)(k + 1) * ks - 1];
-                        VLe[q] = V[c_own + (int64_t)(k + 1) * ks - 1];
-                    }
-                    if (edge_r) URe[q] = U[c_own + (int64_t)(k + 1) * ks + VX];
-                }
-                // level-k rows into LDS: u (own + halo rows), v (own + top halo) and v's left edge
-                if (t.own) {
-                    vstore<T, VX>(&shu[p][t.r + 1][t.lane * VX], uc);
-                    vstore<T, VX>(&shv[p][t.r + 1][t.lane * VX], RV[p]);
-                    if (t.lane == 0) shvl[p][t.r + 1] = VLe[p];
-                }
-                if (t.xrow_l >= 0) vstore<T, VX>(&shu[p][t.xrow_l][t.lane * VX], XU[p]);
-                if (x_is_top) {
-                    vstore<T, VX>(&shv[p][t.xrow_l][t.lane * VX], XV[p]);
-                    if (t.lane == 0) shvl[p][t.xrow_l] = XVL[p];
-                }
-                __syncthreads();
-                T un[VX], us[VX], vn[VX];
-                vload<T, VX>(un, &shu[p][t.r + 2][t.lane * VX]);
-                vload<T, VX>(us, &shu[p][t.r][t.lane * VX]);
-                vload<T, VX>(vn, &shv[p][t.r + 2][t.lane * VX]);
-                const T vnl_edge = shvl[p][t.r + 2];
-                T uleft = shfl_up1<T>(uc[VX - 1]);
-                T uright = shfl_down1<T>(uc[0]);
-                T vleft = shfl_up1<T>(RV[p][VX - 1]);
-                T vnleft = shfl_up1<T>(vn[VX - 1]);
-                T wleft = shfl_up1<T>(wc[VX - 1]);
-                T wtleft = shfl_up1<T>(wt[VX - 1]);
-                if (t.lane == 0) {
-                    uleft = ULe[p];
-                    vleft = VLe[p];
-                    vnleft = vnl_edge;
-                    wleft = WLe[s & 3];
-                    wtleft = WLe[(s + 1) & 3];
-                }
-                if (t.lane == t.nlanes - 1) uright = URe[p];
-                if (ld_own) {
-                    const T dzik = kload(a.dzi, k);
-#pragma unroll
-                    for (int n = 0; n < VX; ++n) {
-                        const T uw = n == 0 ? uleft : uc[n - 1];
-                        const T ue = n == VX - 1 ? uright : uc[n + 1];
-                        const T v_w = n == 0 ? vleft : RV[p][n - 1];
-                        const T v_nw = n == 0 ? vnleft : vn[n - 1];
-                        const T w_w = n == 0 ? wleft : wc[n - 1];
-                        const T w_tw = n == 0 ? wtleft : wt[n - 1];
-                        Q[p][n] = Q[p][n] + advec_u_point<T>(uc[n], ue, uw, un[n], us[n], ut_[n], ub[n], v_w,
-                                                             RV[p][n], v_nw, vn[n], w_w, wc[n], w_tw, wt[n], dxi,
-                                                             dyi, dzik);
-                    }
-                    tstore<NT, T, VX>(a.ut + c_own + (int64_t)k * ks, Q[p]);
-                }
-                if (ld_own && k + 3 <= k1) fload<NT, T, VX>(ub, U + c_own + (int64_t)(k + 3) * ks);
+            if (k >= k1) return;
+            const int p = s & 1, q = p ^ 1;
+            T(&ub)[VX] = RU[(s + 3) & 3];  // level k-1; refilled with k+3 after use
+            T(&uc)[VX] = RU[s & 3];
+            T(&ut_)[VX] = RU[(s + 1) & 3];
+            T(&wc)[VX] = RW[s & 3];
+            T(&wt)[VX] = RW[(s + 1) & 3];
+            T(&wnx)[VX] = RW[(s + 3) & 3];  // w of level k-1 is not needed: prefetch k+3
+            // prefetches, clamped to level k1 (<= ktot+1) near the end of the tile where unused
+            const int64_t l3 = (int64_t)min(k + 3, k1) * ks, l1 = (int64_t)(k + 1) * ks;
+            fload<NT, T, VX>(wnx, W + c_own + l3);
+            EW[(s + 3) & 3] = W[c_ew + l3];
+            fload<NT, T, VX>(RV[q], V + c_own + l1);
+            tload<NT, T, VX>(Q[q], a.ut + c_own + l1);
+            vload<T, VX>(XU[q], U + c_x + l1);
+            vload<T, VX>(XV[q], V + c_x + l1);
+            EU[q] = U[c_eu + l1];
+            EV[q] = V[c_ev + l1];
+            // level-k rows into LDS: u (own + halo rows), v (own + top halo) and v's left edge
+            if (t.own) {
+                vstore<T, VX>(&shu[p][t.r + 1][t.lane * VX], uc);
+                vstore<T, VX>(&shv[p][t.r + 1][t.lane * VX], RV[p]);
+                if (t.lane == 0) shvl[p][t.r + 1] = EV[p];
             }
+            if (t.xrow_l >= 0) vstore<T, VX>(&shu[p][t.xrow_l][t.lane * VX], XU[p]);
+            if (x_is_top) {
+                vstore<T, VX>(&shv[p][t.xrow_l][t.lane * VX], XV[p]);
+                if (t.lane == 1) shvl[p][t.xrow_l] = EV[p];
+            }
+            __syncthreads();
+            T un[VX], us[VX], vn[VX];
+            vload<T, VX>(un, &shu[p][t.r + 2][t.lane * VX]);
+            vload<T, VX>(us, &shu[p][t.r][t.lane * VX]);
+            vload<T, VX>(vn, &shv[p][t.r + 2][t.lane * VX]);
+            const T vnl_edge = shvl[p][t.r + 2];
+            T uleft = shfl_up1<T>(uc[VX - 1]);
+            T uright = shfl_down1<T>(uc[0]);
+            T vleft = shfl_up1<T>(RV[p][VX - 1]);
+            T vnleft = shfl_up1<T>(vn[VX - 1]);
+            T wleft = shfl_up1<T>(wc[VX - 1]);
+            T wtleft = shfl_up1<T>(wt[VX - 1]);
+            T ur = EU[p];
+            if (t.nlanes == 1) ur = __shfl(ur, 1, 64);
+            if (t.lane == 0) {
+                uleft = EU[p];
+                vleft = EV[p];
+                vnleft = vnl_edge;
+                wleft = EW[s & 3];
+                wtleft = EW[(s + 1) & 3];
+            }
+            if (t.lane == t.nlanes - 1) uright = ur;
+            if (ld_own) {
+                const T dzik = kload(a.dzi, k);
+#pragma unroll
+                for (int n = 0; n < VX; ++n) {
+                    const T uw = n == 0 ? uleft : uc[n - 1];
+                    const T ue = n == VX - 1 ? uright : uc[n + 1];
+                    const T v_w = n == 0 ? vleft : RV[p][n - 1];
+                    const T v_nw = n == 0 ? vnleft : vn[n - 1];
+                    const T w_w = n == 0 ? wleft : wc[n - 1];
+                    const T w_tw = n == 0 ? wtleft : wt[n - 1];
+                    Q[p][n] = Q[p][n] + advec_u_point<T>(uc[n], ue, uw, un[n], us[n], ut_[n], ub[n], v_w,
+                                                         RV[p][n], v_nw, vn[n], w_w, wc[n], w_tw, wt[n], dxi,
+                                                         dyi, dzik);
+                }
+                tstore<NT, T, VX>(a.ut + c_own + (int64_t)k * ks, Q[p]);
+            }
+            fload<NT, T, VX>(ub, U + c_own + l3);
         }
     }
 }
