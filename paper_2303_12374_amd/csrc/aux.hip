@@ -181,7 +181,7 @@ __global__ __launch_bounds__(256) void euler_batch_kernel(const StencilArgs<T> *
 {
     for (int n = blockIdx.x; n < ntiles; n += gridDim.x) {
         const int4 tl = tiles[n];
-        const StencilArgs<T> a = grids[tl.x];
+        const StencilArgs<T> a = global_args(grids[tl.x]);
         const Dims d{a.itot, a.jtot, a.ktot, a.bc, a.off, a.js, a.ks};
         const T dt = (T)dts[tl.x];
         for (int r = tl.y; r < tl.z; ++r) {

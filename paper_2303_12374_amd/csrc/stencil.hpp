@@ -30,6 +30,33 @@ struct StencilArgs {
     const T *evisc;          // eddy viscosity at cell centers (diff_smag only)
 };
 
+// The batched kernels read their descriptors from memory, so the compiler
+// cannot see that the pointers in them address global memory and would use
+// flat instructions (counted as both vector-memory and LDS operations, and
+// waited for conservatively).  Passing each pointer through the global
+// address space states the fact; the compiler's address-space inference then
+// selects global loads and stores for every access derived from it.
+template <typename T>
+__device__ __forceinline__ T *as_global(T *p)
+{
+    typedef __attribute__((address_space(1))) T GT;
+    return (T *)(GT *)(uintptr_t)p;
+}
+
+template <typename T>
+__device__ __forceinline__ StencilArgs<T> global_args(const StencilArgs<T> &in)
+{
+    StencilArgs<T> a = in;
+    a.u = as_global(a.u);
+    a.v = as_global(a.v);
+    a.w = as_global(a.w);
+    a.ut = as_global(a.ut);
+    a.vt = as_global(a.vt);
+    a.wt = as_global(a.wt);
+    a.evisc = as_global(a.evisc);
+    return a;
+}
+
 // ---------------------------------------------------------------------------
 // per-point arithmetic
 // ---------------------------------------------------------------------------

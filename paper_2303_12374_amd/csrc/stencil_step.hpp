@@ -47,18 +47,27 @@ __device__ __forceinline__ void put_with_images(T *f, const StencilArgs<T> &a, i
     if (j == a.jtot) yj[ny++] = 0;
     if (j == 1) yj[ny++] = a.jtot + 1;
     const bool x_lo = i0 == 1, x_hi = i0 + VX - 1 == a.itot;
-    for (int z = 0; z < nz; ++z) {
-        T v[VX];
+    // fixed trip counts (at most 4 z images and 3 y images), unrolled: the
+    // number of stores a wave issues is then known on every path, which
+    // keeps the compiler's waits for earlier loads exact
 #pragma unroll
-        for (int n = 0; n < VX; ++n) v[n] = zs[z] == 0 ? T(0) : (zs[z] < 0 ? -val[n] : val[n]);
-        for (int y = 0; y < ny; ++y) {
-            const int64_t base = a.off + (int64_t)yj[y] * a.js + (int64_t)zk[z] * a.ks;
-            if (z == 0 && y == 0)
-                tstore<NT, T, VX>(f + base + i0, v);
-            else
-                vstore<T, VX>(f + base + i0, v);
-            if (x_lo) f[base + a.itot + 1] = v[0];
-            if (x_hi) f[base] = v[VX - 1];
+    for (int z = 0; z < 4; ++z) {
+        if (z < nz) {
+            T v[VX];
+#pragma unroll
+            for (int n = 0; n < VX; ++n) v[n] = zs[z] == 0 ? T(0) : (zs[z] < 0 ? -val[n] : val[n]);
+#pragma unroll
+            for (int y = 0; y < 3; ++y) {
+                if (y < ny) {
+                    const int64_t base = a.off + (int64_t)yj[y] * a.js + (int64_t)zk[z] * a.ks;
+                    if (z == 0 && y == 0)
+                        tstore<NT, T, VX>(f + base + i0, v);
+                    else
+                        vstore<T, VX>(f + base + i0, v);
+                    if (x_lo) f[base + a.itot + 1] = v[0];
+                    if (x_hi) f[base] = v[VX - 1];
+                }
+            }
         }
     }
 }
@@ -75,13 +84,20 @@ __device__ __forceinline__ void step_zl_tile(const StencilArgs<T> &a, int tx, in
 
     const ZlTile<VX, BY, KB> t(a.itot, a.jtot, a.ktot, tx, ty, tz);
     const int64_t js = a.js, ks = a.ks;
-    const int64_t c_own = a.off + t.i0 + (int64_t)(t.j0 + t.r) * js;
-    const int64_t c_x = a.off + t.i0 + (int64_t)t.xrow_g * js;
-    const bool ld_own = t.own && t.lane_on;
-    const bool ld_x = t.xrow_g >= 0 && t.lane_on;
+    // every load of the level loop is unconditional and inside the field
+    // (clamped lane and row, a re-read of the own row for waves without a
+    // halo row, level k1 for the last levels' prefetch, one scalar load per
+    // field for both x edges), as in the diff_uvw tile
+    const int lane_c = min(t.lane, t.nlanes - 1);
+    const int64_t row_c = a.off + t.i0w + (int64_t)min(t.j0 + t.r, a.jtot) * js;
+    const int64_t c_own = row_c + lane_c * VX;
     const bool x_is_top = t.xrow_g >= 0 && t.xrow_l > 0;
-    const bool edge_l = t.own && t.lane == 0;
-    const bool edge_r = t.own && t.lane == t.nlanes - 1;
+    const int64_t xrow0 = a.off + t.i0w + (int64_t)max(t.xrow_g, 0) * js;
+    const int64_t c_x = t.xrow_g >= 0 ? xrow0 + lane_c * VX : c_own;
+    const int le = max(t.nlanes - 1, 1);
+    const int64_t c_e = t.lane == 0 ? row_c - 1 : (t.lane == le ? row_c + t.nlanes * VX : c_own);
+    const int64_t c_xv = x_is_top && t.lane == 0 ? xrow0 - 1 : c_own;  // v left of the top halo row
+    const bool ld_own = t.own && t.lane_on;
     const T *F[3] = {a.u, a.v, a.w};
     T *O[3] = {a.ut, a.vt, a.wt};  // output fields
     const T dxi = a.dxi, dyi = a.dyi, dxi2 = a.dxi * a.dxi, dyi2 = a.dyi * a.dyi, visc = a.visc, dt = a.dt;
@@ -89,126 +105,106 @@ __device__ __forceinline__ void step_zl_tile(const StencilArgs<T> &a, int tx, in
     const int j = t.j0 + t.r;
 
     T R[4][3][VX];        // field ring: slot s%4 holds level kk+s
-    T EL[4][3], ER[4][3]; // x edge values, same ring
-    T X[2][3][VX];        // halo row, by level parity
-    T XVL[2];             // v left edge of the top halo row
-#pragma unroll
-    for (int f = 0; f < 3; ++f) {
-#pragma unroll
-        for (int n = 0; n < VX; ++n) {
-            R[0][f][n] = R[1][f][n] = R[2][f][n] = R[3][f][n] = T(0);
-            X[0][f][n] = X[1][f][n] = T(0);
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) EL[q][f] = ER[q][f] = T(0);
-    }
-    XVL[0] = XVL[1] = T(0);
+    T E[4][3];            // x edge values (left in lane 0, right in lane le), same ring
+    T X[2][3][VX];        // halo row (or a re-read of the own row), by level parity
+    T XVL[2];             // v left edge of the top halo row (lane 0)
 
     const int k0 = t.k0, k1 = t.k1;
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
-        if (ld_own) {
-            vload<T, VX>(R[3][f], F[f] + c_own + (int64_t)(k0 - 1) * ks);
-            vload<T, VX>(R[0][f], F[f] + c_own + (int64_t)k0 * ks);
-            vload<T, VX>(R[1][f], F[f] + c_own + (int64_t)(k0 + 1) * ks);
-            if (k0 + 2 <= k1) vload<T, VX>(R[2][f], F[f] + c_own + (int64_t)(k0 + 2) * ks);
-        }
-        if (ld_x) vload<T, VX>(X[0][f], F[f] + c_x + (int64_t)k0 * ks);
+        vload<T, VX>(R[3][f], F[f] + c_own + (int64_t)(k0 - 1) * ks);
+        vload<T, VX>(R[0][f], F[f] + c_own + (int64_t)k0 * ks);
+        vload<T, VX>(R[1][f], F[f] + c_own + (int64_t)(k0 + 1) * ks);
+        vload<T, VX>(R[2][f], F[f] + c_own + (int64_t)min(k0 + 2, k1) * ks);
+        vload<T, VX>(X[0][f], F[f] + c_x + (int64_t)k0 * ks);
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            if (k0 + q <= k1) {
-                if (edge_l) EL[q][f] = F[f][c_own + (int64_t)(k0 + q) * ks - 1];
-                if (edge_r) ER[q][f] = F[f][c_own + (int64_t)(k0 + q) * ks + VX];
-            }
-        }
+        for (int q = 0; q < 3; ++q) E[q][f] = F[f][c_e + (int64_t)min(k0 + q, k1) * ks];
     }
-    if (x_is_top && t.lane == 0) XVL[0] = a.v[c_x + (int64_t)k0 * ks - 1];
+    XVL[0] = a.v[c_xv + (int64_t)k0 * ks];
 
     vm_drain();
-    for (int kk = k0; kk < k1; kk += 4) {
+    for (int kk = k0;; kk += 4) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const int k = kk + s;
-            if (k < k1) {
-                const int p = s & 1, q = p ^ 1;
-                T(&b)[3][VX] = R[(s + 3) & 3];  // level k-1; refilled with k+3 after use
-                T(&c)[3][VX] = R[s & 3];
-                T(&tp)[3][VX] = R[(s + 1) & 3];
-                // halo row of level k+1
-                if (k + 1 < k1) {
+            if (k >= k1) return;
+            const int p = s & 1, q = p ^ 1;
+            T(&b)[3][VX] = R[(s + 3) & 3];  // level k-1; refilled with k+3 after use
+            T(&c)[3][VX] = R[s & 3];
+            T(&tp)[3][VX] = R[(s + 1) & 3];
+            // halo row of level k+1 (<= k1 <= ktot+1)
 #pragma unroll
-                    for (int f = 0; f < 3; ++f)
-                        if (ld_x) vload<T, VX>(X[q][f], F[f] + c_x + (int64_t)(k + 1) * ks);
-                    if (x_is_top && t.lane == 0) XVL[q] = a.v[c_x + (int64_t)(k + 1) * ks - 1];
-                }
-                // level-k rows into LDS
+            for (int f = 0; f < 3; ++f) vload<T, VX>(X[q][f], F[f] + c_x + (int64_t)(k + 1) * ks);
+            XVL[q] = a.v[c_xv + (int64_t)(k + 1) * ks];
+            // level-k rows into LDS
 #pragma unroll
-                for (int f = 0; f < 3; ++f) {
-                    if (t.own) vstore<T, VX>(&sh[p][f][t.r + 1][t.lane * VX], c[f]);
-                    if (t.xrow_l >= 0) vstore<T, VX>(&sh[p][f][t.xrow_l][t.lane * VX], X[p][f]);
-                }
-                if (t.own && t.lane == 0) shvl[p][t.r + 1] = EL[s & 3][1];
-                if (x_is_top && t.lane == 0) shvl[p][t.xrow_l] = XVL[p];
-                __syncthreads();
-                T nn[3][VX], ss[3][VX], left[3], right[3];
+            for (int f = 0; f < 3; ++f) {
+                if (t.own) vstore<T, VX>(&sh[p][f][t.r + 1][t.lane * VX], c[f]);
+                if (t.xrow_l >= 0) vstore<T, VX>(&sh[p][f][t.xrow_l][t.lane * VX], X[p][f]);
+            }
+            if (t.own && t.lane == 0) shvl[p][t.r + 1] = E[s & 3][1];
+            if (x_is_top && t.lane == 0) shvl[p][t.xrow_l] = XVL[p];
+            __syncthreads();
+            T nn[3][VX], ss[3][VX], left[3], right[3];
 #pragma unroll
-                for (int f = 0; f < 3; ++f) {
-                    vload<T, VX>(nn[f], &sh[p][f][t.r + 2][t.lane * VX]);
-                    vload<T, VX>(ss[f], &sh[p][f][t.r][t.lane * VX]);
-                    left[f] = shfl_up1<T>(c[f][VX - 1]);
-                    right[f] = shfl_down1<T>(c[f][0]);
-                    if (t.lane == 0) left[f] = EL[s & 3][f];
-                    if (t.lane == t.nlanes - 1) right[f] = ER[s & 3][f];
-                }
-                T vnleft = shfl_up1<T>(nn[1][VX - 1]);
-                T wtleft = shfl_up1<T>(tp[2][VX - 1]);
-                if (t.lane == 0) {
-                    vnleft = shvl[p][t.r + 2];
-                    wtleft = EL[(s + 1) & 3][2];
-                }
-                if (ld_own) {
-                    const T dzik = kload(a.dzi, k), dzikm1 = kload(a.dzi, k - 1), dzhik = kload(a.dzhi, k), dzhik1 = kload(a.dzhi, k + 1);
-                    T nu[VX], nv[VX], nw[VX];
+            for (int f = 0; f < 3; ++f) {
+                vload<T, VX>(nn[f], &sh[p][f][t.r + 2][t.lane * VX]);
+                vload<T, VX>(ss[f], &sh[p][f][t.r][t.lane * VX]);
+                left[f] = shfl_up1<T>(c[f][VX - 1]);
+                right[f] = shfl_down1<T>(c[f][0]);
+                T er = E[s & 3][f];
+                if (t.nlanes == 1) er = __shfl(er, 1, 64);
+                if (t.lane == 0) left[f] = E[s & 3][f];
+                if (t.lane == t.nlanes - 1) right[f] = er;
+            }
+            T vnleft = shfl_up1<T>(nn[1][VX - 1]);
+            T wtleft = shfl_up1<T>(tp[2][VX - 1]);
+            if (t.lane == 0) {
+                vnleft = shvl[p][t.r + 2];
+                wtleft = E[(s + 1) & 3][2];
+            }
+            if (ld_own) {
+                const T dzik = kload(a.dzi, k), dzikm1 = kload(a.dzi, k - 1), dzhik = kload(a.dzhi, k),
+                        dzhik1 = kload(a.dzhi, k + 1);
+                T nu[VX], nv[VX], nw[VX];
 #pragma unroll
-                    for (int n = 0; n < VX; ++n) {
-                        const T uw = n == 0 ? left[0] : c[0][n - 1];
-                        const T ue = n == VX - 1 ? right[0] : c[0][n + 1];
-                        const T vw = n == 0 ? left[1] : c[1][n - 1];
-                        const T ve = n == VX - 1 ? right[1] : c[1][n + 1];
-                        const T ww = n == 0 ? left[2] : c[2][n - 1];
-                        const T we = n == VX - 1 ? right[2] : c[2][n + 1];
-                        const T v_nw = n == 0 ? vnleft : nn[1][n - 1];
-                        const T w_tw = n == 0 ? wtleft : tp[2][n - 1];
-                        const T adv = advec_u_point<T>(c[0][n], ue, uw, nn[0][n], ss[0][n], tp[0][n], b[0][n], vw,
-                                                       c[1][n], v_nw, nn[1][n], ww, c[2][n], w_tw, tp[2][n], dxi,
-                                                       dyi, dzik);
-                        const T du = diff_c_point<T>(c[0][n], ue, uw, nn[0][n], ss[0][n], tp[0][n], b[0][n], dxi2,
-                                                     dyi2, dzik, dzhik1, dzhik, visc);
-                        const T dv = diff_c_point<T>(c[1][n], ve, vw, nn[1][n], ss[1][n], tp[1][n], b[1][n], dxi2,
-                                                     dyi2, dzik, dzhik1, dzhik, visc);
-                        const T tu = (T(0) + adv) + du;
-                        const T tv = T(0) + dv;
-                        nu[n] = c[0][n] + dt * tu;
-                        nv[n] = c[1][n] + dt * tv;
-                        if (k >= kw0) {
-                            const T dw = diff_w_point<T>(c[2][n], we, ww, nn[2][n], ss[2][n], tp[2][n], b[2][n],
-                                                         dxi2, dyi2, dzik, dzikm1, dzhik, visc);
-                            nw[n] = c[2][n] + dt * (T(0) + dw);
-                        }
-                    }
-                    put_with_images<T, VX, NT>(O[0], a, 0, t.i0, j, k, nu);
-                    put_with_images<T, VX, NT>(O[1], a, 1, t.i0, j, k, nv);
-                    if (k >= kw0) put_with_images<T, VX, NT>(O[2], a, 2, t.i0, j, k, nw);
-                }
-                // level k-1 is no longer needed: its slot takes level k+3
-                if (k + 3 <= k1) {
-#pragma unroll
-                    for (int f = 0; f < 3; ++f) {
-                        if (ld_own) fload<NT, T, VX>(b[f], F[f] + c_own + (int64_t)(k + 3) * ks);
-                        if (edge_l) EL[(s + 3) & 3][f] = F[f][c_own + (int64_t)(k + 3) * ks - 1];
-                        if (edge_r) ER[(s + 3) & 3][f] = F[f][c_own + (int64_t)(k + 3) * ks + VX];
+                for (int n = 0; n < VX; ++n) {
+                    const T uw = n == 0 ? left[0] : c[0][n - 1];
+                    const T ue = n == VX - 1 ? right[0] : c[0][n + 1];
+                    const T vw = n == 0 ? left[1] : c[1][n - 1];
+                    const T ve = n == VX - 1 ? right[1] : c[1][n + 1];
+                    const T ww = n == 0 ? left[2] : c[2][n - 1];
+                    const T we = n == VX - 1 ? right[2] : c[2][n + 1];
+                    const T v_nw = n == 0 ? vnleft : nn[1][n - 1];
+                    const T w_tw = n == 0 ? wtleft : tp[2][n - 1];
+                    const T adv = advec_u_point<T>(c[0][n], ue, uw, nn[0][n], ss[0][n], tp[0][n], b[0][n], vw,
+                                                   c[1][n], v_nw, nn[1][n], ww, c[2][n], w_tw, tp[2][n], dxi,
+                                                   dyi, dzik);
+                    const T du = diff_c_point<T>(c[0][n], ue, uw, nn[0][n], ss[0][n], tp[0][n], b[0][n], dxi2,
+                                                 dyi2, dzik, dzhik1, dzhik, visc);
+                    const T dv = diff_c_point<T>(c[1][n], ve, vw, nn[1][n], ss[1][n], tp[1][n], b[1][n], dxi2,
+                                                 dyi2, dzik, dzhik1, dzhik, visc);
+                    const T tu = (T(0) + adv) + du;
+                    const T tv = T(0) + dv;
+                    nu[n] = c[0][n] + dt * tu;
+                    nv[n] = c[1][n] + dt * tv;
+                    if (k >= kw0) {
+                        const T dw = diff_w_point<T>(c[2][n], we, ww, nn[2][n], ss[2][n], tp[2][n], b[2][n],
+                                                     dxi2, dyi2, dzik, dzikm1, dzhik, visc);
+                        nw[n] = c[2][n] + dt * (T(0) + dw);
                     }
                 }
+                put_with_images<T, VX, NT>(O[0], a, 0, t.i0, j, k, nu);
+                put_with_images<T, VX, NT>(O[1], a, 1, t.i0, j, k, nv);
+                if (k >= kw0) put_with_images<T, VX, NT>(O[2], a, 2, t.i0, j, k, nw);
+            }
+            // level k-1 is no longer needed: its slot takes level k+3 (clamped
+            // to k1 near the end of the tile, where it is not used)
+            const int64_t l3 = (int64_t)min(k + 3, k1) * ks;
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                fload<NT, T, VX>(b[f], F[f] + c_own + l3);
+                E[(s + 3) & 3][f] = F[f][c_e + l3];
             }
         }
     }
@@ -228,7 +224,7 @@ __global__ __launch_bounds__(64 * BY, WPE) void step_zl_batch(const StencilArgs<
 {
     for (int n = blockIdx.x; n < ntiles; n += gridDim.x) {
         const int4 tl = tiles[n];
-        const StencilArgs<T> a = grids[tl.x];
+        const StencilArgs<T> a = global_args(grids[tl.x]);
         step_zl_tile<T, VX, BY, KB, NT>(a, tl.y, tl.z, tl.w);
     }
 }

@@ -357,7 +357,7 @@ __global__ __launch_bounds__(64 * BY, WPE) void diff_uvw_zl_batch(const StencilA
 {
     for (int n = blockIdx.x; n < ntiles; n += gridDim.x) {
         const int4 tl = tiles[n];
-        const StencilArgs<T> a = grids[tl.x];
+        const StencilArgs<T> a = global_args(grids[tl.x]);
         diff_uvw_zl_tile<T, VX, BY, KB, NT>(a, tl.y, tl.z, tl.w);
     }
 }
@@ -368,7 +368,7 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_zl_batch(const StencilAr
 {
     for (int n = blockIdx.x; n < ntiles; n += gridDim.x) {
         const int4 tl = tiles[n];
-        const StencilArgs<T> a = grids[tl.x];
+        const StencilArgs<T> a = global_args(grids[tl.x]);
         advec_u_zl_tile<T, VX, BY, KB, NT>(a, tl.y, tl.z, tl.w);
     }
 }
@@ -381,7 +381,7 @@ __global__ __launch_bounds__(256) void zero_tendencies_batch(const StencilArgs<T
 {
     for (int n = blockIdx.x; n < ntiles; n += gridDim.x) {
         const int4 tl = tiles[n];
-        const StencilArgs<T> a = grids[tl.x];
+        const StencilArgs<T> a = global_args(grids[tl.x]);
         for (int r = tl.y; r < tl.z; ++r) {
             const int j = 1 + r % a.jtot, k = 1 + r / a.jtot;
             const int64_t base = a.off + (int64_t)j * a.js + (int64_t)k * a.ks;
