@@ -172,7 +172,8 @@ def test_diff_smag_on_one_ghost_cell_grid(dtype):
         assert err <= TOL[dtype], f"smag {n} on gc=1: rel err {err:.3e}"
 
 
-@pytest.mark.parametrize("shape", [(64, 64, 64), (96, 40, 37), (256, 3, 70)], ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("shape", [(64, 64, 64), (96, 40, 37), (256, 3, 70), (260, 6, 9), (130, 5, 11), (65, 4, 7)],
+                         ids=lambda s: "x".join(map(str, s)))
 @pytest.mark.parametrize("dtype", [0, 1], ids=["f32", "f64"])
 @pytest.mark.parametrize("kernel", [3, 4], ids=["advec_u_2i5", "diff_smag"])
 def test_every_les_configuration_bitwise_equal(kernel, dtype, shape):

@@ -22,7 +22,9 @@ def no_wisdom(tmp_path):
     m.kl_set_wisdom_dir(None)
 
 
-SHAPES = [(64, 48, 20), (37, 23, 19), (256, 12, 9), (5, 4, 6), (128, 64, 33), (96, 3, 2)]
+# 260, 130 and 65 leave one active lane in the last x tile at 4, 2 and 1 points per lane
+SHAPES = [(64, 48, 20), (37, 23, 19), (256, 12, 9), (5, 4, 6), (128, 64, 33), (96, 3, 2), (260, 6, 9), (130, 5, 11),
+          (65, 4, 7)]
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))
