@@ -41,6 +41,25 @@ __device__ __forceinline__ void col_load(T (&d)[VX], const T *p, int64_t ks, int
     }
 }
 
+// LDS row of W columns stored as VX planes: column c at (c % VX) * P + c / VX
+// with P = ceil(W / VX).  Lane l's points c = VX*l + m then sit at unit stride
+// across the lanes for every fixed m, so a wave's row access is free of bank
+// conflicts (with VX consecutive 4-byte columns per lane a plain row is read
+// at stride VX).  VX = 1 is the plain row.  Used for 4-byte elements only:
+// 8-byte elements at a 16-byte lane stride measured faster in plain rows.
+template <typename T, int VX>
+constexpr int planar_vx()
+{
+    return sizeof(T) == 4 ? VX : 1;
+}
+
+template <int VX, int W>
+struct PlanarRow {
+    static constexpr int P = (W + VX - 1) / VX;
+    static constexpr int SIZE = VX * P;
+    __device__ static __forceinline__ int at(int c) { return (c % VX) * P + c / VX; }
+};
+
 template <typename T, int VX, int BY, int KB, int XCD, int NT, int WPE>
 __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zl(StencilArgs<T> a)
 {
@@ -48,8 +67,10 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zl(StencilArgs<T> a)
     constexpr int SW = TX + 6;               // u row in LDS: columns i0w-3 .. i0w+TX+2
     constexpr int VW = TX + 1;               // v row in LDS: columns i0w-1 .. i0w+TX-1
     constexpr int NH = (6 + BY - 1) / BY;    // u halo rows per wave (upper bound)
-    __shared__ __align__(16) T su[2][BY + 6][SW];
-    __shared__ __align__(16) T sv[2][BY + 1][VW];
+    typedef PlanarRow<planar_vx<T, VX>(), SW> UR;  // u rows, planar by VX (4-byte T)
+    typedef PlanarRow<planar_vx<T, VX>(), VW> VR;  // v rows, likewise
+    __shared__ __align__(16) T su[2][BY + 6][UR::SIZE];
+    __shared__ __align__(16) T sv[2][BY + 1][VR::SIZE];
 
     int tx, ty, tz;
     tile_of<64, BY, XCD>(a.nbx, a.nby, a.nbz, tx, ty, tz);
@@ -170,18 +191,18 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zl(StencilArgs<T> a)
         if (own && lane_on) {
 #pragma unroll
             for (int n = 0; n < VX; ++n) {
-                su[p][r + 3][3 + xo + n] = S[2][n];
-                sv[p][r][1 + xo + n] = VO[0][n];
+                su[p][r + 3][UR::at(3 + xo + n)] = S[2][n];
+                sv[p][r][VR::at(1 + xo + n)] = VO[0][n];
             }
         }
         if (own && edge_l) {
 #pragma unroll
-            for (int e = 0; e < 3; ++e) su[p][r + 3][e] = OUL[0][e];
-            sv[p][r][0] = VOL[0];
+            for (int e = 0; e < 3; ++e) su[p][r + 3][UR::at(e)] = OUL[0][e];
+            sv[p][r][VR::at(0)] = VOL[0];
         }
         if (own && edge_r) {
 #pragma unroll
-            for (int e = 0; e < 3; ++e) su[p][r + 3][3 + nlanes * VX + e] = OUR[0][e];
+            for (int e = 0; e < 3; ++e) su[p][r + 3][UR::at(3 + nlanes * VX + e)] = OUR[0][e];
         }
 #pragma unroll
         for (int m = 0; m < NH; ++m) {
@@ -189,24 +210,24 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zl(StencilArgs<T> a)
             if (rho >= 0) {
                 if (lane_on) {
 #pragma unroll
-                    for (int n = 0; n < VX; ++n) su[p][rho][3 + xo + n] = HU[0][m][n];
+                    for (int n = 0; n < VX; ++n) su[p][rho][UR::at(3 + xo + n)] = HU[0][m][n];
                 }
                 if (edge_l) {
 #pragma unroll
-                    for (int e = 0; e < 3; ++e) su[p][rho][e] = HUL[0][m][e];
+                    for (int e = 0; e < 3; ++e) su[p][rho][UR::at(e)] = HUL[0][m][e];
                 }
                 if (edge_r) {
 #pragma unroll
-                    for (int e = 0; e < 3; ++e) su[p][rho][3 + nlanes * VX + e] = HUR[0][m][e];
+                    for (int e = 0; e < 3; ++e) su[p][rho][UR::at(3 + nlanes * VX + e)] = HUR[0][m][e];
                 }
             }
         }
         if (vhalo) {
             if (lane_on) {
 #pragma unroll
-                for (int n = 0; n < VX; ++n) sv[p][nv][1 + xo + n] = VH[0][n];
+                for (int n = 0; n < VX; ++n) sv[p][nv][VR::at(1 + xo + n)] = VH[0][n];
             }
-            if (edge_l) sv[p][nv][0] = VHL[0];
+            if (edge_l) sv[p][nv][VR::at(0)] = VHL[0];
         }
         // 2. prefetch level k+1 and the u window's next level
         if (k + 1 < k1) load_level(1, k + 1);
@@ -220,7 +241,7 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zl(StencilArgs<T> a)
         if (own && lane_on) {
             T uxr[VX + 6];
 #pragma unroll
-            for (int m = 0; m < VX + 6; ++m) uxr[m] = su[p][r + 3][xo + m];
+            for (int m = 0; m < VX + 6; ++m) uxr[m] = su[p][r + 3][UR::at(xo + m)];
             T FX[VX + 1];
 #pragma unroll
             for (int f = 0; f <= VX; ++f)
@@ -230,12 +251,12 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zl(StencilArgs<T> a)
             T res[VX];
 #pragma unroll
             for (int n = 0; n < VX; ++n) {
-                const int x = 3 + xo + n;
+                const int xu = UR::at(3 + xo + n);
                 T col[7];
 #pragma unroll
-                for (int m = 0; m < 7; ++m) col[m] = su[p][r + m][x];
-                const T vn = mid(sv[p][r + 1][xo + n], sv[p][r + 1][xo + n + 1]);
-                const T vs = mid(sv[p][r][xo + n], sv[p][r][xo + n + 1]);
+                for (int m = 0; m < 7; ++m) col[m] = su[p][r + m][xu];
+                const T vn = mid(sv[p][r + 1][VR::at(xo + n)], sv[p][r + 1][VR::at(xo + n + 1)]);
+                const T vs = mid(sv[p][r][VR::at(xo + n)], sv[p][r][VR::at(xo + n + 1)]);
                 const T fn = flux5(vn, col[1], col[2], col[3], col[4], col[5], col[6]);
                 const T fs = flux5(vs, col[0], col[1], col[2], col[3], col[4], col[5]);
                 const T wm = n == 0 ? wl : WR[0][n - 1];
@@ -292,8 +313,10 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zlp(StencilArgs<T> a
     constexpr int SW = TX + 6;               // u row in LDS: columns i0w-3 .. i0w+TX+2
     constexpr int VW = TX + 1;               // v row in LDS: columns i0w-1 .. i0w+TX-1
     constexpr int NH = (6 + BY - 1) / BY;    // u halo rows per wave (upper bound)
-    __shared__ __align__(16) T su[2][BY + 6][SW];
-    __shared__ __align__(16) T sv[2][BY + 1][VW];
+    typedef PlanarRow<planar_vx<T, VX>(), SW> UR;  // u rows, planar by VX (4-byte T)
+    typedef PlanarRow<planar_vx<T, VX>(), VW> VR;  // v rows, likewise
+    __shared__ __align__(16) T su[2][BY + 6][UR::SIZE];
+    __shared__ __align__(16) T sv[2][BY + 1][VR::SIZE];
 
     int tx, ty, tz;
     tile_of<64, BY, XCD>(a.nbx, a.nby, a.nbz, tx, ty, tz);
@@ -425,18 +448,18 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zlp(StencilArgs<T> a
         if (own && lane_on) {
 #pragma unroll
             for (int n = 0; n < VX; ++n) {
-                su[P][r + 3][3 + xo + n] = S[2 + P][n];
-                sv[P][r][1 + xo + n] = VO[P][n];
+                su[P][r + 3][UR::at(3 + xo + n)] = S[2 + P][n];
+                sv[P][r][VR::at(1 + xo + n)] = VO[P][n];
             }
         }
         if (own && edge_l) {
 #pragma unroll
-            for (int e = 0; e < 3; ++e) su[P][r + 3][e] = OUL[P][e];
-            sv[P][r][0] = VOL[P];
+            for (int e = 0; e < 3; ++e) su[P][r + 3][UR::at(e)] = OUL[P][e];
+            sv[P][r][VR::at(0)] = VOL[P];
         }
         if (own && edge_r) {
 #pragma unroll
-            for (int e = 0; e < 3; ++e) su[P][r + 3][3 + nlanes * VX + e] = OUR[P][e];
+            for (int e = 0; e < 3; ++e) su[P][r + 3][UR::at(3 + nlanes * VX + e)] = OUR[P][e];
         }
 #pragma unroll
         for (int m = 0; m < NH; ++m) {
@@ -444,24 +467,24 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zlp(StencilArgs<T> a
             if (rho >= 0) {
                 if (lane_on) {
 #pragma unroll
-                    for (int n = 0; n < VX; ++n) su[P][rho][3 + xo + n] = HU[P][m][n];
+                    for (int n = 0; n < VX; ++n) su[P][rho][UR::at(3 + xo + n)] = HU[P][m][n];
                 }
                 if (edge_l) {
 #pragma unroll
-                    for (int e = 0; e < 3; ++e) su[P][rho][e] = HUL[P][m][e];
+                    for (int e = 0; e < 3; ++e) su[P][rho][UR::at(e)] = HUL[P][m][e];
                 }
                 if (edge_r) {
 #pragma unroll
-                    for (int e = 0; e < 3; ++e) su[P][rho][3 + nlanes * VX + e] = HUR[P][m][e];
+                    for (int e = 0; e < 3; ++e) su[P][rho][UR::at(3 + nlanes * VX + e)] = HUR[P][m][e];
                 }
             }
         }
         if (vhalo) {
             if (lane_on) {
 #pragma unroll
-                for (int n = 0; n < VX; ++n) sv[P][nv][1 + xo + n] = VH[P][n];
+                for (int n = 0; n < VX; ++n) sv[P][nv][VR::at(1 + xo + n)] = VH[P][n];
             }
-            if (edge_l) sv[P][nv][0] = VHL[P];
+            if (edge_l) sv[P][nv][VR::at(0)] = VHL[P];
         }
         // 2. prefetch level k+1 into the other slot and the u window's k+5
         if (k + 1 < k1) load_level(std::integral_constant<int, Q>(), k + 1);
@@ -474,7 +497,7 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zlp(StencilArgs<T> a
         if (own && lane_on) {
             T uxr[VX + 6];
 #pragma unroll
-            for (int m = 0; m < VX + 6; ++m) uxr[m] = su[P][r + 3][xo + m];
+            for (int m = 0; m < VX + 6; ++m) uxr[m] = su[P][r + 3][UR::at(xo + m)];
             T FX[VX + 1];
 #pragma unroll
             for (int f = 0; f <= VX; ++f)
@@ -484,12 +507,12 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zlp(StencilArgs<T> a
             T res[VX];
 #pragma unroll
             for (int n = 0; n < VX; ++n) {
-                const int x = 3 + xo + n;
+                const int xu = UR::at(3 + xo + n);
                 T col[7];
 #pragma unroll
-                for (int m = 0; m < 7; ++m) col[m] = su[P][r + m][x];
-                const T vn = mid(sv[P][r + 1][xo + n], sv[P][r + 1][xo + n + 1]);
-                const T vs = mid(sv[P][r][xo + n], sv[P][r][xo + n + 1]);
+                for (int m = 0; m < 7; ++m) col[m] = su[P][r + m][xu];
+                const T vn = mid(sv[P][r + 1][VR::at(xo + n)], sv[P][r + 1][VR::at(xo + n + 1)]);
+                const T vs = mid(sv[P][r][VR::at(xo + n)], sv[P][r][VR::at(xo + n + 1)]);
                 const T fn = flux5(vn, col[1], col[2], col[3], col[4], col[5], col[6]);
                 const T fs = flux5(vs, col[0], col[1], col[2], col[3], col[4], col[5]);
                 const T wm = n == 0 ? wl : WR[P][n - 1];
@@ -542,7 +565,8 @@ __global__ __launch_bounds__(64 * BY, WPE) void diff_smag_zl(StencilArgs<T> a)
     constexpr int PW = TX + 2;              // plane row: columns i0w-1 .. i0w+TX
     constexpr int PH = BY + 2;              // plane rows: j0-1 .. j0+BY
     constexpr int NH = (8 + BY - 1) / BY;   // halo rows per wave (8 = 2 rows x 4 fields)
-    __shared__ __align__(16) T pl[4][4][PH][PW];  // [field][level & 3][row][column]
+    typedef PlanarRow<planar_vx<T, VX>(), PW> SR;  // plane rows, planar by VX (4-byte T)
+    __shared__ __align__(16) T pl[4][4][PH][SR::SIZE];  // [field][level & 3][row][column]
 
     int tx, ty, tz;
     tile_of<64, BY, XCD>(a.nbx, a.nby, a.nbz, tx, ty, tz);
@@ -611,10 +635,10 @@ __global__ __launch_bounds__(64 * BY, WPE) void diff_smag_zl(StencilArgs<T> a)
             for (int f = 0; f < 4; ++f) {
                 if (lane_on) {
 #pragma unroll
-                    for (int n = 0; n < VX; ++n) pl[f][b][r + 1][1 + xo + n] = O[q][f][n];
+                    for (int n = 0; n < VX; ++n) pl[f][b][r + 1][SR::at(1 + xo + n)] = O[q][f][n];
                 }
-                if (lane == 0) pl[f][b][r + 1][0] = OE[q][f];
-                if (lane == le) pl[f][b][r + 1][xr] = OE[q][f];
+                if (lane == 0) pl[f][b][r + 1][SR::at(0)] = OE[q][f];
+                if (lane == le) pl[f][b][r + 1][SR::at(xr)] = OE[q][f];
             }
         }
 #pragma unroll
@@ -622,10 +646,10 @@ __global__ __launch_bounds__(64 * BY, WPE) void diff_smag_zl(StencilArgs<T> a)
             if (hf[m] < 0) continue;
             if (lane_on) {
 #pragma unroll
-                for (int n = 0; n < VX; ++n) pl[hf[m]][b][hrow[m]][1 + xo + n] = H[q][m][n];
+                for (int n = 0; n < VX; ++n) pl[hf[m]][b][hrow[m]][SR::at(1 + xo + n)] = H[q][m][n];
             }
-            if (lane == 0) pl[hf[m]][b][hrow[m]][0] = HE[q][m];
-            if (lane == le) pl[hf[m]][b][hrow[m]][xr] = HE[q][m];
+            if (lane == 0) pl[hf[m]][b][hrow[m]][SR::at(0)] = HE[q][m];
+            if (lane == le) pl[hf[m]][b][hrow[m]][SR::at(xr)] = HE[q][m];
         }
     };
     auto load_tend = [&](int q, int k) {     // k <= k1 <= ktot+1
@@ -660,7 +684,7 @@ __global__ __launch_bounds__(64 * BY, WPE) void diff_smag_zl(StencilArgs<T> a)
             for (int n = 0; n < VX; ++n) {
                 const int x = 1 + xo + n;
                 // operand names: <field><offset>; offsets e/w (x), n/s (y), t/b (z)
-#define P(f, b, dj, di) pl[f][b][rr + (dj)][x + (di)]
+#define P(f, b, dj, di) pl[f][b][rr + (dj)][SR::at(x + (di))]
                 const T uc = P(0, bc, 0, 0), ue = P(0, bc, 0, 1), uw = P(0, bc, 0, -1), un = P(0, bc, 1, 0),
                         us = P(0, bc, -1, 0), ut_ = P(0, bp, 0, 0), ub = P(0, bm, 0, 0), use = P(0, bc, -1, 1),
                         ube = P(0, bm, 0, 1);
