@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace kl {
 
 // Arguments of every tendency kernel (passed by value).
@@ -214,6 +216,24 @@ __device__ __forceinline__ T kload(const T *p, int k)
 __device__ __forceinline__ void vm_drain()
 {
     __builtin_amdgcn_s_waitcnt(0x0F70);
+}
+
+// p advanced by a byte offset.  Written as a uniform base plus a 32-bit
+// per-lane offset, a global access takes its base from scalar registers
+// (global_load ... v_off, s[base]) and needs no 64-bit vector address math.
+template <typename T>
+__device__ __forceinline__ T *boff(T *p, uint32_t bytes)
+{
+    typedef typename std::conditional<std::is_const<T>::value, const char, char>::type C;
+    return reinterpret_cast<T *>(reinterpret_cast<C *>(p) + bytes);
+}
+
+// The row of the block a wave works on: threadIdx.y is the same in all lanes
+// of a wave (the blocks are 64 lanes wide), and saying so lets the compiler
+// keep everything derived from it in scalar registers.
+__device__ __forceinline__ int wave_row()
+{
+    return __builtin_amdgcn_readfirstlane((int)threadIdx.y);
 }
 
 // Field load: cached, or streaming when NT >= 2.

@@ -93,6 +93,101 @@ __device__ __forceinline__ T mean4(T a, T b, T c, T d)
     return T(0.25) * ((a + b) + (c + d));
 }
 
+// The vertical stress terms of u and v are differences of two horizontal
+// face values, each a product of a face viscosity (mean of four centers) and
+// a face gradient; w's vertical term is a difference of two center values.
+// A face's value is the same function of its own operands whichever point
+// uses it, so a z-march computes the top face of level k once and reuses it,
+// bit for bit, as the bottom face of level k+1.
+template <typename T>
+struct SmagFace {
+    T e, g;  // face viscosity and face gradient (the stress is e * g)
+};
+
+// u's face at z_{k+1/2} between u(k) = uc and u(k+1) = ut, with the centers
+// e_w, e_c of level k and e_tw, e_t of level k+1 around it and w_t, w_tw at
+// the face; dzh = dzhi[k+1].
+template <typename T>
+__device__ __forceinline__ SmagFace<T> smag_u_zface(T e_w, T e_c, T e_tw, T e_t, T ut, T uc, T w_t, T w_tw,
+                                                    T dxi, T dzh)
+{
+    return {mean4(e_w, e_c, e_tw, e_t), tfma(ut - uc, dzh, (w_t - w_tw) * dxi)};
+}
+
+// v's face at z_{k+1/2}: e_s, e_c (level k), e_ts, e_t (level k+1), v(k+1) =
+// vt, v(k) = vc, w_t, w_ts at the face; dzh = dzhi[k+1].
+template <typename T>
+__device__ __forceinline__ SmagFace<T> smag_v_zface(T e_s, T e_c, T e_ts, T e_t, T vt, T vc, T w_t, T w_ts,
+                                                    T dyi, T dzh)
+{
+    return {mean4(e_s, e_c, e_ts, e_t), tfma(vt - vc, dzh, (w_t - w_ts) * dyi)};
+}
+
+// w's center value between w(k) = wc and w(k+1) = wt: e_c * (wt - wc).
+template <typename T>
+__device__ __forceinline__ T smag_w_zcenter(T e_c, T wt, T wc)
+{
+    return e_c * (wt - wc);
+}
+
+// The horizontal (x and y) stress terms of u, v and w at one point, summed
+// as tx + ty.
+template <typename T>
+__device__ __forceinline__ T smag_u_xy(T uc, T ue, T uw, T un, T us, T v_n, T v_nw, T v_c, T v_w,
+                                       T e_c, T e_w, T e_n, T e_nw, T e_s, T e_sw, T dxi, T dyi)
+{
+    const T tx = tfma(e_c, ue - uc, -(e_w * (uc - uw))) * (T(2) * dxi * dxi);
+    const T en = mean4(e_w, e_c, e_nw, e_n);
+    const T es = mean4(e_sw, e_s, e_w, e_c);
+    const T gn = tfma(un - uc, dyi, (v_n - v_nw) * dxi), gs = tfma(uc - us, dyi, (v_c - v_w) * dxi);
+    const T ty = tfma(en, gn, -(es * gs)) * dyi;
+    return tx + ty;
+}
+
+template <typename T>
+__device__ __forceinline__ T smag_v_xy(T vc, T ve, T vw, T vn, T vs, T u_e, T u_se, T u_c, T u_s,
+                                       T e_c, T e_s, T e_e, T e_se, T e_w, T e_sw, T dxi, T dyi)
+{
+    const T ee = mean4(e_s, e_se, e_c, e_e);
+    const T ew = mean4(e_sw, e_s, e_w, e_c);
+    const T ge = tfma(ve - vc, dxi, (u_e - u_se) * dyi), gw = tfma(vc - vw, dxi, (u_c - u_s) * dyi);
+    const T tx = tfma(ee, ge, -(ew * gw)) * dxi;
+    const T ty = tfma(e_c, vn - vc, -(e_s * (vc - vs))) * (T(2) * dyi * dyi);
+    return tx + ty;
+}
+
+template <typename T>
+__device__ __forceinline__ T smag_w_xy(T wc, T we, T ww, T wn, T ws, T u_e, T u_be, T u_c, T u_b,
+                                       T v_n, T v_bn, T v_c, T v_b,
+                                       T e_c, T e_b, T e_e, T e_be, T e_w, T e_bw, T e_n, T e_bn, T e_s, T e_bs,
+                                       T dxi, T dyi, T dzhik)
+{
+    const T ee = mean4(e_b, e_be, e_c, e_e);
+    const T ew = mean4(e_bw, e_b, e_w, e_c);
+    const T ge = tfma(we - wc, dxi, (u_e - u_be) * dzhik), gw = tfma(wc - ww, dxi, (u_c - u_b) * dzhik);
+    const T tx = tfma(ee, ge, -(ew * gw)) * dxi;
+    const T en = mean4(e_b, e_bn, e_c, e_n);
+    const T es = mean4(e_bs, e_b, e_s, e_c);
+    const T gn = tfma(wn - wc, dyi, (v_n - v_bn) * dzhik), gs = tfma(wc - ws, dyi, (v_c - v_b) * dzhik);
+    const T ty = tfma(en, gn, -(es * gs)) * dyi;
+    return tx + ty;
+}
+
+// Whole tendencies from the horizontal sum and the two vertical face values.
+template <typename T>
+__device__ __forceinline__ T smag_uv_total(T txy, SmagFace<T> top, SmagFace<T> bot, T dzik)
+{
+    const T tz = tfma(top.e, top.g, -(bot.e * bot.g)) * dzik;
+    return txy + tz;
+}
+
+template <typename T>
+__device__ __forceinline__ T smag_w_total(T txy, T top, T bot, T dzik, T dzikm1, T dzhik)
+{
+    const T tz = tfma(top, dzik, -(bot * dzikm1)) * (T(2) * dzhik);
+    return txy + tz;
+}
+
 // u at (xh_i, y_j, z_k).  v_n/v_nw: v(i, j+1), v(i-1, j+1); v_c/v_w: v(i, j),
 // v(i-1, j); w_t/w_tw: w(i, k+1), w(i-1, k+1); w_c/w_w: w(i, k), w(i-1, k).
 template <typename T>
@@ -102,16 +197,9 @@ __device__ __forceinline__ T smag_u(T uc, T ue, T uw, T un, T us, T ut, T ub,
                                     T e_c, T e_w, T e_n, T e_nw, T e_s, T e_sw, T e_t, T e_tw, T e_b, T e_bw,
                                     T dxi, T dyi, T dzik, T dzhik, T dzhik1)
 {
-    const T tx = tfma(e_c, ue - uc, -(e_w * (uc - uw))) * (T(2) * dxi * dxi);
-    const T en = mean4(e_w, e_c, e_nw, e_n);
-    const T es = mean4(e_sw, e_s, e_w, e_c);
-    const T gn = tfma(un - uc, dyi, (v_n - v_nw) * dxi), gs = tfma(uc - us, dyi, (v_c - v_w) * dxi);
-    const T ty = tfma(en, gn, -(es * gs)) * dyi;
-    const T et = mean4(e_w, e_c, e_tw, e_t);
-    const T eb = mean4(e_bw, e_b, e_w, e_c);
-    const T gt = tfma(ut - uc, dzhik1, (w_t - w_tw) * dxi), gb = tfma(uc - ub, dzhik, (w_c - w_w) * dxi);
-    const T tz = tfma(et, gt, -(eb * gb)) * dzik;
-    return tx + ty + tz;
+    const T txy = smag_u_xy(uc, ue, uw, un, us, v_n, v_nw, v_c, v_w, e_c, e_w, e_n, e_nw, e_s, e_sw, dxi, dyi);
+    return smag_uv_total(txy, smag_u_zface(e_w, e_c, e_tw, e_t, ut, uc, w_t, w_tw, dxi, dzhik1),
+                         smag_u_zface(e_bw, e_b, e_w, e_c, uc, ub, w_c, w_w, dxi, dzhik), dzik);
 }
 
 // v at (x_i, yh_j, z_k).  u_e/u_se: u(i+1, j), u(i+1, j-1); u_c/u_s: u(i, j),
@@ -123,16 +211,9 @@ __device__ __forceinline__ T smag_v(T vc, T ve, T vw, T vn, T vs, T vt, T vb,
                                     T e_c, T e_s, T e_e, T e_se, T e_w, T e_sw, T e_t, T e_ts, T e_b, T e_bs,
                                     T dxi, T dyi, T dzik, T dzhik, T dzhik1)
 {
-    const T ee = mean4(e_s, e_se, e_c, e_e);
-    const T ew = mean4(e_sw, e_s, e_w, e_c);
-    const T ge = tfma(ve - vc, dxi, (u_e - u_se) * dyi), gw = tfma(vc - vw, dxi, (u_c - u_s) * dyi);
-    const T tx = tfma(ee, ge, -(ew * gw)) * dxi;
-    const T ty = tfma(e_c, vn - vc, -(e_s * (vc - vs))) * (T(2) * dyi * dyi);
-    const T et = mean4(e_s, e_c, e_ts, e_t);
-    const T eb = mean4(e_bs, e_b, e_s, e_c);
-    const T gt = tfma(vt - vc, dzhik1, (w_t - w_ts) * dyi), gb = tfma(vc - vb, dzhik, (w_c - w_s) * dyi);
-    const T tz = tfma(et, gt, -(eb * gb)) * dzik;
-    return tx + ty + tz;
+    const T txy = smag_v_xy(vc, ve, vw, vn, vs, u_e, u_se, u_c, u_s, e_c, e_s, e_e, e_se, e_w, e_sw, dxi, dyi);
+    return smag_uv_total(txy, smag_v_zface(e_s, e_c, e_ts, e_t, vt, vc, w_t, w_ts, dyi, dzhik1),
+                         smag_v_zface(e_bs, e_b, e_s, e_c, vc, vb, w_c, w_s, dyi, dzhik), dzik);
 }
 
 // w at (x_i, y_j, zh_k).  u_e/u_be: u(i+1, k), u(i+1, k-1); u_c/u_b: u(i, k),
@@ -144,16 +225,9 @@ __device__ __forceinline__ T smag_w(T wc, T we, T ww, T wn, T ws, T wt, T wb,
                                     T e_c, T e_b, T e_e, T e_be, T e_w, T e_bw, T e_n, T e_bn, T e_s, T e_bs,
                                     T dxi, T dyi, T dzik, T dzikm1, T dzhik)
 {
-    const T ee = mean4(e_b, e_be, e_c, e_e);
-    const T ew = mean4(e_bw, e_b, e_w, e_c);
-    const T ge = tfma(we - wc, dxi, (u_e - u_be) * dzhik), gw = tfma(wc - ww, dxi, (u_c - u_b) * dzhik);
-    const T tx = tfma(ee, ge, -(ew * gw)) * dxi;
-    const T en = mean4(e_b, e_bn, e_c, e_n);
-    const T es = mean4(e_bs, e_b, e_s, e_c);
-    const T gn = tfma(wn - wc, dyi, (v_n - v_bn) * dzhik), gs = tfma(wc - ws, dyi, (v_c - v_b) * dzhik);
-    const T ty = tfma(en, gn, -(es * gs)) * dyi;
-    const T tz = tfma(e_c * (wt - wc), dzik, -(e_b * (wc - wb) * dzikm1)) * (T(2) * dzhik);
-    return tx + ty + tz;
+    const T txy = smag_w_xy(wc, we, ww, wn, ws, u_e, u_be, u_c, u_b, v_n, v_bn, v_c, v_b, e_c, e_b, e_e, e_be, e_w,
+                            e_bw, e_n, e_bn, e_s, e_bs, dxi, dyi, dzhik);
+    return smag_w_total(txy, smag_w_zcenter(e_c, wt, wc), smag_w_zcenter(e_b, wc, wb), dzik, dzikm1, dzhik);
 }
 
 // ---------------------------------------------------------------------------

@@ -74,7 +74,7 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zl(StencilArgs<T> a)
 
     int tx, ty, tz;
     tile_of<64, BY, XCD>(a.nbx, a.nby, a.nbz, tx, ty, tz);
-    const int lane = (int)threadIdx.x, r = (int)threadIdx.y;
+    const int lane = (int)threadIdx.x, r = wave_row();
     const int i0w = 1 + tx * TX;
     const int nlanes = min(64, (a.itot - i0w + 1) / VX);
     const bool lane_on = lane < nlanes;
@@ -320,7 +320,7 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zlp(StencilArgs<T> a
 
     int tx, ty, tz;
     tile_of<64, BY, XCD>(a.nbx, a.nby, a.nbz, tx, ty, tz);
-    const int lane = (int)threadIdx.x, r = (int)threadIdx.y;
+    const int lane = (int)threadIdx.x, r = wave_row();
     const int i0w = 1 + tx * TX;
     const int nlanes = min(64, (a.itot - i0w + 1) / VX);
     const bool lane_on = lane < nlanes;
@@ -570,7 +570,7 @@ __global__ __launch_bounds__(64 * BY, WPE) void diff_smag_zl(StencilArgs<T> a)
 
     int tx, ty, tz;
     tile_of<64, BY, XCD>(a.nbx, a.nby, a.nbz, tx, ty, tz);
-    const int lane = (int)threadIdx.x, r = (int)threadIdx.y;
+    const int lane = (int)threadIdx.x, r = wave_row();
     const int i0w = 1 + tx * TX;
     const int nlanes = min(64, (a.itot - i0w + 1) / VX);
     const bool lane_on = lane < nlanes;
@@ -592,22 +592,23 @@ __global__ __launch_bounds__(64 * BY, WPE) void diff_smag_zl(StencilArgs<T> a)
     // exactly and does not drain the prefetch of level k+2 before it is due.
     const int lane_c = min(lane, nlanes - 1);
     const int le = max(nlanes - 1, 1);      // lane loading the right halo cell
-    const int64_t row_c = a.off + i0w + (int64_t)min(j0 + r, a.jtot) * js;
-    const int64_t c_own = row_c + lane_c * VX;
-    const int64_t e_own = lane == 0 ? row_c - 1 : (lane == le ? row_c + nlanes * VX : c_own);
+    // Addresses: a wave-uniform row start (column i0w-1) plus a per-lane byte
+    // offset, own point (1 + lane_c*VX) or halo column (0 in lane 0,
+    // 1 + nlanes*VX in lane le); the level offset goes into the uniform part.
+    const int64_t row_c = a.off + i0w - 1 + (int64_t)min(j0 + r, a.jtot) * js;
+    const uint32_t o_pt = (uint32_t)(1 + lane_c * VX) * sizeof(T);
+    const uint32_t o_e = lane == 0 ? 0u : (lane == le ? (uint32_t)(1 + nlanes * VX) * sizeof(T) : o_pt);
 
     // rows this wave stages: its own (LDS row r+1) and halo rows h = r, r+BY,
     // ... of the 8 (field h/2; LDS row 0 for even h, nv+1 for odd h)
     int hf[NH], hrow[NH];
-    int64_t hc[NH], he[NH];
+    int64_t hr0[NH];
 #pragma unroll
     for (int m = 0; m < NH; ++m) {
         const int h = r + m * BY;
         hf[m] = h < 8 ? h >> 1 : -1;
         hrow[m] = (h & 1) ? nv + 1 : 0;
-        const int64_t hrow0 = a.off + i0w + (int64_t)(j0 - 1 + hrow[m]) * js;
-        hc[m] = hf[m] < 0 ? c_own : hrow0 + lane_c * VX;
-        he[m] = hf[m] < 0 ? c_own : (lane == 0 ? hrow0 - 1 : (lane == le ? hrow0 + nlanes * VX : hrow0 + lane_c * VX));
+        hr0[m] = hf[m] < 0 ? row_c : a.off + i0w - 1 + (int64_t)(j0 - 1 + hrow[m]) * js;
     }
 
     T O[2][4][VX], OE[2][4];                // own row of the 4 inputs at one level, halo columns
@@ -617,15 +618,17 @@ __global__ __launch_bounds__(64 * BY, WPE) void diff_smag_zl(StencilArgs<T> a)
     auto load_plane = [&](int q, int l) {    // level l of everything staged, into slot q
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
-            vload<T, VX>(O[q][f], F[f] + c_own + (int64_t)l * ks);
-            OE[q][f] = F[f][e_own + (int64_t)l * ks];
+            const T *row = F[f] + row_c + (int64_t)l * ks;
+            vload<T, VX>(O[q][f], boff(row, o_pt));
+            OE[q][f] = *boff(row, o_e);
         }
 #pragma unroll
         for (int m = 0; m < NH; ++m) {
             // a select, not an indexed pointer array, keeps these global loads
             const T *p = hf[m] == 1 ? a.v : (hf[m] == 2 ? a.w : (hf[m] == 3 ? a.evisc : a.u));
-            vload<T, VX>(H[q][m], p + hc[m] + (int64_t)l * ks);
-            HE[q][m] = p[he[m] + (int64_t)l * ks];
+            const T *row = p + hr0[m] + (int64_t)l * ks;
+            vload<T, VX>(H[q][m], boff(row, o_pt));
+            HE[q][m] = *boff(row, o_e);
         }
     };
     auto store_plane = [&](int q, int l) {   // slot q into the LDS planes of level l
@@ -655,7 +658,7 @@ __global__ __launch_bounds__(64 * BY, WPE) void diff_smag_zl(StencilArgs<T> a)
     auto load_tend = [&](int q, int k) {     // k <= k1 <= ktot+1
 #pragma unroll
         for (int f = 0; f < 3; ++f)
-            tload<NT, T, VX>(TT[q][f], (f == 0 ? a.ut : (f == 1 ? a.vt : a.wt)) + c_own + (int64_t)k * ks);
+            tload<NT, T, VX>(TT[q][f], boff((f == 0 ? a.ut : (f == 1 ? a.vt : a.wt)) + row_c + (int64_t)k * ks, o_pt));
     };
 
     // prologue: planes k0-1 and k0 into LDS, level k0+1 and tendencies of k0 in flight
@@ -666,7 +669,34 @@ __global__ __launch_bounds__(64 * BY, WPE) void diff_smag_zl(StencilArgs<T> a)
     load_plane(0, k0 + 1);
     load_tend(0, k0);
 
+    // the vertical face values below level k0; the march carries them upward
+    // (the top face of level k is the bottom face of level k+1, bit for bit)
     const T dxi = a.dxi, dyi = a.dyi;
+    SmagFace<T> BU[VX], BV[VX];
+    T BW[VX];
+#pragma unroll
+    for (int n = 0; n < VX; ++n) {
+        BU[n] = BV[n] = {T(0), T(0)};
+        BW[n] = T(0);
+    }
+    __syncthreads();
+    if (own && lane_on) {
+        const int bm = (k0 - 1) & 3, bc = k0 & 3, rr = r + 1;
+        const T dzhik = kload(a.dzhi, k0);
+#pragma unroll
+        for (int n = 0; n < VX; ++n) {
+            const int x = 1 + xo + n;
+#define P(f, b, dj, di) pl[f][b][rr + (dj)][SR::at(x + (di))]
+            const T uc = P(0, bc, 0, 0), ub = P(0, bm, 0, 0), vc = P(1, bc, 0, 0), vb = P(1, bm, 0, 0);
+            const T wc = P(2, bc, 0, 0), ww = P(2, bc, 0, -1), ws = P(2, bc, -1, 0), wb = P(2, bm, 0, 0);
+            const T ec = P(3, bc, 0, 0), ew = P(3, bc, 0, -1), es = P(3, bc, -1, 0), eb = P(3, bm, 0, 0),
+                    ebw = P(3, bm, 0, -1), ebs = P(3, bm, -1, 0);
+#undef P
+            BU[n] = smag_u_zface<T>(ebw, eb, ew, ec, uc, ub, wc, ww, dxi, dzhik);
+            BV[n] = smag_v_zface<T>(ebs, eb, es, ec, vc, vb, wc, ws, dyi, dzhik);
+            BW[n] = smag_w_zcenter<T>(eb, wc, wb);
+        }
+    }
     vm_drain();
     for (int k = k0; k < k1; ++k) {
         // level k+1 into the ring; prefetch level k+2 and the next tendencies
@@ -692,7 +722,7 @@ __global__ __launch_bounds__(64 * BY, WPE) void diff_smag_zl(StencilArgs<T> a)
                         vs = P(1, bc, -1, 0), vt_ = P(1, bp, 0, 0), vb = P(1, bm, 0, 0), vnw = P(1, bc, 1, -1),
                         vbn = P(1, bm, 1, 0);
                 const T wc = P(2, bc, 0, 0), we = P(2, bc, 0, 1), ww = P(2, bc, 0, -1), wn = P(2, bc, 1, 0),
-                        ws = P(2, bc, -1, 0), wt_ = P(2, bp, 0, 0), wb = P(2, bm, 0, 0), wtw = P(2, bp, 0, -1),
+                        ws = P(2, bc, -1, 0), wt_ = P(2, bp, 0, 0), wtw = P(2, bp, 0, -1),
                         wts = P(2, bp, -1, 0);
                 const T ec = P(3, bc, 0, 0), ee = P(3, bc, 0, 1), ew = P(3, bc, 0, -1), en = P(3, bc, 1, 0),
                         es = P(3, bc, -1, 0), et = P(3, bp, 0, 0), eb = P(3, bm, 0, 0), enw = P(3, bc, 1, -1),
@@ -700,19 +730,27 @@ __global__ __launch_bounds__(64 * BY, WPE) void diff_smag_zl(StencilArgs<T> a)
                         ebw = P(3, bm, 0, -1), ebe = P(3, bm, 0, 1), ets = P(3, bp, -1, 0), ebs = P(3, bm, -1, 0),
                         ebn = P(3, bm, 1, 0);
 #undef P
-                o0[n] = TT[0][0][n] + smag_u<T>(uc, ue, uw, un, us, ut_, ub, vn, vnw, vc, vw, wt_, wtw, wc, ww,
-                                                ec, ew, en, enw, es, esw, et, etw, eb, ebw, dxi, dyi, dzik, dzhik,
-                                                dzhik1);
-                o1[n] = TT[0][1][n] + smag_v<T>(vc, ve, vw, vn, vs, vt_, vb, ue, use, uc, us, wt_, wts, wc, ws,
-                                                ec, es, ee, ese, ew, esw, et, ets, eb, ebs, dxi, dyi, dzik, dzhik,
-                                                dzhik1);
-                o2[n] = TT[0][2][n] + smag_w<T>(wc, we, ww, wn, ws, wt_, wb, ue, ube, uc, ub, vn, vbn, vc, vb,
-                                                ec, eb, ee, ebe, ew, ebw, en, ebn, es, ebs, dxi, dyi, dzik, dzikm1,
-                                                dzhik);
+                // the same operations as smag_u/v/w, with the bottom faces carried
+                const SmagFace<T> tu = smag_u_zface<T>(ew, ec, etw, et, ut_, uc, wt_, wtw, dxi, dzhik1);
+                const SmagFace<T> tv = smag_v_zface<T>(es, ec, ets, et, vt_, vc, wt_, wts, dyi, dzhik1);
+                const T tw = smag_w_zcenter<T>(ec, wt_, wc);
+                o0[n] = TT[0][0][n] + smag_uv_total<T>(smag_u_xy<T>(uc, ue, uw, un, us, vn, vnw, vc, vw, ec, ew, en,
+                                                                    enw, es, esw, dxi, dyi),
+                                                       tu, BU[n], dzik);
+                o1[n] = TT[0][1][n] + smag_uv_total<T>(smag_v_xy<T>(vc, ve, vw, vn, vs, ue, use, uc, us, ec, es, ee,
+                                                                    ese, ew, esw, dxi, dyi),
+                                                       tv, BV[n], dzik);
+                o2[n] = TT[0][2][n] + smag_w_total<T>(smag_w_xy<T>(wc, we, ww, wn, ws, ue, ube, uc, ub, vn, vbn, vc,
+                                                                   vb, ec, eb, ee, ebe, ew, ebw, en, ebn, es, ebs,
+                                                                   dxi, dyi, dzhik),
+                                                      tw, BW[n], dzik, dzikm1, dzhik);
+                BU[n] = tu;
+                BV[n] = tv;
+                BW[n] = tw;
             }
-            tstore<NT, T, VX>(a.ut + c_own + (int64_t)k * ks, o0);
-            tstore<NT, T, VX>(a.vt + c_own + (int64_t)k * ks, o1);
-            if (k >= a.kw0) tstore<NT, T, VX>(a.wt + c_own + (int64_t)k * ks, o2);
+            tstore<NT, T, VX>(boff(a.ut + row_c + (int64_t)k * ks, o_pt), o0);
+            tstore<NT, T, VX>(boff(a.vt + row_c + (int64_t)k * ks, o_pt), o1);
+            if (k >= a.kw0) tstore<NT, T, VX>(boff(a.wt + row_c + (int64_t)k * ks, o_pt), o2);
         }
 
         // advance the register slots

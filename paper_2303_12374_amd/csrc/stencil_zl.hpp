@@ -42,7 +42,7 @@ struct ZlTile {
     {
         constexpr int TX = 64 * VX;
         lane = (int)threadIdx.x;
-        r = (int)threadIdx.y;
+        r = wave_row();
         i0w = 1 + tx * TX;
         i0 = i0w + lane * VX;
         j0 = 1 + ty * BY;
