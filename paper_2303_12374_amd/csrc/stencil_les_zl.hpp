@@ -60,7 +60,11 @@ struct PlanarRow {
     __device__ static __forceinline__ int at(int c) { return (c % VX) * P + c / VX; }
 };
 
-template <typename T, int VX, int BY, int KB, int XCD, int NT, int WPE>
+// YS = 1 evaluates every y face once: each wave its row's north face, wave 0
+// also the tile's south face, exchanged through an LDS row (a second barrier
+// per level).  A face's operands are the same for the two rows it separates,
+// so the values are bitwise those of YS = 0.
+template <typename T, int VX, int BY, int KB, int XCD, int NT, int WPE, int YS = 0>
 __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zl(StencilArgs<T> a)
 {
     constexpr int TX = 64 * VX;
@@ -71,6 +75,7 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zl(StencilArgs<T> a)
     typedef PlanarRow<planar_vx<T, VX>(), VW> VR;  // v rows, likewise
     __shared__ __align__(16) T su[2][BY + 6][UR::SIZE];
     __shared__ __align__(16) T sv[2][BY + 1][VR::SIZE];
+    __shared__ __align__(16) T sfy[YS ? BY + 1 : 1][YS ? TX : 1];  // y-face fluxes of one level
 
     int tx, ty, tz;
     tile_of<64, BY, XCD>(a.nbx, a.nby, a.nbz, tx, ty, tz);
@@ -238,6 +243,29 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zl(StencilArgs<T> a)
         // 3. compute level k
         const T sh = shfl_up1(WR[0][VX - 1]);
         const T wl = edge_l ? WL[0] : sh;
+        T FN[VX], FS[VX];
+        if constexpr (YS) {
+            if (own && lane_on) {
+#pragma unroll
+                for (int n = 0; n < VX; ++n) {
+                    const int xu = UR::at(3 + xo + n);
+                    T col[7];
+#pragma unroll
+                    for (int m = 1; m < 7; ++m) col[m] = su[p][r + m][xu];
+                    const T vn = mid(sv[p][r + 1][VR::at(xo + n)], sv[p][r + 1][VR::at(xo + n + 1)]);
+                    FN[n] = flux5(vn, col[1], col[2], col[3], col[4], col[5], col[6]);
+                    if (r == 0) {
+                        col[0] = su[p][0][xu];
+                        const T vs = mid(sv[p][0][VR::at(xo + n)], sv[p][0][VR::at(xo + n + 1)]);
+                        FS[n] = flux5(vs, col[0], col[1], col[2], col[3], col[4], col[5]);
+                    }
+                }
+                vstore<T, VX>(&sfy[r + 1][xo], FN);
+                if (r == 0) vstore<T, VX>(&sfy[0][xo], FS);
+            }
+            __syncthreads();
+            if (own && lane_on && r > 0) vload<T, VX>(FS, &sfy[r][xo]);
+        }
         if (own && lane_on) {
             T uxr[VX + 6];
 #pragma unroll
@@ -251,14 +279,20 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zl(StencilArgs<T> a)
             T res[VX];
 #pragma unroll
             for (int n = 0; n < VX; ++n) {
-                const int xu = UR::at(3 + xo + n);
-                T col[7];
+                T fn, fs;
+                if constexpr (YS) {
+                    fn = FN[n];
+                    fs = FS[n];
+                } else {
+                    const int xu = UR::at(3 + xo + n);
+                    T col[7];
 #pragma unroll
-                for (int m = 0; m < 7; ++m) col[m] = su[p][r + m][xu];
-                const T vn = mid(sv[p][r + 1][VR::at(xo + n)], sv[p][r + 1][VR::at(xo + n + 1)]);
-                const T vs = mid(sv[p][r][VR::at(xo + n)], sv[p][r][VR::at(xo + n + 1)]);
-                const T fn = flux5(vn, col[1], col[2], col[3], col[4], col[5], col[6]);
-                const T fs = flux5(vs, col[0], col[1], col[2], col[3], col[4], col[5]);
+                    for (int m = 0; m < 7; ++m) col[m] = su[p][r + m][xu];
+                    const T vn = mid(sv[p][r + 1][VR::at(xo + n)], sv[p][r + 1][VR::at(xo + n + 1)]);
+                    const T vs = mid(sv[p][r][VR::at(xo + n)], sv[p][r][VR::at(xo + n + 1)]);
+                    fn = flux5(vn, col[1], col[2], col[3], col[4], col[5], col[6]);
+                    fs = flux5(vs, col[0], col[1], col[2], col[3], col[4], col[5]);
+                }
                 const T wm = n == 0 ? wl : WR[0][n - 1];
                 const T ft = flux_z_2i5(mid(wm, WR[0][n]), S[0][n], S[1][n], S[2][n], S[3][n], S[4][n], S[5][n],
                                         k + 1, kt);

@@ -169,7 +169,7 @@ hipError_t launch_zl_split(const HostArgs &h, hipStream_t s)
     return hipGetLastError();
 }
 
-template <typename T, int VX, int BY, int KB, int XCD, int NT = 0, int WPE = 1, int PAIR = 0>
+template <typename T, int VX, int BY, int KB, int XCD, int NT = 0, int WPE = 1, int PAIR = 0, int YS = 0>
 hipError_t launch_advec5_zl(const HostArgs &h, hipStream_t s)
 {
     StencilArgs<T> a = device_args<T>(h);
@@ -181,7 +181,8 @@ hipError_t launch_advec5_zl(const HostArgs &h, hipStream_t s)
     if (PAIR)
         hipLaunchKernelGGL((advec_u_2i5_zlp<T, VX, BY, KB, XCD, NT, WPE>), dim3((unsigned)nb), dim3(64, BY), 0, s, a);
     else
-        hipLaunchKernelGGL((advec_u_2i5_zl<T, VX, BY, KB, XCD, NT, WPE>), dim3((unsigned)nb), dim3(64, BY), 0, s, a);
+        hipLaunchKernelGGL((advec_u_2i5_zl<T, VX, BY, KB, XCD, NT, WPE, YS>), dim3((unsigned)nb), dim3(64, BY), 0, s,
+                           a);
     return hipGetLastError();
 }
 
@@ -301,6 +302,13 @@ hipError_t launch_smag_zl(const HostArgs &h, hipStream_t s)
     Variant{"a5p_v" KL_STR(VX) "_b64x" KL_STR(BY) "_k" KL_STR(KB) "_x" KL_STR(XCD) "_nt" KL_STR(NT),       \
             KL_KERNEL_ADVEC_U_2I5, DT, FAMILY_ZL, VX, 64, BY, KB, XCD,                                     \
             &launch_advec5_zl<T, VX, BY, KB, XCD, NT, 1, 1>, nullptr, nullptr}
+
+// advec_u_2i5 with each y face evaluated once (shared through LDS), named
+// a5s_v<VX>_b64x<BY>_k<KB>_x<XCD>_nt<NT>.
+#define KL_A5S(T, DT, VX, BY, KB, XCD, NT)                                                                  \
+    Variant{"a5s_v" KL_STR(VX) "_b64x" KL_STR(BY) "_k" KL_STR(KB) "_x" KL_STR(XCD) "_nt" KL_STR(NT),       \
+            KL_KERNEL_ADVEC_U_2I5, DT, FAMILY_ZL, VX, 64, BY, KB, XCD,                                     \
+            &launch_advec5_zl<T, VX, BY, KB, XCD, NT, 1, 0, 1>, nullptr, nullptr}
 
 #define KL_A5(T, DT, VX, BY, KB, XCD, NT)                                                                   \
     Variant{"a5_v" KL_STR(VX) "_b64x" KL_STR(BY) "_k" KL_STR(KB) "_x" KL_STR(XCD) "_nt" KL_STR(NT),        \
