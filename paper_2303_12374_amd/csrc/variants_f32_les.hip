@@ -13,7 +13,14 @@ void add_variants_f32_split(std::vector<Variant> &out)
         KL_ZL3(float, KL_F32, 2, 4, 128, 2, 1),
         KL_ZL3(float, KL_F32, 2, 4, 256, 3, 1),
         KL_ZL3(float, KL_F32, 2, 8, 64, 2, 1),
-        KL_ZL3(float, KL_F32, 2, 4, 64, 2, 1)};
+        KL_ZL3(float, KL_F32, 2, 4, 64, 2, 1),
+        KL_ZL3(float, KL_F32, 4, 16, 64, 2, 1),
+        KL_ZL3(float, KL_F32, 4, 16, 128, 3, 1),
+        KL_ZL3(float, KL_F32, 4, 8, 256, 3, 1),
+        KL_ZL3(float, KL_F32, 4, 8, 128, 3, 1),
+        KL_ZL3(float, KL_F32, 4, 16, 256, 3, 1),
+        KL_ZL3(float, KL_F32, 4, 8, 256, 2, 1),
+        KL_ZL3(float, KL_F32, 4, 8, 512, 3, 1)};
     out.insert(out.end(), v.begin(), v.end());
 }
 

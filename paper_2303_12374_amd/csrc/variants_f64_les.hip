@@ -9,7 +9,11 @@ void add_variants_f64_split(std::vector<Variant> &out)
         KL_ZL3(double, KL_F64, 2, 4, 128, 2, 1),
         KL_ZL3(double, KL_F64, 2, 4, 256, 3, 1),
         KL_ZL3(double, KL_F64, 2, 8, 64, 2, 1),
-        KL_ZL3(double, KL_F64, 2, 4, 64, 2, 1)};
+        KL_ZL3(double, KL_F64, 2, 4, 64, 2, 1),
+        KL_ZL3(double, KL_F64, 2, 8, 256, 3, 1),
+        KL_ZL3(double, KL_F64, 2, 8, 128, 3, 1),
+        KL_ZL3(double, KL_F64, 2, 16, 128, 3, 1),
+        KL_ZL3(double, KL_F64, 2, 16, 64, 2, 1)};
     out.insert(out.end(), v.begin(), v.end());
 }
 
