@@ -340,6 +340,21 @@ def other_dtype_leg(kl, torch, np, shape, dtype, host_fields, visc, steps):
     adv = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
     dif = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
     pair = float(np.mean([e[0].elapsed_time(e[2]) for e in ev]))
+
+    def alone(fn):
+        """Mean duration of one kernel launched back to back (as the tuner
+        times it), beside its duration inside the alternating pair above."""
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    adv_alone = alone(lambda: kl.kl_advec_u_2i5(g, tend[0], *dev[:3], stream))
+    dif_alone = alone(lambda: kl.kl_diff_smag(g, *tend, *dev, stream))
     npts = shape[0] * shape[1] * shape[2]
     names = {n: kl.kl_variant_name(k, dtype, kl.kl_selected_variant(g, k))
              for n, k in (("advec_u", kl.ADVEC_U), ("diff_uvw", kl.DIFF_UVW))}
@@ -380,6 +395,21 @@ def les_leg(kl, torch, np, inputs, shape, host_fields, seed, steps):
     adv = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
     dif = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
     pair = float(np.mean([e[0].elapsed_time(e[2]) for e in ev]))
+
+    def alone(fn):
+        """Mean duration of one kernel launched back to back (as the tuner
+        times it), beside its duration inside the alternating pair above."""
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    adv_alone = alone(lambda: kl.kl_advec_u_2i5(g, tend[0], *dev[:3], stream))
+    dif_alone = alone(lambda: kl.kl_diff_smag(g, *tend, *dev, stream))
     npts = shape[0] * shape[1] * shape[2]
     names = {n: kl.kl_variant_name(k, kl.F32, kl.kl_selected_variant(g, k))
              for n, k in (("advec_u_2i5", kl.ADVEC_U_2I5), ("diff_smag", kl.DIFF_SMAG))}
@@ -392,11 +422,11 @@ def les_leg(kl, torch, np, inputs, shape, host_fields, seed, steps):
             "ms_per_pair": pair, "grid_points_per_s": npts / (pair * 1e-3),
             "hbm_gbps": (b_adv + b_dif) / (pair * 1e6),
             "hbm_frac_of_peak": (b_adv + b_dif) / (pair * 1e6) / PEAK_HBM_GBPS,
-            "kernels": {"advec_u_2i5": {"ms": adv, "gbps": b_adv / (adv * 1e6),
+            "kernels": {"advec_u_2i5": {"ms": adv, "ms_back_to_back": adv_alone, "gbps": b_adv / (adv * 1e6),
                                         "frac": b_adv / (adv * 1e6) / PEAK_HBM_GBPS,
                                         "algorithmic_bytes_per_launch": b_adv,
                                         "traffic": load_traffic("advec_u_2i5", wkey, names["advec_u_2i5"])},
-                        "diff_smag": {"ms": dif, "gbps": b_dif / (dif * 1e6),
+                        "diff_smag": {"ms": dif, "ms_back_to_back": dif_alone, "gbps": b_dif / (dif * 1e6),
                                       "frac": b_dif / (dif * 1e6) / PEAK_HBM_GBPS,
                                       "algorithmic_bytes_per_launch": b_dif,
                                       "traffic": load_traffic("diff_smag", wkey, names["diff_smag"])}},
