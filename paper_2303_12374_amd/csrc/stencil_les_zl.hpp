@@ -84,7 +84,7 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zl(StencilArgs<T> a)
     const int nlanes = min(64, (a.itot - i0w + 1) / VX);
     const bool lane_on = lane < nlanes;
     const int xo = lane * VX;
-    const bool edge_l = lane == 0, edge_r = lane == nlanes - 1;
+    const bool edge_l = lane == 0;
     const int j0 = 1 + ty * BY;
     const int nv = min(BY, a.jtot - j0 + 1);
     const bool own = r < nv;
@@ -95,81 +95,69 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zl(StencilArgs<T> a)
     T *ut = a.ut;
     const T dxi = a.dxi, dyi = a.dyi;
 
-    // level-0 addresses of this lane's points in the own row and the halo rows
-    const int64_t row0 = a.off + i0w + xo;
-    const int64_t c_own = row0 + (int64_t)(j0 + r) * js;
-    const int64_t e_own = a.off + i0w + (int64_t)(j0 + r) * js;           // (i0w, j0 + r, 0)
-    const int iend = i0w + nlanes * VX - 1;                               // last point of the tile
+    // Level-0 addresses.  Every load of the level loop is unconditional and
+    // inside the field: lanes beyond the grid read the last active lane's
+    // points, waves beyond the last row read the last row, waves without a
+    // halo row read their own row.  One scalar load per row carries its x halo:
+    // lanes 0..2 the three columns left of the tile, lanes 3..5 the three
+    // right of it (u rows); lane 0 the column left of the own v row, lane 1 the
+    // one left of the v halo row.
+    const int lane_c = min(lane, nlanes - 1);
+    const int64_t rowo = a.off + i0w + (int64_t)min(j0 + r, a.jtot) * js;   // (i0w, own row, 0)
+    const int64_t c_own = rowo + lane_c * VX;
+    const int ecol = lane < 3 ? lane - 3 : (lane < 6 ? nlanes * VX + lane - 3 : lane_c * VX);
+    const int64_t e_own = rowo + ecol;
     int hrho[NH];   // LDS rows of this wave's u halo rows, -1 if none
     int64_t hc[NH], he[NH];
 #pragma unroll
     for (int m = 0; m < NH; ++m) {
         const int h = r + m * BY;
         hrho[m] = h < 6 ? (h < 3 ? h : nv + h) : -1;
-        const int jg = j0 - 3 + (hrho[m] < 0 ? 3 : hrho[m]);
-        hc[m] = row0 + (int64_t)jg * js;
-        he[m] = a.off + i0w + (int64_t)jg * js;
+        const int64_t hrow0 = a.off + i0w + (int64_t)(j0 - 3 + (hrho[m] < 0 ? 3 : hrho[m])) * js;
+        hc[m] = hrho[m] < 0 ? c_own : hrow0 + lane_c * VX;
+        he[m] = hrho[m] < 0 ? c_own : hrow0 + ecol;
     }
     const bool vhalo = r == BY - 1;                                       // loads v row j0 + nv
-    const int64_t c_vh = row0 + (int64_t)(j0 + nv) * js;
-    const int64_t e_vh = a.off + i0w + (int64_t)(j0 + nv) * js;
+    const int64_t vrow = a.off + i0w + (int64_t)(j0 + nv) * js;           // (i0w, j0 + nv, 0)
+    const int64_t c_vh = vhalo ? vrow + lane_c * VX : c_own;
+    const int64_t e_v = lane == 0 ? rowo - 1 : (lane == 1 && vhalo ? vrow - 1 : c_own);
+    const int64_t e_w = lane == 0 ? rowo - 1 : c_own;
+    const int lx_u = lane < 3 ? lane : nlanes * VX + lane;                // LDS column of a lane's u halo value
 
     // registers: current (level k) and next (level k+1) copies of what the
     // LDS planes receive, the w row at k+1 (next: k+2), ut at k (next: k+1)
     T S[7][VX];                              // u(k-2) .. u(k+4) of the own column
-    T HU[2][NH][VX], HUL[2][NH][3], HUR[2][NH][3];
-    T OUL[2][3], OUR[2][3];                  // x halo of the own u row
-    T VO[2][VX], VOL[2];                     // own v row and its left halo cell
-    T VH[2][VX], VHL[2];                     // v halo row and its left halo cell
+    T HU[2][NH][VX], HE[2][NH];              // u halo rows and their x-halo values
+    T OE[2];                                 // x-halo value of the own u row
+    T VO[2][VX], VH[2][VX], VE[2];           // own v row, v halo row, their left halo values
     T WR[2][VX], WL[2];                      // w at k+1 (and k+2), left neighbour cell (lane 0)
     T UT[2][VX];
 
-    auto load_level = [&](int q, int k) {    // everything level k needs, into slot q
+    auto load_level = [&](int q, int k) {    // everything level k needs, into slot q (k <= ktot)
+        const int64_t lk = (int64_t)k * ks;
 #pragma unroll
         for (int m = 0; m < NH; ++m) {
-            const bool on = hrho[m] >= 0;
-            if (on && lane_on) vload<T, VX>(HU[q][m], u + hc[m] + (int64_t)k * ks);
-            if (on && edge_l) {
-#pragma unroll
-                for (int e = 0; e < 3; ++e) HUL[q][m][e] = u[he[m] + (int64_t)k * ks - 3 + e];
-            }
-            if (on && edge_r) {
-#pragma unroll
-                for (int e = 0; e < 3; ++e) HUR[q][m][e] = u[he[m] + (iend - i0w) + (int64_t)k * ks + 1 + e];
-            }
+            vload<T, VX>(HU[q][m], u + hc[m] + lk);
+            HE[q][m] = u[he[m] + lk];
         }
-        if (own) {
-            if (edge_l) {
-#pragma unroll
-                for (int e = 0; e < 3; ++e) OUL[q][e] = u[e_own + (int64_t)k * ks - 3 + e];
-                VOL[q] = v[e_own + (int64_t)k * ks - 1];
-            }
-            if (edge_r) {
-#pragma unroll
-                for (int e = 0; e < 3; ++e) OUR[q][e] = u[e_own + (iend - i0w) + (int64_t)k * ks + 1 + e];
-            }
-            if (lane_on) {
-                vload<T, VX>(VO[q], v + c_own + (int64_t)k * ks);
-                vload<T, VX>(WR[q], w + c_own + (int64_t)(k + 1) * ks);
-                tload<NT, T, VX>(UT[q], ut + c_own + (int64_t)k * ks);
-            }
-            if (edge_l) WL[q] = w[e_own + (int64_t)(k + 1) * ks - 1];
-        }
-        if (vhalo) {
-            if (lane_on) vload<T, VX>(VH[q], v + c_vh + (int64_t)k * ks);
-            if (edge_l) VHL[q] = v[e_vh + (int64_t)k * ks - 1];
-        }
+        OE[q] = u[e_own + lk];
+        vload<T, VX>(VO[q], v + c_own + lk);
+        vload<T, VX>(VH[q], v + c_vh + lk);
+        VE[q] = v[e_v + lk];
+        vload<T, VX>(WR[q], w + c_own + lk + ks);
+        WL[q] = w[e_w + lk + ks];
+        tload<NT, T, VX>(UT[q], ut + c_own + lk);
     };
 
     // prologue: the u window, the flux through face k0, level k0's data
 #pragma unroll
-    for (int m = 0; m < 7; ++m) col_load<T, VX>(S[m], u + c_own, ks, k0 - 2 + m, kt, own && lane_on);
+    for (int m = 0; m < 7; ++m) col_load<T, VX>(S[m], u + c_own, ks, k0 - 2 + m, kt, true);
     T FB[VX];
     {
         T ub3[VX], w0[VX];
-        col_load<T, VX>(ub3, u + c_own, ks, k0 - 3, kt, own && lane_on);
-        col_load<T, VX>(w0, w + c_own, ks, k0, kt, own && lane_on);
-        T wl0 = (own && edge_l) ? w[e_own + (int64_t)k0 * ks - 1] : T(0);
+        col_load<T, VX>(ub3, u + c_own, ks, k0 - 3, kt, true);
+        col_load<T, VX>(w0, w + c_own, ks, k0, kt, true);
+        T wl0 = w[e_w + (int64_t)k0 * ks];
         const T sh = shfl_up1(w0[VX - 1]);
         if (!edge_l) wl0 = sh;
 #pragma unroll
@@ -177,15 +165,6 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zl(StencilArgs<T> a)
             const T wm = n == 0 ? wl0 : w0[n - 1];
             FB[n] = flux_z_2i5(mid(wm, w0[n]), ub3[n], S[0][n], S[1][n], S[2][n], S[3][n], S[4][n], k0, kt);
         }
-    }
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-#pragma unroll
-        for (int n = 0; n < VX; ++n) VO[q][n] = VH[q][n] = WR[q][n] = UT[q][n] = T(0);
-#pragma unroll
-        for (int m = 0; m < NH; ++m)
-#pragma unroll
-            for (int n = 0; n < VX; ++n) HU[q][m][n] = T(0);
     }
     load_level(0, k0);
 
@@ -200,15 +179,8 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zl(StencilArgs<T> a)
                 sv[p][r][VR::at(1 + xo + n)] = VO[0][n];
             }
         }
-        if (own && edge_l) {
-#pragma unroll
-            for (int e = 0; e < 3; ++e) su[p][r + 3][UR::at(e)] = OUL[0][e];
-            sv[p][r][VR::at(0)] = VOL[0];
-        }
-        if (own && edge_r) {
-#pragma unroll
-            for (int e = 0; e < 3; ++e) su[p][r + 3][UR::at(3 + nlanes * VX + e)] = OUR[0][e];
-        }
+        if (own && lane < 6) su[p][r + 3][UR::at(lx_u)] = OE[0];
+        if (own && lane == 0) sv[p][r][VR::at(0)] = VE[0];
 #pragma unroll
         for (int m = 0; m < NH; ++m) {
             const int rho = hrho[m];
@@ -217,14 +189,7 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zl(StencilArgs<T> a)
 #pragma unroll
                     for (int n = 0; n < VX; ++n) su[p][rho][UR::at(3 + xo + n)] = HU[0][m][n];
                 }
-                if (edge_l) {
-#pragma unroll
-                    for (int e = 0; e < 3; ++e) su[p][rho][UR::at(e)] = HUL[0][m][e];
-                }
-                if (edge_r) {
-#pragma unroll
-                    for (int e = 0; e < 3; ++e) su[p][rho][UR::at(3 + nlanes * VX + e)] = HUR[0][m][e];
-                }
+                if (lane < 6) su[p][rho][UR::at(lx_u)] = HE[0][m];
             }
         }
         if (vhalo) {
@@ -232,12 +197,12 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zl(StencilArgs<T> a)
 #pragma unroll
                 for (int n = 0; n < VX; ++n) sv[p][nv][VR::at(1 + xo + n)] = VH[0][n];
             }
-            if (edge_l) sv[p][nv][VR::at(0)] = VHL[0];
+            if (lane == 1) sv[p][nv][VR::at(0)] = VE[0];
         }
         // 2. prefetch level k+1 and the u window's next level
-        if (k + 1 < k1) load_level(1, k + 1);
+        load_level(1, min(k + 1, k1 - 1));   // clamped at the last level, where it is unused
         T unext[VX];
-        col_load<T, VX>(unext, u + c_own, ks, k + 5, kt, own && lane_on && k + 1 < k1);
+        col_load<T, VX>(unext, u + c_own, ks, k + 5, kt, k + 1 < k1);
         __syncthreads();
 
         // 3. compute level k
@@ -315,23 +280,14 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zl(StencilArgs<T> a)
             WR[0][n] = WR[1][n];
             UT[0][n] = UT[1][n];
         }
-        VOL[0] = VOL[1];
-        VHL[0] = VHL[1];
+        VE[0] = VE[1];
         WL[0] = WL[1];
-#pragma unroll
-        for (int e = 0; e < 3; ++e) {
-            OUL[0][e] = OUL[1][e];
-            OUR[0][e] = OUR[1][e];
-        }
+        OE[0] = OE[1];
 #pragma unroll
         for (int m = 0; m < NH; ++m) {
 #pragma unroll
             for (int n = 0; n < VX; ++n) HU[0][m][n] = HU[1][m][n];
-#pragma unroll
-            for (int e = 0; e < 3; ++e) {
-                HUL[0][m][e] = HUL[1][m][e];
-                HUR[0][m][e] = HUR[1][m][e];
-            }
+            HE[0][m] = HE[1][m];
         }
     }
 }
