@@ -743,6 +743,16 @@ def main():
                       "fused_grid_points_per_s": npts / (fused_ms * 1e-3),
                       "fused_hbm_gbps_6_values": 6 * s * npts / (fused_ms * 1e6),
                       "separate_hbm_gbps_26_values": 26 * s * npts / (sep_ms * 1e6)}
+    # FP64 reductions over the same grid: conservation sums of the tendencies
+    # and checksums of the fields (3 fields read each, accumulated in double)
+    log("FP64 reductions: conservation sums and checksums")
+    red = torch.zeros(9, dtype=torch.float64, device="cuda")
+    cons_ms = time_fn(lambda: kl.kl_reduce_fp64(g, 0, ut, vt, wt, red, stream))
+    chk_ms = time_fn(lambda: kl.kl_reduce_fp64(g, 1, u, v, w, red, stream))
+    result["reductions"] = {"conservation_ms": cons_ms, "checksums_ms": chk_ms,
+                            "conservation_hbm_gbps": 3 * s * npts / (cons_ms * 1e6),
+                            "checksums_hbm_gbps": 3 * s * npts / (chk_ms * 1e6),
+                            "note": "3 fields read per call (algorithmic bytes 3*N*s), sums in FP64"}
     del dev, tend, u, v, w, ut, vt, wt, out
     torch.cuda.empty_cache()
     if not args.no_overhead:

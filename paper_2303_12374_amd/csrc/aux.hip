@@ -208,7 +208,7 @@ __global__ __launch_bounds__(256) void zero_interior_kernel(Dims d, T *f, int nb
 // ---------------------------------------------------------------------------
 // FP64 reductions: pass 1 gives each of RB blocks a fixed set of rows
 // (row r = (j, k) pairs, rows b, b + RB, ...), each thread a fixed set of
-// columns; block partials are combined by a fixed LDS tree.  Pass 2 reduces
+// row slots and columns; block partials are combined by a fixed LDS tree.  Pass 2 reduces
 // the RB partials in one block the same way.  No atomics, so the result is
 // bitwise reproducible.
 // ---------------------------------------------------------------------------
@@ -242,7 +242,28 @@ __device__ void block_tree(double (&acc)[NQ], const int (&is_max)[NQ], double *o
     }
 }
 
-template <typename T>
+// Pass 1.  Each thread reads V consecutive points of a row with one vector
+// load (V > 1 when the rows are aligned to it).  A row has cpr = itot / V
+// chunks; when a row has fewer chunks than the block has threads, a pass
+// covers rpp = RT / cpr rows at once (thread t: row slot t / cpr, chunk
+// t % cpr).  Block b owns rows b, b + RB, b + 2 RB, ...; slot s takes the
+// n-th of them for n = s, s + rpp, ...; two rows are loaded before either
+// is accumulated.  The mapping depends only on the grid, so the result is
+// the same on every run.
+template <typename T, int V>
+__device__ __forceinline__ void red_load(T (&x)[V], const T *p)
+{
+    if constexpr (V == 1) {
+        x[0] = *p;
+    } else {
+        typedef T VT __attribute__((ext_vector_type(V)));
+        const VT y = *reinterpret_cast<const VT *>(p);
+#pragma unroll
+        for (int n = 0; n < V; ++n) x[n] = y[n];
+    }
+}
+
+template <typename T, int V>
 __global__ __launch_bounds__(RT) void reduce_pass1(Dims d, int what, int kw0, const T *f0, const T *f1,
                                                   const T *f2, const T *dzi, const T *dzhi,
                                                   double *partial)
@@ -255,29 +276,69 @@ __global__ __launch_bounds__(RT) void reduce_pass1(Dims d, int what, int kw0, co
         is_max[q] = (what == 1 && q % 3 == 2);
     }
     const int64_t nrows = (int64_t)d.jtot * d.ktot;
+    const int cpr = d.itot / V;
+    const bool wide = cpr >= RT;
+    const int rpp = wide ? 1 : RT / cpr;
+    const int slot = wide ? 0 : (int)threadIdx.x / cpr;
+    const int c0 = wide ? (int)threadIdx.x : (int)threadIdx.x % cpr;
+    const int cstep = wide ? RT : cpr;
+    const int64_t rstep = (int64_t)rpp * RB;
     const T *f3[3] = {f0, f1, f2};
-    for (int64_t r = blockIdx.x; r < nrows; r += RB) {
-        const int j = 1 + (int)(r % d.jtot);
-        const int k = 1 + (int)(r / d.jtot);
-        const int64_t base = at(d, 0, j, k);
+
+    // one row's contribution of chunk c, values already loaded
+    auto add = [&](const T (&x)[3][V], int k) {
         if (what == 0) {
-            const double wz = 1.0 / (double)dzi[k];
-            const double wzh = 1.0 / (double)dzhi[k];
-            for (int i = 1 + (int)threadIdx.x; i <= d.itot; i += RT) {
-                acc[0] += (double)f0[base + i] * wz;
-                acc[1] += (double)f1[base + i] * wz;
-                if (k >= kw0) acc[2] += (double)f2[base + i] * wzh;
+            const double wz = 1.0 / (double)dzi[k], wzh = 1.0 / (double)dzhi[k];
+#pragma unroll
+            for (int n = 0; n < V; ++n) {
+                acc[0] += (double)x[0][n] * wz;
+                acc[1] += (double)x[1][n] * wz;
+                if (k >= kw0) acc[2] += (double)x[2][n] * wzh;
             }
         } else {
 #pragma unroll
             for (int f = 0; f < 3; ++f) {
                 if (f3[f] == nullptr) continue;
-                for (int i = 1 + (int)threadIdx.x; i <= d.itot; i += RT) {
-                    const double x = (double)f3[f][base + i];
-                    acc[3 * f] += x;
-                    acc[3 * f + 1] += x * x;
-                    acc[3 * f + 2] = fmax(acc[3 * f + 2], fabs(x));
+#pragma unroll
+                for (int n = 0; n < V; ++n) {
+                    const double y = (double)x[f][n];
+                    acc[3 * f] += y;
+                    acc[3 * f + 1] += y * y;
+                    acc[3 * f + 2] = fmax(acc[3 * f + 2], fabs(y));
                 }
+            }
+        }
+    };
+    auto load = [&](T (&x)[3][V], int64_t base) {
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            if (f3[f] != nullptr)
+                red_load<T, V>(x[f], f3[f] + base);
+            else
+#pragma unroll
+                for (int n = 0; n < V; ++n) x[f][n] = T(0);
+        }
+    };
+
+    if (slot < rpp) {
+        int64_t r = (int64_t)blockIdx.x + (int64_t)slot * RB;
+        for (; r + rstep < nrows; r += 2 * rstep) {
+            const int ja = 1 + (int)(r % d.jtot), ka = 1 + (int)(r / d.jtot);
+            const int jb = 1 + (int)((r + rstep) % d.jtot), kb = 1 + (int)((r + rstep) / d.jtot);
+            for (int c = c0; c < cpr; c += cstep) {
+                T xa[3][V], xb[3][V];
+                load(xa, at(d, 1 + c * V, ja, ka));
+                load(xb, at(d, 1 + c * V, jb, kb));
+                add(xa, ka);
+                add(xb, kb);
+            }
+        }
+        if (r < nrows) {
+            const int j = 1 + (int)(r % d.jtot), k = 1 + (int)(r / d.jtot);
+            for (int c = c0; c < cpr; c += cstep) {
+                T x[3][V];
+                load(x, at(d, 1 + c * V, j, k));
+                add(x, k);
             }
         }
     }
@@ -455,14 +516,32 @@ hipError_t launch_reduce(const HostArgs &a, int what, const void *f0, const void
 {
     const Dims d = dims_of(a);
     double *partial = (double *)scratch;
-    if (a.dtype == KL_F32)
-        hipLaunchKernelGGL(reduce_pass1<float>, dim3(RB), dim3(RT), 0, s, d, what, a.kw0, (const float *)f0,
-                           (const float *)f1, (const float *)f2, (const float *)a.dzi,
-                           (const float *)a.dzhi, partial);
-    else
-        hipLaunchKernelGGL(reduce_pass1<double>, dim3(RB), dim3(RT), 0, s, d, what, a.kw0,
-                           (const double *)f0, (const double *)f1, (const double *)f2,
-                           (const double *)a.dzi, (const double *)a.dzhi, partial);
+    // vector width: 4 floats or 2 doubles (16 bytes) when every row start of
+    // the interior and every field pointer is aligned to it, else 1
+    const int vw = a.dtype == KL_F32 ? 4 : 2;
+    const size_t vb = (size_t)vw * (a.dtype == KL_F32 ? 4 : 8);
+    bool vec = a.itot % vw == 0 && (a.off + 1) % vw == 0 && a.js % vw == 0 && a.ks % vw == 0;
+    for (const void *p : {f0, f1, f2})
+        if (p && (uintptr_t)p % vb) vec = false;
+    if (a.dtype == KL_F32) {
+        if (vec)
+            hipLaunchKernelGGL((reduce_pass1<float, 4>), dim3(RB), dim3(RT), 0, s, d, what, a.kw0,
+                               (const float *)f0, (const float *)f1, (const float *)f2, (const float *)a.dzi,
+                               (const float *)a.dzhi, partial);
+        else
+            hipLaunchKernelGGL((reduce_pass1<float, 1>), dim3(RB), dim3(RT), 0, s, d, what, a.kw0,
+                               (const float *)f0, (const float *)f1, (const float *)f2, (const float *)a.dzi,
+                               (const float *)a.dzhi, partial);
+    } else {
+        if (vec)
+            hipLaunchKernelGGL((reduce_pass1<double, 2>), dim3(RB), dim3(RT), 0, s, d, what, a.kw0,
+                               (const double *)f0, (const double *)f1, (const double *)f2, (const double *)a.dzi,
+                               (const double *)a.dzhi, partial);
+        else
+            hipLaunchKernelGGL((reduce_pass1<double, 1>), dim3(RB), dim3(RT), 0, s, d, what, a.kw0,
+                               (const double *)f0, (const double *)f1, (const double *)f2, (const double *)a.dzi,
+                               (const double *)a.dzhi, partial);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(reduce_pass2, dim3(1), dim3(RT), 0, s, what, (const double *)partial, out);
