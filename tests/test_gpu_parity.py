@@ -164,11 +164,15 @@ def test_step_increment_matches_oracle(dtype):
         assert np.max(np.abs(inc - dte * r)) <= bound
 
 
+@pytest.mark.parametrize("shape", [(70, 33, 21), (64, 33, 21), (1024, 3, 4)], ids=lambda s: "x".join(map(str, s)))
 @pytest.mark.parametrize("dtype", [0, 1], ids=["f32", "f64"])
-def test_reductions_match_oracle(dtype):
+def test_reductions_match_oracle(dtype, shape):
+    """itot = 70 takes the one-point-per-thread path; 64 and 1024 the 16-byte
+    vector path (several rows per pass at 64; at 1024 a row is one pass or,
+    in FP64, two chunks per thread)."""
     import torch
     m = kl()
-    c = Case(70, 33, 21, dtype, bc=0, seed=12)
+    c = Case(*shape, dtype, bc=0, seed=12)
     g = c.g
     out = torch.zeros(9, dtype=torch.float64, device="cuda")
     m.kl_reduce_fp64(g, 1, *c.dev, out)
