@@ -341,20 +341,6 @@ def other_dtype_leg(kl, torch, np, shape, dtype, host_fields, visc, steps):
     dif = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
     pair = float(np.mean([e[0].elapsed_time(e[2]) for e in ev]))
 
-    def alone(fn):
-        """Mean duration of one kernel launched back to back (as the tuner
-        times it), beside its duration inside the alternating pair above."""
-        fn()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(steps):
-            fn()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / steps
-
-    adv_alone = alone(lambda: kl.kl_advec_u_2i5(g, tend[0], *dev[:3], stream))
-    dif_alone = alone(lambda: kl.kl_diff_smag(g, *tend, *dev, stream))
     npts = shape[0] * shape[1] * shape[2]
     names = {n: kl.kl_variant_name(k, dtype, kl.kl_selected_variant(g, k))
              for n, k in (("advec_u", kl.ADVEC_U), ("diff_uvw", kl.DIFF_UVW))}
