@@ -172,26 +172,6 @@ __global__ __launch_bounds__(256) void euler_kernel(Dims d, T dt, int kw0, T *u,
     euler_point<T>(d, dt, kw0, u, v, w, ut, vt, wt, i, j, k);
 }
 
-// Batched Euler update: tile = (grid, first row, end row), rows j-1 + jtot*(k-1);
-// dts[grid] is the grid's time step.
-template <typename T>
-__global__ __launch_bounds__(256) void euler_batch_kernel(const StencilArgs<T> *__restrict__ grids,
-                                                         const int4 *__restrict__ tiles, int ntiles,
-                                                         const double *__restrict__ dts)
-{
-    for (int n = blockIdx.x; n < ntiles; n += gridDim.x) {
-        const int4 tl = tiles[n];
-        const StencilArgs<T> a = global_args(grids[tl.x]);
-        const Dims d{a.itot, a.jtot, a.ktot, a.bc, a.off, a.js, a.ks};
-        const T dt = (T)dts[tl.x];
-        for (int r = tl.y; r < tl.z; ++r) {
-            const int j = 1 + r % a.jtot, k = 1 + r / a.jtot;
-            for (int i = 1 + (int)threadIdx.x; i <= a.itot; i += 256)
-                euler_point<T>(d, dt, a.kw0, (T *)a.u, (T *)a.v, (T *)a.w, a.ut, a.vt, a.wt, i, j, k);
-        }
-    }
-}
-
 template <typename T>
 __global__ __launch_bounds__(256) void zero_interior_kernel(Dims d, T *f, int nbx)
 {
@@ -559,18 +539,6 @@ hipError_t launch_hash(const HostArgs &a, const void *f, uint64_t *out, void *sc
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(hash_pass2, dim3(1), dim3(RT), 0, s, (const uint64_t *)partial, out);
-    return hipGetLastError();
-}
-
-hipError_t launch_euler_batch(int dtype, const void *descs, const void *tiles, int ntiles, int nblocks,
-                              const double *dts, hipStream_t s)
-{
-    if (dtype == KL_F32)
-        hipLaunchKernelGGL(euler_batch_kernel<float>, dim3(nblocks), dim3(256), 0, s,
-                           (const StencilArgs<float> *)descs, (const int4 *)tiles, ntiles, dts);
-    else
-        hipLaunchKernelGGL(euler_batch_kernel<double>, dim3(nblocks), dim3(256), 0, s,
-                           (const StencilArgs<double> *)descs, (const int4 *)tiles, ntiles, dts);
     return hipGetLastError();
 }
 

@@ -83,8 +83,6 @@ hipError_t launch_gen_uniform(const HostArgs &a, uint64_t seed, void *u, void *v
                               hipStream_t s);
 size_t reduce_scratch_bytes();
 // Batched row-tile kernels: descs = StencilArgs<T>[], tiles = int4 {grid, row0, row1, 0}[].
-hipError_t launch_euler_batch(int dtype, const void *descs, const void *tiles, int ntiles, int nblocks,
-                              const double *dts, hipStream_t s);
 hipError_t launch_zero_batch(int dtype, const void *descs, const void *tiles, int ntiles, int nblocks,
                              hipStream_t s);
 // Configuration of grid g for `kernel` in batched (persistent) form, or -1.
