@@ -537,16 +537,23 @@ namespace kl {
 // Workgroup = 64 x BY threads (wave r owns row j0 + r, each lane VX points),
 // tile 64*VX x BY, levels [k0, k0 + KB).  The stencil of a point reaches one
 // cell in every direction, in all four inputs (u, v, w, evisc), on levels
-// k-1, k and k+1.  Each input lives in LDS as a ring of four planes of
-// (BY+2) x (TX+2) cells (one halo cell on each side); at level k every
-// wave writes level k+1 of its own row (and its share of the halo rows,
-// the edge lanes the halo columns), while levels k-1 .. k+1 are read.  A
-// plane is rewritten only four levels later, after every wave has passed two
-// barriers since its last reader, so one barrier per level suffices.
-// Global loads of level k+2 are issued one level ahead.  Every point calls
-// the shared per-component functions with the default configuration's
-// operands, so results are bitwise identical.
+// k-1, k and k+1.  The operands on level k-1 are exactly the ones the same
+// lane read on level k one step earlier, so they are carried in registers
+// (struct Below) together with the bottom faces, and LDS holds only levels k
+// and k+1 of each input, plus the plane being refilled: a ring of three
+// planes of (BY+2) x (TX+2) cells (one halo cell on each side).  At level k
+// the waves read levels k and k+1 and then write level k+2 into the plane of
+// level k-1, whose last readers finished before this level's barrier, so
+// one barrier per level suffices.  The global loads of level k+2 are issued
+// before the arithmetic of level k, after those of the tendencies of level
+// k.  Every point calls the shared per-component functions with the default
+// configuration's operands, so results are bitwise identical.
 // ---------------------------------------------------------------------------
+
+template <typename T>
+struct SmagBelow {                          // operands of level k-1 at one point
+    T u, ue, v, vn, e, ew, ee, es, en;
+};
 
 template <typename T, int VX, int BY, int KB, int XCD, int NT, int WPE>
 __global__ __launch_bounds__(64 * BY, WPE) void diff_smag_zl(StencilArgs<T> a)
@@ -556,7 +563,7 @@ __global__ __launch_bounds__(64 * BY, WPE) void diff_smag_zl(StencilArgs<T> a)
     constexpr int PH = BY + 2;              // plane rows: j0-1 .. j0+BY
     constexpr int NH = (8 + BY - 1) / BY;   // halo rows per wave (8 = 2 rows x 4 fields)
     typedef PlanarRow<planar_vx<T, VX>(), PW> SR;  // plane rows, planar by VX (4-byte T)
-    __shared__ __align__(16) T pl[4][4][PH][SR::SIZE];  // [field][level & 3][row][column]
+    __shared__ __align__(16) T pl[4][3][PH][SR::SIZE];  // [field][ring plane][row][column]
 
     int tx, ty, tz;
     tile_of<64, BY, XCD>(a.nbx, a.nby, a.nbz, tx, ty, tz);
@@ -601,37 +608,36 @@ __global__ __launch_bounds__(64 * BY, WPE) void diff_smag_zl(StencilArgs<T> a)
         hr0[m] = hf[m] < 0 ? row_c : a.off + i0w - 1 + (int64_t)(j0 - 1 + hrow[m]) * js;
     }
 
-    T O[2][4][VX], OE[2][4];                // own row of the 4 inputs at one level, halo columns
-    T H[2][NH][VX], HE[2][NH];              // halo rows
-    T TT[2][3][VX];                          // ut, vt, wt at level k (next: k+1)
+    T O[4][VX], OE[4];                      // own row of the 4 inputs at one level, halo columns
+    T H[NH][VX], HE[NH];                    // halo rows
+    T TT[3][VX];                            // ut, vt, wt at level k
 
-    auto load_plane = [&](int q, int l) {    // level l of everything staged, into slot q
+    auto load_plane = [&](int l) {           // level l of everything this wave stages
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
             const T *row = F[f] + row_c + (int64_t)l * ks;
-            vload<T, VX>(O[q][f], boff(row, o_pt));
-            OE[q][f] = *boff(row, o_e);
+            vload<T, VX>(O[f], boff(row, o_pt));
+            OE[f] = *boff(row, o_e);
         }
 #pragma unroll
         for (int m = 0; m < NH; ++m) {
             // a select, not an indexed pointer array, keeps these global loads
             const T *p = hf[m] == 1 ? a.v : (hf[m] == 2 ? a.w : (hf[m] == 3 ? a.evisc : a.u));
             const T *row = p + hr0[m] + (int64_t)l * ks;
-            vload<T, VX>(H[q][m], boff(row, o_pt));
-            HE[q][m] = *boff(row, o_e);
+            vload<T, VX>(H[m], boff(row, o_pt));
+            HE[m] = *boff(row, o_e);
         }
     };
-    auto store_plane = [&](int q, int l) {   // slot q into the LDS planes of level l
-        const int b = l & 3;
+    auto store_plane = [&](int b) {          // the staged level into ring plane b
         if (own) {
 #pragma unroll
             for (int f = 0; f < 4; ++f) {
                 if (lane_on) {
 #pragma unroll
-                    for (int n = 0; n < VX; ++n) pl[f][b][r + 1][SR::at(1 + xo + n)] = O[q][f][n];
+                    for (int n = 0; n < VX; ++n) pl[f][b][r + 1][SR::at(1 + xo + n)] = O[f][n];
                 }
-                if (lane == 0) pl[f][b][r + 1][SR::at(0)] = OE[q][f];
-                if (lane == le) pl[f][b][r + 1][SR::at(xr)] = OE[q][f];
+                if (lane == 0) pl[f][b][r + 1][SR::at(0)] = OE[f];
+                if (lane == le) pl[f][b][r + 1][SR::at(xr)] = OE[f];
             }
         }
 #pragma unroll
@@ -639,64 +645,58 @@ __global__ __launch_bounds__(64 * BY, WPE) void diff_smag_zl(StencilArgs<T> a)
             if (hf[m] < 0) continue;
             if (lane_on) {
 #pragma unroll
-                for (int n = 0; n < VX; ++n) pl[hf[m]][b][hrow[m]][SR::at(1 + xo + n)] = H[q][m][n];
+                for (int n = 0; n < VX; ++n) pl[hf[m]][b][hrow[m]][SR::at(1 + xo + n)] = H[m][n];
             }
-            if (lane == 0) pl[hf[m]][b][hrow[m]][SR::at(0)] = HE[q][m];
-            if (lane == le) pl[hf[m]][b][hrow[m]][SR::at(xr)] = HE[q][m];
+            if (lane == 0) pl[hf[m]][b][hrow[m]][SR::at(0)] = HE[m];
+            if (lane == le) pl[hf[m]][b][hrow[m]][SR::at(xr)] = HE[m];
         }
     };
-    auto load_tend = [&](int q, int k) {     // k <= k1 <= ktot+1
-#pragma unroll
-        for (int f = 0; f < 3; ++f)
-            tload<NT, T, VX>(TT[q][f], boff((f == 0 ? a.ut : (f == 1 ? a.vt : a.wt)) + row_c + (int64_t)k * ks, o_pt));
-    };
 
-    // prologue: planes k0-1 and k0 into LDS, level k0+1 and tendencies of k0 in flight
-    load_plane(0, k0 - 1);
-    store_plane(0, k0 - 1);
-    load_plane(0, k0);
-    store_plane(0, k0);
-    load_plane(0, k0 + 1);
-    load_tend(0, k0);
-
-    // the vertical face values below level k0; the march carries them upward
-    // (the top face of level k is the bottom face of level k+1, bit for bit)
+    // prologue: levels k0-1, k0 and k0+1 into ring planes 0, 1 and 2; the
+    // operands and vertical faces of level k0-1 into registers
+    load_plane(k0 - 1);
+    store_plane(0);
+    load_plane(k0);
+    store_plane(1);
+    load_plane(k0 + 1);
     const T dxi = a.dxi, dyi = a.dyi;
     SmagFace<T> BU[VX], BV[VX];
     T BW[VX];
-#pragma unroll
-    for (int n = 0; n < VX; ++n) {
-        BU[n] = BV[n] = {T(0), T(0)};
-        BW[n] = T(0);
-    }
+    SmagBelow<T> L[VX];
     __syncthreads();
     if (own && lane_on) {
-        const int bm = (k0 - 1) & 3, bc = k0 & 3, rr = r + 1;
+        const int rr = r + 1;
         const T dzhik = kload(a.dzhi, k0);
 #pragma unroll
         for (int n = 0; n < VX; ++n) {
             const int x = 1 + xo + n;
 #define P(f, b, dj, di) pl[f][b][rr + (dj)][SR::at(x + (di))]
-            const T uc = P(0, bc, 0, 0), ub = P(0, bm, 0, 0), vc = P(1, bc, 0, 0), vb = P(1, bm, 0, 0);
-            const T wc = P(2, bc, 0, 0), ww = P(2, bc, 0, -1), ws = P(2, bc, -1, 0), wb = P(2, bm, 0, 0);
-            const T ec = P(3, bc, 0, 0), ew = P(3, bc, 0, -1), es = P(3, bc, -1, 0), eb = P(3, bm, 0, 0),
-                    ebw = P(3, bm, 0, -1), ebs = P(3, bm, -1, 0);
+            const T uc = P(0, 1, 0, 0), ub = P(0, 0, 0, 0), vc = P(1, 1, 0, 0), vb = P(1, 0, 0, 0);
+            const T wc = P(2, 1, 0, 0), ww = P(2, 1, 0, -1), ws = P(2, 1, -1, 0), wb = P(2, 0, 0, 0);
+            const T ec = P(3, 1, 0, 0), ew = P(3, 1, 0, -1), es = P(3, 1, -1, 0), eb = P(3, 0, 0, 0),
+                    ebw = P(3, 0, 0, -1), ebs = P(3, 0, -1, 0);
+            L[n] = {ub, P(0, 0, 0, 1), vb, P(1, 0, 1, 0), eb, ebw, P(3, 0, 0, 1), ebs, P(3, 0, 1, 0)};
 #undef P
             BU[n] = smag_u_zface<T>(ebw, eb, ew, ec, uc, ub, wc, ww, dxi, dzhik);
             BV[n] = smag_v_zface<T>(ebs, eb, es, ec, vc, vb, wc, ws, dyi, dzhik);
             BW[n] = smag_w_zcenter<T>(eb, wc, wb);
         }
     }
+    store_plane(2);
     vm_drain();
+
+    // ring planes of levels k-1, k and k+1, rotated every level
+    int bm = 0, bc = 1, bp = 2;
     for (int k = k0; k < k1; ++k) {
-        // level k+1 into the ring; prefetch level k+2 and the next tendencies
-        store_plane(0, k + 1);
-        load_plane(1, min(k + 2, k1));       // clamped at the end of the tile, where it is unused
-        load_tend(1, k + 1);
-        __syncthreads();
+        __syncthreads();                     // level k+1 visible, level k-1 no longer read
+        // the tendencies of level k, then level k+2 (clamped at the end of
+        // the tile, where it is unused): the arithmetic waits for the former only
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+            tload<NT, T, VX>(TT[f], boff((f == 0 ? a.ut : (f == 1 ? a.vt : a.wt)) + row_c + (int64_t)k * ks, o_pt));
+        load_plane(min(k + 2, k1));
 
         if (own && lane_on) {
-            const int bm = (k - 1) & 3, bc = k & 3, bp = (k + 1) & 3;
             const T dzik = kload(a.dzi, k), dzikm1 = kload(a.dzi, k - 1), dzhik = kload(a.dzhi, k), dzhik1 = kload(a.dzhi, k + 1);
             const int rr = r + 1;
             T o0[VX], o1[VX], o2[VX];
@@ -706,60 +706,46 @@ __global__ __launch_bounds__(64 * BY, WPE) void diff_smag_zl(StencilArgs<T> a)
                 // operand names: <field><offset>; offsets e/w (x), n/s (y), t/b (z)
 #define P(f, b, dj, di) pl[f][b][rr + (dj)][SR::at(x + (di))]
                 const T uc = P(0, bc, 0, 0), ue = P(0, bc, 0, 1), uw = P(0, bc, 0, -1), un = P(0, bc, 1, 0),
-                        us = P(0, bc, -1, 0), ut_ = P(0, bp, 0, 0), ub = P(0, bm, 0, 0), use = P(0, bc, -1, 1),
-                        ube = P(0, bm, 0, 1);
+                        us = P(0, bc, -1, 0), ut_ = P(0, bp, 0, 0), use = P(0, bc, -1, 1);
                 const T vc = P(1, bc, 0, 0), ve = P(1, bc, 0, 1), vw = P(1, bc, 0, -1), vn = P(1, bc, 1, 0),
-                        vs = P(1, bc, -1, 0), vt_ = P(1, bp, 0, 0), vb = P(1, bm, 0, 0), vnw = P(1, bc, 1, -1),
-                        vbn = P(1, bm, 1, 0);
+                        vs = P(1, bc, -1, 0), vt_ = P(1, bp, 0, 0), vnw = P(1, bc, 1, -1);
                 const T wc = P(2, bc, 0, 0), we = P(2, bc, 0, 1), ww = P(2, bc, 0, -1), wn = P(2, bc, 1, 0),
                         ws = P(2, bc, -1, 0), wt_ = P(2, bp, 0, 0), wtw = P(2, bp, 0, -1),
                         wts = P(2, bp, -1, 0);
                 const T ec = P(3, bc, 0, 0), ee = P(3, bc, 0, 1), ew = P(3, bc, 0, -1), en = P(3, bc, 1, 0),
-                        es = P(3, bc, -1, 0), et = P(3, bp, 0, 0), eb = P(3, bm, 0, 0), enw = P(3, bc, 1, -1),
-                        esw = P(3, bc, -1, -1), ese = P(3, bc, -1, 1), etw = P(3, bp, 0, -1),
-                        ebw = P(3, bm, 0, -1), ebe = P(3, bm, 0, 1), ets = P(3, bp, -1, 0), ebs = P(3, bm, -1, 0),
-                        ebn = P(3, bm, 1, 0);
+                        es = P(3, bc, -1, 0), et = P(3, bp, 0, 0), enw = P(3, bc, 1, -1),
+                        esw = P(3, bc, -1, -1), ese = P(3, bc, -1, 1), etw = P(3, bp, 0, -1), ets = P(3, bp, -1, 0);
 #undef P
+                const SmagBelow<T> b = L[n];
                 // the same operations as smag_u/v/w, with the bottom faces carried
                 const SmagFace<T> tu = smag_u_zface<T>(ew, ec, etw, et, ut_, uc, wt_, wtw, dxi, dzhik1);
                 const SmagFace<T> tv = smag_v_zface<T>(es, ec, ets, et, vt_, vc, wt_, wts, dyi, dzhik1);
                 const T tw = smag_w_zcenter<T>(ec, wt_, wc);
-                o0[n] = TT[0][0][n] + smag_uv_total<T>(smag_u_xy<T>(uc, ue, uw, un, us, vn, vnw, vc, vw, ec, ew, en,
-                                                                    enw, es, esw, dxi, dyi),
-                                                       tu, BU[n], dzik);
-                o1[n] = TT[0][1][n] + smag_uv_total<T>(smag_v_xy<T>(vc, ve, vw, vn, vs, ue, use, uc, us, ec, es, ee,
-                                                                    ese, ew, esw, dxi, dyi),
-                                                       tv, BV[n], dzik);
-                o2[n] = TT[0][2][n] + smag_w_total<T>(smag_w_xy<T>(wc, we, ww, wn, ws, ue, ube, uc, ub, vn, vbn, vc,
-                                                                   vb, ec, eb, ee, ebe, ew, ebw, en, ebn, es, ebs,
-                                                                   dxi, dyi, dzhik),
-                                                      tw, BW[n], dzik, dzikm1, dzhik);
+                o0[n] = TT[0][n] + smag_uv_total<T>(smag_u_xy<T>(uc, ue, uw, un, us, vn, vnw, vc, vw, ec, ew, en,
+                                                                 enw, es, esw, dxi, dyi),
+                                                    tu, BU[n], dzik);
+                o1[n] = TT[1][n] + smag_uv_total<T>(smag_v_xy<T>(vc, ve, vw, vn, vs, ue, use, uc, us, ec, es, ee,
+                                                                 ese, ew, esw, dxi, dyi),
+                                                    tv, BV[n], dzik);
+                o2[n] = TT[2][n] + smag_w_total<T>(smag_w_xy<T>(wc, we, ww, wn, ws, ue, b.ue, uc, b.u, vn, b.vn, vc,
+                                                                b.v, ec, b.e, ee, b.ee, ew, b.ew, en, b.en, es, b.es,
+                                                                dxi, dyi, dzhik),
+                                                   tw, BW[n], dzik, dzikm1, dzhik);
                 BU[n] = tu;
                 BV[n] = tv;
                 BW[n] = tw;
+                L[n] = {uc, ue, vc, vn, ec, ew, ee, es, en};
             }
             tstore<NT, T, VX>(boff(a.ut + row_c + (int64_t)k * ks, o_pt), o0);
             tstore<NT, T, VX>(boff(a.vt + row_c + (int64_t)k * ks, o_pt), o1);
             if (k >= a.kw0) tstore<NT, T, VX>(boff(a.wt + row_c + (int64_t)k * ks, o_pt), o2);
         }
 
-        // advance the register slots
-#pragma unroll
-        for (int f = 0; f < 4; ++f) {
-#pragma unroll
-            for (int n = 0; n < VX; ++n) O[0][f][n] = O[1][f][n];
-            OE[0][f] = OE[1][f];
-        }
-#pragma unroll
-        for (int m = 0; m < NH; ++m) {
-#pragma unroll
-            for (int n = 0; n < VX; ++n) H[0][m][n] = H[1][m][n];
-            HE[0][m] = HE[1][m];
-        }
-#pragma unroll
-        for (int f = 0; f < 3; ++f)
-#pragma unroll
-            for (int n = 0; n < VX; ++n) TT[0][f][n] = TT[1][f][n];
+        store_plane(bm);                     // level k+2 over level k-1
+        const int t = bm;
+        bm = bc;
+        bc = bp;
+        bp = t;
     }
 }
 
