@@ -4,10 +4,12 @@
 // Each grid gets its configurations from the wisdom files like a single-grid
 // launch (nearest problem size on this GPU, Section "Kernel Selection and
 // Compilation"); grids whose selected configuration has no persistent form
-// use an LDS z-march configuration sized to the grid.  Grids are grouped by
-// (kernel, dtype, configuration); every group becomes one persistent kernel
-// walking a static tile list, so the graph holds: [zero tendencies] ->
-// advec_u groups -> diff_uvw groups.
+// use an LDS z-march configuration sized to the grid.  The configuration
+// selected for the most grid points then takes every grid it can serve, the
+// next one the rest it can serve, and so on (all configurations give the same
+// bits).  Grids are grouped by (kernel, dtype, configuration); every group
+// becomes one persistent kernel walking a static tile list, so the graph
+// holds: [zero tendencies] -> advec_u groups -> diff_uvw groups.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -82,6 +84,38 @@ int batch_variant(const kl_grid_t *g, int kernel, void *const f[6])
     return -1;
 }
 
+// Regroup the grids of one kernel: the configurations in decreasing order of
+// the grid points they were selected for, each taking every remaining grid
+// it can serve (a persistent form, eligible, a wave segment no wider than
+// the grid's rows).  Fewer groups mean fewer serial persistent kernels and
+// fewer partly idle ends of their tile lists.
+void merge_batch_groups(int kernel, const std::vector<kl_grid_t> &grids, void *const *fields, std::vector<int> &sel)
+{
+    const int nptr = kernel == KL_KERNEL_ADVEC_U ? 4 : 6;
+    std::map<std::pair<int, int>, int64_t> weight;  // (dtype, configuration) -> grid points
+    for (size_t n = 0; n < grids.size(); ++n)
+        weight[{grids[n].dtype, sel[n]}] += (int64_t)grids[n].itot * grids[n].jtot * grids[n].ktot;
+    std::vector<std::pair<int64_t, std::pair<int, int>>> order;
+    for (const auto &w : weight) order.push_back({w.second, w.first});
+    std::stable_sort(order.begin(), order.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
+    std::vector<char> placed(grids.size(), 0);
+    for (const auto &o : order) {
+        const int dtype = o.second.first, vi = o.second.second;
+        const Variant &v = variants(kernel, dtype)[vi];
+        for (size_t n = 0; n < grids.size(); ++n) {
+            const kl_grid_t *g = &grids[n];
+            if (placed[n] || g->dtype != dtype) continue;
+            void *const *f = fields + 6 * n;
+            const void *ptrs[6] = {f[0], f[1], f[2], f[3], f[4], f[5]};
+            if (sel[n] == vi ||
+                (v.batch && 64 * v.vx <= std::max(64, g->itot) && variant_eligible(v, g, ptrs, nptr))) {
+                sel[n] = vi;
+                placed[n] = 1;
+            }
+        }
+    }
+}
+
 hipError_t launch_zero_batch(int dtype, const void *descs, const void *tiles, int ntiles, int nblocks, hipStream_t s)
 {
     if (dtype == KL_F32)
@@ -141,10 +175,15 @@ int build(Batch &b, void *const *fields)
     // groups
     std::map<std::tuple<int, int, int>, size_t> gidx;
     for (int kernel = 0; kernel < 2; ++kernel) {
+        std::vector<int> sel(b.grids.size());
+        for (size_t n = 0; n < b.grids.size(); ++n) {
+            sel[n] = batch_variant(&b.grids[n], kernel, fields + 6 * n);
+            if (sel[n] < 0) return fail(KL_ERR_INVALID, "grid %zu: no batched configuration fits", n);
+        }
+        merge_batch_groups(kernel, b.grids, fields, sel);
         for (size_t n = 0; n < b.grids.size(); ++n) {
             const kl_grid_t *g = &b.grids[n];
-            const int vi = batch_variant(g, kernel, fields + 6 * n);
-            if (vi < 0) return fail(KL_ERR_INVALID, "grid %zu: no batched configuration fits", n);
+            const int vi = sel[n];
             const auto key = std::make_tuple(kernel, g->dtype, vi);
             auto it = gidx.find(key);
             if (it == gidx.end()) {

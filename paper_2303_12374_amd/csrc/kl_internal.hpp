@@ -87,6 +87,8 @@ hipError_t launch_zero_batch(int dtype, const void *descs, const void *tiles, in
                              hipStream_t s);
 // Configuration of grid g for `kernel` in batched (persistent) form, or -1.
 int batch_variant(const kl_grid_t *g, int kernel, void *const f[6]);
+// Regroup grids (6 field pointers each) for fewer persistent kernels: see batch.hip.
+void merge_batch_groups(int kernel, const std::vector<kl_grid_t> &grids, void *const *fields, std::vector<int> &sel);
 
 // Wisdom (wisdom.cpp).
 struct DeviceIdent {

@@ -240,15 +240,18 @@ int run_tick(Server &S, int slot)
     const std::vector<Req *> &act = S.active;
     std::vector<StencilArgs<float>> df;
     std::vector<StencilArgs<double>> dd;
-    std::vector<int> didx(act.size());
+    std::vector<int> didx(act.size()), sel(act.size());
+    std::vector<kl_grid_t> grids(act.size());
+    std::vector<void *> fields(6 * act.size());
     std::map<std::tuple<int, int>, std::vector<int4>> groups;  // (dtype, configuration) -> tiles
     for (size_t n = 0; n < act.size(); ++n) {
         Req &q = *act[n];
-        void *f[6];
+        void **f = fields.data() + 6 * n;
         for (int m = 0; m < 3; ++m) {
             f[m] = q.f[3 * q.cur + m];
             f[3 + m] = q.f[3 * (1 - q.cur) + m];
         }
+        grids[n] = q.g;
         HostArgs a = make_args(&q.g);
         a.u = f[0];
         a.v = f[1];
@@ -265,9 +268,16 @@ int run_tick(Server &S, int slot)
             didx[n] = (int)dd.size();
             dd.push_back(device_args<double>(a));
         }
-        const int vi = batch_variant(&q.g, KL_KERNEL_STEP, f);
-        if (vi < 0)
+        sel[n] = batch_variant(&q.g, KL_KERNEL_STEP, f);
+        if (sel[n] < 0)
             return fail(KL_ERR_INVALID, "no step configuration for request %llu", (unsigned long long)q.ticket);
+    }
+    // as few groups (launches per tick) as the configurations allow; every
+    // configuration gives the same bits, so a request may change group
+    merge_batch_groups(KL_KERNEL_STEP, grids, fields.data(), sel);
+    for (size_t n = 0; n < act.size(); ++n) {
+        const Req &q = *act[n];
+        const int vi = sel[n];
         const Variant &v = variants(KL_KERNEL_STEP, q.g.dtype)[vi];
         auto &tl = groups[std::make_tuple(q.g.dtype, vi)];
         const int nbx = (int)cdivu(q.g.itot, 64 * v.vx), nby = (int)cdivu(q.g.jtot, v.by),
