@@ -361,8 +361,10 @@ int kl_tune_capture(const char *path, const char *wisdom_dir, double budget_s, v
  * g, device pointers owned by the caller) and capture, on `stream`, one HIP
  * graph that runs, for all grids: tendencies := 0 (when zero_tendencies),
  * ut += advec_u, (ut,vt,wt) += diff_uvw, as persistent tile-walking kernels
- * (one per configuration group, configurations taken from the wisdom files)
- * that each walk a static, deterministic tile list.  The grid descriptors
+ * (one per configuration group: configurations taken from the wisdom files,
+ * then regrouped so that the configuration selected for the most grid points
+ * serves every grid it can, and so on; all give the same bits) that each
+ * walk a static, deterministic tile list.  The grid descriptors
  * are copied; the library owns the tile tables and the graph. */
 int kl_batch_create(const kl_grid_t *grids, void *const *fields, int32_t n, double visc,
                     int32_t zero_tendencies, void *stream, void **batch);
