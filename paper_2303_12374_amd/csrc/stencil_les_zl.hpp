@@ -12,8 +12,8 @@
 //   * x faces: each lane reads VX+6 values of its LDS row and evaluates the
 //     VX+1 faces around its points once (a face is shared by two points);
 //   * y faces: two per point, from the seven LDS rows of its column;
-//   * z faces: the u column lives in a seven-level register window (levels
-//     k-2 .. k+4); the lower face's flux is the upper face's flux of the
+//   * z faces: the u column lives in a six-level register window (levels
+//     k-2 .. k+3, level k+4 loaded during level k); the lower face's flux is the upper face's flux of the
 //     level below, carried over; the advecting w of the left neighbour comes
 //     from the neighbouring lane by a shuffle.
 // Every global load is issued one level ahead.  The per-face and per-point
@@ -125,13 +125,14 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zl(StencilArgs<T> a)
     const int lx_u = lane < 3 ? lane : nlanes * VX + lane;                // LDS column of a lane's u halo value
 
     // registers: current (level k) and next (level k+1) copies of what the
-    // LDS planes receive, the w row at k+1 (next: k+2), ut at k (next: k+1)
-    T S[7][VX];                              // u(k-2) .. u(k+4) of the own column
+    // LDS planes receive, the w row at k+1 (next: k+2), ut at k (loaded at
+    // the start of level k, used at its end)
+    T S[6][VX];                              // u(k-2) .. u(k+3) of the own column
     T HU[2][NH][VX], HE[2][NH];              // u halo rows and their x-halo values
     T OE[2];                                 // x-halo value of the own u row
     T VO[2][VX], VH[2][VX], VE[2];           // own v row, v halo row, their left halo values
     T WR[2][VX], WL[2];                      // w at k+1 (and k+2), left neighbour cell (lane 0)
-    T UT[2][VX];
+    T UT[VX];
 
     auto load_level = [&](int q, int k) {    // everything level k needs, into slot q (k <= ktot)
         const int64_t lk = (int64_t)k * ks;
@@ -146,12 +147,11 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zl(StencilArgs<T> a)
         VE[q] = v[e_v + lk];
         vload<T, VX>(WR[q], w + c_own + lk + ks);
         WL[q] = w[e_w + lk + ks];
-        tload<NT, T, VX>(UT[q], ut + c_own + lk);
     };
 
     // prologue: the u window, the flux through face k0, level k0's data
 #pragma unroll
-    for (int m = 0; m < 7; ++m) col_load<T, VX>(S[m], u + c_own, ks, k0 - 2 + m, kt, true);
+    for (int m = 0; m < 6; ++m) col_load<T, VX>(S[m], u + c_own, ks, k0 - 2 + m, kt, true);
     T FB[VX];
     {
         T ub3[VX], w0[VX];
@@ -199,10 +199,12 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zl(StencilArgs<T> a)
             }
             if (lane == 1) sv[p][nv][VR::at(0)] = VE[0];
         }
-        // 2. prefetch level k+1 and the u window's next level
+        // 2. ut of level k (waited for at the end of the level's arithmetic),
+        //    then the prefetch of level k+1 and of the u window's next level
+        tload<NT, T, VX>(UT, ut + c_own + (int64_t)k * ks);
         load_level(1, min(k + 1, k1 - 1));   // clamped at the last level, where it is unused
         T unext[VX];
-        col_load<T, VX>(unext, u + c_own, ks, k + 5, kt, k + 1 < k1);
+        col_load<T, VX>(unext, u + c_own, ks, k + 4, kt, k + 1 < k1);
         __syncthreads();
 
         // 3. compute level k
@@ -261,7 +263,7 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zl(StencilArgs<T> a)
                 const T wm = n == 0 ? wl : WR[0][n - 1];
                 const T ft = flux_z_2i5(mid(wm, WR[0][n]), S[0][n], S[1][n], S[2][n], S[3][n], S[4][n], S[5][n],
                                         k + 1, kt);
-                res[n] = UT[0][n] + advec_2i5_combine(FX[n + 1], FX[n], fn, fs, ft, FB[n], dxi, dyi, dzik);
+                res[n] = UT[n] + advec_2i5_combine(FX[n + 1], FX[n], fn, fs, ft, FB[n], dxi, dyi, dzik);
                 FB[n] = ft;
             }
             tstore<NT, T, VX>(ut + c_own + (int64_t)k * ks, res);
@@ -269,16 +271,15 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zl(StencilArgs<T> a)
 
         // 4. advance the window and the register slots
 #pragma unroll
-        for (int m = 0; m < 6; ++m)
+        for (int m = 0; m < 5; ++m)
 #pragma unroll
             for (int n = 0; n < VX; ++n) S[m][n] = S[m + 1][n];
 #pragma unroll
         for (int n = 0; n < VX; ++n) {
-            S[6][n] = unext[n];
+            S[5][n] = unext[n];
             VO[0][n] = VO[1][n];
             VH[0][n] = VH[1][n];
             WR[0][n] = WR[1][n];
-            UT[0][n] = UT[1][n];
         }
         VE[0] = VE[1];
         WL[0] = WL[1];
