@@ -162,3 +162,28 @@ def test_wisdom_other_kernel_records_ignored(tmp_path):
     (tmp_path / "advec_u.wisdom").write_text(_rec(v1, (64, 64, 64), kernel="diff_uvw") + "\n")
     assert kl.kl_wisdom_lookup(str(tmp_path), kl.ADVEC_U, kl.F32, "AMD Instinct MI355X", "gfx950",
                                64, 64, 64) == ("default", 5)
+
+
+def test_committed_wisdom_names_registered_configurations():
+    """Every record of the committed wisdom files names a configuration this
+    build has (a record naming a missing one would be skipped at selection,
+    so a stale record would silently fall back to another choice)."""
+    kernels = {"advec_u": kl.ADVEC_U, "diff_uvw": kl.DIFF_UVW, "step": kl.STEP,
+               "advec_u_2i5": kl.ADVEC_U_2I5, "diff_smag": kl.DIFF_SMAG}
+    dtypes = {"f32": kl.F32, "f64": kl.F64}
+    wdir = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "wisdom")
+    names = {}
+    seen = 0
+    for fn in sorted(os.listdir(wdir)):
+        with open(os.path.join(wdir, fn)) as f:
+            for line in f:
+                if not line.strip():
+                    continue
+                rec = json.loads(line)
+                key = (kernels[rec["kernel"]], dtypes[rec["dtype"]])
+                if key not in names:
+                    names[key] = {kl.kl_variant_name(*key, i) for i in range(kl.kl_num_variants(*key))}
+                assert rec["variant"] in names[key], f"{fn}: {rec['variant']} ({rec['dtype']}) is not registered"
+                assert rec["kernel"] + ".wisdom" == fn
+                seen += 1
+    assert seen > 0
