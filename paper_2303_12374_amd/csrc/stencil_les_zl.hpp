@@ -13,10 +13,11 @@
 //     VX+1 faces around its points once (a face is shared by two points);
 //   * y faces: two per point, from the seven LDS rows of its column;
 //   * z faces: the u column lives in a six-level register window (levels
-//     k-2 .. k+3, level k+4 loaded during level k); the lower face's flux is the upper face's flux of the
-//     level below, carried over; the advecting w of the left neighbour comes
-//     from the neighbouring lane by a shuffle.
-// Every global load is issued one level ahead.  The per-face and per-point
+//     k-2 .. k+3, level k+4 loaded during level k); the lower face's flux is
+//     the upper face's flux of the level below, carried over; the advecting
+//     w of the left neighbour comes from the neighbouring lane by a shuffle.
+// Every global load is issued one level ahead, except ut, which is loaded at
+// the start of its own level and used at its end.  The per-face and per-point
 // arithmetic is the shared one of stencil_les.hpp with the same operands, so
 // results equal the default configuration's bitwise.
 #pragma once
