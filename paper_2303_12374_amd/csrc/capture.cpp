@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 #include <stdio.h>
 #include <stdlib.h>
+#include <string.h>
 #include <sys/stat.h>
 #include <time.h>
 #include <unistd.h>
@@ -178,6 +179,106 @@ double num(const JVal &o, const char *key, bool *ok)
     return v->num;
 }
 
+// An integer-valued header number within [lo, hi]; *ok = false otherwise.
+int64_t inum(const JVal &o, const char *key, int64_t lo, int64_t hi, bool *ok)
+{
+    bool here = true;
+    const double x = num(o, key, &here);
+    if (!here || !(x >= (double)lo && x <= (double)hi) || x != (double)(int64_t)x) {
+        *ok = false;
+        return 0;
+    }
+    return (int64_t)x;
+}
+
+// Read a capture's header and check it against the payload before anything
+// is allocated or launched: the kernel name and id agree, the dtype is
+// "f32" or "f64", the grid passes the library's own grid checks, the arrays
+// are dzi, dzhi (ktot+2 elements each) and the kernel's fields in order,
+// every field covers the whole ghost box of its layout (the cells a kernel
+// may touch) and the file holds all of their bytes.  On success *g has
+// every member but the metric pointers, and elems[a] the element count of
+// array a.
+int parse_capture(const char *path, kl_grid_t *g, int *kernel_out, long *payload, std::vector<int64_t> &elems)
+{
+    JVal hdr;
+    std::string text;
+    int rc = read_header(path, hdr, text, payload);
+    if (rc) return rc;
+    bool ok = true;
+    const int kernel = (int)inum(hdr, "kernel_id", 0, KL_NUM_KERNELS - 1, &ok);
+    const JVal *kn = hdr.get("kernel"), *dt = hdr.get("dtype"), *ps = hdr.get("problem_size"),
+               *arrs = hdr.get("arrays");
+    if (!ok || !kn || kn->kind != JVal::STR || !dt || dt->kind != JVal::STR || !ps || ps->kind != JVal::ARR ||
+        ps->arr.size() != 3 || !arrs || arrs->kind != JVal::ARR)
+        return fail(KL_ERR_INVALID, "capture %s: incomplete header", path);
+    if (kn->str != kernel_name(kernel))
+        return fail(KL_ERR_INVALID, "capture %s: kernel \"%s\" does not match kernel_id %d", path, kn->str.c_str(),
+                    kernel);
+    if (dt->str != "f32" && dt->str != "f64")
+        return fail(KL_ERR_INVALID, "capture %s: dtype \"%s\" is neither f32 nor f64", path, dt->str.c_str());
+    memset(g, 0, sizeof *g);
+    g->dtype = dt->str == "f64" ? KL_F64 : KL_F32;
+    const int64_t big = (int64_t)1 << 40;
+    for (int d = 0; d < 3; ++d) {
+        const JVal &x = ps->arr[d];
+        if (x.kind != JVal::NUM || !(x.num >= 1 && x.num <= (double)INT32_MAX) || x.num != (double)(int64_t)x.num)
+            return fail(KL_ERR_INVALID, "capture %s: problem_size[%d]", path, d);
+    }
+    g->itot = (int32_t)ps->arr[0].num;
+    g->jtot = (int32_t)ps->arr[1].num;
+    g->ktot = (int32_t)ps->arr[2].num;
+    g->gc = (int32_t)inum(hdr, "gc", 0, 16, &ok);
+    g->off = inum(hdr, "off", 0, big, &ok);
+    g->jstride = inum(hdr, "jstride", 1, big, &ok);
+    g->kstride = inum(hdr, "kstride", 1, big, &ok);
+    g->dxi = num(hdr, "dxi", &ok);
+    g->dyi = num(hdr, "dyi", &ok);
+    g->bc = (int32_t)inum(hdr, "bc", 0, 16, &ok);
+    if (!ok) return fail(KL_ERR_INVALID, "capture %s: incomplete or out-of-range header", path);
+    // the library's grid checks (the metric pointers are not known yet)
+    g->dzi = g->dzhi = (const void *)g;
+    rc = check_grid(g);
+    g->dzi = g->dzhi = nullptr;
+    if (rc) return rc;
+    const int nf = kernel_nptr(kernel);
+    if ((int)arrs->arr.size() != 2 + nf)
+        return fail(KL_ERR_INVALID, "capture %s: %zu arrays, kernel %s needs %d", path, arrs->arr.size(),
+                    kernel_name(kernel), 2 + nf);
+    // the last cell of the ghost box, relative to the captured base
+    const int64_t gc = g->gc;
+    const int64_t last = g->off + (g->itot + gc) + (g->jtot + gc) * g->jstride + (int64_t)(g->ktot + 1) * g->kstride;
+    const size_t es = g->dtype == KL_F32 ? 4 : 8;
+    elems.assign(2 + nf, 0);
+    int64_t total = 0;
+    for (int a = 0; a < 2 + nf; ++a) {
+        const JVal &ar = arrs->arr[a];
+        const JVal *nm = ar.kind == JVal::OBJ ? ar.get("name") : nullptr;
+        const char *want = a == 0 ? "dzi" : (a == 1 ? "dzhi" : field_names[a - 2]);
+        if (!nm || nm->kind != JVal::STR || nm->str != want)
+            return fail(KL_ERR_INVALID, "capture %s: array %d must be \"%s\"", path, a, want);
+        bool aok = true;
+        elems[a] = inum(ar, "elems", 1, big, &aok);
+        if (!aok) return fail(KL_ERR_INVALID, "capture %s: array %s: bad element count", path, want);
+        if (a < 2 && elems[a] != (int64_t)g->ktot + 2)
+            return fail(KL_ERR_INVALID, "capture %s: %s holds %lld values, ktot+2 = %d needed", path, want,
+                        (long long)elems[a], g->ktot + 2);
+        if (a >= 2 && elems[a] <= last)
+            return fail(KL_ERR_INVALID, "capture %s: field %s holds %lld cells, its layout spans %lld", path, want,
+                        (long long)elems[a], (long long)(last + 1));
+        if (a > 2 && elems[a] != elems[2])
+            return fail(KL_ERR_INVALID, "capture %s: field %s size differs from u", path, want);
+        total += elems[a];
+    }
+    struct stat st;
+    if (stat(path, &st) != 0) return fail(KL_ERR_IO, "capture %s: cannot stat", path);
+    if ((int64_t)st.st_size < (int64_t)*payload + total * (int64_t)es)
+        return fail(KL_ERR_IO, "capture %s: truncated payload (%lld bytes, header describes %lld)", path,
+                    (long long)st.st_size, (long long)(*payload + total * (int64_t)es));
+    *kernel_out = kernel;
+    return KL_OK;
+}
+
 }  // namespace
 
 // Called before every selected launch: captures the first launch per
@@ -246,33 +347,13 @@ int kl_tune_capture(const char *path, const char *wisdom_dir, double budget_s, v
 {
     clear_error();
     if (!path) return fail(KL_ERR_INVALID, "NULL path");
-    JVal hdr;
-    std::string text;
-    long payload;
-    int rc = read_header(path, hdr, text, &payload);
-    if (rc) return rc;
-    bool ok = true;
-    const int kernel = (int)num(hdr, "kernel_id", &ok);
-    const JVal *dt = hdr.get("dtype"), *ps = hdr.get("problem_size"), *arrs = hdr.get("arrays");
-    if (!ok || kernel < 0 || kernel >= KL_NUM_KERNELS || !dt || dt->kind != JVal::STR || !ps ||
-        ps->kind != JVal::ARR || ps->arr.size() != 3 || !arrs || arrs->kind != JVal::ARR)
-        return fail(KL_ERR_INVALID, "capture %s: incomplete header", path);
     kl_grid_t g;
-    memset(&g, 0, sizeof g);
-    g.dtype = dt->str == "f64" ? KL_F64 : KL_F32;
-    g.itot = (int32_t)ps->arr[0].num;
-    g.jtot = (int32_t)ps->arr[1].num;
-    g.ktot = (int32_t)ps->arr[2].num;
-    g.gc = (int32_t)num(hdr, "gc", &ok);
-    g.off = (int64_t)num(hdr, "off", &ok);
-    g.jstride = (int64_t)num(hdr, "jstride", &ok);
-    g.kstride = (int64_t)num(hdr, "kstride", &ok);
-    g.dxi = num(hdr, "dxi", &ok);
-    g.dyi = num(hdr, "dyi", &ok);
-    g.bc = (int32_t)num(hdr, "bc", &ok);
-    if (!ok) return fail(KL_ERR_INVALID, "capture %s: incomplete header", path);
+    int kernel;
+    long payload;
+    std::vector<int64_t> elems;
+    int rc = parse_capture(path, &g, &kernel, &payload, elems);
+    if (rc) return rc;
     const int nf = kernel_nptr(kernel);
-    if ((int)arrs->arr.size() != 2 + nf) return fail(KL_ERR_INVALID, "capture %s: %zu arrays", path, arrs->arr.size());
     const size_t es = g.dtype == KL_F32 ? 4 : 8;
     const int64_t line = 128 / (int64_t)es;
     // device copies: metrics, then fields (with slack for aligned vector access)
@@ -292,13 +373,7 @@ int kl_tune_capture(const char *path, const char *wisdom_dir, double budget_s, v
     }
     std::vector<char> buf;
     for (int a = 0; a < 2 + nf; ++a) {
-        bool aok = true;
-        const int64_t elems = (int64_t)num(arrs->arr[a], "elems", &aok);
-        if (!aok || elems <= 0) {
-            fclose(fp);
-            return fail(KL_ERR_INVALID, "capture %s: array %d", path, a);
-        }
-        buf.resize((size_t)elems * es);
+        buf.resize((size_t)elems[a] * es);
         if (fread(buf.data(), 1, buf.size(), fp) != buf.size()) {
             fclose(fp);
             return fail(KL_ERR_IO, "capture %s: truncated payload", path);
@@ -317,11 +392,9 @@ int kl_tune_capture(const char *path, const char *wisdom_dir, double budget_s, v
     for (int n = 0; n < nf; ++n) fields[n] = dev[2 + n];
     // kl_tune takes six field pointers; the advection kernels' unused
     // tendency slots get full-size buffers of the same layout
-    bool aok = true;
-    const int64_t felems = (int64_t)num(arrs->arr[2], "elems", &aok);
     for (int n = nf; n < 6; ++n) {
         void *p = nullptr;
-        const hipError_t e = hipMalloc(&p, (size_t)felems * es + 2 * line * es);
+        const hipError_t e = hipMalloc(&p, (size_t)elems[2] * es + 2 * line * es);
         if (e != hipSuccess) return hip_fail(e, "hipMalloc");
         dev.push_back(p);
         fields[n] = p;

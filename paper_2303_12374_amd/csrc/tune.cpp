@@ -102,7 +102,10 @@ int tune_one(const kl_grid_t *g, int kernel, void *const *f, const std::string &
     // In pair mode a diffusion kernel is timed right after the selected
     // advection kernel of its scheme, as it runs in a time step, so the
     // memory-side cache state it starts from is the one advection leaves.
-    const int pk = after_advec ? partner_of(kernel) : -1;
+    // advec_u_2i5 needs three ghost cells; on a narrower grid diff_smag is
+    // timed on its own.
+    int pk = after_advec ? partner_of(kernel) : -1;
+    if (pk == KL_KERNEL_ADVEC_U_2I5 && g->gc < 3) pk = -1;
     int adv = pk >= 0 ? select_variant(g, pk) : -1;
     if (adv > 0 && !variant_eligible(variants(pk, g->dtype)[adv], g, ptrs, 4)) adv = 0;
     auto before = [&]() { return adv >= 0 ? run_variant(g, pk, adv, f, visc, s, dt) : KL_OK; };
