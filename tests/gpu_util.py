@@ -75,6 +75,19 @@ def rel_err(got, ref):
     return num / den
 
 
+def accumulate_bound(r, expect, dtype):
+    """Bound on max|got - expect| for a kernel that adds its tendency t to a
+    value x0 already in the output (got = fl(x0 + t), one rounding), where
+    expect = x0 + r with r the oracle's tendency.  The tendency itself meets
+    the kernel tolerance, |t - r| <= TOL * max|r|; the addition rounds once,
+    at most half an ulp of |x0 + t| <= max|expect| + TOL * max|r|.  The bound
+    takes a whole ulp (eps) for that rounding."""
+    eps = float(np.finfo(np.float32 if dtype == 0 else np.float64).eps)
+    rmax = float(np.max(np.abs(r))) if r.size else 0.0
+    emax = float(np.max(np.abs(expect))) if expect.size else 0.0
+    return TOL[dtype] * rmax + eps * (emax + TOL[dtype] * rmax)
+
+
 def outside_interior_mask(g):
     """Boolean mask (flat, alloc) of cells outside the interior box."""
     m = np.ones(g.alloc, bool)
@@ -93,4 +106,4 @@ def is_finite(x):
     return bool(np.all(np.isfinite(x)))
 
 
-__all__ = ["Case", "rel_err", "outside_interior_mask", "TOL", "VISC", "math"]
+__all__ = ["Case", "rel_err", "accumulate_bound", "outside_interior_mask", "TOL", "VISC", "math"]

@@ -15,6 +15,17 @@ pytestmark = pytest.mark.gpu
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 TOL = {0: 1e-5, 1: 1e-12}
+SENTINEL = -5.0
+
+
+def outside_untouched(g, t):
+    """Every cell of t outside the interior still holds SENTINEL (checked on
+    the device: the interior is overwritten in a copy)."""
+    x = t.clone()
+    g.interior(x).fill_(SENTINEL)
+    ok = bool((x == SENTINEL).all())
+    del x
+    return ok
 
 
 def kl():
@@ -55,10 +66,12 @@ def test_full_size_sampled_parity(shape, dtype):
                          g.dzi_h.astype(np.float64), g.dzhi_h.astype(np.float64), 0)
         oracle.fill_ghosts(og, *host)
         sel = [m.kl_selected_variant(g, k) for k in (m.ADVEC_U, m.DIFF_UVW)]
-        t = [g.zeros_interior(fill=0.0) for _ in range(4)]
+        t = [g.zeros_interior(fill=SENTINEL) for _ in range(4)]
         m.kl_advec_u(g, t[0], *dev)
         m.kl_diff_uvw(g, t[1], t[2], t[3], *dev, visc)
         torch.cuda.synchronize()
+        for n, x in enumerate(t):
+            assert outside_untouched(g, x), f"output {n} written outside the interior"
         rng = np.random.default_rng(5)
         pts = sample_points(itot, jtot, ktot, 3000, rng)
         idx = torch.tensor([g.off + i + j * g.js + k * g.ks for i, j, k in pts], device="cuda")
@@ -115,10 +128,12 @@ def test_full_size_les_sampled_parity(dtype):
                          g.dzi_h.astype(np.float64), g.dzhi_h.astype(np.float64), 0, 3)
         oracle.fill_ghosts(og, *host[:3])
         oracle.fill_scalar(og, host[3])
-        t = [g.zeros_interior(fill=0.0) for _ in range(4)]
+        t = [g.zeros_interior(fill=SENTINEL) for _ in range(4)]
         m.kl_advec_u_2i5(g, t[0], *dev[:3])
         m.kl_diff_smag(g, t[1], t[2], t[3], *dev)
         torch.cuda.synchronize()
+        for n, x in enumerate(t):
+            assert outside_untouched(g, x), f"output {n} written outside the interior"
         rng = np.random.default_rng(9)
         pts = sample_points(itot, jtot, ktot, 3000, rng)
         idx = torch.tensor([g.off + i + j * g.js + k * g.ks for i, j, k in pts], device="cuda")

@@ -93,8 +93,10 @@ def test_served_request_matches_oracle(dtype, bc):
         assert res.t_arrive_ns <= res.t_admit_ns <= res.t_done_ns
         got = S.fields(res, req)
         ref, g, host = oracle_run(*req[:3], dtype, bc, 3, 2e-3, 1e-5, 77)
+        # 3 steps: the state error stays far inside the kernel tolerance (the
+        # derivation is in test_gpu_parity.test_step_matches_oracle)
         for a, b in zip(got, ref):
-            assert rel_err(a, b) <= 10 * TOL[dtype]
+            assert rel_err(a, b) <= TOL[dtype]
         # FP64 checksums of the final state
         cs = np.array(res.checksum)
         for n in range(3):
