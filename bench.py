@@ -67,15 +67,37 @@ def load_traffic(kernel_name, workload_key, variant):
         return None
 
 
-def cpu_baseline(itot, jtot, k_sample, seed, visc, min_reps=7, min_seconds=10.0):
+def cpu_info():
+    """Host CPU model and the thread counts available to this process."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = None
+    return {"model": model, "logical_cpus": os.cpu_count(), "cpus_in_affinity": affinity}
+
+
+def cpu_baseline(itot, jtot, k_sample, seed, visc, min_reps=7, min_seconds=10.0, threads=None):
     """The CPU oracle (FP64, OpenMP over k) on a 512 x 512 x k_sample slab of
     the same field recipe; grid-points/s of one advec_u + diff_uvw pair,
-    repeated until at least min_seconds of oracle work (and min_reps runs)."""
+    repeated until at least min_seconds of oracle work (and min_reps runs).
+    threads: OpenMP threads (None = the OpenMP default, all host threads)."""
     import numpy as np
 
     import oracle
     from paper_2303_12374_amd import inputs
     lib = oracle.load()
+    default_threads = lib.ora_threads()
+    if threads is not None:
+        lib.ora_set_threads(int(threads))
     zg = inputs.zgrid(k_sample, inputs.domain_height(itot, jtot, k_sample), 1.5)
     fs = inputs.sinusoid_fields(seed, itot, jtot, k_sample, zg)
     off, js, ks, alloc = inputs.plain_layout(itot, jtot, k_sample)
@@ -92,9 +114,10 @@ def cpu_baseline(itot, jtot, k_sample, seed, visc, min_reps=7, min_seconds=10.0)
         oracle.diff_uvw(g, tend[0], tend[1], tend[2], *host, visc)
         times.append(time.perf_counter() - t0)
     best = float(np.median(times))
-    threads = lib.ora_threads() if hasattr(lib, "ora_threads") else os.cpu_count()
+    used = lib.ora_threads()
+    lib.ora_set_threads(default_threads)
     npts = itot * jtot * k_sample
-    return {"value": npts / best, "unit": "grid-points/s", "cores": int(threads), "kind": "oracle",
+    return {"value": npts / best, "unit": "grid-points/s", "cores": int(used), "kind": "oracle",
             "sample": f"{itot}x{jtot}x{k_sample} slab of the same recipe, FP64 oracle, one advec_u+diff_uvw "
                       f"pair, median of {len(times)} runs ({best:.3f} s each, {sum(times):.1f} s total)"}
 
@@ -223,6 +246,12 @@ def served_leg(kl, torch, wisdom, n_req=2000, budget_gib=8.0, load=0.8, sweep=(0
         return np.array(lat) * 1e3, t_free
 
     ls, serial_makespan = serial(t_arr)
+    # the first requests of the same trace, at the same arrival times: serial
+    # plain execution run on the GPU, and the server on exactly those requests
+    n_pre = min(200, len(reqs))
+    pre_serial = serial_plain_run(kl, torch, np, reqs[:n_pre], t_arr[:n_pre], plain_dir)
+    kl.kl_set_wisdom_dir(wisdom)
+    pre_served = served_run(kl, torch, reqs[:n_pre], t_arr[:n_pre], budget_gib)
     run = served_run(kl, torch, reqs, t_arr, budget_gib)
     sweep_out = []
     for ld in sweep:
@@ -241,12 +270,56 @@ def served_leg(kl, torch, wisdom, n_req=2000, budget_gib=8.0, load=0.8, sweep=(0
             "p50_ms": run["p50_ms"], "p99_ms": run["p99_ms"], "mean_ms": run["mean_ms"],
             "grid_point_steps_per_s": run["grid_point_steps_per_s"], "makespan_s": run["makespan_s"],
             "ticks": run["ticks"], "launches": run["launches"], "peak_bytes": run["peak_bytes"],
-            "serial_plain": {"p50_ms": float(np.percentile(ls, 50)), "p99_ms": float(np.percentile(ls, 99)),
-                             "grid_point_steps_per_s": pts_steps / serial_makespan,
-                             "makespan_s": serial_makespan,
-                             "method": "each request's measured plain kl_step time x steps, queued serially "
-                                       "on the same arrival times"},
+            "serial_plain_simulated": {
+                "p50_ms": float(np.percentile(ls, 50)), "p99_ms": float(np.percentile(ls, 99)),
+                "grid_point_steps_per_s": pts_steps / serial_makespan, "makespan_s": serial_makespan,
+                "method": "SIMULATED over the full trace: each request's plain kl_step time (measured per grid "
+                          "and dtype) x steps, queued serially on the same arrival times; excludes set-up, "
+                          "ghost fill, checksums and host synchronisation"},
+            "prefix_measured": {
+                "requests": n_pre,
+                "serial_plain": dict(pre_serial, method="RUN on the GPU: per request, in arrival order after "
+                                     "its arrival, allocate, generate, ghost fill, nsteps plain kl_step "
+                                     "(default configurations), FP64 checksums, synchronise"),
+                "served": {k: pre_served[k] for k in ("p50_ms", "p99_ms", "mean_ms", "grid_point_steps_per_s",
+                                                        "makespan_s")},
+                "arrivals": f"the first {n_pre} requests of the trace at the same arrival times"},
             "load_sweep": sweep_out}
+
+
+def serial_plain_run(kl, torch, np, reqs, t_arr, plain_wisdom):
+    """Serial plain execution of requests, run on the GPU (not simulated):
+    in arrival order, once a request has arrived, the plain path does the
+    work the server does for it -- allocate its six arrays, the seeded
+    initial state (kl_generate_fields), ghost fill, nsteps kl_step with the
+    default configurations, FP64 checksums -- and waits for it.  Latency is
+    completion minus arrival, as for the server."""
+    kl.kl_set_wisdom_dir(plain_wisdom)
+    stream = torch.cuda.current_stream()
+    cs = torch.zeros(9, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    lat, first_arr, last_done = [], None, None
+    base = time.perf_counter()
+    for r, ta in zip(reqs, t_arr):
+        while time.perf_counter() - base < ta:
+            time.sleep(min(0.0005, max(0.0, ta - (time.perf_counter() - base))))
+        g = kl.Grid(*r["shape"], dtype=r["dtype"], bc=kl.BC_ZWALL_ZEROGRAD)
+        f = [torch.empty(g.alloc, dtype=g.tdtype, device="cuda") for _ in range(6)]
+        kl.kl_generate_fields(g, r["seed"], *f[:3], stream)
+        kl.kl_fill_ghosts(g, *f[:3], stream)
+        for _ in range(r["steps"]):
+            kl.kl_step(g, 1e-5, 1e-4, *f, stream)
+        kl.kl_reduce_fp64(g, 1, *f[:3], cs, stream)
+        stream.synchronize()
+        done = time.perf_counter() - base
+        lat.append((done - ta) * 1e3)
+        first_arr = ta if first_arr is None else first_arr
+        last_done = done
+        del f, g
+    pts_steps = sum(r["shape"][0] * r["shape"][1] * r["shape"][2] * r["steps"] for r in reqs)
+    span = last_done - first_arr
+    return {"requests": len(reqs), "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(np.mean(lat)), "grid_point_steps_per_s": pts_steps / span, "makespan_s": span}
 
 
 def served_run(kl, torch, reqs, t_arr, budget_gib):
@@ -301,6 +374,131 @@ def served_run(kl, torch, reqs, t_arr, budget_gib):
             "mean_ms": float(np.mean(lat)), "grid_point_steps_per_s": pts_steps / span, "makespan_s": span,
             "requests_per_s": len(reqs) / span, "wall_s": wall, "ticks": stats[0], "launches": stats[1],
             "peak_bytes": stats[3]}
+
+
+STREAM_MIXES = {"r1w1 (copy)": (1, 1), "r2w1": (2, 1), "r3w3 (fused step)": (3, 3), "r4w1 (advec_u)": (4, 1),
+                "r6w3 (diff_uvw)": (6, 3), "r7w3 (diff_smag)": (7, 3)}
+
+
+def ceiling_leg(kl, torch, np, nbytes=1 << 29, reps=10):
+    """HBM rate of plain streaming kernels (kl_stream_probe) in this process:
+    the copy and each tendency kernel's read/write mix with no stencil, with
+    cached and with non-temporal accesses; median of reps launches each.
+    Arrays of nbytes (512 MiB) each: far beyond the 256 MB Infinity Cache."""
+    bufs = [torch.empty(nbytes, dtype=torch.uint8, device="cuda") for _ in range(10)]
+    for b in bufs:
+        b.fill_(1)
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, (nr, nw) in STREAM_MIXES.items():
+        src, dst = bufs[:nr], bufs[nr:nr + nw]
+        row = {}
+        for nt in (False, True):
+            for _ in range(2):
+                kl.kl_stream_probe(src, dst, nbytes, nt, stream)
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+            for e0, e1 in ev:
+                e0.record(stream)
+                kl.kl_stream_probe(src, dst, nbytes, nt, stream)
+                e1.record(stream)
+            torch.cuda.synchronize()
+            ms = float(np.median([e0.elapsed_time(e1) for e0, e1 in ev]))
+            row["nontemporal_gbps" if nt else "cached_gbps"] = (nr + nw) * nbytes / (ms * 1e6)
+        row["best_gbps"] = max(row["cached_gbps"], row["nontemporal_gbps"])
+        out[name] = row
+    del bufs
+    torch.cuda.empty_cache()
+    return {"arrays_bytes": nbytes, "mixes": out, "copy_gbps": out["r1w1 (copy)"]["best_gbps"],
+            "note": "kl_stream_probe: 16-byte accesses, 4 chunks per thread per pass, XOR of the sources "
+                    "to every destination; no stencil and no reuse"}
+
+
+def precision_leg(kl, torch, np, shape, host_fields, visc):
+    """Normwise error of the FP32 path against the FP64 path on the whole
+    grid: one advec_u + diff_uvw pair (selected configurations) on the same
+    FP64 field recipe, in FP32 (fields, metrics and viscosity rounded to FP32)
+    and in FP64.  The FP64 path is held to the FP64 oracle at 1e-12 by the
+    parity tests, so this is the FP32 path's error against the oracle to
+    that accuracy."""
+    outs = {}
+    for dtype in (kl.F32, kl.F64):
+        g = kl.Grid(*shape, dtype=dtype, bc=kl.BC_ZWALL_ZEROGRAD)
+        dev = [g.upload(f.astype(kl.NP_DTYPE[dtype])) for f in host_fields]
+        kl.kl_fill_ghosts(g, *dev)
+        t = [g.zeros_interior(fill=0.0) for _ in range(4)]
+        kl.kl_advec_u(g, t[0], *dev)
+        kl.kl_diff_uvw(g, t[1], t[2], t[3], *dev, visc)
+        torch.cuda.synchronize()
+        del dev
+        outs[dtype] = (g, t)
+    res = {}
+    g32, t32 = outs[kl.F32]
+    g64, t64 = outs[kl.F64]
+    for n, name in enumerate(("advec_u", "diff_uvw_u", "diff_uvw_v", "diff_uvw_w")):
+        a = g32.interior(t32[n]).to(torch.float64)
+        b = g64.interior(t64[n])
+        den = float(b.abs().max())
+        a.sub_(b)
+        res[name] = float(a.abs().max()) / den if den > 0 else float(a.abs().max())
+        del a
+    del outs, t32, t64
+    torch.cuda.empty_cache()
+    return {"normwise_rel_err": res, "max": max(res.values()),
+            "definition": "max|f32 - f64| / max|f64| per output over the whole interior, both GPU paths on "
+                          "the same FP64 sinusoid fields; the FP64 path meets the oracle to 1e-12",
+            "grid": list(shape)}
+
+
+def pair_leg(kl, torch, np, inputs, shape, dtype, recipe, seed, visc, steps, warmup=3):
+    """advec_u + diff_uvw on one grid: the configurations selected from the
+    wisdom files against the default (untuned) configurations, per-launch
+    durations from HIP events on the launch stream."""
+    g = kl.Grid(*shape, dtype=dtype, bc=kl.BC_ZWALL_ZEROGRAD)
+    if recipe == "sinusoid":
+        fs = inputs.sinusoid_fields(seed, *shape, g.zg)
+    else:
+        fs = inputs.random_fields(seed, *shape)
+    dev = [g.upload(f.astype(kl.NP_DTYPE[dtype])) for f in fs]
+    del fs
+    kl.kl_fill_ghosts(g, *dev)
+    tend = [g.zeros_interior(fill=0.0) for _ in range(3)]
+    stream = torch.cuda.current_stream()
+    s = 4 if dtype == kl.F32 else 8
+    npts = shape[0] * shape[1] * shape[2]
+
+    def run(adv_fn, dif_fn):
+        for _ in range(warmup):
+            adv_fn()
+            dif_fn()
+        torch.cuda.synchronize()
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+        for e in ev:
+            e[0].record(stream)
+            adv_fn()
+            e[1].record(stream)
+            dif_fn()
+            e[2].record(stream)
+        torch.cuda.synchronize()
+        adv = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+        dif = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+        pair = float(np.mean([e[0].elapsed_time(e[2]) for e in ev]))
+        return {"ms_per_pair": pair, "advec_u_ms": adv, "diff_uvw_ms": dif,
+                "grid_points_per_s": npts / (pair * 1e-3), "hbm_gbps": 14 * s * npts / (pair * 1e6),
+                "hbm_frac_of_peak": 14 * s * npts / (pair * 1e6) / PEAK_HBM_GBPS,
+                "advec_u_gbps": 5 * s * npts / (adv * 1e6), "diff_uvw_gbps": 9 * s * npts / (dif * 1e6)}
+
+    tuned = run(lambda: kl.kl_advec_u(g, tend[0], *dev, stream),
+                lambda: kl.kl_diff_uvw(g, *tend, *dev, visc, stream))
+    untuned = run(lambda: kl.kl_launch_variant(g, kl.ADVEC_U, 0, dev + tend, visc, stream),
+                  lambda: kl.kl_launch_variant(g, kl.DIFF_UVW, 0, dev + tend, visc, stream))
+    names = {n: kl.kl_variant_name(k, dtype, kl.kl_selected_variant(g, k))
+             for n, k in (("advec_u", kl.ADVEC_U), ("diff_uvw", kl.DIFF_UVW))}
+    del dev, tend
+    torch.cuda.empty_cache()
+    return {"workload": f"advec_u+diff_uvw {shape[0]}x{shape[1]}x{shape[2]} "
+                        f"{'F32' if dtype == kl.F32 else 'F64'}, {recipe} fields seed {seed}, z walls, tanh z",
+            "tuned": tuned, "untuned": untuned, "speedup_tuned_vs_untuned": untuned["ms_per_pair"] / tuned["ms_per_pair"],
+            "configurations": names, "steps": steps}
 
 
 def copy_probe(torch, nelem=1 << 27, reps=5):
@@ -533,6 +731,10 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--served-requests", type=int, default=2000)
+    ap.add_argument("--no-ceiling", action="store_true", help="skip the streaming-probe ceilings")
+    ap.add_argument("--no-precision", action="store_true", help="skip the FP32-vs-FP64 error of the pair")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the 256^3 FP32/FP64 and 1024x1024x128 FP32 pair legs")
     ap.add_argument("--copy-probe", action="store_true", help="run only the copy probe used to scale counters")
     ap.add_argument("--with-copy-probe", action="store_true", help="run the copy probe first")
     ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_JSON"),
@@ -597,7 +799,7 @@ def main():
     dev = []
     for f in fs:
         dev.append(g.upload(f.astype(kl.NP_DTYPE[dtype])))
-    if args.no_other_dtype and args.no_les:
+    if args.no_other_dtype and args.no_les and args.no_precision:
         del fs
     kl.kl_fill_ghosts(g, *dev)
     tend = [g.zeros_interior(fill=0.0) for _ in range(3)]
@@ -695,6 +897,22 @@ def main():
                      "dispatches_per_launch": 3 if sel_names[dominant].startswith("zl3") else 1},
         "untuned": untuned,
     }
+    if not args.no_ceiling:
+        log("streaming ceilings: copy and the kernels' read/write mixes")
+        ceil = ceiling_leg(kl, torch, np)
+        mixes = ceil["mixes"]
+        ceil["kernel_frac_of_own_mix"] = {
+            "advec_u": (bytes_adv / (adv_ms * 1e6)) / mixes["r4w1 (advec_u)"]["best_gbps"],
+            "diff_uvw": (bytes_dif / (dif_ms * 1e6)) / mixes["r6w3 (diff_uvw)"]["best_gbps"]}
+        ceil["kernel_frac_of_copy"] = {"advec_u": (bytes_adv / (adv_ms * 1e6)) / ceil["copy_gbps"],
+                                       "diff_uvw": (bytes_dif / (dif_ms * 1e6)) / ceil["copy_gbps"],
+                                       "pair": pair_gbps / ceil["copy_gbps"]}
+        result["ceiling"] = ceil
+        result["roofline"]["copy_ceiling_gbps"] = ceil["copy_gbps"]
+        result["roofline"]["frac_of_copy_ceiling"] = achieved / ceil["copy_gbps"]
+    if not args.no_precision:
+        log("FP32 path against the FP64 path on the whole grid")
+        result["precision"] = precision_leg(kl, torch, np, (itot, jtot, ktot), fs, visc)
     if not args.no_other_dtype:
         other = kl.F64 if dtype == kl.F32 else kl.F32
         log(f"the same pair in {'FP64' if other == kl.F64 else 'FP32'}")
@@ -703,7 +921,7 @@ def main():
     if not args.no_les:
         log("the paper's schemes: advec_u_2i5 + diff_smag")
         result["les"] = les_leg(kl, torch, np, inputs, (itot, jtot, ktot), fs, seed, max(5, args.steps // 2))
-    if not (args.no_other_dtype and args.no_les):
+    if not (args.no_other_dtype and args.no_les and args.no_precision):
         del fs
     # one time step: separate kernels (kl_step) versus the fused step kernel
     log("time step: kl_step (zero, advec_u, diff_uvw, Euler) vs kl_step_fused")
@@ -741,6 +959,14 @@ def main():
                             "note": "3 fields read per call (algorithmic bytes 3*N*s), sums in FP64"}
     del dev, tend, u, v, w, ut, vt, wt, out
     torch.cuda.empty_cache()
+    if not args.no_configs:
+        legs = {}
+        for key, shape, dt, recipe, sd in (("256x256x256_f32", (256, 256, 256), kl.F32, "random", 1),
+                                           ("256x256x256_f64", (256, 256, 256), kl.F64, "random", 1),
+                                           ("1024x1024x128_f32", (1024, 1024, 128), kl.F32, "sinusoid", 2)):
+            log(f"pair leg {key}: tuned vs untuned")
+            legs[key] = pair_leg(kl, torch, np, inputs, shape, dt, recipe, sd, visc, max(5, args.steps // 2))
+        result["configs"] = legs
     if not args.no_overhead:
         log("launch overhead: first call per problem size vs later calls")
         result["launch_overhead"] = launch_overhead_leg(kl, torch, np)
@@ -752,8 +978,13 @@ def main():
         result["served"] = served_leg(kl, torch, args.wisdom, args.served_requests)
         result["p99_latency_ms"] = result["served"]["p99_ms"]
     if not args.no_cpu_baseline:
-        log("timing the CPU oracle on a bounded sample")
-        result["cpu_baseline"] = cpu_baseline(itot, jtot, args.cpu_sample_k, seed, float(np.float32(visc)))
+        log("timing the CPU oracle on a bounded sample (all host threads, then one thread)")
+        cb = cpu_baseline(itot, jtot, args.cpu_sample_k, seed, float(np.float32(visc)))
+        one = cpu_baseline(itot, jtot, args.cpu_sample_k, seed, float(np.float32(visc)), min_reps=3,
+                           min_seconds=10.0, threads=1)
+        cb["single_thread"] = {"value": one["value"], "cores": one["cores"], "sample": one["sample"]}
+        cb["cpu"] = cpu_info()
+        result["cpu_baseline"] = cb
     print(json.dumps(result), flush=True)
 
 

@@ -239,6 +239,18 @@ int kl_generate_fields(const kl_grid_t *g, uint64_t seed, void *u, void *v, void
  * probability.  `out` is one device uint64. */
 int kl_hash_interior(const kl_grid_t *g, const void *f, uint64_t *out, void *stream);
 
+/* Streaming probe (a measurement aid, not a stencil): one kernel reads
+ * `bytes` from each of src[0..nread-1] and writes `bytes` to each of
+ * dst[0..nwrite-1] (each destination gets the XOR of the sources), 16 bytes
+ * per lane per access, with non-temporal loads and stores when nontemporal
+ * is non-zero.  It gives the HBM rate of a tendency kernel's access mix
+ * without its stencil.  Built mixes (nread, nwrite): (1,1) copy, (2,1),
+ * (3,3), (4,1), (6,3), (7,3).  Every array is device memory of at least
+ * `bytes` bytes, 16-byte aligned; bytes is a positive multiple of 16384.
+ * KL_ERR_INVALID otherwise.  Asynchronous on `stream`. */
+int kl_stream_probe(int32_t nread, int32_t nwrite, const void *const *src, void *const *dst, int64_t bytes,
+                    int32_t nontemporal, void *stream);
+
 /* ---- configurations (the AOT variant registry) --------------------------- */
 
 /* Number of compiled configurations of `kernel` (KL_KERNEL_*) for `dtype`;

@@ -74,6 +74,8 @@ def _declare(lib):
     lib.ora_point_les.argtypes = dims + [_I, _D, _D, _P, _P, _P, _P, _P, _P, _I, _I, _I, _P]
     lib.ora_threads.argtypes = []
     lib.ora_threads.restype = ctypes.c_int
+    lib.ora_set_threads.argtypes = [_I]
+    lib.ora_set_threads.restype = None
     for f in ("ora_fill_ghosts", "ora_advec_u", "ora_diff_uvw", "ora_euler", "ora_step",
               "ora_conservation", "ora_checksums", "ora_point", "ora_fill_ghosts_gc",
               "ora_fill_scalar", "ora_advec_u_2i5", "ora_diff_smag", "ora_point_les"):

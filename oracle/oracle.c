@@ -569,9 +569,13 @@ void ora_point(int itot, int jtot, int ktot, int64_t off, int64_t js, int64_t ks
 }
 
 /* Number of OpenMP threads the parallel loops above use. */
+/* ora_set_threads(n) sets it (n >= 1); the arithmetic of every loop is the
+ * same for any thread count (each output cell is written by one iteration). */
 #ifdef _OPENMP
 #include <omp.h>
 int ora_threads(void) { return omp_get_max_threads(); }
+void ora_set_threads(int n) { if (n >= 1) omp_set_num_threads(n); }
 #else
 int ora_threads(void) { return 1; }
+void ora_set_threads(int n) { (void)n; }
 #endif

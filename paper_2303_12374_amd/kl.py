@@ -89,6 +89,8 @@ _sig = {
     "kl_reduce_fp64": (c_int, [_G, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "kl_generate_fields": (c_int, [_G, c_uint64, c_void_p, c_void_p, c_void_p, c_void_p]),
     "kl_hash_interior": (c_int, [_G, c_void_p, c_void_p, c_void_p]),
+    "kl_stream_probe": (c_int, [c_int32, c_int32, POINTER(c_void_p), POINTER(c_void_p), c_int64, c_int32,
+                                c_void_p]),
     "kl_num_variants": (c_int, [c_int32, c_int32]),
     "kl_variant_name": (c_int, [c_int32, c_int32, c_int32, c_char_p, c_size_t]),
     "kl_variant_eligible": (c_int, [_G, c_int32, c_int32, POINTER(c_void_p)]),
@@ -232,6 +234,13 @@ def kl_generate_fields(g, seed, u, v, w, stream=None):
 
 def kl_hash_interior(g, f, out, stream=None):
     _check(_lib.kl_hash_interior(byref(_cg(g)), _ptr(f), _ptr(out), _stream(stream)))
+
+
+def kl_stream_probe(srcs, dsts, nbytes, nontemporal=False, stream=None):
+    src = (c_void_p * len(srcs))(*[_ptr(x) for x in srcs])
+    dst = (c_void_p * len(dsts))(*[_ptr(x) for x in dsts])
+    _check(_lib.kl_stream_probe(len(srcs), len(dsts), src, dst, int(nbytes), int(bool(nontemporal)),
+                                _stream(stream)))
 
 
 def kl_num_variants(kernel, dtype) -> int:
