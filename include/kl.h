@@ -299,16 +299,19 @@ int kl_clear_plan_cache(void);
 
 /* Host-only (no GPU work): run the selection heuristic over the wisdom file
  * of `kernel` in `wisdom_dir` (NULL = current wisdom directory) for a given
- * device name, architecture (e.g. "gfx950"), dtype and problem size.
- * *level receives 1 (this GPU, this size), 2 (this GPU, closest size by
+ * device name, architecture (e.g. "gfx950"), compute-unit count, dtype and
+ * problem size.  A record is "this GPU" when its device name matches and,
+ * where both the record and cu_count state one (cu_count > 0), its
+ * compute-unit count matches too: boards of one architecture can report the
+ * same name.  *level receives 1 (this GPU, this size), 2 (this GPU, closest size by
  * Euclidean distance), 3 (this architecture, closest size), 4 (any record,
  * closest size) or 5 (no usable record: the default configuration);
  * `variant` receives the configuration name ("default" at level 5).  Lines
  * that do not parse, other dtypes and unknown configuration names are
  * skipped; among equally close records the later one in the file wins. */
 int kl_wisdom_lookup(const char *wisdom_dir, int32_t kernel, int32_t dtype, const char *device_name,
-                     const char *arch, int32_t itot, int32_t jtot, int32_t ktot, char *variant,
-                     size_t len, int32_t *level);
+                     const char *arch, int32_t cu_count, int32_t itot, int32_t jtot, int32_t ktot,
+                     char *variant, size_t len, int32_t *level);
 
 /* Tune the kernels in kernel_mask (KL_TUNE_* bits: advec_u, diff_uvw, the
  * fused step, advec_u_2i5, diff_smag; KL_TUNE_PAIR: time each diffusion

@@ -3,7 +3,8 @@
 // size, with provenance (Section "Wisdom Files"), and the record-selection
 // heuristic run on the first launch per problem size (Section "Kernel
 // Selection and Compilation"):
-//   1. a record for this GPU and this exact problem size;
+//   1. a record for this GPU (device name, and compute-unit count where the
+//      record states it) and this exact problem size;
 //   2. else the record for this GPU whose problem size is closest
 //      (Euclidean distance);
 //   3. else the closest record for this GPU architecture;
@@ -40,6 +41,7 @@ namespace {
 struct Record {
     std::string device, arch, variant;
     int dtype;
+    int cu_count;  // 0 when the record does not state it
     double size[3];
 };
 
@@ -60,6 +62,8 @@ bool parse_record(const std::string &line, int kernel, Record &r)
         r.size[d] = ps->arr[d].num;
     }
     r.dtype = dt->str == "f32" ? KL_F32 : KL_F64;
+    const JVal *cu = v.get("cu_count");
+    r.cu_count = cu && cu->kind == JVal::NUM ? (int)cu->num : 0;
     r.device = dev->str;
     r.arch = arch->str;
     r.variant = var->str;
@@ -135,7 +139,11 @@ int wisdom_select(const std::string &dir, int kernel, int dtype, const DeviceIde
         if (r.dtype != dtype || !variant_known(kernel, dtype, r.variant)) continue;
         double d2 = 0;
         for (int d = 0; d < 3; ++d) d2 += (r.size[d] - want[d]) * (r.size[d] - want[d]);
-        const bool same_gpu = r.device == dev.name, same_arch = r.arch == dev.arch;
+        // one board: the same device name and, where both sides state it, the same
+        // compute-unit count (boards of one architecture can share a name)
+        const bool same_gpu = r.device == dev.name &&
+                              (dev.cu_count <= 0 || r.cu_count <= 0 || r.cu_count == dev.cu_count);
+        const bool same_arch = r.arch == dev.arch;
         // level 1: same GPU, exact size; 2: same GPU; 3: same arch; 4: any
         const int lvl = (same_gpu && d2 == 0) ? 1 : same_gpu ? 2 : same_arch ? 3 : 4;
         for (int l = lvl; l <= 4; ++l) {
@@ -223,14 +231,14 @@ int kl_set_wisdom_dir(const char *dir)
 }
 
 int kl_wisdom_lookup(const char *wisdom_dir_, int32_t kernel, int32_t dtype, const char *device_name,
-                     const char *arch, int32_t itot, int32_t jtot, int32_t ktot, char *variant, size_t len,
-                     int32_t *level)
+                     const char *arch, int32_t cu_count, int32_t itot, int32_t jtot, int32_t ktot, char *variant,
+                     size_t len, int32_t *level)
 {
     clear_error();
     if (kernel < 0 || kernel >= KL_NUM_KERNELS) return fail(KL_ERR_INVALID, "kernel %d", kernel);
     if (dtype != KL_F32 && dtype != KL_F64) return fail(KL_ERR_INVALID, "dtype %d", dtype);
     if (!device_name || !arch || !variant || !level || len == 0) return fail(KL_ERR_INVALID, "NULL argument");
-    DeviceIdent id{device_name, arch, 0};
+    DeviceIdent id{device_name, arch, cu_count};
     std::string name;
     int lvl = 5;
     const std::string dir = wisdom_dir_ && *wisdom_dir_ ? std::string(wisdom_dir_) : kl::wisdom_dir();

@@ -99,7 +99,7 @@ _sig = {
     "kl_selected_variant": (c_int, [_G, c_int32]),
     "kl_set_wisdom_dir": (c_int, [c_char_p]),
     "kl_clear_plan_cache": (c_int, []),
-    "kl_wisdom_lookup": (c_int, [c_char_p, c_int32, c_int32, c_char_p, c_char_p, c_int32, c_int32,
+    "kl_wisdom_lookup": (c_int, [c_char_p, c_int32, c_int32, c_char_p, c_char_p, c_int32, c_int32, c_int32,
                                  c_int32, c_char_p, c_size_t, POINTER(c_int32)]),
     "kl_tune": (c_int, [_G, POINTER(c_void_p), c_uint32, c_char_p, c_double, c_void_p,
                         POINTER(c_double), c_int32, POINTER(c_int32)]),
@@ -279,11 +279,11 @@ def kl_clear_plan_cache():
     _check(_lib.kl_clear_plan_cache())
 
 
-def kl_wisdom_lookup(wisdom_dir, kernel, dtype, device_name, arch, itot, jtot, ktot):
+def kl_wisdom_lookup(wisdom_dir, kernel, dtype, device_name, arch, itot, jtot, ktot, cu_count=0):
     buf = ctypes.create_string_buffer(128)
     level = c_int32()
     _check(_lib.kl_wisdom_lookup(None if wisdom_dir is None else str(wisdom_dir).encode(), kernel, dtype,
-                                 device_name.encode(), arch.encode(), itot, jtot, ktot, buf, 128,
+                                 device_name.encode(), arch.encode(), cu_count, itot, jtot, ktot, buf, 128,
                                  byref(level)))
     return buf.value.decode(), level.value
 

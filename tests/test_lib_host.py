@@ -117,9 +117,12 @@ def test_variant_registry():
         kl.kl_variant_name(kl.ADVEC_U, kl.F32, 10 ** 6)
 
 
-def _rec(variant, size, device="AMD Instinct MI355X", arch="gfx950", dtype="f32", kernel="advec_u"):
-    return json.dumps({"kernel": kernel, "dtype": dtype, "problem_size": list(size), "device": device,
-                       "arch": arch, "variant": variant, "time_ms": 1.0})
+def _rec(variant, size, device="AMD Instinct MI355X", arch="gfx950", dtype="f32", kernel="advec_u", cu=None):
+    r = {"kernel": kernel, "dtype": dtype, "problem_size": list(size), "device": device,
+         "arch": arch, "variant": variant, "time_ms": 1.0}
+    if cu is not None:
+        r["cu_count"] = cu
+    return json.dumps(r)
 
 
 def test_wisdom_selection_levels(tmp_path):
@@ -155,6 +158,33 @@ def test_wisdom_selection_levels(tmp_path):
     with open(tmp_path / "advec_u.wisdom", "a") as f:
         f.write(_rec(v[2], (256, 256, 256)) + "\n")
     assert look("AMD Instinct MI355X", "gfx950", (256, 256, 256)) == (v[2], 1)
+
+
+def test_wisdom_selection_board_cu_count(tmp_path):
+    """Boards of one architecture can report the same device name (every
+    gfx950 board here reports "AMD Radeon Graphics"); a record's compute-unit
+    count tells them apart at levels 1 and 2, and a record or caller that
+    states none matches any board of that name."""
+    v = [kl.kl_variant_name(kl.ADVEC_U, kl.F32, i) for i in range(1, 4)]
+    d = str(tmp_path)
+    name = "AMD Radeon Graphics"
+    (tmp_path / "advec_u.wisdom").write_text("\n".join([
+        _rec(v[0], (256, 256, 256), device=name, cu=256),
+        _rec(v[1], (256, 256, 256), device=name, cu=304),
+    ]) + "\n")
+    look = lambda cu, size=(256, 256, 256): kl.kl_wisdom_lookup(d, kl.ADVEC_U, kl.F32, name, "gfx950", *size,
+                                                                 cu_count=cu)
+    assert look(256) == (v[0], 1)
+    assert look(304) == (v[1], 1)
+    # another board of the same name and architecture: level 3 (same architecture)
+    assert look(128) == (v[1], 3)
+    assert look(256, (300, 300, 300)) == (v[0], 2)
+    # no count given: any board of that name, the later record wins the tie
+    assert look(0) == (v[1], 1)
+    # a record without a count matches every board of its name
+    with open(tmp_path / "advec_u.wisdom", "a") as f:
+        f.write(_rec(v[2], (256, 256, 256), device=name) + "\n")
+    assert look(128) == (v[2], 1)
 
 
 def test_wisdom_other_kernel_records_ignored(tmp_path):
