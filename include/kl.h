@@ -223,6 +223,19 @@ int kl_step_fused(const kl_grid_t *g, double visc, double dt, const void *u, con
 int kl_reduce_fp64(const kl_grid_t *g, int32_t what, const void *f0, const void *f1,
                    const void *f2, double *out, void *stream);
 
+/* kl_reduce_fp64 for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, hosts that forbid hipMalloc.  Same
+ * arguments, kernels and result bits as kl_reduce_fp64; it calls no
+ * hipMalloc or hipFree.  The pass-1 partials (4096 x 9 doubles, 288 KiB) go
+ * to one fixed array in device memory per GPU, which the library holds until
+ * the process ends.  That need does not depend on the grid, so no grid size
+ * valid for kl_reduce_fp64 is refused for it; devices with ordinal >= 64 get
+ * KL_ERR_INVALID.  Every call on one GPU shares that array: calls that
+ * overlap on one GPU (two streams, two threads) race and may return wrong
+ * sums; serialise them.  Nothing in the array needs to start at zero. */
+int kl_reduce_fp64_noalloc(const kl_grid_t *g, int32_t what, const void *f0, const void *f1,
+                           const void *f2, double *out, void *stream);
+
 /* Fill the interiors of u, v, w with the library's seeded initial state:
  * U[-1,1) noise plus the mean flow (1, 0.5, 0).  The noise value of
  * interior point (i, j, k) of field f (0 u, 1 v, 2 w) comes from the

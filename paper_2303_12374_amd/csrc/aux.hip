@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "kl_internal.hpp"
 #include "stencil.hpp"
 
@@ -556,4 +558,58 @@ hipError_t launch_gen_uniform(const HostArgs &a, uint64_t seed, void *u, void *v
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Reductions without allocation.  The pass-1 partials go to a fixed array in
+// device memory that the code object brings with it, so the call needs no
+// hipMalloc.  Each device holds its own copy until the process ends; its
+// address is looked up once per device, with that device current.  In host
+// code `scratch` names a host-side stand-in, so only the looked-up address is
+// ever handed to a kernel.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[RB * RQ];
+constexpr size_t NOALLOC_SCRATCH_BYTES = sizeof(double) * RB * RQ;  // 288 KiB
+constexpr int NOALLOC_MAX_DEVICES = 64;
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[NOALLOC_MAX_DEVICES];
+}  // namespace
+
 }  // namespace kl
+
+extern "C" int kl_reduce_fp64_noalloc(const kl_grid_t *g, int32_t what, const void *f0, const void *f1,
+                                      const void *f2, double *out, void *stream)
+{
+    using namespace kl;
+    clear_error();
+    int rc = check_grid(g);
+    if (rc) return rc;
+    if (what != 0 && what != 1) return fail(KL_ERR_INVALID, "what=%d", what);
+    if (!out) return fail(KL_ERR_INVALID, "out is NULL");
+    if (what == 0 && (!f0 || !f1 || !f2)) return fail(KL_ERR_INVALID, "conservation sums need ut, vt, wt");
+    // the partial count is fixed (one row of RQ values per pass-1 block), not
+    // a function of the grid; refuse if it ever outgrew the array
+    if (reduce_scratch_bytes() > NOALLOC_SCRATCH_BYTES)
+        return fail(KL_ERR_INVALID, "reduction needs %zu B of scratch, the fixed array holds %zu B",
+                    reduce_scratch_bytes(), NOALLOC_SCRATCH_BYTES);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return fail(KL_ERR_INVALID, "device %d beyond the %d the fixed scratch table covers", dev,
+                    NOALLOC_MAX_DEVICES);
+    void *ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch_ptr[dev]) {
+            e = hipGetSymbolAddress(&g_scratch_ptr[dev], HIP_SYMBOL(scratch));
+            if (e != hipSuccess) {
+                g_scratch_ptr[dev] = nullptr;
+                return hip_fail(e, "hipGetSymbolAddress(scratch)");
+            }
+        }
+        ptr = g_scratch_ptr[dev];
+    }
+    e = launch_reduce(make_args(g), what, f0, f1, f2, out, ptr, (hipStream_t)stream);
+    return e == hipSuccess ? KL_OK : hip_fail(e, "reduce_noalloc");
+}

@@ -87,6 +87,7 @@ _sig = {
     "kl_step_fused": (c_int, [_G, c_double, c_double, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                               c_void_p, c_void_p]),
     "kl_reduce_fp64": (c_int, [_G, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "kl_reduce_fp64_noalloc": (c_int, [_G, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "kl_generate_fields": (c_int, [_G, c_uint64, c_void_p, c_void_p, c_void_p, c_void_p]),
     "kl_hash_interior": (c_int, [_G, c_void_p, c_void_p, c_void_p]),
     "kl_stream_probe": (c_int, [c_int32, c_int32, POINTER(c_void_p), POINTER(c_void_p), c_int64, c_int32,
@@ -225,6 +226,11 @@ def kl_step_fused(g, visc, dt, u, v, w, u_out, v_out, w_out, stream=None):
 def kl_reduce_fp64(g, what, f0, f1, f2, out, stream=None):
     _check(_lib.kl_reduce_fp64(byref(_cg(g)), what, _ptr(f0), _ptr(f1), _ptr(f2), _ptr(out),
                                _stream(stream)))
+
+
+def kl_reduce_fp64_noalloc(g, what, f0, f1, f2, out, stream=None):
+    _check(_lib.kl_reduce_fp64_noalloc(byref(_cg(g)), what, _ptr(f0), _ptr(f1), _ptr(f2), _ptr(out),
+                                       _stream(stream)))
 
 
 def kl_generate_fields(g, seed, u, v, w, stream=None):
