@@ -20,7 +20,10 @@ import torch  # noqa: F401  (loads torch's HIP runtime before libkl binds to it)
 from . import inputs
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libkl.so")
+# KL_LIBRARY may name another build of this same library (the tests use it
+# for a build whose host code carries the address and undefined-behaviour
+# sanitizers); there is no fallback when the named file is missing.
+LIB_PATH = os.environ.get("KL_LIBRARY") or os.path.join(HERE, "libkl.so")
 
 F32, F64 = 0, 1
 BC_ZWALL_ZEROGRAD, BC_ZWALL_NOPEN, BC_ZPERIODIC = 0, 1, 2
