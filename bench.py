@@ -122,10 +122,12 @@ def cpu_baseline(itot, jtot, k_sample, seed, visc, min_reps=7, min_seconds=10.0,
                       f"pair, median of {len(times)} runs ({best:.3f} s each, {sum(times):.1f} s total)"}
 
 
-def batched_leg(kl, inputs, torch, steps=10, warmup=3):
+def batched_leg(kl, inputs, torch, steps=10, warmup=3, tune_dir=None):
     """56 grids (48 with each axis from {32,64,96,128,192}, seed 3, plus 8 of
     256x256x32), FP32: one graph replay of the persistent tile-walking kernels
-    versus 56 x (advec_u + diff_uvw) single-grid launches."""
+    of the fused advec_u + diff_uvw pass versus 56 x (advec_u + diff_uvw)
+    single-grid launches (default and selected configurations) and 56
+    single-grid fused launches."""
     import numpy as np
     shapes = inputs.batch_shapes(3)
     grids, fields = [], []
@@ -138,8 +140,12 @@ def batched_leg(kl, inputs, torch, steps=10, warmup=3):
         fields.append(f)
     npts = sum(g.npoints for g in grids)
     b = kl.kl_batch_create(grids, fields, 1e-5, False)
-    nk, nt = kl.kl_batch_info(b)
     stream = torch.cuda.current_stream()
+    tuned = None
+    if tune_dir:
+        tuned = kl.kl_batch_tune(b, tune_dir, 120.0, stream)
+    nk, nt = kl.kl_batch_info(b)
+    groups = kl.kl_batch_groups(b)
 
     def time_it(fn, k):
         for _ in range(warmup):
@@ -165,17 +171,31 @@ def batched_leg(kl, inputs, torch, steps=10, warmup=3):
             kl.kl_advec_u(g, f[3], *f[:3], stream)
             kl.kl_diff_uvw(g, *f[3:], *f[:3], 1e-5, stream)
 
+    def fused():
+        for g, f in zip(grids, fields):
+            kl.kl_advec_diff(g, *f[3:], *f[:3], 1e-5, stream)
+
     plain_ms = time_it(plain, max(3, steps // 2))
     sel_ms = time_it(selected, max(3, steps // 2))
+    fused_ms = time_it(fused, max(3, steps // 2))
     kl.kl_batch_destroy(b)
     del fields
     torch.cuda.empty_cache()
     return {"workload": "56 grids FP32 (48 x {32,64,96,128,192}^3 per axis, seed 3; 8 x 256x256x32)",
             "points": npts, "graph_kernels": nk, "tiles": nt,
+            "configurations": [name for _, name, _ in groups],
+            "tuned_now": None if tuned is None else
+            {kl.kl_variant_name(kl.ADVEC_DIFF, kl.F32, i) if i >= 0 else "per_grid": ms for i, ms in tuned},
             "batched_ms": batched_ms, "batched_grid_points_per_s": npts / (batched_ms * 1e-3),
             "plain_112_launches_ms": plain_ms, "selected_112_launches_ms": sel_ms,
+            "fused_56_launches_ms": fused_ms,
             "speedup_vs_plain": plain_ms / batched_ms, "speedup_vs_selected": sel_ms / batched_ms,
-            "hbm_gbps_algorithmic": 14 * 4 * npts / (batched_ms * 1e6)}
+            "speedup_vs_fused_launches": fused_ms / batched_ms,
+            "hbm_gbps_algorithmic": 9 * 4 * npts / (batched_ms * 1e6),
+            "hbm_frac_of_peak": 9 * 4 * npts / (batched_ms * 1e6) / PEAK_HBM_GBPS,
+            "bytes_note": "the graph runs the fused pass: 9 values per point (u, v, w, ut, vt, wt read; "
+                          "ut, vt, wt written); the two separate kernels move 14",
+            "hbm_gbps_14_value_equivalent": 14 * 4 * npts / (batched_ms * 1e6)}
 
 
 def served_trace(n=2000, seed=4, rate=None):
@@ -721,6 +741,8 @@ def main():
     ap.add_argument("--recipe", default="sinusoid", choices=["sinusoid", "random"])
     ap.add_argument("--wisdom", default=os.path.join(ROOT, "wisdom"))
     ap.add_argument("--tune", action="store_true", help="tune both kernels first (appends to --wisdom)")
+    ap.add_argument("--tune-batch", action="store_true",
+                    help="tune the batched workload as a whole first (kl_batch_tune; appends to --wisdom)")
     ap.add_argument("--tune-budget", type=float, default=60.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-k", type=int, default=128)
@@ -871,6 +893,27 @@ def main():
                    "grid_points_per_s": npts * k / (t_ms * 1e-3),
                    "speedup_tuned_vs_untuned": (t_ms / k) / ms_per_step}
 
+    # the same pair as one fused pass (kl_advec_diff): bitwise the same
+    # tendencies, 9 values per point moved instead of 14
+    k_f = max(5, args.steps // 2)
+    for _ in range(2):
+        kl.kl_advec_diff(g, ut, vt, wt, u, v, w, visc, stream)
+    torch.cuda.synchronize()
+    ev_f = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev_f[0].record(stream)
+    for _ in range(k_f):
+        kl.kl_advec_diff(g, ut, vt, wt, u, v, w, visc, stream)
+    ev_f[1].record(stream)
+    torch.cuda.synchronize()
+    fused_ms = ev_f[0].elapsed_time(ev_f[1]) / k_f
+    pair_fused = {"ms": fused_ms, "grid_points_per_s": npts / (fused_ms * 1e-3),
+                  "hbm_gbps": 9 * npts * s / (fused_ms * 1e6),
+                  "hbm_frac_of_peak": 9 * npts * s / (fused_ms * 1e6) / PEAK_HBM_GBPS,
+                  "speedup_vs_separate_pair": ms_per_step / fused_ms,
+                  "configuration": kl.kl_variant_name(kl.ADVEC_DIFF, dtype, kl.kl_selected_variant(g, kl.ADVEC_DIFF)),
+                  "note": "advec_u then diff_uvw as one pass (kl_advec_diff), bitwise the separate kernels' "
+                          "tendencies; 9 values per point (u, v, w, ut, vt, wt read, ut, vt, wt written)"}
+
     result = {
         "metric": METRIC,
         "value": value,
@@ -896,6 +939,7 @@ def main():
                      "algorithmic_bytes_per_launch": dom_bytes,
                      "dispatches_per_launch": 3 if sel_names[dominant].startswith("zl3") else 1},
         "untuned": untuned,
+        "pair_fused": pair_fused,
     }
     if not args.no_ceiling:
         log("streaming ceilings: copy and the kernels' read/write mixes")
@@ -972,7 +1016,7 @@ def main():
         result["launch_overhead"] = launch_overhead_leg(kl, torch, np)
     if not args.no_batched:
         log("batched form: 56 grids in one graph vs 112 single-grid launches")
-        result["batched"] = batched_leg(kl, inputs, torch)
+        result["batched"] = batched_leg(kl, inputs, torch, tune_dir=args.wisdom if args.tune_batch else None)
     if not args.no_served:
         log(f"served form: {args.served_requests} requests")
         result["served"] = served_leg(kl, torch, args.wisdom, args.served_requests)

@@ -61,7 +61,10 @@
  *    surfaces at the caller's next synchronisation.
  *  - Tendency kernels ACCUMULATE (+=) into the interior cells of their
  *    outputs and never write ghost or padding cells; they read ghost cells
- *    of u, v, w, which the caller fills first (kl_fill_ghosts).
+ *    of u, v, w, which the caller fills first (kl_fill_ghosts).  x is
+ *    periodic in every mode, and a configuration may take an x neighbour
+ *    across the periodic boundary from the interior cell rather than from
+ *    its ghost copy: after the ghost fill both hold the same value.
  */
 #ifndef KL_H_
 #define KL_H_
@@ -95,13 +98,15 @@ typedef enum {
 } kl_status_t;
 
 /* Kernels with tunable configurations.  KL_KERNEL_STEP is the fused time
- * step of kl_step_fused. */
+ * step of kl_step_fused; KL_KERNEL_ADVEC_DIFF is advec_u followed by
+ * diff_uvw in one pass (kl_advec_diff, and the batched form). */
 enum {
     KL_KERNEL_ADVEC_U = 0,
     KL_KERNEL_DIFF_UVW = 1,
     KL_KERNEL_STEP = 2,
     KL_KERNEL_ADVEC_U_2I5 = 3,
-    KL_KERNEL_DIFF_SMAG = 4
+    KL_KERNEL_DIFF_SMAG = 4,
+    KL_KERNEL_ADVEC_DIFF = 5
 };
 
 /* kl_tune kernel_mask bits. */
@@ -111,7 +116,8 @@ enum {
     KL_TUNE_STEP = 4u,
     KL_TUNE_PAIR = 8u, /* time each diffusion kernel right after its advection kernel */
     KL_TUNE_ADVEC_U_2I5 = 16u,
-    KL_TUNE_DIFF_SMAG = 32u
+    KL_TUNE_DIFF_SMAG = 32u,
+    KL_TUNE_ADVEC_DIFF = 64u
 };
 
 /* One grid.  Element (i, j, k) of every field is at index
@@ -175,6 +181,18 @@ int kl_advec_u(const kl_grid_t *g, void *ut, const void *u, const void *v, const
  * (formula above).  u, v, w must be ghost-filled.  Selection as kl_advec_u. */
 int kl_diff_uvw(const kl_grid_t *g, void *ut, void *vt, void *wt,
                 const void *u, const void *v, const void *w, double visc, void *stream);
+
+/* kl_advec_u followed by kl_diff_uvw, as one pass over the grid: ut +=
+ * advec_u, then ut += diff_u, vt += diff_v, wt += diff_w on each field's
+ * computed range.  The additions are made in that order and rounded as in
+ * the two separate calls, so the tendencies are bitwise those of
+ * kl_advec_u; kl_diff_uvw, while the pass reads u, v, w, ut, vt, wt once
+ * and writes ut, vt, wt once (9 values per point instead of 14).  The two
+ * kernels are the paper's pair (Section "Experimental Evaluation"); fusing
+ * them is this library's.  u, v, w must be ghost-filled; ut, vt, wt must not
+ * overlap u, v, w.  Selection as kl_advec_u (wisdom file advec_diff.wisdom). */
+int kl_advec_diff(const kl_grid_t *g, void *ut, void *vt, void *wt, const void *u, const void *v,
+                  const void *w, double visc, void *stream);
 
 /* ut += advec_u_2i5(u, v, w) on the interior (scheme above).  Requires
  * g->gc >= 3; u, v, w ghost-filled.  Selection as kl_advec_u (wisdom file
@@ -327,7 +345,7 @@ int kl_wisdom_lookup(const char *wisdom_dir, int32_t kernel, int32_t dtype, cons
                      char *variant, size_t len, int32_t *level);
 
 /* Tune the kernels in kernel_mask (KL_TUNE_* bits: advec_u, diff_uvw, the
- * fused step, advec_u_2i5, diff_smag; KL_TUNE_PAIR: time each diffusion
+ * fused step, advec_u_2i5, diff_smag, the fused advec_diff; KL_TUNE_PAIR: time each diffusion
  * kernel right after the selected advection kernel of its scheme, as in a
  * time step, so that the cache state it starts from is realistic) for this
  * grid on the current device: every eligible configuration is checked for
@@ -388,14 +406,50 @@ int kl_tune_capture(const char *path, const char *wisdom_dir, double budget_s, v
 /* Build a batch of n grids (fields[6*g + f] = {u, v, w, ut, vt, wt} of grid
  * g, device pointers owned by the caller) and capture, on `stream`, one HIP
  * graph that runs, for all grids: tendencies := 0 (when zero_tendencies),
- * ut += advec_u, (ut,vt,wt) += diff_uvw, as persistent tile-walking kernels
- * (one per configuration group: configurations taken from the wisdom files,
- * then regrouped so that the configuration selected for the most grid points
- * serves every grid it can, and so on; all give the same bits) that each
- * walk a static, deterministic tile list.  The grid descriptors
- * are copied; the library owns the tile tables and the graph. */
+ * then ut += advec_u followed by (ut,vt,wt) += diff_uvw fused in one pass
+ * as in kl_advec_diff (bitwise the two separate kernels), as persistent
+ * tile-walking kernels (one per configuration group: advec_diff
+ * configurations taken from the wisdom files, then regrouped so that the
+ * configuration selected for the most grid points serves every grid it
+ * can, and so on; all give the same bits) whose blocks draw tiles from a
+ * work queue, largest tiles first.  Every tile is computed once, by one
+ * block, with the same arithmetic, so the results do not depend on which
+ * block takes it.  The queue returns to zero at the end of every replay;
+ * replays of one batch must not overlap (launch them on one stream).  The
+ * grid descriptors are copied; the library owns the tile tables, the queues
+ * and the graph. */
 int kl_batch_create(const kl_grid_t *grids, void *const *fields, int32_t n, double visc,
                     int32_t zero_tendencies, void *stream, void **batch);
+
+/* Tune a batch as a whole (the batch-level form of kl_tune): time the
+ * batch with its per-grid selection and then with each persistent
+ * advec_diff configuration serving every grid it can (the mean of
+ * 10 graph replays after 2 warm-ups, on `stream`), after checking that each
+ * gives the same output bits as the per-grid selection (sum of the bit
+ * hashes of every grid's ut, vt, wt after one replay on zeroed tendencies).
+ * A configuration fastest for one grid launched alone, where latency
+ * decides, need not be fastest inside a full batch, where bytes per tile
+ * decide.  The fastest is appended to <wisdom_dir>/advec_diff_batch.wisdom
+ * (NULL = current wisdom directory) under the batch's signature, a hash of
+ * the sorted (itot, jtot, ktot, bc, gc) of its grids of one dtype, with the
+ * variant name ("per_grid" when the per-grid selection won), the time, the
+ * per-grid selection's time and provenance; kl_batch_create uses a record
+ * with the batch's signature (this GPU, else this architecture, else any)
+ * before the per-grid selection.  The batch is rebuilt with the winner.
+ * Tunes each dtype of the batch in turn until budget_s seconds are spent
+ * (the per-grid selection is always timed).  The tendencies of every grid
+ * are clobbered.  timings_out (if not NULL) receives up to max_timings
+ * pairs (configuration index, -1 for the per-grid selection; ms, or -1 for
+ * a configuration whose bits differed), *n_timings their count.
+ * Synchronous. */
+int kl_batch_tune(void *batch, const char *wisdom_dir, double budget_s, void *stream, double *timings_out,
+                  int32_t max_timings, int32_t *n_timings);
+
+/* Configuration group `group` (0 .. n_kernels of kl_batch_info minus the
+ * zeroing kernels) of a batch: its dtype, configuration name (into name,
+ * truncated to len) and tile count (host pointers; any may be NULL).
+ * KL_ERR_NOTFOUND past the last group. */
+int kl_batch_group(void *batch, int32_t group, int32_t *dtype, char *name, size_t len, int64_t *n_tiles);
 
 /* Replay the batch's graph on `stream` (asynchronous). */
 int kl_batch_run(void *batch, void *stream);

@@ -323,6 +323,18 @@ int kl_diff_uvw(const kl_grid_t *g, void *ut, void *vt, void *wt, const void *u,
     return launch_selected(g, KL_KERNEL_DIFF_UVW, f, visc, (hipStream_t)stream);
 }
 
+int kl_advec_diff(const kl_grid_t *g, void *ut, void *vt, void *wt, const void *u, const void *v, const void *w,
+                  double visc, void *stream)
+{
+    clear_error();
+    int rc = check_grid(g);
+    if (rc) return rc;
+    const void *p[6] = {u, v, w, ut, vt, wt};
+    if ((rc = check_ptrs(p, 6))) return rc;
+    void *f[6] = {(void *)u, (void *)v, (void *)w, ut, vt, wt};
+    return launch_selected(g, KL_KERNEL_ADVEC_DIFF, f, visc, (hipStream_t)stream);
+}
+
 int kl_euler(const kl_grid_t *g, double dt, void *u, void *v, void *w, const void *ut, const void *vt,
              const void *wt, void *stream)
 {

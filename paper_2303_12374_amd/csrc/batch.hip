@@ -1,22 +1,42 @@
 // Batched form: many independent grids advanced by persistent tile-walking
 // kernels captured once in a HIP graph.
 //
-// Each grid gets its configurations from the wisdom files like a single-grid
-// launch (nearest problem size on this GPU, Section "Kernel Selection and
-// Compilation"); grids whose selected configuration has no persistent form
-// use an LDS z-march configuration sized to the grid.  The configuration
-// selected for the most grid points then takes every grid it can serve, the
-// next one the rest it can serve, and so on (all configurations give the same
-// bits).  Grids are grouped by (kernel, dtype, configuration); every group
-// becomes one persistent kernel walking a static tile list, so the graph
-// holds: [zero tendencies] -> advec_u groups -> diff_uvw groups.
+// Every grid runs advec_u followed by diff_uvw as one fused pass (the tile of
+// kl_advec_diff: 9 values per point moved instead of 14, bitwise the result
+// of the two separate kernels).  Each grid gets its configuration from the
+// wisdom files like a single-grid launch (nearest problem size on this GPU,
+// Section "Kernel Selection and Compilation"); grids whose selected
+// configuration has no persistent form use an LDS z-march configuration
+// sized to the grid.  The configuration selected for the most grid points
+// then takes every grid it can serve, the next one the rest it can serve, and
+// so on (all configurations give the same bits).  Grids are grouped by
+// (dtype, configuration); every group becomes one persistent kernel whose
+// blocks draw tiles from a work queue over the group's tile list, so the
+// graph holds: [zero tendencies] -> the fused groups (one launch when one
+// configuration serves every grid).
+//
+// A configuration that is fastest for one grid launched alone (where the
+// launch is short and latency decides) need not be fastest inside a batch
+// (where the GPU is full and bytes per tile decide), so a batch can also be
+// tuned as a whole: kl_batch_tune times the batch with each configuration
+// serving every grid it can and appends the fastest to
+// advec_diff_batch.wisdom under the batch's signature (its multiset of
+// grid shapes, boundary modes and dtype).  kl_batch_create takes a record
+// with the batch's signature, for this GPU if there is one, else for this
+// architecture, else any, before the per-grid selection.
 #include <hip/hip_runtime.h>
+#include <stdio.h>
 
 #include <algorithm>
+#include <chrono>
+#include <fstream>
 #include <map>
+#include <sstream>
+#include <string>
 #include <tuple>
 #include <vector>
 
+#include "json.hpp"
 #include "kl_internal.hpp"
 #include "variants.hpp"
 
@@ -26,14 +46,18 @@ namespace {
 struct Group {
     int kernel, dtype, variant;
     std::vector<int4> tiles;
+    std::vector<int64_t> cost;  // grid points of each tile
     void *d_tiles = nullptr;
+    int *d_queue = nullptr;  // work queue of the persistent kernel (two ints)
     int nblocks = 0;
 };
 
 struct Batch {
     std::vector<kl_grid_t> grids;
+    std::vector<void *> fields;  // 6 per grid
     double visc = 0;
     bool zero = false;
+    int forced[2] = {-1, -1};  // configuration serving every grid it can, per dtype (-1: per-grid selection)
     void *d_desc[2] = {nullptr, nullptr};  // StencilArgs<float>[] and StencilArgs<double>[], indexed by grid
     std::vector<int4> ztiles[2];
     void *d_ztiles[2] = {nullptr, nullptr};
@@ -44,17 +68,31 @@ struct Batch {
     int64_t ntiles = 0;
     int nkernels = 0;
 
-    ~Batch()
+    // release everything build() made, so that it can run again
+    void release()
     {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
         for (int d = 0; d < 2; ++d) {
             if (d_desc[d]) (void)hipFree(d_desc[d]);
             if (d_ztiles[d]) (void)hipFree(d_ztiles[d]);
+            d_desc[d] = nullptr;
+            d_ztiles[d] = nullptr;
+            ztiles[d].clear();
+            zblocks[d] = 0;
         }
-        for (auto &g : groups)
+        for (auto &g : groups) {
             if (g.d_tiles) (void)hipFree(g.d_tiles);
+            if (g.d_queue) (void)hipFree(g.d_queue);
+        }
+        groups.clear();
+        ntiles = 0;
+        nkernels = 0;
     }
+
+    ~Batch() { release(); }
 };
 
 }  // namespace
@@ -64,7 +102,7 @@ int batch_variant(const kl_grid_t *g, int kernel, void *const f[6])
 {
     const auto &vs = variants(kernel, g->dtype);
     const void *ptrs[6] = {f[0], f[1], f[2], f[3], f[4], f[5]};
-    const int nptr = kernel == KL_KERNEL_ADVEC_U ? 4 : 6;
+    const int nptr = kernel_nptr(kernel);
     const int sel = select_variant(g, kernel);
     // a selected configuration whose wave segment (64 * vx points) is wider
     // than the grid's rows would leave most lanes idle: size one to the grid
@@ -91,7 +129,7 @@ int batch_variant(const kl_grid_t *g, int kernel, void *const f[6])
 // fewer partly idle ends of their tile lists.
 void merge_batch_groups(int kernel, const std::vector<kl_grid_t> &grids, void *const *fields, std::vector<int> &sel)
 {
-    const int nptr = kernel == KL_KERNEL_ADVEC_U ? 4 : 6;
+    const int nptr = kernel_nptr(kernel);
     std::map<std::pair<int, int>, int64_t> weight;  // (dtype, configuration) -> grid points
     for (size_t n = 0; n < grids.size(); ++n)
         weight[{grids[n].dtype, sel[n]}] += (int64_t)grids[n].itot * grids[n].jtot * grids[n].ktot;
@@ -156,6 +194,90 @@ hipError_t upload(void **dst, const void *src, size_t bytes)
     return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
 }
 
+// Whether configuration v can run grid g in a persistent kernel: it has a
+// persistent form, fits the layout and pointers, and its wave segment (64 vx
+// points) is no wider than the grid's rows.
+bool serves(const Variant &v, const kl_grid_t *g, void *const *f)
+{
+    const void *ptrs[6] = {f[0], f[1], f[2], f[3], f[4], f[5]};
+    return v.batch && 64 * v.vx <= std::max(64, g->itot) && variant_eligible(v, g, ptrs, 6);
+}
+
+// Signature of the grids of one dtype: FNV-1a over their sorted (itot, jtot,
+// ktot, bc, gc) tuples, so that the same grids in any order match.
+uint64_t batch_signature(const std::vector<kl_grid_t> &grids, int dtype, int64_t *npts, int *ngrids)
+{
+    std::vector<std::tuple<int, int, int, int, int>> key;
+    *npts = 0;
+    for (const kl_grid_t &g : grids)
+        if (g.dtype == dtype) {
+            key.emplace_back(g.itot, g.jtot, g.ktot, g.bc, g.gc);
+            *npts += (int64_t)g.itot * g.jtot * g.ktot;
+        }
+    std::sort(key.begin(), key.end());
+    *ngrids = (int)key.size();
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](int64_t x) {
+        for (int q = 0; q < 8; ++q) {
+            h ^= (uint64_t)((x >> (8 * q)) & 0xff);
+            h *= 1099511628211ull;
+        }
+    };
+    mix((int64_t)key.size());
+    for (const auto &t : key) {
+        mix(std::get<0>(t));
+        mix(std::get<1>(t));
+        mix(std::get<2>(t));
+        mix(std::get<3>(t));
+        mix(std::get<4>(t));
+    }
+    return h;
+}
+
+std::string batch_wisdom_path(const std::string &dir) { return dir + "/advec_diff_batch.wisdom"; }
+
+std::string hex64(uint64_t x)
+{
+    char buf[24];
+    snprintf(buf, sizeof buf, "%016llx", (unsigned long long)x);
+    return buf;
+}
+
+// Configuration index recorded for this signature and dtype (this GPU, else
+// this architecture, else any GPU; the later record wins within a level), or
+// -1.  Records naming a configuration this build lacks are skipped.
+int batch_wisdom_lookup(const std::string &dir, int dtype, uint64_t sig)
+{
+    std::ifstream in(batch_wisdom_path(dir));
+    if (!in) return -1;
+    DeviceIdent dev;
+    const bool have_dev = current_device_ident(&dev) == KL_OK;
+    const auto &vs = variants(KL_KERNEL_ADVEC_DIFF, dtype);
+    int choice[3] = {-1, -1, -1};  // per level; -2 for a "per_grid" record
+    std::string line;
+    while (std::getline(in, line)) {
+        JVal v;
+        if (!parse_json(line, v) || v.kind != JVal::OBJ) continue;
+        const JVal *k = v.get("kernel"), *dt = v.get("dtype"), *sg = v.get("signature"), *var = v.get("variant"),
+                   *dn = v.get("device"), *ar = v.get("arch"), *cu = v.get("cu_count");
+        if (!k || k->kind != JVal::STR || k->str != "advec_diff_batch") continue;
+        if (!dt || dt->kind != JVal::STR || dt->str != (dtype == KL_F32 ? "f32" : "f64")) continue;
+        if (!sg || sg->kind != JVal::STR || sg->str != hex64(sig)) continue;
+        if (!var || var->kind != JVal::STR) continue;
+        int idx = var->str == "per_grid" ? -2 : -1;  // -2: the per-grid selection was fastest
+        for (size_t n = 0; n < vs.size(); ++n)
+            if (var->str == vs[n].name && vs[n].batch) idx = (int)n;
+        if (idx == -1) continue;
+        const bool same_gpu = have_dev && dn && dn->kind == JVal::STR && dn->str == dev.name &&
+                              (!cu || cu->kind != JVal::NUM || (int)cu->num == dev.cu_count);
+        const bool same_arch = have_dev && ar && ar->kind == JVal::STR && ar->str == dev.arch;
+        choice[same_gpu ? 0 : same_arch ? 1 : 2] = idx;
+    }
+    for (int l = 0; l < 3; ++l)
+        if (choice[l] != -1) return choice[l] == -2 ? -1 : choice[l];
+    return -1;
+}
+
 int build(Batch &b, void *const *fields)
 {
     int dev = 0;
@@ -174,10 +296,17 @@ int build(Batch &b, void *const *fields)
     }
     // groups
     std::map<std::tuple<int, int, int>, size_t> gidx;
-    for (int kernel = 0; kernel < 2; ++kernel) {
+    {
+        const int kernel = KL_KERNEL_ADVEC_DIFF;
         std::vector<int> sel(b.grids.size());
         for (size_t n = 0; n < b.grids.size(); ++n) {
-            sel[n] = batch_variant(&b.grids[n], kernel, fields + 6 * n);
+            const kl_grid_t *g = &b.grids[n];
+            const int fv = b.forced[g->dtype];
+            if (fv >= 0 && serves(variants(kernel, g->dtype)[fv], g, fields + 6 * n)) {
+                sel[n] = fv;
+                continue;
+            }
+            sel[n] = batch_variant(g, kernel, fields + 6 * n);
             if (sel[n] < 0) return fail(KL_ERR_INVALID, "grid %zu: no batched configuration fits", n);
         }
         merge_batch_groups(kernel, b.grids, fields, sel);
@@ -196,18 +325,34 @@ int build(Batch &b, void *const *fields)
             }
             Group &gr = b.groups[it->second];
             const Variant &v = variants(kernel, g->dtype)[vi];
-            const int nbx = (int)cdivu(g->itot, 64 * v.vx), nby = (int)cdivu(g->jtot, v.by),
-                      nbz = (int)cdivu(g->ktot, v.kb);
+            const int tw = 64 * v.vx;
+            const int nbx = (int)cdivu(g->itot, tw), nby = (int)cdivu(g->jtot, v.by), nbz = (int)cdivu(g->ktot, v.kb);
             for (int tz = 0; tz < nbz; ++tz)
                 for (int ty = 0; ty < nby; ++ty)
-                    for (int tx = 0; tx < nbx; ++tx) gr.tiles.push_back(make_int4((int)n, tx, ty, tz));
+                    for (int tx = 0; tx < nbx; ++tx) {
+                        gr.tiles.push_back(make_int4((int)n, tx, ty, tz));
+                        gr.cost.push_back((int64_t)std::min(tw, g->itot - tx * tw) *
+                                          std::min(v.by, g->jtot - ty * v.by) * std::min(v.kb, g->ktot - tz * v.kb));
+                    }
         }
     }
     for (Group &gr : b.groups) {
+        // The blocks draw tiles from a queue: the largest tiles go first, so
+        // the walk ends on small ones and the blocks finish about level.  The
+        // sort is stable, so the equal tiles of one grid stay in order and
+        // neighbours (which share halo rows) are drawn close together.
+        std::vector<size_t> ord(gr.tiles.size());
+        for (size_t n = 0; n < ord.size(); ++n) ord[n] = n;
+        std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) { return gr.cost[x] > gr.cost[y]; });
+        std::vector<int4> sorted(ord.size());
+        for (size_t n = 0; n < ord.size(); ++n) sorted[n] = gr.tiles[ord[n]];
+        gr.tiles.swap(sorted);
         if ((e = upload(&gr.d_tiles, gr.tiles.data(), gr.tiles.size() * sizeof(int4))) != hipSuccess)
             return hip_fail(e, "tiles");
+        if ((e = hipMalloc((void **)&gr.d_queue, 2 * sizeof(int))) != hipSuccess) return hip_fail(e, "queue");
+        if ((e = hipMemset(gr.d_queue, 0, 2 * sizeof(int))) != hipSuccess) return hip_fail(e, "queue");
         const Variant &v = variants(gr.kernel, gr.dtype)[gr.variant];
-        gr.nblocks = (int)std::min<int64_t>((int64_t)gr.tiles.size(), (int64_t)ncu * v.occupancy());
+        gr.nblocks = persistent_blocks((int64_t)gr.tiles.size(), ncu, v.occupancy());
         b.ntiles += (int64_t)gr.tiles.size();
     }
     // zeroing tiles: 32 rows each
@@ -237,14 +382,12 @@ int build(Batch &b, void *const *fields)
         if (e != hipSuccess) rc = hip_fail(e, "zero launch");
         ++b.nkernels;
     }
-    for (int kernel = 0; kernel < 2 && rc == KL_OK; ++kernel) {
-        for (Group &gr : b.groups) {
-            if (gr.kernel != kernel || rc != KL_OK) continue;
-            const Variant &v = variants(gr.kernel, gr.dtype)[gr.variant];
-            e = v.batch(b.d_desc[gr.dtype], gr.d_tiles, (int)gr.tiles.size(), gr.nblocks, cs);
-            if (e != hipSuccess) rc = hip_fail(e, v.name);
-            ++b.nkernels;
-        }
+    for (Group &gr : b.groups) {
+        if (rc != KL_OK) break;
+        const Variant &v = variants(gr.kernel, gr.dtype)[gr.variant];
+        e = v.batch(b.d_desc[gr.dtype], gr.d_tiles, (int)gr.tiles.size(), gr.nblocks, gr.d_queue, cs);
+        if (e != hipSuccess) rc = hip_fail(e, v.name);
+        ++b.nkernels;
     }
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(cs, &graph);
@@ -281,8 +424,15 @@ int kl_batch_create(const kl_grid_t *grids, void *const *fields, int32_t n, doub
     Batch *b = new (std::nothrow) Batch();
     if (!b) return fail(KL_ERR_NOMEM, "batch");
     b->grids.assign(grids, grids + n);
+    b->fields.assign(fields, fields + 6 * (size_t)n);
     b->visc = visc;
     b->zero = zero_tendencies != 0;
+    for (int dt = 0; dt < 2; ++dt) {
+        int64_t np;
+        int ng;
+        const uint64_t sig = batch_signature(b->grids, dt, &np, &ng);
+        if (ng > 0) b->forced[dt] = batch_wisdom_lookup(wisdom_dir(), dt, sig);
+    }
     const int rc = build(*b, fields);
     if (rc != KL_OK) {
         delete b;
@@ -309,6 +459,146 @@ int kl_batch_info(void *batch, int32_t *n_kernels, int64_t *n_tiles)
     if (n_kernels) *n_kernels = b->nkernels;
     if (n_tiles) *n_tiles = b->ntiles;
     return KL_OK;
+}
+
+int kl_batch_group(void *batch, int32_t group, int32_t *dtype, char *name, size_t len, int64_t *n_tiles)
+{
+    clear_error();
+    if (!batch) return fail(KL_ERR_INVALID, "batch is NULL");
+    Batch *b = (Batch *)batch;
+    if (group < 0 || group >= (int)b->groups.size()) return fail(KL_ERR_NOTFOUND, "group %d", group);
+    const Group &gr = b->groups[group];
+    if (dtype) *dtype = gr.dtype;
+    if (name && len) snprintf(name, len, "%s", variants(gr.kernel, gr.dtype)[gr.variant].name);
+    if (n_tiles) *n_tiles = (int64_t)gr.tiles.size();
+    return KL_OK;
+}
+
+int kl_batch_tune(void *batch, const char *wisdom_dir_, double budget_s, void *stream, double *timings_out,
+                  int32_t max_timings, int32_t *n_timings)
+{
+    clear_error();
+    if (!batch) return fail(KL_ERR_INVALID, "batch is NULL");
+    Batch *b = (Batch *)batch;
+    hipStream_t s = (hipStream_t)stream;
+    const std::string dir = wisdom_dir_ && *wisdom_dir_ ? std::string(wisdom_dir_) : wisdom_dir();
+    if (n_timings) *n_timings = 0;
+    DeviceIdent dev;
+    int rc = current_device_ident(&dev);
+    if (rc) return rc;
+    const size_t ng = b->grids.size();
+    uint64_t *dhash = nullptr;
+    hipError_t e = hipMalloc((void **)&dhash, 3 * ng * sizeof(uint64_t));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+    std::vector<uint64_t> hh(3 * ng);
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    for (auto &x : ev)
+        if ((e = hipEventCreate(&x)) != hipSuccess) rc = hip_fail(e, "hipEventCreate");
+    void *ws = workspace(reduce_scratch_bytes(), s);
+    if (!ws && rc == KL_OK) rc = fail(KL_ERR_NOMEM, "tune workspace");
+
+    // zero the tendencies of the grids of dtype dt, replay once, and return
+    // the sum of the outputs' bit hashes
+    auto run_and_hash = [&](int dt, uint64_t *sum) -> int {
+        for (size_t n = 0; n < ng; ++n) {
+            if (b->grids[n].dtype != dt) continue;
+            const HostArgs a = make_args(&b->grids[n]);
+            for (int q = 3; q < 6; ++q)
+                if ((e = launch_zero_interior(a, b->fields[6 * n + q], s)) != hipSuccess) return hip_fail(e, "zero");
+        }
+        if ((e = hipGraphLaunch(b->exec, s)) != hipSuccess) return hip_fail(e, "graph launch");
+        for (size_t n = 0; n < ng; ++n) {
+            if (b->grids[n].dtype != dt) continue;
+            const HostArgs a = make_args(&b->grids[n]);
+            for (int q = 0; q < 3; ++q)
+                if ((e = launch_hash(a, b->fields[6 * n + 3 + q], dhash + 3 * n + q, ws, s)) != hipSuccess)
+                    return hip_fail(e, "hash");
+        }
+        if ((e = hipMemcpyAsync(hh.data(), dhash, hh.size() * sizeof(uint64_t), hipMemcpyDeviceToHost, s)) !=
+                hipSuccess ||
+            (e = hipStreamSynchronize(s)) != hipSuccess)
+            return hip_fail(e, "hash copy");
+        uint64_t acc = 0;
+        for (size_t n = 0; n < ng; ++n)
+            if (b->grids[n].dtype == dt) acc += hh[3 * n] * 3 + hh[3 * n + 1] * 5 + hh[3 * n + 2] * 7;
+        *sum = acc;
+        return KL_OK;
+    };
+    auto time_replays = [&](double *ms) -> int {
+        for (int w = 0; w < 2; ++w)
+            if ((e = hipGraphLaunch(b->exec, s)) != hipSuccess) return hip_fail(e, "graph launch");
+        const int reps = 10;
+        if ((e = hipEventRecord(ev[0], s)) != hipSuccess) return hip_fail(e, "event");
+        for (int r = 0; r < reps; ++r)
+            if ((e = hipGraphLaunch(b->exec, s)) != hipSuccess) return hip_fail(e, "graph launch");
+        if ((e = hipEventRecord(ev[1], s)) != hipSuccess || (e = hipEventSynchronize(ev[1])) != hipSuccess)
+            return hip_fail(e, "event");
+        float t = 0;
+        if ((e = hipEventElapsedTime(&t, ev[0], ev[1])) != hipSuccess) return hip_fail(e, "event");
+        *ms = t / reps;
+        return KL_OK;
+    };
+    auto rebuild = [&]() -> int {
+        b->release();
+        return build(*b, b->fields.data());
+    };
+
+    const auto t_start = std::chrono::steady_clock::now();
+    int nt = 0;
+    for (int dt = 0; dt < 2 && rc == KL_OK; ++dt) {
+        int64_t npts;
+        int ngr;
+        const uint64_t sig = batch_signature(b->grids, dt, &npts, &ngr);
+        if (ngr == 0) continue;
+        const auto &vs = variants(KL_KERNEL_ADVEC_DIFF, dt);
+        // candidate -1 is the per-grid selection; then every persistent configuration
+        std::vector<int> cand = {-1};
+        for (size_t n = 0; n < vs.size(); ++n)
+            if (vs[n].batch) cand.push_back((int)n);
+        uint64_t ref = 0;
+        double best_ms = 1e300, sel_ms = -1;
+        int best = -1, evaluated = 0;
+        for (size_t c = 0; c < cand.size() && rc == KL_OK; ++c) {
+            if (c > 0 && std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count() > budget_s)
+                break;
+            b->forced[dt] = cand[c];
+            if ((rc = rebuild())) break;
+            uint64_t h = 0;
+            if ((rc = run_and_hash(dt, &h))) break;
+            double ms = -1;
+            if (c == 0)
+                ref = h;
+            if (h == ref) {
+                if ((rc = time_replays(&ms))) break;
+                if (c == 0) sel_ms = ms;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = cand[c];
+                }
+            }
+            ++evaluated;
+            if (timings_out && nt < max_timings) {
+                timings_out[2 * nt] = cand[c];
+                timings_out[2 * nt + 1] = ms;
+                ++nt;
+            }
+        }
+        if (rc) break;
+        b->forced[dt] = best;
+        std::ostringstream o;
+        o << "{\"kernel\":\"advec_diff_batch\",\"dtype\":\"" << (dt == KL_F32 ? "f32" : "f64")
+          << "\",\"signature\":\"" << hex64(sig) << "\",\"grids\":" << ngr << ",\"points\":" << npts
+          << ",\"variant\":\"" << (best >= 0 ? vs[best].name : "per_grid") << "\",\"time_ms\":" << best_ms
+          << ",\"per_grid_selection_ms\":" << sel_ms << ",\"evaluated\":" << evaluated << ","
+          << provenance_json(dev) << "}";
+        rc = wisdom_append_file(dir, "advec_diff_batch.wisdom", o.str());
+    }
+    if (rc == KL_OK) rc = rebuild();
+    for (auto x : ev)
+        if (x) (void)hipEventDestroy(x);
+    (void)hipFree(dhash);
+    if (n_timings) *n_timings = nt;
+    return rc;
 }
 
 int kl_batch_destroy(void *batch)

@@ -400,7 +400,7 @@ int kl_tune_capture(const char *path, const char *wisdom_dir, double budget_s, v
         fields[n] = p;
     }
     static const uint32_t bits[KL_NUM_KERNELS] = {KL_TUNE_ADVEC_U, KL_TUNE_DIFF_UVW, KL_TUNE_STEP,
-                                                  KL_TUNE_ADVEC_U_2I5, KL_TUNE_DIFF_SMAG};
+                                                  KL_TUNE_ADVEC_U_2I5, KL_TUNE_DIFF_SMAG, KL_TUNE_ADVEC_DIFF};
     rc = kl_tune(&g, fields, bits[kernel], wisdom_dir, budget_s, stream, timings_out, max_timings, n_timings);
     const hipError_t e = hipDeviceSynchronize();
     if (rc) return rc;

@@ -32,13 +32,23 @@ inline int kernel_nptr(int kernel)
     return (kernel == KL_KERNEL_ADVEC_U || kernel == KL_KERNEL_ADVEC_U_2I5) ? 4
            : (kernel == KL_KERNEL_DIFF_SMAG ? 7 : 6);
 }
-constexpr int KL_NUM_KERNELS = 5;
+constexpr int KL_NUM_KERNELS = 6;
 
 typedef hipError_t (*LaunchFn)(const HostArgs &, hipStream_t);
 // Persistent batched launch: descriptor table (StencilArgs<T>[]), tile table
-// (int4 {grid, tx, ty, tz}[]), tile count, number of blocks.
-typedef hipError_t (*BatchFn)(const void *, const void *, int, int, hipStream_t);
+// (int4 {grid, tx, ty, tz}[]), tile count, number of blocks, and a work queue
+// (two device ints, zero at launch and zero again at the end) or null for
+// the static round-robin assignment.
+typedef hipError_t (*BatchFn)(const void *, const void *, int, int, int *, hipStream_t);
 typedef int (*OccFn)();  // resident blocks per CU of the batched kernel
+
+// Blocks of a persistent tile walk: every resident slot (ncu * occ), at most
+// one per tile.
+inline int persistent_blocks(int64_t ntiles, int ncu, int occ)
+{
+    const int64_t nb = ntiles < (int64_t)ncu * occ ? ntiles : (int64_t)ncu * occ;
+    return (int)(nb > 0 ? nb : 1);
+}
 
 enum { FAMILY_PLAIN = 0, FAMILY_ZC = 1, FAMILY_ZL = 2 };
 
@@ -102,6 +112,7 @@ const char *kernel_name(int kernel);
 int wisdom_select(const std::string &dir, int kernel, int dtype, const DeviceIdent &dev,
                   int itot, int jtot, int ktot, std::string *variant, int *level);
 int wisdom_append(const std::string &dir, int kernel, const std::string &json_line);
+int wisdom_append_file(const std::string &dir, const std::string &file, const std::string &json_line);
 std::string provenance_json(const DeviceIdent &dev);
 
 // Plan cache (api.cpp).

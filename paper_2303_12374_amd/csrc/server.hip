@@ -315,8 +315,9 @@ int run_tick(Server &S, int slot)
         const int nt = (int)kv.second.size();
         auto oc = S.occ.find(&v);
         if (oc == S.occ.end()) oc = S.occ.emplace(&v, v.occupancy()).first;
-        const int nb = (int)std::min<int64_t>(nt, (int64_t)S.ncu * oc->second);
-        if ((e = v.batch(d + o_desc[dt], d + o_g[gi], nt, nb, S.stream)) != hipSuccess) return hip_fail(e, v.name);
+        const int nb = persistent_blocks(nt, S.ncu, oc->second);
+        if ((e = v.batch(d + o_desc[dt], d + o_g[gi], nt, nb, nullptr, S.stream)) != hipSuccess)
+            return hip_fail(e, v.name);
         ++S.launches;
         ++gi;
     }

@@ -72,7 +72,9 @@ __device__ __forceinline__ void put_with_images(T *f, const StencilArgs<T> &a, i
     }
 }
 
-template <typename T, int VX, int BY, int KB, int NT>
+enum { FUSE_STEP = 0, FUSE_PAIR = 1 };
+
+template <typename T, int VX, int BY, int KB, int NT, int MODE = FUSE_STEP>
 __device__ __forceinline__ void step_zl_tile(const StencilArgs<T> &a, int tx, int ty, int tz)
 {
     static_assert(BY >= 2, "two halo rows need two waves");
@@ -95,11 +97,11 @@ __device__ __forceinline__ void step_zl_tile(const StencilArgs<T> &a, int tx, in
     const int64_t xrow0 = a.off + t.i0w + (int64_t)max(t.xrow_g, 0) * js;
     const int64_t c_x = t.xrow_g >= 0 ? xrow0 + lane_c * VX : c_own;
     const int le = max(t.nlanes - 1, 1);
-    const int64_t c_e = t.lane == 0 ? row_c - 1 : (t.lane == le ? row_c + t.nlanes * VX : c_own);
-    const int64_t c_xv = x_is_top && t.lane == 0 ? xrow0 - 1 : c_own;  // v left of the top halo row
+    const int64_t c_e = t.lane == 0 ? row_c + t.xl : (t.lane == le ? row_c + t.xr : c_own);
+    const int64_t c_xv = x_is_top && t.lane == 0 ? xrow0 + t.xl : c_own;  // v left of the top halo row
     const bool ld_own = t.own && t.lane_on;
     const T *F[3] = {a.u, a.v, a.w};
-    T *O[3] = {a.ut, a.vt, a.wt};  // output fields
+    T *O[3] = {a.ut, a.vt, a.wt};  // output fields (FUSE_STEP) or tendencies (FUSE_PAIR)
     const T dxi = a.dxi, dyi = a.dyi, dxi2 = a.dxi * a.dxi, dyi2 = a.dyi * a.dyi, visc = a.visc, dt = a.dt;
     const int kw0 = a.kw0;
     const int j = t.j0 + t.r;
@@ -108,6 +110,7 @@ __device__ __forceinline__ void step_zl_tile(const StencilArgs<T> &a, int tx, in
     T E[4][3];            // x edge values (left in lane 0, right in lane le), same ring
     T X[2][3][VX];        // halo row (or a re-read of the own row), by level parity
     T XVL[2];             // v left edge of the top halo row (lane 0)
+    T Q[MODE == FUSE_PAIR ? 2 : 1][3][VX];  // tendencies of levels k, k+1 by parity (FUSE_PAIR)
 
     const int k0 = t.k0, k1 = t.k1;
 #pragma unroll
@@ -119,6 +122,7 @@ __device__ __forceinline__ void step_zl_tile(const StencilArgs<T> &a, int tx, in
         vload<T, VX>(X[0][f], F[f] + c_x + (int64_t)k0 * ks);
 #pragma unroll
         for (int q = 0; q < 3; ++q) E[q][f] = F[f][c_e + (int64_t)min(k0 + q, k1) * ks];
+        if constexpr (MODE == FUSE_PAIR) tload<NT, T, VX>(Q[0][f], O[f] + c_own + (int64_t)k0 * ks);
     }
     XVL[0] = a.v[c_xv + (int64_t)k0 * ks];
 
@@ -136,6 +140,10 @@ __device__ __forceinline__ void step_zl_tile(const StencilArgs<T> &a, int tx, in
 #pragma unroll
             for (int f = 0; f < 3; ++f) vload<T, VX>(X[q][f], F[f] + c_x + (int64_t)(k + 1) * ks);
             XVL[q] = a.v[c_xv + (int64_t)(k + 1) * ks];
+            if constexpr (MODE == FUSE_PAIR) {
+#pragma unroll
+                for (int f = 0; f < 3; ++f) tload<NT, T, VX>(Q[q][f], O[f] + c_own + (int64_t)(k + 1) * ks);
+            }
             // level-k rows into LDS
 #pragma unroll
             for (int f = 0; f < 3; ++f) {
@@ -184,19 +192,34 @@ __device__ __forceinline__ void step_zl_tile(const StencilArgs<T> &a, int tx, in
                                                  dyi2, dzik, dzhik1, dzhik, visc);
                     const T dv = diff_c_point<T>(c[1][n], ve, vw, nn[1][n], ss[1][n], tp[1][n], b[1][n], dxi2,
                                                  dyi2, dzik, dzhik1, dzhik, visc);
-                    const T tu = (T(0) + adv) + du;
-                    const T tv = T(0) + dv;
-                    nu[n] = c[0][n] + dt * tu;
-                    nv[n] = c[1][n] + dt * tv;
+                    if constexpr (MODE == FUSE_PAIR) {
+                        nu[n] = (Q[p][0][n] + adv) + du;
+                        nv[n] = Q[p][1][n] + dv;
+                    } else {
+                        const T tu = (T(0) + adv) + du;
+                        const T tv = T(0) + dv;
+                        nu[n] = c[0][n] + dt * tu;
+                        nv[n] = c[1][n] + dt * tv;
+                    }
                     if (k >= kw0) {
                         const T dw = diff_w_point<T>(c[2][n], we, ww, nn[2][n], ss[2][n], tp[2][n], b[2][n],
                                                      dxi2, dyi2, dzik, dzikm1, dzhik, visc);
-                        nw[n] = c[2][n] + dt * (T(0) + dw);
+                        if constexpr (MODE == FUSE_PAIR)
+                            nw[n] = Q[p][2][n] + dw;
+                        else
+                            nw[n] = c[2][n] + dt * (T(0) + dw);
                     }
                 }
-                put_with_images<T, VX, NT>(O[0], a, 0, t.i0, j, k, nu);
-                put_with_images<T, VX, NT>(O[1], a, 1, t.i0, j, k, nv);
-                if (k >= kw0) put_with_images<T, VX, NT>(O[2], a, 2, t.i0, j, k, nw);
+                if constexpr (MODE == FUSE_PAIR) {
+                    const int64_t o = c_own + (int64_t)k * ks;
+                    tstore<NT, T, VX>(O[0] + o, nu);
+                    tstore<NT, T, VX>(O[1] + o, nv);
+                    if (k >= kw0) tstore<NT, T, VX>(O[2] + o, nw);
+                } else {
+                    put_with_images<T, VX, NT>(O[0], a, 0, t.i0, j, k, nu);
+                    put_with_images<T, VX, NT>(O[1], a, 1, t.i0, j, k, nv);
+                    if (k >= kw0) put_with_images<T, VX, NT>(O[2], a, 2, t.i0, j, k, nw);
+                }
             }
             // level k-1 is no longer needed: its slot takes level k+3 (clamped
             // to k1 near the end of the tile, where it is not used)
@@ -210,23 +233,57 @@ __device__ __forceinline__ void step_zl_tile(const StencilArgs<T> &a, int tx, in
     }
 }
 
-template <typename T, int VX, int BY, int KB, int XCD, int NT = 0, int WPE = 1>
+template <typename T, int VX, int BY, int KB, int XCD, int NT = 0, int WPE = 1, int MODE = FUSE_STEP>
 __global__ __launch_bounds__(64 * BY, WPE) void step_zl(StencilArgs<T> a)
 {
     int tx, ty, tz;
     tile_of<64, BY, XCD>(a.nbx, a.nby, a.nbz, tx, ty, tz);
-    step_zl_tile<T, VX, BY, KB, NT>(a, tx, ty, tz);
+    step_zl_tile<T, VX, BY, KB, NT, MODE>(a, tx, ty, tz);
 }
 
-template <typename T, int VX, int BY, int KB, int NT = 0, int WPE = 1>
+template <typename T, int VX, int BY, int KB, int NT = 0, int WPE = 1, int MODE = FUSE_STEP>
 __global__ __launch_bounds__(64 * BY, WPE) void step_zl_batch(const StencilArgs<T> *__restrict__ grids,
-                                                             const int4 *__restrict__ tiles, int ntiles)
+                                                             const int4 *__restrict__ tiles, int ntiles,
+                                                             int *queue)
 {
-    for (int n = blockIdx.x; n < ntiles; n += gridDim.x) {
+    for (int n = next_tile(queue, -1); n < ntiles; n = next_tile(queue, n)) {
         const int4 tl = tiles[n];
         const StencilArgs<T> a = global_args(grids[tl.x]);
-        step_zl_tile<T, VX, BY, KB, NT>(a, tl.y, tl.z, tl.w);
+        step_zl_tile<T, VX, BY, KB, NT, MODE>(a, tl.y, tl.z, tl.w);
     }
+    walk_done(queue);
+}
+
+// Default configuration of the fused advec_u + diff_uvw pass: one thread per
+// point, 256 threads along x (the two default kernels' arithmetic, in their
+// order, at one point).
+template <typename T>
+__global__ __launch_bounds__(256) void advec_diff_plain(StencilArgs<T> a)
+{
+    unsigned b = blockIdx.x;
+    const int bx = b % a.nbx;
+    b /= a.nbx;
+    const int j = 1 + (int)(b % a.jtot);
+    const int k = 1 + (int)(b / a.jtot);
+    const int i = 1 + bx * 256 + (int)threadIdx.x;
+    if (i > a.itot) return;
+    const int64_t c = a.off + i + j * a.js + (int64_t)k * a.ks;
+    const int64_t js = a.js, ks = a.ks;
+    const T dxi2 = a.dxi * a.dxi, dyi2 = a.dyi * a.dyi;
+    const T dzik = a.dzi[k], dzhik = a.dzhi[k], dzhik1 = a.dzhi[k + 1];
+    const T *u = a.u, *v = a.v, *w = a.w;
+    const T adv = advec_u_point<T>(u[c], u[c + 1], u[c - 1], u[c + js], u[c - js], u[c + ks], u[c - ks],
+                                   v[c - 1], v[c], v[c - 1 + js], v[c + js],
+                                   w[c - 1], w[c], w[c - 1 + ks], w[c + ks],
+                                   a.dxi, a.dyi, dzik);
+    const T du = diff_c_point<T>(u[c], u[c + 1], u[c - 1], u[c + js], u[c - js], u[c + ks], u[c - ks], dxi2,
+                                 dyi2, dzik, dzhik1, dzhik, a.visc);
+    a.ut[c] = (a.ut[c] + adv) + du;
+    a.vt[c] = a.vt[c] + diff_c_point<T>(v[c], v[c + 1], v[c - 1], v[c + js], v[c - js], v[c + ks],
+                                        v[c - ks], dxi2, dyi2, dzik, dzhik1, dzhik, a.visc);
+    if (k >= a.kw0)
+        a.wt[c] = a.wt[c] + diff_w_point<T>(w[c], w[c + 1], w[c - 1], w[c + js], w[c - js], w[c + ks],
+                                            w[c - ks], dxi2, dyi2, dzik, a.dzi[k - 1], dzhik, a.visc);
 }
 
 }  // namespace kl

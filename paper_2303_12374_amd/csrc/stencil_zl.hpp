@@ -10,7 +10,10 @@
 //     LDS plane, the two halo rows (j0-1 and the row after the last valid
 //     one) are written by wave 0 and by the "top" wave; one barrier a level;
 //   * x neighbours: lane shuffles, with the two values beyond the wave's
-//     segment loaded by the edge lanes.
+//     segment loaded by the edge lanes.  x is periodic in every boundary
+//     mode, so at the ends of a row those two values are read from the
+//     row's interior (the periodic images that the ghost cells hold after
+//     the ghost fill): no line of x ghost cells is fetched.
 // The per-point arithmetic is the shared one of stencil.hpp, so results are
 // bitwise equal to every other configuration.
 #pragma once
@@ -35,6 +38,7 @@ __device__ __forceinline__ T shfl_down1(T x)
 template <int VX, int BY, int KB>
 struct ZlTile {
     int lane, r, i0w, i0, j0, nv, k0, k1, nlanes, top;
+    int xl, xr;  // offsets from i0w of the left and right x neighbours of the segment (periodic)
     bool lane_on, own;
     int xrow_g, xrow_l;  // extra (halo) row of this wave: global row and LDS row, -1 if none
 
@@ -52,6 +56,8 @@ struct ZlTile {
         nlanes = min(64, (itot - i0w + 1) / VX);
         lane_on = lane < nlanes;
         own = r < nv;
+        xl = i0w == 1 ? itot - 1 : -1;
+        xr = i0w + nlanes * VX > itot ? 1 - i0w : nlanes * VX;
         top = nv < BY ? nv : BY - 1;
         xrow_g = xrow_l = -1;
         if (r == 0) {
@@ -104,7 +110,7 @@ __device__ __forceinline__ void diff_uvw_zl_tile(const StencilArgs<T> &a, int tx
     const int64_t c_own = row_c + lane_c * VX;                         // own point (clamped)
     const int64_t c_x = t.xrow_g >= 0 ? a.off + t.i0w + lane_c * VX + (int64_t)t.xrow_g * js : c_own;
     const int le = max(t.nlanes - 1, 1);                               // lane loading the right edge
-    const int64_t c_e = t.lane == 0 ? row_c - 1 : (t.lane == le ? row_c + t.nlanes * VX : c_own);
+    const int64_t c_e = t.lane == 0 ? row_c + t.xl : (t.lane == le ? row_c + t.xr : c_own);
     const bool ld_own = t.own && t.lane_on;
     const T *F[3] = {a.u, a.v, a.w};
     T *Tt[3] = {a.ut, a.vt, a.wt};
@@ -220,9 +226,9 @@ __device__ __forceinline__ void advec_u_zl_tile(const StencilArgs<T> &a, int tx,
     const int64_t xrow0 = a.off + t.i0w + (int64_t)max(t.xrow_g, 0) * js;   // (i0w, halo row, 0)
     const int64_t c_x = t.xrow_g >= 0 ? xrow0 + lane_c * VX : c_own;
     const int le = max(t.nlanes - 1, 1);                               // lane loading the right u edge
-    const int64_t c_eu = t.lane == 0 ? row_c - 1 : (t.lane == le ? row_c + t.nlanes * VX : c_own);
-    const int64_t c_ev = t.lane == 0 ? row_c - 1 : (t.lane == 1 && x_is_top ? xrow0 - 1 : c_own);
-    const int64_t c_ew = t.lane == 0 ? row_c - 1 : c_own;
+    const int64_t c_eu = t.lane == 0 ? row_c + t.xl : (t.lane == le ? row_c + t.xr : c_own);
+    const int64_t c_ev = t.lane == 0 ? row_c + t.xl : (t.lane == 1 && x_is_top ? xrow0 + t.xl : c_own);
+    const int64_t c_ew = t.lane == 0 ? row_c + t.xl : c_own;
     const bool ld_own = t.own && t.lane_on;
     const T dxi = a.dxi, dyi = a.dyi;
     const T *U = a.u, *V = a.v, *W = a.w;
@@ -348,29 +354,62 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_zl(StencilArgs<T> a)
     advec_u_zl_tile<T, VX, BY, KB, NT>(a, tx, ty, tz);
 }
 
-// Persistent batched kernels: block b runs tiles b, b + gridDim.x, ... of a
-// static tile list; tile = (grid, tx, ty, tz) into a table of per-grid
-// arguments.  The assignment is fixed, so results do not depend on timing.
+// Next tile of a block in a persistent walk over a tile list (prev = -1 for
+// the first).  Without a queue the assignment is static: block b takes tiles
+// b, b + gridDim.x, ...  With a queue (two device ints, both 0 at launch)
+// one lane draws the next ticket from queue[0], so blocks that finish their
+// tiles early take more and the walk ends with the blocks about level.
+// Every tile is computed once, by one block, with the same arithmetic, so
+// the results do not depend on which block takes which tile.
+__device__ __forceinline__ int next_tile(int *queue, int prev)
+{
+    if (!queue) return prev < 0 ? (int)blockIdx.x : prev + (int)gridDim.x;
+    __shared__ int ticket;
+    __syncthreads();  // every wave has read the previous ticket
+    if (threadIdx.x == 0 && threadIdx.y == 0) ticket = atomicAdd(queue, 1);
+    __syncthreads();
+    return ticket;
+}
+
+// End of a block's walk: the last block to finish returns the queue to 0 for
+// the next launch (each block counts itself in queue[1] after its last draw).
+__device__ __forceinline__ void walk_done(int *queue)
+{
+    if (!queue || threadIdx.x != 0 || threadIdx.y != 0) return;
+    __threadfence();
+    if (atomicAdd(queue + 1, 1) == (int)gridDim.x - 1) {
+        __threadfence();
+        atomicExch(queue, 0);
+        atomicExch(queue + 1, 0);
+    }
+}
+
+// Persistent batched kernels: each block walks tiles of a tile list
+// (next_tile); tile = (grid, tx, ty, tz) into a table of per-grid arguments.
 template <typename T, int VX, int BY, int KB, int NT = 0, int WPE = 1>
 __global__ __launch_bounds__(64 * BY, WPE) void diff_uvw_zl_batch(const StencilArgs<T> *__restrict__ grids,
-                                                                 const int4 *__restrict__ tiles, int ntiles)
+                                                                 const int4 *__restrict__ tiles, int ntiles,
+                                                                 int *queue)
 {
-    for (int n = blockIdx.x; n < ntiles; n += gridDim.x) {
+    for (int n = next_tile(queue, -1); n < ntiles; n = next_tile(queue, n)) {
         const int4 tl = tiles[n];
         const StencilArgs<T> a = global_args(grids[tl.x]);
         diff_uvw_zl_tile<T, VX, BY, KB, NT>(a, tl.y, tl.z, tl.w);
     }
+    walk_done(queue);
 }
 
 template <typename T, int VX, int BY, int KB, int NT = 0, int WPE = 1>
 __global__ __launch_bounds__(64 * BY, WPE) void advec_u_zl_batch(const StencilArgs<T> *__restrict__ grids,
-                                                                const int4 *__restrict__ tiles, int ntiles)
+                                                                const int4 *__restrict__ tiles, int ntiles,
+                                                                int *queue)
 {
-    for (int n = blockIdx.x; n < ntiles; n += gridDim.x) {
+    for (int n = next_tile(queue, -1); n < ntiles; n = next_tile(queue, n)) {
         const int4 tl = tiles[n];
         const StencilArgs<T> a = global_args(grids[tl.x]);
         advec_u_zl_tile<T, VX, BY, KB, NT>(a, tl.y, tl.z, tl.w);
     }
+    walk_done(queue);
 }
 
 // Batched zeroing of the tendencies: tile = (grid, first row, end row) over

@@ -75,7 +75,8 @@ int values_per_point(int kernel)
     switch (kernel) {
     case KL_KERNEL_ADVEC_U:
     case KL_KERNEL_ADVEC_U_2I5: return 5;
-    case KL_KERNEL_DIFF_UVW: return 9;
+    case KL_KERNEL_DIFF_UVW:
+    case KL_KERNEL_ADVEC_DIFF: return 9;
     case KL_KERNEL_DIFF_SMAG: return 10;
     default: return 6;
     }
@@ -181,7 +182,7 @@ int tune_one(const kl_grid_t *g, int kernel, void *const *f, const std::string &
 uint32_t tune_bit(int kernel)
 {
     static const uint32_t bits[KL_NUM_KERNELS] = {KL_TUNE_ADVEC_U, KL_TUNE_DIFF_UVW, KL_TUNE_STEP,
-                                                  KL_TUNE_ADVEC_U_2I5, KL_TUNE_DIFF_SMAG};
+                                                  KL_TUNE_ADVEC_U_2I5, KL_TUNE_DIFF_SMAG, KL_TUNE_ADVEC_DIFF};
     return bits[kernel];
 }
 
@@ -192,7 +193,8 @@ extern "C" int kl_tune(const kl_grid_t *g, void *const fields[6], uint32_t kerne
     int rc = check_grid(g);
     if (rc) return rc;
     if (!fields) return fail(KL_ERR_INVALID, "fields is NULL");
-    const uint32_t kernels = KL_TUNE_ADVEC_U | KL_TUNE_DIFF_UVW | KL_TUNE_STEP | KL_TUNE_ADVEC_U_2I5 | KL_TUNE_DIFF_SMAG;
+    const uint32_t kernels = KL_TUNE_ADVEC_U | KL_TUNE_DIFF_UVW | KL_TUNE_STEP | KL_TUNE_ADVEC_U_2I5 |
+                             KL_TUNE_DIFF_SMAG | KL_TUNE_ADVEC_DIFF;
     if ((kernel_mask & kernels) == 0 || (kernel_mask & ~(kernels | KL_TUNE_PAIR)))
         return fail(KL_ERR_INVALID, "kernel_mask %u", kernel_mask);
     const int nf = (kernel_mask & KL_TUNE_DIFF_SMAG) ? 7 : 6;

@@ -60,6 +60,8 @@ hipError_t launch_plain(const HostArgs &h, hipStream_t s)
         hipLaunchKernelGGL(diff_uvw_plain<T>, dim3((unsigned)nb), dim3(256), 0, s, a);
     else if (KERNEL == KL_KERNEL_ADVEC_U_2I5)
         hipLaunchKernelGGL(advec_u_2i5_plain<T>, dim3((unsigned)nb), dim3(256), 0, s, a);
+    else if (KERNEL == KL_KERNEL_ADVEC_DIFF)
+        hipLaunchKernelGGL(advec_diff_plain<T>, dim3((unsigned)nb), dim3(256), 0, s, a);
     else
         hipLaunchKernelGGL(diff_smag_plain<T>, dim3((unsigned)nb), dim3(256), 0, s, a);
     return hipGetLastError();
@@ -98,14 +100,14 @@ hipError_t launch_zl(const HostArgs &h, hipStream_t s)
 }
 
 template <typename T, int KERNEL, int VX, int BY, int KB, int NT = 0, int WPE = 1>
-hipError_t launch_zl_batch(const void *descs, const void *tiles, int ntiles, int nblocks, hipStream_t s)
+hipError_t launch_zl_batch(const void *descs, const void *tiles, int ntiles, int nblocks, int *queue, hipStream_t s)
 {
     if (KERNEL == KL_KERNEL_ADVEC_U)
         hipLaunchKernelGGL((advec_u_zl_batch<T, VX, BY, KB, NT, WPE>), dim3(nblocks), dim3(64, BY), 0, s,
-                           (const StencilArgs<T> *)descs, (const int4 *)tiles, ntiles);
+                           (const StencilArgs<T> *)descs, (const int4 *)tiles, ntiles, queue);
     else
         hipLaunchKernelGGL((diff_uvw_zl_batch<T, VX, BY, KB, NT, WPE>), dim3(nblocks), dim3(64, BY), 0, s,
-                           (const StencilArgs<T> *)descs, (const int4 *)tiles, ntiles);
+                           (const StencilArgs<T> *)descs, (const int4 *)tiles, ntiles, queue);
     return hipGetLastError();
 }
 
@@ -121,7 +123,7 @@ int zl_batch_occupancy()
     return e == hipSuccess && n > 0 ? n : 1;
 }
 
-template <typename T, int VX, int BY, int KB, int XCD, int NT = 0, int WPE = 1>
+template <typename T, int VX, int BY, int KB, int XCD, int NT = 0, int WPE = 1, int MODE = FUSE_STEP>
 hipError_t launch_step(const HostArgs &h, hipStream_t s)
 {
     StencilArgs<T> a = device_args<T>(h);
@@ -130,24 +132,25 @@ hipError_t launch_step(const HostArgs &h, hipStream_t s)
     a.nbz = (int)cdivu(h.ktot, KB);
     const uint64_t nb = (uint64_t)a.nbx * a.nby * a.nbz;
     if (!grid_fits(nb, 64 * BY)) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((step_zl<T, VX, BY, KB, XCD, NT, WPE>), dim3((unsigned)nb), dim3(64, BY), 0, s, a);
+    hipLaunchKernelGGL((step_zl<T, VX, BY, KB, XCD, NT, WPE, MODE>), dim3((unsigned)nb), dim3(64, BY), 0, s, a);
     return hipGetLastError();
 }
 
-template <typename T, int VX, int BY, int KB, int NT = 0, int WPE = 1>
-hipError_t launch_step_batch(const void *descs, const void *tiles, int ntiles, int nblocks, hipStream_t s)
+template <typename T, int VX, int BY, int KB, int NT = 0, int WPE = 1, int MODE = FUSE_STEP>
+hipError_t launch_step_batch(const void *descs, const void *tiles, int ntiles, int nblocks, int *queue,
+                             hipStream_t s)
 {
-    hipLaunchKernelGGL((step_zl_batch<T, VX, BY, KB, NT, WPE>), dim3(nblocks), dim3(64, BY), 0, s,
-                       (const StencilArgs<T> *)descs, (const int4 *)tiles, ntiles);
+    hipLaunchKernelGGL((step_zl_batch<T, VX, BY, KB, NT, WPE, MODE>), dim3(nblocks), dim3(64, BY), 0, s,
+                       (const StencilArgs<T> *)descs, (const int4 *)tiles, ntiles, queue);
     return hipGetLastError();
 }
 
-template <typename T, int VX, int BY, int KB, int NT = 0, int WPE = 1>
+template <typename T, int VX, int BY, int KB, int NT = 0, int WPE = 1, int MODE = FUSE_STEP>
 int step_batch_occupancy()
 {
     int n = 0;
     const hipError_t e =
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_zl_batch<T, VX, BY, KB, NT, WPE>, 64 * BY, 0);
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_zl_batch<T, VX, BY, KB, NT, WPE, MODE>, 64 * BY, 0);
     return e == hipSuccess && n > 0 ? n : 1;
 }
 
@@ -278,6 +281,20 @@ hipError_t launch_smag_zl(const HostArgs &h, hipStream_t s)
         KL_ST(T, DT, VX, 4, 128, 2, 1), KL_ST(T, DT, VX, 8, 64, 0, 1), KL_ST(T, DT, VX, 4, 32, 0, 0),    \
         KL_ST(T, DT, VX, 4, 8, 0, 0), KL_ST(T, DT, VX, 4, 16, 0, 0), KL_ST(T, DT, VX, 8, 8, 0, 0),       \
         KL_ST(T, DT, VX, 2, 16, 0, 0)
+
+// Fused advec_u + diff_uvw configurations (kernel KL_KERNEL_ADVEC_DIFF): the
+// fused-step tile accumulating into the tendencies.
+#define KL_AD(T, DT, VX, BY, KB, XCD, NT)                                                                 \
+    Variant{"ad_v" KL_STR(VX) "_b64x" KL_STR(BY) "_k" KL_STR(KB) "_x" KL_STR(XCD) "_nt" KL_STR(NT),      \
+            KL_KERNEL_ADVEC_DIFF, DT, FAMILY_ZL, VX, 64, BY, KB, XCD,                                    \
+            &launch_step<T, VX, BY, KB, XCD, NT, 1, FUSE_PAIR>, &launch_step_batch<T, VX, BY, KB, NT, 1, FUSE_PAIR>, \
+            &step_batch_occupancy<T, VX, BY, KB, NT, 1, FUSE_PAIR>}
+
+#define KL_AD_SET(T, DT, VX)                                                                             \
+    KL_AD(T, DT, VX, 4, 8, 0, 0), KL_AD(T, DT, VX, 8, 8, 0, 0), KL_AD(T, DT, VX, 4, 32, 0, 0),           \
+        KL_AD(T, DT, VX, 8, 32, 0, 0), KL_AD(T, DT, VX, 8, 32, 2, 1), KL_AD(T, DT, VX, 4, 64, 2, 1),     \
+        KL_AD(T, DT, VX, 8, 64, 2, 1), KL_AD(T, DT, VX, 4, 128, 2, 1), KL_AD(T, DT, VX, 8, 128, 2, 1),   \
+        KL_AD(T, DT, VX, 8, 256, 2, 1), KL_AD(T, DT, VX, 4, 256, 2, 1)
 
 // Top-down slab order (XCD = 3) for a kernel that follows another sweep.
 #define KL_REV_SET(T, DT, KERN, VX)                                                                     \

@@ -13,12 +13,17 @@ void add_variants_f64_small(int kernel, std::vector<Variant> &out);
 void add_variants_f64_rev(int kernel, std::vector<Variant> &out);
 void add_variants_f64_les(int kernel, std::vector<Variant> &out);
 void add_variants_f64_split(std::vector<Variant> &out);
+void add_variants_f64_ad(std::vector<Variant> &out);
 
 static std::vector<Variant> build_f64(int kernel)
 {
     std::vector<Variant> v;
     if (kernel == KL_KERNEL_STEP) {  // index 0: a fused step with scalar lanes (fits any itot)
         add_variants_f64_step(v);
+        return v;
+    }
+    if (kernel == KL_KERNEL_ADVEC_DIFF) {
+        add_variants_f64_ad(v);
         return v;
     }
     if (kernel == KL_KERNEL_ADVEC_U_2I5 || kernel == KL_KERNEL_DIFF_SMAG) {
@@ -51,11 +56,13 @@ const std::vector<Variant> &variants_f64(int kernel)
     static const std::vector<Variant> step = build_f64(KL_KERNEL_STEP);
     static const std::vector<Variant> advec5 = build_f64(KL_KERNEL_ADVEC_U_2I5);
     static const std::vector<Variant> smag = build_f64(KL_KERNEL_DIFF_SMAG);
+    static const std::vector<Variant> ad = build_f64(KL_KERNEL_ADVEC_DIFF);
     switch (kernel) {
     case KL_KERNEL_ADVEC_U: return advec;
     case KL_KERNEL_DIFF_UVW: return diff;
     case KL_KERNEL_STEP: return step;
     case KL_KERNEL_ADVEC_U_2I5: return advec5;
+    case KL_KERNEL_ADVEC_DIFF: return ad;
     default: return smag;
     }
 }

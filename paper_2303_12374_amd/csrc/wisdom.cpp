@@ -89,6 +89,7 @@ const char *kernel_name(int kernel)
     case KL_KERNEL_DIFF_UVW: return "diff_uvw";
     case KL_KERNEL_STEP: return "step";
     case KL_KERNEL_ADVEC_U_2I5: return "advec_u_2i5";
+    case KL_KERNEL_ADVEC_DIFF: return "advec_diff";
     default: return "diff_smag";
     }
 }
@@ -180,8 +181,13 @@ static int mkdirs(const std::string &dir)
 
 int wisdom_append(const std::string &dir, int kernel, const std::string &json_line)
 {
+    return wisdom_append_file(dir, std::string(kernel_name(kernel)) + ".wisdom", json_line);
+}
+
+int wisdom_append_file(const std::string &dir, const std::string &file, const std::string &json_line)
+{
     if (mkdirs(dir) != 0) return fail(KL_ERR_IO, "cannot create wisdom dir %s: %s", dir.c_str(), strerror(errno));
-    const std::string path = wisdom_path(dir, kernel);
+    const std::string path = dir + "/" + file;
     const int fd = open(path.c_str(), O_WRONLY | O_APPEND | O_CREAT, 0644);
     if (fd < 0) return fail(KL_ERR_IO, "cannot open %s: %s", path.c_str(), strerror(errno));
     flock(fd, LOCK_EX);

@@ -27,10 +27,11 @@ LIB_PATH = os.environ.get("KL_LIBRARY") or os.path.join(HERE, "libkl.so")
 
 F32, F64 = 0, 1
 BC_ZWALL_ZEROGRAD, BC_ZWALL_NOPEN, BC_ZPERIODIC = 0, 1, 2
-ADVEC_U, DIFF_UVW, STEP, ADVEC_U_2I5, DIFF_SMAG = 0, 1, 2, 3, 4
-TUNE_ADVEC_U, TUNE_DIFF_UVW, TUNE_STEP, TUNE_PAIR, TUNE_ADVEC_U_2I5, TUNE_DIFF_SMAG = 1, 2, 4, 8, 16, 32
+ADVEC_U, DIFF_UVW, STEP, ADVEC_U_2I5, DIFF_SMAG, ADVEC_DIFF = 0, 1, 2, 3, 4, 5
+TUNE_ADVEC_U, TUNE_DIFF_UVW, TUNE_STEP, TUNE_PAIR, TUNE_ADVEC_U_2I5, TUNE_DIFF_SMAG, TUNE_ADVEC_DIFF = \
+    1, 2, 4, 8, 16, 32, 64
 KERNEL_NAMES = {ADVEC_U: "advec_u", DIFF_UVW: "diff_uvw", STEP: "step", ADVEC_U_2I5: "advec_u_2i5",
-                DIFF_SMAG: "diff_smag"}
+                DIFF_SMAG: "diff_smag", ADVEC_DIFF: "advec_diff"}
 OK, ERR_INVALID, ERR_DEVICE, ERR_NOMEM, ERR_BUDGET, ERR_AGAIN, ERR_NOTFOUND, ERR_IO = 0, -1, -2, -3, -4, -5, -6, -7
 
 TORCH_DTYPE = {F32: torch.float32, F64: torch.float64}
@@ -83,6 +84,8 @@ _sig = {
     "kl_advec_u": (c_int, [_G, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "kl_diff_uvw": (c_int, [_G, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                             c_double, c_void_p]),
+    "kl_advec_diff": (c_int, [_G, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                              c_double, c_void_p]),
     "kl_euler": (c_int, [_G, c_double, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                          c_void_p]),
     "kl_step": (c_int, [_G, c_double, c_double, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
@@ -114,6 +117,8 @@ _sig = {
                                 POINTER(c_int32)]),
     "kl_batch_create": (c_int, [_G, POINTER(c_void_p), c_int32, c_double, c_int32, c_void_p,
                                 POINTER(c_void_p)]),
+    "kl_batch_tune": (c_int, [c_void_p, c_char_p, c_double, c_void_p, c_void_p, c_int32, POINTER(c_int32)]),
+    "kl_batch_group": (c_int, [c_void_p, c_int32, POINTER(c_int32), c_char_p, c_size_t, POINTER(c_int64)]),
     "kl_batch_run": (c_int, [c_void_p, c_void_p]),
     "kl_batch_info": (c_int, [c_void_p, POINTER(c_int32), POINTER(c_int64)]),
     "kl_batch_destroy": (c_int, [c_void_p]),
@@ -209,6 +214,11 @@ def kl_advec_u(g, ut, u, v, w, stream=None):
 def kl_diff_uvw(g, ut, vt, wt, u, v, w, visc, stream=None):
     _check(_lib.kl_diff_uvw(byref(_cg(g)), _ptr(ut), _ptr(vt), _ptr(wt), _ptr(u), _ptr(v), _ptr(w),
                             float(visc), _stream(stream)))
+
+
+def kl_advec_diff(g, ut, vt, wt, u, v, w, visc, stream=None):
+    _check(_lib.kl_advec_diff(byref(_cg(g)), _ptr(ut), _ptr(vt), _ptr(wt), _ptr(u), _ptr(v), _ptr(w),
+                              float(visc), _stream(stream)))
 
 
 def kl_euler(g, dt, u, v, w, ut, vt, wt, stream=None):
@@ -363,6 +373,32 @@ def kl_batch_info(batch):
     nk, nt = c_int32(), c_int64()
     _check(_lib.kl_batch_info(c_void_p(batch), byref(nk), byref(nt)))
     return nk.value, nt.value
+
+
+def kl_batch_tune(batch, wisdom_dir=None, budget_s=60.0, stream=None, max_timings=256):
+    """Tune a batch as a whole; returns [(configuration index or -1 for the
+    per-grid selection, ms or -1)]."""
+    out = (c_double * (2 * max_timings))()
+    n = c_int32()
+    _check(_lib.kl_batch_tune(c_void_p(batch), None if wisdom_dir is None else str(wisdom_dir).encode(),
+                              float(budget_s), _stream(stream), out, max_timings, byref(n)))
+    return [(int(out[2 * i]), out[2 * i + 1]) for i in range(n.value)]
+
+
+def kl_batch_groups(batch):
+    """[(dtype, configuration name, tiles)] of the batch's persistent kernels."""
+    res = []
+    g = 0
+    while True:
+        dt = c_int32()
+        nt = c_int64()
+        buf = ctypes.create_string_buffer(128)
+        rc = _lib.kl_batch_group(c_void_p(batch), g, byref(dt), buf, 128, byref(nt))
+        if rc == ERR_NOTFOUND:
+            return res
+        _check(rc)
+        res.append((dt.value, buf.value.decode(), nt.value))
+        g += 1
 
 
 def kl_batch_destroy(batch):

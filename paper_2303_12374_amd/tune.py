@@ -9,7 +9,7 @@ the field values.
 
     python -m paper_2303_12374_amd.tune --wisdom wisdom \\
         --shapes 512x512x512,256x256x256 --dtypes f32,f64 --budget 60 \\
-        --kernels advec_u,diff_uvw,step,advec_u_2i5,diff_smag
+        --kernels advec_u,diff_uvw,step,advec_u_2i5,diff_smag,advec_diff
 """
 from __future__ import annotations
 
@@ -26,7 +26,7 @@ def parse_shape(s: str):
     return tuple(parts)
 
 
-KERNELS = ("advec_u", "diff_uvw", "step", "advec_u_2i5", "diff_smag")
+KERNELS = ("advec_u", "diff_uvw", "step", "advec_u_2i5", "diff_smag", "advec_diff")
 
 
 def tune_shape(kl, shape, dtype, wisdom, budget, bc=0, log=None, kernels=KERNELS[:3]):
@@ -34,7 +34,8 @@ def tune_shape(kl, shape, dtype, wisdom, budget, bc=0, log=None, kernels=KERNELS
     out = {}
     kl.kl_set_wisdom_dir(wisdom)
     bits = {kl.ADVEC_U: kl.TUNE_ADVEC_U, kl.DIFF_UVW: kl.TUNE_DIFF_UVW | kl.TUNE_PAIR, kl.STEP: kl.TUNE_STEP,
-            kl.ADVEC_U_2I5: kl.TUNE_ADVEC_U_2I5, kl.DIFF_SMAG: kl.TUNE_DIFF_SMAG | kl.TUNE_PAIR}
+            kl.ADVEC_U_2I5: kl.TUNE_ADVEC_U_2I5, kl.DIFF_SMAG: kl.TUNE_DIFF_SMAG | kl.TUNE_PAIR,
+            kl.ADVEC_DIFF: kl.TUNE_ADVEC_DIFF}
     grids = {}
     for name in kernels:
         kern = KERNELS.index(name)

@@ -131,3 +131,45 @@ def test_batch_rejects_bad_arguments():
     f = [g.full() for _ in range(6)]
     with pytest.raises(m.KLError):
         m.kl_batch_create([g], [f[:5] + [None]], 1e-5, True)
+
+
+def test_batch_tune_records_and_reuses_the_winner(tmp_path):
+    """kl_batch_tune times the per-grid selection and every persistent
+    configuration on the batch itself, appends the winner per dtype under the
+    batch's signature, and a new batch of the same grids (in another order)
+    takes it; the results stay bitwise those of single-grid launches."""
+    import json
+    m = kl()
+    shapes = [(64, 32, 40), (32, 64, 24), (128, 16, 16), (96, 40, 20), (48, 24, 12), (40, 40, 8)]
+    dts = [0, 0, 0, 0, 1, 1]
+    bcs = [0, 2, 1, 0, 0, 2]
+    grids = make_grids(shapes, dts, bcs, seed=41)
+    wd = tmp_path / "wtune"
+    b = m.kl_batch_create([g for g, _, _ in grids], [f + t for _, f, t in grids], 1e-5, True)
+    try:
+        res = m.kl_batch_tune(b, wd, 30.0)
+    finally:
+        m.kl_batch_destroy(b)
+    assert res[0][0] == -1 and res[0][1] > 0, "the per-grid selection is timed first"
+    assert all(ms > 0 for _, ms in res), "a configuration gave different bits"
+    recs = [json.loads(x) for x in (wd / "advec_diff_batch.wisdom").read_text().splitlines()]
+    assert sorted(r["dtype"] for r in recs) == ["f32", "f64"]
+    assert {r["grids"] for r in recs} == {4, 2}
+    m.kl_set_wisdom_dir(str(wd))
+    order = [3, 0, 5, 2, 4, 1]
+    regrids = [grids[n] for n in order]
+    ref = plain(m, regrids, 1e-5)
+    b = m.kl_batch_create([g for g, _, _ in regrids], [f + t for _, f, t in regrids], 1e-5, True)
+    try:
+        groups = m.kl_batch_groups(b)
+        for r in recs:
+            if r["variant"] != "per_grid":
+                dt = 0 if r["dtype"] == "f32" else 1
+                assert any(d == dt and name == r["variant"] for d, name, _ in groups), (r, groups)
+        m.kl_batch_run(b)
+        torch.cuda.synchronize()
+        for (g, _, t), rr in zip(regrids, ref):
+            for x, y in zip(t, rr):
+                assert np.array_equal(x.cpu().numpy(), y)
+    finally:
+        m.kl_batch_destroy(b)

@@ -198,8 +198,7 @@ def test_committed_wisdom_names_registered_configurations():
     """Every record of the committed wisdom files names a configuration this
     build has (a record naming a missing one would be skipped at selection,
     so a stale record would silently fall back to another choice)."""
-    kernels = {"advec_u": kl.ADVEC_U, "diff_uvw": kl.DIFF_UVW, "step": kl.STEP,
-               "advec_u_2i5": kl.ADVEC_U_2I5, "diff_smag": kl.DIFF_SMAG}
+    kernels = {name: k for k, name in kl.KERNEL_NAMES.items()}
     dtypes = {"f32": kl.F32, "f64": kl.F64}
     wdir = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "wisdom")
     names = {}
