@@ -169,6 +169,9 @@ struct Server {
     DevBuf tab[2];        // per-tick tables (descriptors, tiles, time steps), one per tick in flight
     hipEvent_t ev[2] = {nullptr, nullptr};
     std::map<const Variant *, int> occ;  // resident blocks per CU of batched kernels
+    // work queue of the persistent step kernels (two device ints): the kernels
+    // run one after another on the server stream, and each returns it to zero
+    int *d_queue = nullptr;
 
     Server(void *arena_ptr, size_t ab, size_t bb) : base((char *)arena_ptr), arena_bytes(ab), budget(bb), arena(ab) {}
 };
@@ -244,6 +247,7 @@ int run_tick(Server &S, int slot)
     std::vector<kl_grid_t> grids(act.size());
     std::vector<void *> fields(6 * act.size());
     std::map<std::tuple<int, int>, std::vector<int4>> groups;  // (dtype, configuration) -> tiles
+    std::map<std::tuple<int, int>, std::vector<std::pair<int64_t, int4>>> sized;  // the same, with tile sizes
     for (size_t n = 0; n < act.size(); ++n) {
         Req &q = *act[n];
         void **f = fields.data() + 6 * n;
@@ -279,12 +283,25 @@ int run_tick(Server &S, int slot)
         const Req &q = *act[n];
         const int vi = sel[n];
         const Variant &v = variants(KL_KERNEL_STEP, q.g.dtype)[vi];
-        auto &tl = groups[std::make_tuple(q.g.dtype, vi)];
-        const int nbx = (int)cdivu(q.g.itot, 64 * v.vx), nby = (int)cdivu(q.g.jtot, v.by),
-                  nbz = (int)cdivu(q.g.ktot, v.kb);
+        auto &tl = sized[std::make_tuple(q.g.dtype, vi)];
+        const int tw = 64 * v.vx;
+        const int nbx = (int)cdivu(q.g.itot, tw), nby = (int)cdivu(q.g.jtot, v.by), nbz = (int)cdivu(q.g.ktot, v.kb);
         for (int tz = 0; tz < nbz; ++tz)
             for (int ty = 0; ty < nby; ++ty)
-                for (int tx = 0; tx < nbx; ++tx) tl.push_back(make_int4(didx[n], tx, ty, tz));
+                for (int tx = 0; tx < nbx; ++tx)
+                    tl.emplace_back((int64_t)std::min(tw, q.g.itot - tx * tw) * std::min(v.by, q.g.jtot - ty * v.by) *
+                                        std::min(v.kb, q.g.ktot - tz * v.kb),
+                                    make_int4(didx[n], tx, ty, tz));
+    }
+    // the blocks draw tiles from a queue: largest first (stable, so the tiles
+    // of one request stay in order), as in the batched form
+    for (auto &kv : sized) {
+        std::stable_sort(kv.second.begin(), kv.second.end(),
+                         [](const std::pair<int64_t, int4> &x, const std::pair<int64_t, int4> &y) {
+                             return x.first > y.first;
+                         });
+        auto &tl = groups[kv.first];
+        for (const auto &t : kv.second) tl.push_back(t.second);
     }
     // pack tables: [desc f32][desc f64][group tiles...]
     size_t off = 0;
@@ -316,7 +333,7 @@ int run_tick(Server &S, int slot)
         auto oc = S.occ.find(&v);
         if (oc == S.occ.end()) oc = S.occ.emplace(&v, v.occupancy()).first;
         const int nb = persistent_blocks(nt, S.ncu, oc->second);
-        if ((e = v.batch(d + o_desc[dt], d + o_g[gi], nt, nb, nullptr, S.stream)) != hipSuccess)
+        if ((e = v.batch(d + o_desc[dt], d + o_g[gi], nt, nb, S.d_queue, S.stream)) != hipSuccess)
             return hip_fail(e, v.name);
         ++S.launches;
         ++gi;
@@ -484,7 +501,10 @@ int kl_server_create(void *arena, size_t arena_bytes, size_t budget_bytes, void 
     if (e == hipSuccess) S->ncu = prop.multiProcessorCount;
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking);
     for (int n = 0; n < 2 && e == hipSuccess; ++n) e = hipEventCreateWithFlags(&S->ev[n], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipMalloc((void **)&S->d_queue, 2 * sizeof(int));
+    if (e == hipSuccess) e = hipMemset(S->d_queue, 0, 2 * sizeof(int));
     if (e != hipSuccess) {
+        if (S->d_queue) (void)hipFree(S->d_queue);
         delete S;
         return hip_fail(e, "server create");
     }
@@ -603,6 +623,7 @@ int kl_server_destroy(void *srv)
     for (int n = 0; n < 2; ++n)
         if (S->ev[n]) (void)hipEventDestroy(S->ev[n]);
     if (S->stream) (void)hipStreamDestroy(S->stream);
+    if (S->d_queue) (void)hipFree(S->d_queue);
     delete S;
     return KL_OK;
 }

@@ -17,7 +17,10 @@
 //     the upper face's flux of the level below, carried over; the advecting
 //     w of the left neighbour comes from the neighbouring lane by a shuffle.
 // Every global load is issued one level ahead, except ut, which is loaded at
-// the start of its own level and used at its end.  The per-face and per-point
+// the start of its own level and used at its end.  The x halo columns beyond
+// the ends of a row are read from their periodic images in the row's
+// interior (x is periodic in every mode), so no line of x ghost cells is
+// fetched.  The per-face and per-point
 // arithmetic is the shared one of stencil_les.hpp with the same operands, so
 // results equal the default configuration's bitwise.
 #pragma once
@@ -106,8 +109,10 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zl(StencilArgs<T> a)
     const int lane_c = min(lane, nlanes - 1);
     const int64_t rowo = a.off + i0w + (int64_t)min(j0 + r, a.jtot) * js;   // (i0w, own row, 0)
     const int64_t c_own = rowo + lane_c * VX;
-    const int ecol = lane < 3 ? lane - 3 : (lane < 6 ? nlanes * VX + lane - 3 : lane_c * VX);
+    const int ecol = lane < 3 ? wrap_x(i0w - 3 + lane, a.itot) - i0w
+                              : (lane < 6 ? wrap_x(i0w + nlanes * VX + lane - 3, a.itot) - i0w : lane_c * VX);
     const int64_t e_own = rowo + ecol;
+    const int xl1 = wrap_x(i0w - 1, a.itot) - i0w;                        // column left of the tile
     int hrho[NH];   // LDS rows of this wave's u halo rows, -1 if none
     int64_t hc[NH], he[NH];
 #pragma unroll
@@ -121,8 +126,8 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zl(StencilArgs<T> a)
     const bool vhalo = r == BY - 1;                                       // loads v row j0 + nv
     const int64_t vrow = a.off + i0w + (int64_t)(j0 + nv) * js;           // (i0w, j0 + nv, 0)
     const int64_t c_vh = vhalo ? vrow + lane_c * VX : c_own;
-    const int64_t e_v = lane == 0 ? rowo - 1 : (lane == 1 && vhalo ? vrow - 1 : c_own);
-    const int64_t e_w = lane == 0 ? rowo - 1 : c_own;
+    const int64_t e_v = lane == 0 ? rowo + xl1 : (lane == 1 && vhalo ? vrow + xl1 : c_own);
+    const int64_t e_w = lane == 0 ? rowo + xl1 : c_own;
     const int lx_u = lane < 3 ? lane : nlanes * VX + lane;                // LDS column of a lane's u halo value
 
     // registers: current (level k) and next (level k+1) copies of what the
@@ -333,6 +338,14 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zlp(StencilArgs<T> a
     const int64_t c_own = row0 + (int64_t)(j0 + r) * js;
     const int64_t e_own = a.off + i0w + (int64_t)(j0 + r) * js;           // (i0w, j0 + r, 0)
     const int iend = i0w + nlanes * VX - 1;                               // last point of the tile
+    // offsets from i0w of the periodic images of the x halo columns
+    int xlo[3], xhi[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        xlo[e] = wrap_x(i0w - 3 + e, a.itot) - i0w;
+        xhi[e] = wrap_x(iend + 1 + e, a.itot) - i0w;
+    }
+    const int xl1 = xlo[2];
     int hrho[NH];   // LDS rows of this wave's u halo rows, -1 if none
     int64_t hc[NH], he[NH];
 #pragma unroll
@@ -365,33 +378,33 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zlp(StencilArgs<T> a
             if (on && lane_on) vload<T, VX>(HU[q][m], u + hc[m] + (int64_t)k * ks);
             if (on && edge_l) {
 #pragma unroll
-                for (int e = 0; e < 3; ++e) HUL[q][m][e] = u[he[m] + (int64_t)k * ks - 3 + e];
+                for (int e = 0; e < 3; ++e) HUL[q][m][e] = u[he[m] + (int64_t)k * ks + xlo[e]];
             }
             if (on && edge_r) {
 #pragma unroll
-                for (int e = 0; e < 3; ++e) HUR[q][m][e] = u[he[m] + (iend - i0w) + (int64_t)k * ks + 1 + e];
+                for (int e = 0; e < 3; ++e) HUR[q][m][e] = u[he[m] + (int64_t)k * ks + xhi[e]];
             }
         }
         if (own) {
             if (edge_l) {
 #pragma unroll
-                for (int e = 0; e < 3; ++e) OUL[q][e] = u[e_own + (int64_t)k * ks - 3 + e];
-                VOL[q] = v[e_own + (int64_t)k * ks - 1];
+                for (int e = 0; e < 3; ++e) OUL[q][e] = u[e_own + (int64_t)k * ks + xlo[e]];
+                VOL[q] = v[e_own + (int64_t)k * ks + xl1];
             }
             if (edge_r) {
 #pragma unroll
-                for (int e = 0; e < 3; ++e) OUR[q][e] = u[e_own + (iend - i0w) + (int64_t)k * ks + 1 + e];
+                for (int e = 0; e < 3; ++e) OUR[q][e] = u[e_own + (int64_t)k * ks + xhi[e]];
             }
             if (lane_on) {
                 vload<T, VX>(VO[q], v + c_own + (int64_t)k * ks);
                 vload<T, VX>(WR[q], w + c_own + (int64_t)(k + 1) * ks);
                 tload<NT, T, VX>(UT[q], ut + c_own + (int64_t)k * ks);
             }
-            if (edge_l) WL[q] = w[e_own + (int64_t)(k + 1) * ks - 1];
+            if (edge_l) WL[q] = w[e_own + (int64_t)(k + 1) * ks + xl1];
         }
         if (vhalo) {
             if (lane_on) vload<T, VX>(VH[q], v + c_vh + (int64_t)k * ks);
-            if (edge_l) VHL[q] = v[e_vh + (int64_t)k * ks - 1];
+            if (edge_l) VHL[q] = v[e_vh + (int64_t)k * ks + xl1];
         }
     };
 
@@ -405,7 +418,7 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zlp(StencilArgs<T> a
         T ub3[VX], w0[VX];
         col_load<T, VX>(ub3, u + c_own, ks, k0 - 3, kt, own && lane_on);
         col_load<T, VX>(w0, w + c_own, ks, k0, kt, own && lane_on);
-        T wl0 = (own && edge_l) ? w[e_own + (int64_t)k0 * ks - 1] : T(0);
+        T wl0 = (own && edge_l) ? w[e_own + (int64_t)k0 * ks + xl1] : T(0);
         const T sh = shfl_up1(w0[VX - 1]);
         if (!edge_l) wl0 = sh;
 #pragma unroll
@@ -591,12 +604,15 @@ __global__ __launch_bounds__(64 * BY, WPE) void diff_smag_zl(StencilArgs<T> a)
     // exactly and does not drain the prefetch of level k+2 before it is due.
     const int lane_c = min(lane, nlanes - 1);
     const int le = max(nlanes - 1, 1);      // lane loading the right halo cell
-    // Addresses: a wave-uniform row start (column i0w-1) plus a per-lane byte
-    // offset, own point (1 + lane_c*VX) or halo column (0 in lane 0,
-    // 1 + nlanes*VX in lane le); the level offset goes into the uniform part.
-    const int64_t row_c = a.off + i0w - 1 + (int64_t)min(j0 + r, a.jtot) * js;
-    const uint32_t o_pt = (uint32_t)(1 + lane_c * VX) * sizeof(T);
-    const uint32_t o_e = lane == 0 ? 0u : (lane == le ? (uint32_t)(1 + nlanes * VX) * sizeof(T) : o_pt);
+    // Addresses: a wave-uniform row start (column 0) plus a per-lane byte
+    // offset, own point (i0w + lane_c*VX) or halo column (in lane 0 the
+    // periodic image of column i0w-1, in lane le that of i0w + nlanes*VX:
+    // x is periodic, so the halo columns come from the row's interior and no
+    // x ghost line is fetched); the level offset goes into the uniform part.
+    const int64_t row_c = a.off + (int64_t)min(j0 + r, a.jtot) * js;
+    const uint32_t o_pt = (uint32_t)(i0w + lane_c * VX) * sizeof(T);
+    const uint32_t o_e = lane == 0 ? (uint32_t)wrap_x(i0w - 1, a.itot) * sizeof(T)
+                                   : (lane == le ? (uint32_t)wrap_x(i0w + nlanes * VX, a.itot) * sizeof(T) : o_pt);
 
     // rows this wave stages: its own (LDS row r+1) and halo rows h = r, r+BY,
     // ... of the 8 (field h/2; LDS row 0 for even h, nv+1 for odd h)
@@ -607,7 +623,7 @@ __global__ __launch_bounds__(64 * BY, WPE) void diff_smag_zl(StencilArgs<T> a)
         const int h = r + m * BY;
         hf[m] = h < 8 ? h >> 1 : -1;
         hrow[m] = (h & 1) ? nv + 1 : 0;
-        hr0[m] = hf[m] < 0 ? row_c : a.off + i0w - 1 + (int64_t)(j0 - 1 + hrow[m]) * js;
+        hr0[m] = hf[m] < 0 ? row_c : a.off + (int64_t)(j0 - 1 + hrow[m]) * js;
     }
 
     T O[4][VX], OE[4];                      // own row of the 4 inputs at one level, halo columns

@@ -34,6 +34,16 @@ __device__ __forceinline__ T shfl_down1(T x)
     return __shfl_down(x, 1u, 64);
 }
 
+// Interior x index of the periodic image of column c (any integer): x is
+// periodic in every boundary mode, and after the ghost fill a ghost column
+// holds the value of this interior column.
+__device__ __forceinline__ int wrap_x(int c, int itot)
+{
+    int q = (c - 1) % itot;
+    if (q < 0) q += itot;
+    return q + 1;
+}
+
 // Geometry of one zl tile as seen by one thread.
 template <int VX, int BY, int KB>
 struct ZlTile {

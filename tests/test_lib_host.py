@@ -209,10 +209,12 @@ def test_committed_wisdom_names_registered_configurations():
                 if not line.strip():
                     continue
                 rec = json.loads(line)
-                key = (kernels[rec["kernel"]], dtypes[rec["dtype"]])
+                batch = rec["kernel"] == "advec_diff_batch"  # batch-level records (kl_batch_tune)
+                key = (kl.ADVEC_DIFF if batch else kernels[rec["kernel"]], dtypes[rec["dtype"]])
                 if key not in names:
                     names[key] = {kl.kl_variant_name(*key, i) for i in range(kl.kl_num_variants(*key))}
-                assert rec["variant"] in names[key], f"{fn}: {rec['variant']} ({rec['dtype']}) is not registered"
+                ok = rec["variant"] in names[key] or (batch and rec["variant"] == "per_grid")
+                assert ok, f"{fn}: {rec['variant']} ({rec['dtype']}) is not registered"
                 assert rec["kernel"] + ".wisdom" == fn
                 seen += 1
     assert seen > 0
