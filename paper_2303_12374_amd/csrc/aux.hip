@@ -133,7 +133,7 @@ __device__ __forceinline__ void euler_point(const Dims &d, T dt, int kw0, T *u, 
     for (int f = 0; f < 3; ++f) {
         if (f == 2 && k < kw0) continue;
         T *p = f3[f];
-        const T val = p[c] + dt * t3[f][c];
+        const T val = euler_value<T>(p[c], dt, t3[f][c]);
         // z images with their factors
         int zk[4], zs[4], nz = 1;
         zk[0] = k;

@@ -63,37 +63,43 @@ __device__ __forceinline__ StencilArgs<T> global_args(const StencilArgs<T> &in)
 // per-point arithmetic
 // ---------------------------------------------------------------------------
 
+// Fused multiply-add and absolute value of the field type.  The per-point
+// functions use explicit fused operations where they save instructions (the
+// tiles are partly bound by their arithmetic); every configuration calls the
+// same functions with the same operands, and the rest of the code is built
+// with -ffp-contract=off, so all configurations still agree bitwise.
+__device__ __forceinline__ float tfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double tfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float tabs(float a) { return __builtin_fabsf(a); }
+__device__ __forceinline__ double tabs(double a) { return __builtin_fabs(a); }
+
 // advec_u tendency at one u point.  Arguments are named by their offset from
 // the point: u at (i,j,k) and its six neighbours, v at (i-1..i, j..j+1, k),
-// w at (i-1..i, j, k..k+1).
+// w at (i-1..i, j, k..k+1).  Every face value is a midpoint (a+b)/2; each
+// flux is a product of two of them, so the two factors 1/2 are applied once,
+// exactly, as 1/4 of the grid factor (a power-of-two scaling rounds
+// nothing).  The x flux's sums and squares are functions of the face only,
+// so a lane's neighbouring points share them.
 template <typename T>
 __device__ __forceinline__ T advec_u_point(T uc, T ue, T uw, T un_, T us_, T ut_, T ub_,
                                            T v_w, T v_c, T v_nw, T v_n,
                                            T w_w, T w_c, T w_tw, T w_t,
                                            T dxi, T dyi, T dzik)
 {
-    const T h = T(0.5);
-    const T fx_hi = h * (uc + ue);
-    const T fx_lo = h * (uw + uc);
-    const T adv_x = (fx_hi * fx_hi - fx_lo * fx_lo) * dxi;
-    const T vn = h * (v_nw + v_n);
-    const T vs = h * (v_w + v_c);
-    const T un = h * (uc + un_);
-    const T us = h * (us_ + uc);
-    const T adv_y = (vn * un - vs * us) * dyi;
-    const T wt = h * (w_tw + w_t);
-    const T wb = h * (w_w + w_c);
-    const T ut = h * (uc + ut_);
-    const T ub = h * (ub_ + uc);
-    const T adv_z = (wt * ut - wb * ub) * dzik;
-    return -(adv_x + adv_y + adv_z);
+    const T sx_hi = uc + ue;
+    const T sx_lo = uw + uc;
+    const T adv_x = (sx_hi * sx_hi - sx_lo * sx_lo) * (T(0.25) * dxi);
+    const T adv_y = tfma(v_nw + v_n, uc + un_, -((v_w + v_c) * (us_ + uc))) * (T(0.25) * dyi);
+    const T adv_z = tfma(w_tw + w_t, uc + ut_, -((w_w + w_c) * (ub_ + uc)));
+    return -tfma(adv_z, T(0.25) * dzik, adv_x + adv_y);
 }
 
-// Horizontal part of the Laplacian.
+// Horizontal part of the Laplacian (phi_e - 2 phi + phi_w) dxi^2 + (phi_n -
+// 2 phi + phi_s) dyi^2; phi_e - 2 phi is one fused operation (exact 2 phi).
 template <typename T>
 __device__ __forceinline__ T lap_xy(T c, T e, T w, T n, T s, T dxi2, T dyi2)
 {
-    return (e - T(2) * c + w) * dxi2 + (n - T(2) * c + s) * dyi2;
+    return tfma(tfma(T(-2), c, e) + w, dxi2, (tfma(T(-2), c, n) + s) * dyi2);
 }
 
 // diff tendency of u or v at a cell-center level k: the vertical term takes
@@ -102,7 +108,7 @@ template <typename T>
 __device__ __forceinline__ T diff_c_point(T c, T e, T w, T n, T s, T t, T b,
                                           T dxi2, T dyi2, T dzi_k, T dzhi_k1, T dzhi_k, T visc)
 {
-    const T fz = ((t - c) * dzhi_k1 - (c - b) * dzhi_k) * dzi_k;
+    const T fz = tfma(t - c, dzhi_k1, -((c - b) * dzhi_k)) * dzi_k;
     return visc * (lap_xy(c, e, w, n, s, dxi2, dyi2) + fz);
 }
 
@@ -112,8 +118,15 @@ template <typename T>
 __device__ __forceinline__ T diff_w_point(T c, T e, T w, T n, T s, T t, T b,
                                           T dxi2, T dyi2, T dzi_k, T dzi_km1, T dzhi_k, T visc)
 {
-    const T fz = ((t - c) * dzi_k - (c - b) * dzi_km1) * dzhi_k;
+    const T fz = tfma(t - c, dzi_k, -((c - b) * dzi_km1)) * dzhi_k;
     return visc * (lap_xy(c, e, w, n, s, dxi2, dyi2) + fz);
+}
+
+// Forward-Euler update of one value: f + dt * ft, one fused operation.
+template <typename T>
+__device__ __forceinline__ T euler_value(T f, T dt, T ft)
+{
+    return tfma(dt, ft, f);
 }
 
 // ---------------------------------------------------------------------------

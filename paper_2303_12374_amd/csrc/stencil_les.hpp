@@ -20,14 +20,10 @@ namespace kl {
 // fifth-order advection: face fluxes
 // ---------------------------------------------------------------------------
 
-// Fused multiply-add of the field type.  The face and stress functions below
-// are written with explicit fused operations (fewer instructions on a path
-// that is close to the ALU limit); every configuration calls the same
-// functions, so configurations still agree bitwise.
-__device__ __forceinline__ float tfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double tfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
-__device__ __forceinline__ float tabs(float a) { return __builtin_fabsf(a); }
-__device__ __forceinline__ double tabs(double a) { return __builtin_fabs(a); }
+// The face and stress functions below are written with explicit fused
+// operations (tfma, stencil.hpp): fewer instructions on a path that is close
+// to the ALU limit; every configuration calls the same functions, so
+// configurations still agree bitwise.
 
 // Face between a0 and a1, advecting velocity U: U * c6 - |U| * d5 with the
 // sixth-order centered value c6 and the fifth-difference dissipation d5,

@@ -198,8 +198,8 @@ __device__ __forceinline__ void step_zl_tile(const StencilArgs<T> &a, int tx, in
                     } else {
                         const T tu = (T(0) + adv) + du;
                         const T tv = T(0) + dv;
-                        nu[n] = c[0][n] + dt * tu;
-                        nv[n] = c[1][n] + dt * tv;
+                        nu[n] = euler_value<T>(c[0][n], dt, tu);
+                        nv[n] = euler_value<T>(c[1][n], dt, tv);
                     }
                     if (k >= kw0) {
                         const T dw = diff_w_point<T>(c[2][n], we, ww, nn[2][n], ss[2][n], tp[2][n], b[2][n],
@@ -207,7 +207,7 @@ __device__ __forceinline__ void step_zl_tile(const StencilArgs<T> &a, int tx, in
                         if constexpr (MODE == FUSE_PAIR)
                             nw[n] = Q[p][2][n] + dw;
                         else
-                            nw[n] = c[2][n] + dt * (T(0) + dw);
+                            nw[n] = euler_value<T>(c[2][n], dt, T(0) + dw);
                     }
                 }
                 if constexpr (MODE == FUSE_PAIR) {
