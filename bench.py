@@ -35,7 +35,26 @@ KERNEL_SOURCES = {
                     _CSRC + "stencil_les_zl.hpp"],
     "diff_smag": [_CSRC + "stencil.hpp", _CSRC + "stencil_zl.hpp", _CSRC + "stencil_les.hpp",
                   _CSRC + "stencil_les_zl.hpp"],
+    "step": [_CSRC + "stencil.hpp", _CSRC + "stencil_zl.hpp", _CSRC + "stencil_step.hpp"],
+    "advec_diff": [_CSRC + "stencil.hpp", _CSRC + "stencil_zl.hpp", _CSRC + "stencil_step.hpp"],
 }
+
+
+def kernel_of_symbol(sym):
+    """Library kernel a rocprofv3 kernel symbol belongs to, or None.  The
+    step tile serves both the fused step (last template argument 0) and the
+    fused advec_u + diff_uvw pass (1)."""
+    import re
+    m = re.search(r"kl::(\w+?)_(zl3|zlp|zl|zc|plain)(_batch)?<([^>]*)>", sym)
+    if not m:
+        m = re.search(r"kl::(step)_zl(_batch)?<([^>]*)>", sym)
+        if not m:
+            return None
+        return "advec_diff" if m.group(3).split(",")[-1].strip() == "1" else "step"
+    name = m.group(1)
+    if name == "step":
+        return "advec_diff" if m.group(4).split(",")[-1].strip() == "1" else "step"
+    return name if name in KERNEL_SOURCES else None
 
 
 def log(msg):
@@ -706,12 +725,8 @@ def summarize_counters(fetch_csv, write_csv, workload_key, out_json, out_txt, co
         f_kib = statistics.median(fetch[k])
         w_kib = statistics.median(write[k])
         hbm = f_kib * 1024 * fs + w_kib * 1024 * ws
-        name = None
-        for cand in ("advec_u_2i5", "diff_smag", "advec_u", "diff_uvw"):   # longest names first
-            if f"kl::{cand}_" in k:
-                name = cand
-                break
-        if name and f"<{elem}," not in k:
+        name = kernel_of_symbol(k)
+        if name and (f"<{elem}," not in k or "_batch" in k or "_plain" in k):
             name = None
         lines.append(f"| `{k[:90]}` | {len(fetch[k])} | {f_kib:.0f} | {w_kib:.0f} | {hbm:.4g} |")
         if name:
@@ -729,6 +744,67 @@ def summarize_counters(fetch_csv, write_csv, workload_key, out_json, out_txt, co
             lines.append(f"| **{key.split(':')[0]}** (one call = {len(rec['kernel_symbols'])} dispatches) | | "
                          f"{rec['fetch_kib']:.0f} | {rec['write_kib']:.0f} | {rec['hbm_bytes_per_launch']:.4g} |")
     return out, "\n".join(lines) + "\n"
+
+
+def summarize_trace(trace_csv, bench_json, command):
+    """Markdown summary of a rocprofv3 kernel trace of a bench.py run: per
+    dispatch durations of the kernels each timed leg selected, per call (a
+    split configuration runs several dispatches per call), beside the HIP
+    event times the same run reported."""
+    import csv
+    import statistics
+    with open(bench_json) as f:
+        line = json.loads([ln for ln in f if ln.startswith("{")][-1])
+    durs = {}
+    with open(trace_csv) as f:
+        for r in csv.DictReader(f):
+            durs.setdefault(r["Kernel_Name"], []).append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    grid = line["config"]["grid"]
+    legs = [("advec_u", line["config"]["configurations"]["advec_u"], line["kernels"]["advec_u"]["ms"]),
+            ("diff_uvw", line["config"]["configurations"]["diff_uvw"], line["kernels"]["diff_uvw"]["ms"])]
+    if line.get("pair_fused"):
+        legs.append(("advec_diff", line["pair_fused"]["configuration"], line["pair_fused"]["ms"]))
+    if line.get("step"):
+        legs.append(("step", line["step"]["fused_configuration"], line["step"]["fused_ms"]))
+    for k in ("advec_u_2i5", "diff_smag"):
+        if line.get("les"):
+            legs.append((k, line["les"]["configurations"][k], line["les"]["kernels"][k]["ms_back_to_back"]))
+    elem = "float" if line["dtype"] == "f32" else "double"
+    out = [f"# Kernel trace: bench.py, {'x'.join(map(str, grid))} {line['dtype'].upper()} (MI355X)", "",
+           f"command: `{command}`", "",
+           "Per dispatch durations from the profiler (ns).  A call of a split configuration (zl3) is three",
+           "dispatches, one per velocity component.  `bench ms` is the same run's mean per call from HIP events",
+           "on the launch stream (the fifth-order kernels: back to back).", "",
+           "| call | configuration | kernel symbol | dispatches | average ns | min ns | max ns |",
+           "|---|---|---|---|---|---|---|"]
+    summary = []
+    for call, cfg, bench_ms in legs:
+        syms = [s for s in durs if kernel_of_symbol(s) == call and f"<{elem}," in s and "_batch" not in s
+                and "_plain" not in s]
+        # the selected configuration's symbols: template arguments vx, by, kb (and the z-march order)
+        try:
+            parts = cfg.split("_")
+            vx, by, kb, xcd = int(parts[1][1:]), int(parts[2].split("x")[1]), int(parts[3][1:]), int(parts[4][1:])
+        except (IndexError, ValueError):
+            continue  # the default configuration: no tile parameters to match
+        pick = [s for s in syms if s.split("<", 1)[1].replace(" ", "").startswith(f"{elem},{vx},{by},{kb},{xcd},")]
+        total = 0.0
+        for s in pick:
+            d = durs[s]
+            out.append(f"| {call} | `{cfg}` | `{s[:80]}` | {len(d)} | {statistics.mean(d):.0f} | {min(d)} | {max(d)} |")
+            total += statistics.mean(d)
+        summary.append((call, cfg, total / 1e6, bench_ms))
+    out += ["", "| call | configuration | trace ms per call | bench ms per call | trace / bench |", "|---|---|---|---|---|"]
+    for call, cfg, tms, bms in summary:
+        out.append(f"| {call} | `{cfg}` | {tms:.4f} | {bms:.4f} | {tms / bms if bms else float('nan'):.3f} |")
+    if line.get("batched"):
+        syms = [s for s in durs if "_batch<" in s and "step_zl_batch" in s]
+        out += ["", "Batched form (one graph replay per call):", "",
+                "| kernel symbol | dispatches | average ns |", "|---|---|---|"]
+        for s in syms:
+            out.append(f"| `{s[:90]}` | {len(durs[s])} | {statistics.mean(durs[s]):.0f} |")
+        out.append(f"\nbench: {line['batched']['batched_ms']:.4f} ms per replay ({line['batched']['configurations']})")
+    return "\n".join(out) + "\n"
 
 
 def main():
@@ -759,17 +835,30 @@ def main():
                     help="skip the 256^3 FP32/FP64 and 1024x1024x128 FP32 pair legs")
     ap.add_argument("--copy-probe", action="store_true", help="run only the copy probe used to scale counters")
     ap.add_argument("--with-copy-probe", action="store_true", help="run the copy probe first")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_CSV", "BENCH_JSON"),
+                    help="write profiles/kernel_trace_bench_<grid>_<dtype>.md from a rocprofv3 --kernel-trace run "
+                         "of bench.py and that run's JSON line (no GPU work)")
     ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_JSON"),
                     help="write profiles/counters.json from two rocprofv3 --pmc runs of "
                          "'bench.py --with-copy-probe' and that run's JSON line (no GPU work)")
     args = ap.parse_args()
+
+    if args.summarize_trace:
+        itot, jtot, ktot = (int(x) for x in args.size.split(","))
+        cmd = ("rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o trace -- python3 bench.py "
+               "--no-cpu-baseline")
+        txt = summarize_trace(args.summarize_trace[0], args.summarize_trace[1], cmd)
+        with open(os.path.join(ROOT, "profiles", f"kernel_trace_bench_{itot}x{jtot}x{ktot}_{args.dtype}.md"), "w") as f:
+            f.write(txt)
+        print(txt)
+        return
 
     if args.summarize_counters:
         itot, jtot, ktot = (int(x) for x in args.size.split(","))
         wkey = f"{itot}x{jtot}x{ktot}_{args.dtype}"
         cmd = ("rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv -d <dir> -o bench -- python3 "
                "bench.py --with-copy-probe --steps 3 --warmup 1 --no-cpu-baseline --no-untuned --no-batched "
-               "--no-served --no-other-dtype --no-overhead")
+               "--no-served --no-other-dtype --no-overhead --no-precision --no-configs --no-ceiling")
         fetch_csv, write_csv, bench_json = args.summarize_counters
         out, txt = summarize_counters(fetch_csv, write_csv, wkey, None, None, cmd,
                                       "float" if args.dtype == "f32" else "double")
@@ -777,6 +866,10 @@ def main():
             line = json.loads([ln for ln in f if ln.startswith("{")][-1])
         sel = dict(line["config"]["configurations"])
         sel.update((line.get("les") or {}).get("configurations", {}))
+        if line.get("step"):
+            sel["step"] = line["step"]["fused_configuration"]
+        if line.get("pair_fused"):
+            sel["advec_diff"] = line["pair_fused"]["configuration"]
         path = os.path.join(ROOT, "profiles", "counters.json")
         old = json.load(open(path)) if os.path.exists(path) else {}
         for k, v in out.items():

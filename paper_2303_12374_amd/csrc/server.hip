@@ -7,9 +7,12 @@
 // their footprint fits the memory budget (and the arena), and every tick
 // advances all admitted requests by one fused step (advec_u + diff_uvw +
 // forward Euler + ghost refill in one kernel, one persistent launch per
-// configuration group), each request ping-ponging between two field buffers.  Requests therefore join and leave between ticks while
-// others are running.  All per-point arithmetic is shared with the single-
-// grid path, so a request's result does not depend on what it ran beside.
+// configuration group), each request ping-ponging between two field
+// buffers.  Requests therefore join and leave between ticks while others are
+// running.  All per-point arithmetic is shared with the single-grid path, so
+// a request's result does not depend on what it ran beside.  The host logic
+// (arena, admission, tick loop, tickets) is served::Server of
+// server_core.hpp; this file is its device executor and the C entry points.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <string.h>
@@ -26,75 +29,15 @@
 #include <vector>
 
 #include "kl_internal.hpp"
+#include "server_core.hpp"
 #include "variants.hpp"
 
 namespace kl {
 namespace {
 
-constexpr size_t ALIGN = 256;
-inline size_t round_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
-
-int64_t now_ns()
-{
-    return std::chrono::duration_cast<std::chrono::nanoseconds>(
-               std::chrono::steady_clock::now().time_since_epoch())
-        .count();
-}
-
-// First-fit sub-allocator over [0, cap) with coalescing frees.
-class Arena {
-   public:
-    explicit Arena(size_t cap) { free_[0] = cap; }
-    bool alloc(size_t bytes, size_t *off)
-    {
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= bytes) {
-                *off = it->first;
-                const size_t rest = it->second - bytes, start = it->first + bytes;
-                free_.erase(it);
-                if (rest) free_[start] = rest;
-                return true;
-            }
-        }
-        return false;
-    }
-    void release(size_t off, size_t bytes)
-    {
-        auto it = free_.emplace(off, bytes).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-
-   private:
-    std::map<size_t, size_t> free_;
-};
-
-struct Req {
-    uint64_t ticket = 0;
-    kl_request_t r;
-    int state = 0, err = 0;
-    int64_t t_arrive = 0, t_admit = 0, t_done = 0;
-    int steps_left = 0;
-    size_t off = 0, bytes = 0;
-    bool fresh = false;
-    int cur = 0;  // the state is in f[3*cur .. 3*cur+2]; the other three take the next step
-    double dt = 0;
-    kl_grid_t g;
-    void *f[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-    double *d_sum = nullptr;
-    double checksum[9];
-    std::vector<char> metrics;  // host copy of dzi | dzhi in the field dtype
-};
+using served::ALIGN;
+using served::Req;
+using served::round_up;
 
 // Vertical metrics of a served grid: centers-primary tanh stretch
 // (gamma = 1.5, Lz = ktot / max(itot, jtot)) with z walls, uniform when
@@ -151,334 +94,243 @@ struct DevBuf {
     }
 };
 
-struct Server {
-    char *base = nullptr;
-    size_t arena_bytes = 0, budget = 0, used = 0, peak = 0;
-    Arena arena{0};
+// The served form's device work (the executor of served::Server): request
+// set-up, one persistent fused-step launch per configuration group per tick,
+// FP64 checksums of finished requests, and one event per tick slot, all on
+// the server's own stream.
+struct GpuExec {
     int device = 0, ncu = 256;
     hipStream_t stream = nullptr;
-    std::mutex mu;
-    std::condition_variable cv;
-    std::deque<Req *> queue;
-    std::vector<Req *> active;
-    std::unordered_map<uint64_t, Req *> reqs;
-    uint64_t next_ticket = 1;
-    bool stop = false;
-    std::thread th;
-    int64_t ticks = 0, launches = 0, ndone = 0, point_steps = 0;
-    DevBuf tab[2];        // per-tick tables (descriptors, tiles, time steps), one per tick in flight
     hipEvent_t ev[2] = {nullptr, nullptr};
+    DevBuf tab[2];  // per-tick tables (descriptors, tiles), one per tick in flight
     std::map<const Variant *, int> occ;  // resident blocks per CU of batched kernels
     // work queue of the persistent step kernels (two device ints): the kernels
     // run one after another on the server stream, and each returns it to zero
     int *d_queue = nullptr;
 
-    Server(void *arena_ptr, size_t ab, size_t bb) : base((char *)arena_ptr), arena_bytes(ab), budget(bb), arena(ab) {}
-};
-
-size_t footprint(const kl_request_t &q, int64_t *off, int64_t *js, int64_t *ks, int64_t *alloc)
-{
-    kl_layout(q.itot, q.jtot, q.ktot, q.dtype, off, js, ks, alloc);
-    const size_t s = q.dtype == KL_F32 ? 4 : 8;
-    return 6 * round_up((size_t)*alloc * s) + 2 * round_up((size_t)(q.ktot + 2) * s) + ALIGN;
-}
-
-// Lay out an admitted request in its arena block and queue its initial state.
-int init_request(Server &S, Req &q)
-{
-    int64_t off, js, ks, alloc;
-    footprint(q.r, &off, &js, &ks, &alloc);
-    const size_t s = q.r.dtype == KL_F32 ? 4 : 8;
-    char *p = S.base + q.off;
-    for (int n = 0; n < 6; ++n) {
-        q.f[n] = p;
-        p += round_up((size_t)alloc * s);
-    }
-    char *dzi = p;
-    p += round_up((size_t)(q.r.ktot + 2) * s);
-    char *dzhi = p;
-    p += round_up((size_t)(q.r.ktot + 2) * s);
-    q.d_sum = (double *)p;
-    std::vector<double> mi, mhi;
-    double dzmin;
-    served_metrics(q.r, mi, mhi, &dzmin);
-    const int kc = q.r.ktot + 2;
-    q.metrics.resize(2 * kc * s);
-    for (int k = 0; k < kc; ++k) {
-        if (s == 4) {
-            ((float *)q.metrics.data())[k] = (float)mi[k];
-            ((float *)q.metrics.data())[kc + k] = (float)mhi[k];
-        } else {
-            ((double *)q.metrics.data())[k] = mi[k];
-            ((double *)q.metrics.data())[kc + k] = mhi[k];
-        }
-    }
-    q.g.itot = q.r.itot;
-    q.g.jtot = q.r.jtot;
-    q.g.ktot = q.r.ktot;
-    q.g.gc = 1;
-    q.g.off = off;
-    q.g.jstride = js;
-    q.g.kstride = ks;
-    q.g.dxi = q.r.dtype == KL_F32 ? (double)(float)q.r.itot : (double)q.r.itot;
-    q.g.dyi = q.r.dtype == KL_F32 ? (double)(float)q.r.jtot : (double)q.r.jtot;
-    q.g.dzi = dzi;
-    q.g.dzhi = dzhi;
-    q.g.dtype = q.r.dtype;
-    q.g.bc = q.r.bc;
-    q.dt = q.r.dt > 0 ? q.r.dt : 0.1 * std::min(std::min(1.0 / q.r.itot, 1.0 / q.r.jtot), dzmin);
-    hipError_t e = hipMemcpyAsync(dzi, q.metrics.data(), kc * s, hipMemcpyHostToDevice, S.stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(dzhi, q.metrics.data() + kc * s, kc * s, hipMemcpyHostToDevice, S.stream);
-    HostArgs a = make_args(&q.g);
-    if (e == hipSuccess) e = launch_gen_uniform(a, q.r.seed, q.f[0], q.f[1], q.f[2], S.stream);
-    if (e == hipSuccess) e = launch_fill_ghosts(a, q.f[0], q.f[1], q.f[2], S.stream);
-    return e == hipSuccess ? KL_OK : hip_fail(e, "request init");
-}
-
-// Enqueue one tick on the server stream: every active request advances one
-// fused step from its current buffer into the other.  Tables go through slot
-// `slot`, which the previous use has released.
-int run_tick(Server &S, int slot)
-{
-    const std::vector<Req *> &act = S.active;
-    std::vector<StencilArgs<float>> df;
-    std::vector<StencilArgs<double>> dd;
-    std::vector<int> didx(act.size()), sel(act.size());
-    std::vector<kl_grid_t> grids(act.size());
-    std::vector<void *> fields(6 * act.size());
-    std::map<std::tuple<int, int>, std::vector<int4>> groups;  // (dtype, configuration) -> tiles
-    std::map<std::tuple<int, int>, std::vector<std::pair<int64_t, int4>>> sized;  // the same, with tile sizes
-    for (size_t n = 0; n < act.size(); ++n) {
-        Req &q = *act[n];
-        void **f = fields.data() + 6 * n;
-        for (int m = 0; m < 3; ++m) {
-            f[m] = q.f[3 * q.cur + m];
-            f[3 + m] = q.f[3 * (1 - q.cur) + m];
-        }
-        grids[n] = q.g;
-        HostArgs a = make_args(&q.g);
-        a.u = f[0];
-        a.v = f[1];
-        a.w = f[2];
-        a.ut = f[3];
-        a.vt = f[4];
-        a.wt = f[5];
-        a.visc = q.r.visc;
-        a.dt = q.dt;
-        if (q.g.dtype == KL_F32) {
-            didx[n] = (int)df.size();
-            df.push_back(device_args<float>(a));
-        } else {
-            didx[n] = (int)dd.size();
-            dd.push_back(device_args<double>(a));
-        }
-        sel[n] = batch_variant(&q.g, KL_KERNEL_STEP, f);
-        if (sel[n] < 0)
-            return fail(KL_ERR_INVALID, "no step configuration for request %llu", (unsigned long long)q.ticket);
-    }
-    // as few groups (launches per tick) as the configurations allow; every
-    // configuration gives the same bits, so a request may change group
-    merge_batch_groups(KL_KERNEL_STEP, grids, fields.data(), sel);
-    for (size_t n = 0; n < act.size(); ++n) {
-        const Req &q = *act[n];
-        const int vi = sel[n];
-        const Variant &v = variants(KL_KERNEL_STEP, q.g.dtype)[vi];
-        auto &tl = sized[std::make_tuple(q.g.dtype, vi)];
-        const int tw = 64 * v.vx;
-        const int nbx = (int)cdivu(q.g.itot, tw), nby = (int)cdivu(q.g.jtot, v.by), nbz = (int)cdivu(q.g.ktot, v.kb);
-        for (int tz = 0; tz < nbz; ++tz)
-            for (int ty = 0; ty < nby; ++ty)
-                for (int tx = 0; tx < nbx; ++tx)
-                    tl.emplace_back((int64_t)std::min(tw, q.g.itot - tx * tw) * std::min(v.by, q.g.jtot - ty * v.by) *
-                                        std::min(v.kb, q.g.ktot - tz * v.kb),
-                                    make_int4(didx[n], tx, ty, tz));
-    }
-    // the blocks draw tiles from a queue: largest first (stable, so the tiles
-    // of one request stay in order), as in the batched form
-    for (auto &kv : sized) {
-        std::stable_sort(kv.second.begin(), kv.second.end(),
-                         [](const std::pair<int64_t, int4> &x, const std::pair<int64_t, int4> &y) {
-                             return x.first > y.first;
-                         });
-        auto &tl = groups[kv.first];
-        for (const auto &t : kv.second) tl.push_back(t.second);
-    }
-    // pack tables: [desc f32][desc f64][group tiles...]
-    size_t off = 0;
-    auto place = [&](size_t bytes) {
-        const size_t o = off;
-        off += round_up(bytes);
-        return o;
-    };
-    const size_t o_df = place(df.size() * sizeof(df[0])), o_dd = place(dd.size() * sizeof(dd[0]));
-    std::vector<size_t> o_g;
-    for (auto &kv : groups) o_g.push_back(place(kv.second.size() * sizeof(int4)));
-    hipError_t e = S.tab[slot].ensure(off);
-    if (e != hipSuccess) return hip_fail(e, "tick tables");
-    char *h = (char *)S.tab[slot].h;
-    char *d = (char *)S.tab[slot].d;
-    memcpy(h + o_df, df.data(), df.size() * sizeof(df[0]));
-    memcpy(h + o_dd, dd.data(), dd.size() * sizeof(dd[0]));
+    hipError_t open()
     {
+        hipError_t e = hipGetDevice(&device);
+        hipDeviceProp_t prop;
+        if (e == hipSuccess) e = hipGetDeviceProperties(&prop, device);
+        if (e == hipSuccess) ncu = prop.multiProcessorCount;
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking);
+        for (int n = 0; n < 2 && e == hipSuccess; ++n) e = hipEventCreateWithFlags(&ev[n], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipMalloc((void **)&d_queue, 2 * sizeof(int));
+        if (e == hipSuccess) e = hipMemset(d_queue, 0, 2 * sizeof(int));
+        return e;
+    }
+
+    ~GpuExec()
+    {
+        for (int n = 0; n < 2; ++n)
+            if (ev[n]) (void)hipEventDestroy(ev[n]);
+        if (stream) (void)hipStreamDestroy(stream);
+        if (d_queue) (void)hipFree(d_queue);
+    }
+
+    void thread_init() { (void)hipSetDevice(device); }
+
+    size_t footprint(const kl_request_t &q, int64_t *off, int64_t *js, int64_t *ks, int64_t *alloc)
+    {
+        kl_layout(q.itot, q.jtot, q.ktot, q.dtype, off, js, ks, alloc);
+        const size_t s = q.dtype == KL_F32 ? 4 : 8;
+        return 6 * round_up((size_t)*alloc * s) + 2 * round_up((size_t)(q.ktot + 2) * s) + ALIGN;
+    }
+
+    // Lay out an admitted request in its arena block and queue its initial state.
+    int init_request(Req &q, char *block)
+    {
+        int64_t off, js, ks, alloc;
+        footprint(q.r, &off, &js, &ks, &alloc);
+        const size_t s = q.r.dtype == KL_F32 ? 4 : 8;
+        char *p = block;
+        for (int n = 0; n < 6; ++n) {
+            q.f[n] = p;
+            p += round_up((size_t)alloc * s);
+        }
+        char *dzi = p;
+        p += round_up((size_t)(q.r.ktot + 2) * s);
+        char *dzhi = p;
+        p += round_up((size_t)(q.r.ktot + 2) * s);
+        q.d_sum = (double *)p;
+        std::vector<double> mi, mhi;
+        double dzmin;
+        served_metrics(q.r, mi, mhi, &dzmin);
+        const int kc = q.r.ktot + 2;
+        q.metrics.resize(2 * kc * s);
+        for (int k = 0; k < kc; ++k) {
+            if (s == 4) {
+                ((float *)q.metrics.data())[k] = (float)mi[k];
+                ((float *)q.metrics.data())[kc + k] = (float)mhi[k];
+            } else {
+                ((double *)q.metrics.data())[k] = mi[k];
+                ((double *)q.metrics.data())[kc + k] = mhi[k];
+            }
+        }
+        q.g.itot = q.r.itot;
+        q.g.jtot = q.r.jtot;
+        q.g.ktot = q.r.ktot;
+        q.g.gc = 1;
+        q.g.off = off;
+        q.g.jstride = js;
+        q.g.kstride = ks;
+        q.g.dxi = q.r.dtype == KL_F32 ? (double)(float)q.r.itot : (double)q.r.itot;
+        q.g.dyi = q.r.dtype == KL_F32 ? (double)(float)q.r.jtot : (double)q.r.jtot;
+        q.g.dzi = dzi;
+        q.g.dzhi = dzhi;
+        q.g.dtype = q.r.dtype;
+        q.g.bc = q.r.bc;
+        q.dt = q.r.dt > 0 ? q.r.dt : 0.1 * std::min(std::min(1.0 / q.r.itot, 1.0 / q.r.jtot), dzmin);
+        hipError_t e = hipMemcpyAsync(dzi, q.metrics.data(), kc * s, hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(dzhi, q.metrics.data() + kc * s, kc * s, hipMemcpyHostToDevice, stream);
+        HostArgs a = make_args(&q.g);
+        if (e == hipSuccess) e = launch_gen_uniform(a, q.r.seed, q.f[0], q.f[1], q.f[2], stream);
+        if (e == hipSuccess) e = launch_fill_ghosts(a, q.f[0], q.f[1], q.f[2], stream);
+        return e == hipSuccess ? KL_OK : hip_fail(e, "request init");
+    }
+
+    // Enqueue one tick on the server stream: every active request advances one
+    // fused step from its current buffer into the other (the caller flips
+    // each request's current buffer after this returns).  Tables go through
+    // slot `slot`, which the previous use has released.
+    int run_tick(int slot, const std::vector<Req *> &act, int64_t *launches)
+    {
+        std::vector<StencilArgs<float>> df;
+        std::vector<StencilArgs<double>> dd;
+        std::vector<int> didx(act.size()), sel(act.size());
+        std::vector<kl_grid_t> grids(act.size());
+        std::vector<void *> fields(6 * act.size());
+        std::map<std::tuple<int, int>, std::vector<int4>> groups;  // (dtype, configuration) -> tiles
+        std::map<std::tuple<int, int>, std::vector<std::pair<int64_t, int4>>> sized;  // the same, with tile sizes
+        for (size_t n = 0; n < act.size(); ++n) {
+            Req &q = *act[n];
+            void **f = fields.data() + 6 * n;
+            for (int m = 0; m < 3; ++m) {
+                f[m] = q.f[3 * q.cur + m];
+                f[3 + m] = q.f[3 * (1 - q.cur) + m];
+            }
+            grids[n] = q.g;
+            HostArgs a = make_args(&q.g);
+            a.u = f[0];
+            a.v = f[1];
+            a.w = f[2];
+            a.ut = f[3];
+            a.vt = f[4];
+            a.wt = f[5];
+            a.visc = q.r.visc;
+            a.dt = q.dt;
+            if (q.g.dtype == KL_F32) {
+                didx[n] = (int)df.size();
+                df.push_back(device_args<float>(a));
+            } else {
+                didx[n] = (int)dd.size();
+                dd.push_back(device_args<double>(a));
+            }
+            sel[n] = batch_variant(&q.g, KL_KERNEL_STEP, f);
+            if (sel[n] < 0)
+                return fail(KL_ERR_INVALID, "no step configuration for request %llu", (unsigned long long)q.ticket);
+        }
+        // as few groups (launches per tick) as the configurations allow; every
+        // configuration gives the same bits, so a request may change group
+        merge_batch_groups(KL_KERNEL_STEP, grids, fields.data(), sel);
+        for (size_t n = 0; n < act.size(); ++n) {
+            const Req &q = *act[n];
+            const int vi = sel[n];
+            const Variant &v = variants(KL_KERNEL_STEP, q.g.dtype)[vi];
+            auto &tl = sized[std::make_tuple(q.g.dtype, vi)];
+            const int tw = 64 * v.vx;
+            const int nbx = (int)cdivu(q.g.itot, tw), nby = (int)cdivu(q.g.jtot, v.by), nbz = (int)cdivu(q.g.ktot, v.kb);
+            for (int tz = 0; tz < nbz; ++tz)
+                for (int ty = 0; ty < nby; ++ty)
+                    for (int tx = 0; tx < nbx; ++tx)
+                        tl.emplace_back((int64_t)std::min(tw, q.g.itot - tx * tw) * std::min(v.by, q.g.jtot - ty * v.by) *
+                                            std::min(v.kb, q.g.ktot - tz * v.kb),
+                                        make_int4(didx[n], tx, ty, tz));
+        }
+        // the blocks draw tiles from a queue: largest first (stable, so the tiles
+        // of one request stay in order), as in the batched form
+        for (auto &kv : sized) {
+            std::stable_sort(kv.second.begin(), kv.second.end(),
+                             [](const std::pair<int64_t, int4> &x, const std::pair<int64_t, int4> &y) {
+                                 return x.first > y.first;
+                             });
+            auto &tl = groups[kv.first];
+            for (const auto &t : kv.second) tl.push_back(t.second);
+        }
+        // pack tables: [desc f32][desc f64][group tiles...]
+        size_t off = 0;
+        auto place = [&](size_t bytes) {
+            const size_t o = off;
+            off += round_up(bytes);
+            return o;
+        };
+        const size_t o_df = place(df.size() * sizeof(df[0])), o_dd = place(dd.size() * sizeof(dd[0]));
+        std::vector<size_t> o_g;
+        for (auto &kv : groups) o_g.push_back(place(kv.second.size() * sizeof(int4)));
+        hipError_t e = tab[slot].ensure(off);
+        if (e != hipSuccess) return hip_fail(e, "tick tables");
+        char *h = (char *)tab[slot].h;
+        char *d = (char *)tab[slot].d;
+        memcpy(h + o_df, df.data(), df.size() * sizeof(df[0]));
+        memcpy(h + o_dd, dd.data(), dd.size() * sizeof(dd[0]));
+        {
+            size_t gi = 0;
+            for (auto &kv : groups) memcpy(h + o_g[gi++], kv.second.data(), kv.second.size() * sizeof(int4));
+        }
+        if ((e = hipMemcpyAsync(d, h, off, hipMemcpyHostToDevice, stream)) != hipSuccess) return hip_fail(e, "tables");
+        const size_t o_desc[2] = {o_df, o_dd};
         size_t gi = 0;
-        for (auto &kv : groups) memcpy(h + o_g[gi++], kv.second.data(), kv.second.size() * sizeof(int4));
+        for (auto &kv : groups) {
+            const int dt = std::get<0>(kv.first), vi = std::get<1>(kv.first);
+            const Variant &v = variants(KL_KERNEL_STEP, dt)[vi];
+            const int nt = (int)kv.second.size();
+            auto oc = occ.find(&v);
+            if (oc == occ.end()) oc = occ.emplace(&v, v.occupancy()).first;
+            const int nb = persistent_blocks(nt, ncu, oc->second);
+            if ((e = v.batch(d + o_desc[dt], d + o_g[gi], nt, nb, d_queue, stream)) != hipSuccess)
+                return hip_fail(e, v.name);
+            ++*launches;
+            ++gi;
+        }
+        return KL_OK;
     }
-    if ((e = hipMemcpyAsync(d, h, off, hipMemcpyHostToDevice, S.stream)) != hipSuccess) return hip_fail(e, "tables");
-    const size_t o_desc[2] = {o_df, o_dd};
-    size_t gi = 0;
-    for (auto &kv : groups) {
-        const int dt = std::get<0>(kv.first), vi = std::get<1>(kv.first);
-        const Variant &v = variants(KL_KERNEL_STEP, dt)[vi];
-        const int nt = (int)kv.second.size();
-        auto oc = S.occ.find(&v);
-        if (oc == S.occ.end()) oc = S.occ.emplace(&v, v.occupancy()).first;
-        const int nb = persistent_blocks(nt, S.ncu, oc->second);
-        if ((e = v.batch(d + o_desc[dt], d + o_g[gi], nt, nb, S.d_queue, S.stream)) != hipSuccess)
-            return hip_fail(e, v.name);
-        ++S.launches;
-        ++gi;
-    }
-    for (Req *q : act) q->cur ^= 1;
-    return KL_OK;
-}
 
-// Enqueue the FP64 checksums of requests whose last step was just enqueued.
-int enqueue_checksums(Server &S, const std::vector<Req *> &done)
-{
-    if (done.empty()) return KL_OK;
-    void *ws = workspace(reduce_scratch_bytes(), S.stream);
-    if (!ws) return fail(KL_ERR_NOMEM, "server workspace");
-    for (Req *q : done) {
-        void *const *cur = q->f + 3 * q->cur;
-        const hipError_t e = launch_reduce(make_args(&q->g), 1, cur[0], cur[1], cur[2], q->d_sum, ws, S.stream);
-        if (e != hipSuccess) return hip_fail(e, "checksum");
-        ++S.launches;
+    // Enqueue the FP64 checksums of requests whose last step was just enqueued.
+    int enqueue_checksums(const std::vector<Req *> &done, int64_t *launches)
+    {
+        if (done.empty()) return KL_OK;
+        void *ws = workspace(reduce_scratch_bytes(), stream);
+        if (!ws) return fail(KL_ERR_NOMEM, "server workspace");
+        for (Req *q : done) {
+            void *const *cur = q->f + 3 * q->cur;
+            const hipError_t e = launch_reduce(make_args(&q->g), 1, cur[0], cur[1], cur[2], q->d_sum, ws, stream);
+            if (e != hipSuccess) return hip_fail(e, "checksum");
+            ++*launches;
+        }
+        return KL_OK;
     }
-    return KL_OK;
-}
 
-// A tick whose work is on the stream but not known to be complete.
-struct InFlight {
-    int slot;
-    int rc;
-    int64_t pts;
-    std::vector<Req *> finishing;
+    int record(int slot)
+    {
+        const hipError_t e = hipEventRecord(ev[slot], stream);
+        return e == hipSuccess ? KL_OK : hip_fail(e, "tick event");
+    }
+
+    int wait(int slot)
+    {
+        const hipError_t e = hipEventSynchronize(ev[slot]);
+        return e == hipSuccess ? KL_OK : hip_fail(e, "tick");
+    }
+
+    int fetch_checksum(Req &q)
+    {
+        const hipError_t e = hipMemcpy(q.checksum, q.d_sum, 9 * sizeof(double), hipMemcpyDeviceToHost);
+        return e == hipSuccess ? KL_OK : hip_fail(e, "checksum copy");
+    }
 };
 
-// Wait for the oldest tick in flight and publish the requests it finished.
-void complete(Server &S, std::deque<InFlight> &inflight)
-{
-    InFlight t = inflight.front();
-    inflight.pop_front();
-    int rc = t.rc;
-    if (rc == KL_OK) {
-        const hipError_t e = hipEventSynchronize(S.ev[t.slot]);
-        if (e != hipSuccess) rc = hip_fail(e, "tick");
-    }
-    for (Req *q : t.finishing) {
-        if (rc == KL_OK) {
-            const hipError_t e = hipMemcpy(q->checksum, q->d_sum, 9 * sizeof(double), hipMemcpyDeviceToHost);
-            if (e != hipSuccess) rc = hip_fail(e, "checksum copy");
-        }
-    }
-    const int64_t now = now_ns();
-    std::lock_guard<std::mutex> lk(S.mu);
-    ++S.ticks;
-    if (rc == KL_OK) S.point_steps += t.pts;
-    for (Req *q : t.finishing) {
-        q->state = rc == KL_OK ? 2 : 3;
-        q->err = rc;
-        q->t_done = now;
-        ++S.ndone;
-    }
-    S.cv.notify_all();
-}
-
-void server_loop(Server *Sp)
-{
-    Server &S = *Sp;
-    (void)hipSetDevice(S.device);
-    std::deque<InFlight> inflight;  // at most one tick waits while the next is prepared
-    int64_t tick = 0;
-    for (;;) {
-        std::vector<Req *> fresh;
-        bool idle = false;
-        {
-            std::unique_lock<std::mutex> lk(S.mu);
-            for (;;) {
-                // admission in arrival order while the head fits budget and arena
-                while (!S.queue.empty()) {
-                    Req *q = S.queue.front();
-                    if (S.used + q->bytes > S.budget) break;
-                    size_t off;
-                    if (!S.arena.alloc(q->bytes, &off)) break;
-                    q->off = off;
-                    S.used += q->bytes;
-                    S.peak = std::max(S.peak, S.used);
-                    q->state = 1;
-                    q->t_admit = now_ns();
-                    q->steps_left = q->r.nsteps;
-                    S.queue.pop_front();
-                    S.active.push_back(q);
-                    fresh.push_back(q);
-                }
-                if (!S.active.empty()) break;
-                if (!inflight.empty()) {
-                    idle = true;  // nothing to enqueue: retire the tick in flight first
-                    break;
-                }
-                if (S.stop) {
-                    // nothing runs and the head cannot be admitted now: fail what is left
-                    for (Req *q : S.queue) {
-                        q->state = 3;
-                        q->err = KL_ERR_BUDGET;
-                        q->t_done = now_ns();
-                    }
-                    S.queue.clear();
-                    return;
-                }
-                S.cv.wait(lk);
-            }
-        }
-        if (idle) {
-            complete(S, inflight);
-            continue;
-        }
-        const int slot = (int)(tick & 1);
-        int rc = KL_OK;
-        for (Req *q : fresh)
-            if (rc == KL_OK) rc = init_request(S, *q);
-        if (rc == KL_OK) rc = run_tick(S, slot);
-        InFlight t{slot, rc, 0, {}};
-        std::vector<Req *> still;
-        for (Req *q : S.active) {
-            --q->steps_left;
-            t.pts += (int64_t)q->g.itot * q->g.jtot * q->g.ktot;
-            if (q->steps_left == 0 || rc != KL_OK)
-                t.finishing.push_back(q);
-            else
-                still.push_back(q);
-        }
-        if (rc == KL_OK) rc = enqueue_checksums(S, t.finishing);
-        if (rc == KL_OK) {
-            const hipError_t e = hipEventRecord(S.ev[slot], S.stream);
-            if (e != hipSuccess) rc = hip_fail(e, "tick event");
-        }
-        t.rc = rc;
-        {
-            std::lock_guard<std::mutex> lk(S.mu);
-            if (rc != KL_OK) {  // a failed tick fails every request it carried
-                for (Req *q : still) t.finishing.push_back(q);
-                still.clear();
-            }
-            S.active.swap(still);
-        }
-        inflight.push_back(t);
-        ++tick;
-        // keep one tick queued on the GPU while the host prepares the next
-        while (inflight.size() > 1) complete(S, inflight);
-    }
-}
+typedef served::Server<GpuExec> Server;
 
 }  // namespace
 }  // namespace kl
@@ -495,20 +347,12 @@ int kl_server_create(void *arena, size_t arena_bytes, size_t budget_bytes, void 
     if ((uintptr_t)arena % ALIGN) return fail(KL_ERR_INVALID, "arena must be %zu-byte aligned", ALIGN);
     Server *S = new (std::nothrow) Server(arena, arena_bytes, budget_bytes);
     if (!S) return fail(KL_ERR_NOMEM, "server");
-    hipError_t e = hipGetDevice(&S->device);
-    hipDeviceProp_t prop;
-    if (e == hipSuccess) e = hipGetDeviceProperties(&prop, S->device);
-    if (e == hipSuccess) S->ncu = prop.multiProcessorCount;
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking);
-    for (int n = 0; n < 2 && e == hipSuccess; ++n) e = hipEventCreateWithFlags(&S->ev[n], hipEventDisableTiming);
-    if (e == hipSuccess) e = hipMalloc((void **)&S->d_queue, 2 * sizeof(int));
-    if (e == hipSuccess) e = hipMemset(S->d_queue, 0, 2 * sizeof(int));
+    const hipError_t e = S->exec.open();
     if (e != hipSuccess) {
-        if (S->d_queue) (void)hipFree(S->d_queue);
         delete S;
         return hip_fail(e, "server create");
     }
-    S->th = std::thread(server_loop, S);
+    S->th = std::thread(served::server_loop<GpuExec>, S);
     *srv = S;
     return KL_OK;
 }
@@ -517,94 +361,28 @@ int kl_submit(void *srv, const kl_request_t *req, uint64_t *ticket)
 {
     clear_error();
     if (!srv || !req || !ticket) return fail(KL_ERR_INVALID, "NULL argument");
-    Server &S = *(Server *)srv;
-    const kl_request_t &r = *req;
-    if (r.itot < 1 || r.jtot < 1 || r.ktot < 1 || (r.bc != KL_BC_ZPERIODIC && r.ktot < 2))
-        return fail(KL_ERR_INVALID, "request sizes %d x %d x %d", r.itot, r.jtot, r.ktot);
-    if (r.dtype != KL_F32 && r.dtype != KL_F64) return fail(KL_ERR_INVALID, "request dtype %d", r.dtype);
-    if (r.bc < 0 || r.bc > 2) return fail(KL_ERR_INVALID, "request bc %d", r.bc);
-    if (r.nsteps < 1) return fail(KL_ERR_INVALID, "request nsteps %d", r.nsteps);
-    Req *q = new (std::nothrow) Req();
-    if (!q) return fail(KL_ERR_NOMEM, "request");
-    q->r = r;
-    int64_t off, js, ks, alloc;
-    q->bytes = footprint(r, &off, &js, &ks, &alloc);
-    if (q->bytes > S.budget) {
-        const size_t b = q->bytes;
-        delete q;
-        return fail(KL_ERR_BUDGET, "request needs %zu bytes, budget is %zu", b, S.budget);
-    }
-    q->t_arrive = now_ns();
-    std::lock_guard<std::mutex> lk(S.mu);
-    if (S.stop) {
-        delete q;
-        return fail(KL_ERR_INVALID, "server is stopping");
-    }
-    q->ticket = S.next_ticket++;
-    S.reqs[q->ticket] = q;
-    S.queue.push_back(q);
-    *ticket = q->ticket;
-    S.cv.notify_all();
-    return KL_OK;
+    return served::submit(*(Server *)srv, req, ticket);
 }
 
 int kl_poll(void *srv, uint64_t ticket, kl_result_t *out)
 {
     clear_error();
     if (!srv || !out) return fail(KL_ERR_INVALID, "NULL argument");
-    Server &S = *(Server *)srv;
-    std::lock_guard<std::mutex> lk(S.mu);
-    auto it = S.reqs.find(ticket);
-    if (it == S.reqs.end()) return fail(KL_ERR_NOTFOUND, "ticket %llu", (unsigned long long)ticket);
-    const Req &q = *it->second;
-    memset(out, 0, sizeof *out);
-    out->state = q.state;
-    out->err = q.err;
-    out->t_arrive_ns = q.t_arrive;
-    out->t_admit_ns = q.t_admit;
-    out->t_done_ns = q.t_done;
-    if (q.state >= 2) {
-        memcpy(out->checksum, q.checksum, sizeof q.checksum);
-        for (int n = 0; n < 3; ++n) out->fields[n] = q.f[3 * q.cur + n];
-        out->off = q.g.off;
-        out->jstride = q.g.jstride;
-        out->kstride = q.g.kstride;
-        return KL_OK;
-    }
-    return KL_ERR_AGAIN;
+    return served::poll(*(Server *)srv, ticket, out);
 }
 
 int kl_release(void *srv, uint64_t ticket)
 {
     clear_error();
     if (!srv) return fail(KL_ERR_INVALID, "NULL server");
-    Server &S = *(Server *)srv;
-    std::lock_guard<std::mutex> lk(S.mu);
-    auto it = S.reqs.find(ticket);
-    if (it == S.reqs.end()) return fail(KL_ERR_NOTFOUND, "ticket %llu", (unsigned long long)ticket);
-    Req *q = it->second;
-    if (q->state < 2) return fail(KL_ERR_AGAIN, "ticket %llu is not finished", (unsigned long long)ticket);
-    if (q->t_admit) {  // admitted requests hold an arena block until released
-        S.arena.release(q->off, q->bytes);
-        S.used -= q->bytes;
-    }
-    S.reqs.erase(it);
-    delete q;
-    S.cv.notify_all();
-    return KL_OK;
+    return served::release(*(Server *)srv, ticket);
 }
 
 int kl_server_stats(void *srv, int64_t out[5])
 {
     clear_error();
     if (!srv || !out) return fail(KL_ERR_INVALID, "NULL argument");
-    Server &S = *(Server *)srv;
-    std::lock_guard<std::mutex> lk(S.mu);
-    out[0] = S.ticks;
-    out[1] = S.launches;
-    out[2] = S.ndone;
-    out[3] = (int64_t)S.peak;
-    out[4] = S.point_steps;
+    served::stats(*(Server *)srv, out);
     return KL_OK;
 }
 
@@ -613,17 +391,7 @@ int kl_server_destroy(void *srv)
     clear_error();
     if (!srv) return fail(KL_ERR_INVALID, "NULL server");
     Server *S = (Server *)srv;
-    {
-        std::lock_guard<std::mutex> lk(S->mu);
-        S->stop = true;
-        S->cv.notify_all();
-    }
-    if (S->th.joinable()) S->th.join();
-    for (auto &kv : S->reqs) delete kv.second;
-    for (int n = 0; n < 2; ++n)
-        if (S->ev[n]) (void)hipEventDestroy(S->ev[n]);
-    if (S->stream) (void)hipStreamDestroy(S->stream);
-    if (S->d_queue) (void)hipFree(S->d_queue);
+    served::shutdown(*S);
     delete S;
     return KL_OK;
 }
