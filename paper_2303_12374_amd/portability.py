@@ -25,7 +25,7 @@ The analysis functions take plain dictionaries and run on the CPU; only
 ``collect`` needs the GPU.
 
     python -m paper_2303_12374_amd.portability --out profiles/portability_mi355x \\
-        --kernels advec_u,diff_uvw,advec_u_2i5,diff_smag \\
+        --kernels advec_u,diff_uvw,advec_diff,advec_u_2i5,diff_smag \\
         --shapes 256x256x256,512x512x512,1024x1024x128 --dtypes f32,f64
 """
 from __future__ import annotations
@@ -161,9 +161,9 @@ def collect(kl, kernels, shapes, dtypes, budget=120.0, log=None) -> dict:
     one); records go to a scratch wisdom directory."""
     import torch
     names = {"advec_u": kl.ADVEC_U, "diff_uvw": kl.DIFF_UVW, "advec_u_2i5": kl.ADVEC_U_2I5,
-             "diff_smag": kl.DIFF_SMAG}
+             "diff_smag": kl.DIFF_SMAG, "advec_diff": kl.ADVEC_DIFF}
     bits = {kl.ADVEC_U: kl.TUNE_ADVEC_U, kl.DIFF_UVW: kl.TUNE_DIFF_UVW, kl.ADVEC_U_2I5: kl.TUNE_ADVEC_U_2I5,
-            kl.DIFF_SMAG: kl.TUNE_DIFF_SMAG}
+            kl.DIFF_SMAG: kl.TUNE_DIFF_SMAG, kl.ADVEC_DIFF: kl.TUNE_ADVEC_DIFF}
     data = {}
     with tempfile.TemporaryDirectory() as tmp:
         for shape in shapes:
@@ -195,7 +195,7 @@ def collect(kl, kernels, shapes, dtypes, budget=120.0, log=None) -> dict:
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--out", required=True, help="output prefix: writes <out>.md and <out>.json")
-    ap.add_argument("--kernels", default="advec_u,diff_uvw,advec_u_2i5,diff_smag")
+    ap.add_argument("--kernels", default="advec_u,diff_uvw,advec_diff,advec_u_2i5,diff_smag")
     ap.add_argument("--shapes", default="256x256x256,512x512x512,1024x1024x128")
     ap.add_argument("--dtypes", default="f32,f64")
     ap.add_argument("--budget", type=float, default=120.0, help="seconds per scenario")
