@@ -192,6 +192,22 @@ def collect(kl, kernels, shapes, dtypes, budget=120.0, log=None) -> dict:
     return data
 
 
+def merge_collections(blobs):
+    """Scenario tables of several collection runs on one device as one table
+    (a later run's scenario replaces an earlier one of the same key); the
+    commands are kept in order."""
+    data, cmds = {}, []
+    for b in blobs:
+        data.update(b["data"])
+        cmds.append(b["meta"].get("command", ""))
+    meta = dict(blobs[0]["meta"])
+    devices = {b["meta"].get("device") for b in blobs}
+    if len(devices) > 1:
+        raise SystemExit(f"collections from different devices: {sorted(map(str, devices))}")
+    meta["command"] = " ; ".join(cmds)
+    return data, meta
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--out", required=True, help="output prefix: writes <out>.md and <out>.json")
@@ -199,11 +215,11 @@ def main(argv=None):
     ap.add_argument("--shapes", default="256x256x256,512x512x512,1024x1024x128")
     ap.add_argument("--dtypes", default="f32,f64")
     ap.add_argument("--budget", type=float, default=120.0, help="seconds per scenario")
-    ap.add_argument("--from-json", default="", help="re-analyse a collected JSON file (no GPU)")
+    ap.add_argument("--from-json", default="",
+                    help="re-analyse collected JSON files (comma-separated, merged; no GPU)")
     a = ap.parse_args(argv)
     if a.from_json:
-        blob = json.load(open(a.from_json))
-        data, meta = blob["data"], blob["meta"]
+        data, meta = merge_collections([json.load(open(p)) for p in a.from_json.split(",")])
     else:
         from paper_2303_12374_amd import kl
         shapes = [tuple(int(x) for x in s.split("x")) for s in a.shapes.split(",")]

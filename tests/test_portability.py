@@ -62,3 +62,19 @@ def test_analysis_matrix_and_ppm_rows():
     assert rep["scenarios"][s2]["config_C_fraction"] == pytest.approx(0.25)
     md = P.report_markdown(rep, {"device": "test", "command": "x"})
     assert "PPM: k" in md and "runtime selection" in md and not math.isnan(rows[s2]["ppm"])
+
+
+def test_merged_collections_keep_every_scenario_and_command(tmp_path):
+    t = table()
+    k1, k2 = list(t)
+    a = {"meta": {"device": "gpu", "command": "run f32"}, "data": {k1: t[k1]}}
+    b = {"meta": {"device": "gpu", "command": "run f64"}, "data": {k2: t[k2]}}
+    data, meta = P.merge_collections([a, b])
+    assert set(data) == {k1, k2} and meta["command"] == "run f32 ; run f64"
+    with pytest.raises(SystemExit):
+        P.merge_collections([a, {"meta": {"device": "other"}, "data": {}}])
+    import json
+    pa, pb = tmp_path / "a.json", tmp_path / "b.json"
+    pa.write_text(json.dumps(a)), pb.write_text(json.dumps(b))
+    assert P.main(["--out", str(tmp_path / "m"), "--from-json", f"{pa},{pb}"]) == 0
+    assert "run f32 ; run f64" in (tmp_path / "m.md").read_text()
