@@ -231,6 +231,20 @@ __device__ __forceinline__ void vm_drain()
     __builtin_amdgcn_s_waitcnt(0x0F70);
 }
 
+// Mark the values as read here (an empty asm statement with the registers as
+// inputs).  The compiler then waits for the loads that filled them at this
+// point on every path, even where their arithmetic was moved into a branch
+// (a value used only by a predicated store).  A prefetched register that is
+// left pending on one path makes the compiler's wait placement merge the
+// paths conservatively and wait for every outstanding memory operation
+// before the register is next reused, which defeats the prefetch.
+template <typename T, int N>
+__device__ __forceinline__ void settle(const T (&v)[N])
+{
+#pragma unroll
+    for (int n = 0; n < N; ++n) asm volatile("" ::"v"(v[n]));
+}
+
 // p advanced by a byte offset.  Written as a uniform base plus a 32-bit
 // per-lane offset, a global access takes its base from scalar registers
 // (global_load ... v_off, s[base]) and needs no 64-bit vector address math.

@@ -276,6 +276,14 @@ hipError_t launch_smag_zl(const HostArgs &h, hipStream_t s)
             KL_KERNEL_STEP, DT, FAMILY_ZL, VX, 64, BY, KB, XCD, &launch_step<T, VX, BY, KB, XCD, NT>,     \
             &launch_step_batch<T, VX, BY, KB, NT>, &step_batch_occupancy<T, VX, BY, KB, NT>}
 
+// The same with a register cap of 512 / WPE per lane (WPE waves per SIMD)
+// and the ring options of MODE (FUSE_HALO3, FUSE_RING6), named by TAG.
+#define KL_STW(T, DT, VX, BY, KB, XCD, NT, WPE, MODE, TAG)                                               \
+    Variant{"step_v" KL_STR(VX) "_b64x" KL_STR(BY) "_k" KL_STR(KB) "_x" KL_STR(XCD) "_nt" KL_STR(NT)     \
+            "_w" KL_STR(WPE) TAG,                                                                        \
+            KL_KERNEL_STEP, DT, FAMILY_ZL, VX, 64, BY, KB, XCD, &launch_step<T, VX, BY, KB, XCD, NT, WPE, MODE>, \
+            &launch_step_batch<T, VX, BY, KB, NT, WPE, MODE>, &step_batch_occupancy<T, VX, BY, KB, NT, WPE, MODE>}
+
 #define KL_ST_SET(T, DT, VX)                                                                             \
     KL_ST(T, DT, VX, 8, 32, 0, 0), KL_ST(T, DT, VX, 4, 64, 2, 1), KL_ST(T, DT, VX, 8, 32, 2, 1),         \
         KL_ST(T, DT, VX, 4, 128, 2, 1), KL_ST(T, DT, VX, 8, 64, 0, 1), KL_ST(T, DT, VX, 4, 32, 0, 0),    \
@@ -289,6 +297,14 @@ hipError_t launch_smag_zl(const HostArgs &h, hipStream_t s)
             KL_KERNEL_ADVEC_DIFF, DT, FAMILY_ZL, VX, 64, BY, KB, XCD,                                    \
             &launch_step<T, VX, BY, KB, XCD, NT, 1, FUSE_PAIR>, &launch_step_batch<T, VX, BY, KB, NT, 1, FUSE_PAIR>, \
             &step_batch_occupancy<T, VX, BY, KB, NT, 1, FUSE_PAIR>}
+
+#define KL_ADW(T, DT, VX, BY, KB, XCD, NT, WPE, MODE, TAG)                                               \
+    Variant{"ad_v" KL_STR(VX) "_b64x" KL_STR(BY) "_k" KL_STR(KB) "_x" KL_STR(XCD) "_nt" KL_STR(NT)       \
+            "_w" KL_STR(WPE) TAG,                                                                        \
+            KL_KERNEL_ADVEC_DIFF, DT, FAMILY_ZL, VX, 64, BY, KB, XCD,                                    \
+            &launch_step<T, VX, BY, KB, XCD, NT, WPE, FUSE_PAIR | (MODE)>,                                \
+            &launch_step_batch<T, VX, BY, KB, NT, WPE, FUSE_PAIR | (MODE)>,                               \
+            &step_batch_occupancy<T, VX, BY, KB, NT, WPE, FUSE_PAIR | (MODE)>}
 
 #define KL_AD_SET(T, DT, VX)                                                                             \
     KL_AD(T, DT, VX, 4, 8, 0, 0), KL_AD(T, DT, VX, 8, 8, 0, 0), KL_AD(T, DT, VX, 4, 32, 0, 0),           \
