@@ -6,7 +6,6 @@ namespace kl {
 void add_variants_f32_step(std::vector<Variant> &out)
 {
     static const std::vector<Variant> v = {KL_ST_SET(float, KL_F32, 1), KL_ST_SET(float, KL_F32, 2), KL_ST_SET(float, KL_F32, 4),
-                                             KL_STW(float, KL_F32, 4, 4, 32, 2, 1, 3, 0, ""),
                                              KL_STW(float, KL_F32, 4, 4, 32, 2, 1, 1, FUSE_HALO3, "_h3"),
                                              KL_STW(float, KL_F32, 4, 4, 64, 2, 1, 1, FUSE_HALO3, "_h3"),
                                              KL_STW(float, KL_F32, 4, 4, 16, 2, 1, 1, FUSE_HALO3, "_h3"),
