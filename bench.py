@@ -293,6 +293,10 @@ def served_leg(kl, torch, wisdom, n_req=2000, budget_gib=8.0, load=0.8, sweep=(0
     kl.kl_set_wisdom_dir(wisdom)
     pre_served = served_run(kl, torch, reqs[:n_pre], t_arr[:n_pre], budget_gib)
     run = served_run(kl, torch, reqs, t_arr, budget_gib)
+    # the same trace with a budget that never holds a request back (64 GiB
+    # against a peak of about 9 GB in flight): what admission costs
+    unl_gib = 64.0
+    run_unl = served_run(kl, torch, reqs, t_arr, unl_gib)
     sweep_out = []
     for ld in sweep:
         ta = np.cumsum([r["gap"] for r in reqs]) / (ld * served_capacity)
@@ -324,6 +328,9 @@ def served_leg(kl, torch, wisdom, n_req=2000, budget_gib=8.0, load=0.8, sweep=(0
                 "served": {k: pre_served[k] for k in ("p50_ms", "p99_ms", "mean_ms", "grid_point_steps_per_s",
                                                         "makespan_s")},
                 "arrivals": f"the first {n_pre} requests of the trace at the same arrival times"},
+            "unlimited_budget": {"budget_gib": unl_gib,
+                                 **{k: run_unl[k] for k in ("p50_ms", "p99_ms", "mean_ms", "grid_point_steps_per_s",
+                                                            "makespan_s", "peak_bytes")}},
             "load_sweep": sweep_out}
 
 
