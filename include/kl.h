@@ -421,6 +421,26 @@ int kl_tune_capture(const char *path, const char *wisdom_dir, double budget_s, v
 int kl_batch_create(const kl_grid_t *grids, void *const *fields, int32_t n, double visc,
                     int32_t zero_tendencies, void *stream, void **batch);
 
+/* Steps of a batch's graph besides the tendencies (kl_batch_create_ex). */
+enum {
+    KL_BATCH_ZERO_TENDENCIES = 1u, /* ut, vt, wt := 0 before the tendencies */
+    KL_BATCH_FILL_GHOSTS = 2u,     /* first: the ghost cells of u, v, w as kl_fill_ghosts (all grids, one kernel per dtype) */
+    KL_BATCH_SUMS = 4u             /* last: each grid's conservation sums as kl_reduce_fp64(what = 0) */
+};
+
+/* kl_batch_create with the graph's other steps chosen by `flags`
+ * (KL_BATCH_*): [ghost fill] -> [tendencies := 0] -> the fused tendency
+ * groups -> [conservation sums].  The ghost fill gives every grid's u, v, w
+ * the same ghost values, bit for bit, as kl_fill_ghosts.  With
+ * KL_BATCH_SUMS, `sums` is a device array of 3 doubles per grid (grid g at
+ * sums[3g .. 3g+2]: sum ut*dz_k, sum vt*dz_k, sum wt*dzh_k), written by every
+ * replay with the bits kl_reduce_fp64(what = 0) gives for that grid; the
+ * library owns the partials (4096 x 9 doubles per grid).  Unknown flag bits,
+ * or KL_BATCH_SUMS without `sums`, are KL_ERR_INVALID.  kl_batch_create is
+ * this call with flags = zero_tendencies ? KL_BATCH_ZERO_TENDENCIES : 0. */
+int kl_batch_create_ex(const kl_grid_t *grids, void *const *fields, int32_t n, double visc, uint32_t flags,
+                       double *sums, void *stream, void **batch);
+
 /* Tune a batch as a whole (the batch-level form of kl_tune): time the
  * batch with its per-grid selection and then with each persistent
  * advec_diff configuration serving every grid it can (the mean of
@@ -446,7 +466,7 @@ int kl_batch_tune(void *batch, const char *wisdom_dir, double budget_s, void *st
                   int32_t max_timings, int32_t *n_timings);
 
 /* Configuration group `group` (0 .. n_kernels of kl_batch_info minus the
- * zeroing kernels) of a batch: its dtype, configuration name (into name,
+ * zeroing, ghost-fill and sum kernels) of a batch: its dtype, configuration name (into name,
  * truncated to len) and tile count (host pointers; any may be NULL).
  * KL_ERR_NOTFOUND past the last group. */
 int kl_batch_group(void *batch, int32_t group, int32_t *dtype, char *name, size_t len, int64_t *n_tiles);
@@ -454,7 +474,8 @@ int kl_batch_group(void *batch, int32_t group, int32_t *dtype, char *name, size_
 /* Replay the batch's graph on `stream` (asynchronous). */
 int kl_batch_run(void *batch, void *stream);
 
-/* Number of persistent kernels and tiles of a batch (host ints). */
+/* Number of kernels in the batch's graph (zeroing, ghost fill and sums included) and tiles of its
+ * fused tendency groups (host ints). */
 int kl_batch_info(void *batch, int32_t *n_kernels, int64_t *n_tiles);
 
 int kl_batch_destroy(void *batch);

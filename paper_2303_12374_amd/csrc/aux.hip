@@ -62,10 +62,9 @@ __device__ __forceinline__ int src_k(const Dims &d, int f, int k, int &sign)
 // writes, so the cells can be filled in any order.  kind[f] is the z rule
 // of field f (0 and 1: the u/v rule, 2: the w rule); a NULL field is skipped.
 template <typename T>
-__global__ __launch_bounds__(256) void fill_ghosts_kernel(Dims d, T *u, T *v, T *w, int k0, int k1, int k2,
-                                                         int64_t n0, int64_t n1, int64_t n2, int64_t n3)
+__device__ __forceinline__ void fill_cell(const Dims &d, T *u, T *v, T *w, int k0, int k1, int k2, int64_t n0,
+                                          int64_t n1, int64_t n2, int64_t n3, int64_t t)
 {
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int gc = d.gc;
     const int ic = d.itot + 2 * gc, jc = d.jtot + 2 * gc;
     int i, j, k;
@@ -110,6 +109,32 @@ __global__ __launch_bounds__(256) void fill_ghosts_kernel(Dims d, T *u, T *v, T 
         const int sk = src_k(d, kind[f], k, sign);
         p[dst] = sign == 0 ? T(0) : (sign < 0 ? -p[at(d, si, sj, sk)] : p[at(d, si, sj, sk)]);
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void fill_ghosts_kernel(Dims d, T *u, T *v, T *w, int k0, int k1, int k2,
+                                                         int64_t n0, int64_t n1, int64_t n2, int64_t n3)
+{
+    fill_cell<T>(d, u, v, w, k0, k1, k2, n0, n1, n2, n3, (int64_t)blockIdx.x * 256 + threadIdx.x);
+}
+
+// Ghost fill of the velocity fields of many grids in one launch: block b
+// fills cells [256 lb, 256 lb + 256) of grid job g, (g, lb) = blocks[b];
+// the same cell map and copies as the single-grid fill.
+struct FillJob {
+    Dims d;
+    void *u, *v, *w;
+    int64_t n0, n1, n2, n3;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void fill_ghosts_batch_kernel(const FillJob *__restrict__ jobs,
+                                                               const int2 *__restrict__ blocks)
+{
+    const int2 b = blocks[blockIdx.x];
+    const FillJob j = jobs[b.x];
+    fill_cell<T>(j.d, as_global((T *)j.u), as_global((T *)j.v), as_global((T *)j.w), 0, 1, 2, j.n0, j.n1, j.n2,
+                 j.n3, (int64_t)b.y * 256 + threadIdx.x);
 }
 
 // Forward Euler at one interior point: the thread writes the updated cell
@@ -245,10 +270,10 @@ __device__ __forceinline__ void red_load(T (&x)[V], const T *p)
     }
 }
 
+// Pass-1 block b of a reduction (partial + b * RQ receives its partial).
 template <typename T, int V>
-__global__ __launch_bounds__(RT) void reduce_pass1(Dims d, int what, int kw0, const T *f0, const T *f1,
-                                                  const T *f2, const T *dzi, const T *dzhi,
-                                                  double *partial)
+__device__ __forceinline__ void reduce_block(const Dims &d, int what, int kw0, const T *f0, const T *f1,
+                                             const T *f2, const T *dzi, const T *dzhi, int b, double *partial)
 {
     double acc[RQ];
     int is_max[RQ];
@@ -303,7 +328,7 @@ __global__ __launch_bounds__(RT) void reduce_pass1(Dims d, int what, int kw0, co
     };
 
     if (slot < rpp) {
-        int64_t r = (int64_t)blockIdx.x + (int64_t)slot * RB;
+        int64_t r = (int64_t)b + (int64_t)slot * RB;
         for (; r + rstep < nrows; r += 2 * rstep) {
             const int ja = 1 + (int)(r % d.jtot), ka = 1 + (int)(r / d.jtot);
             const int jb = 1 + (int)((r + rstep) % d.jtot), kb = 1 + (int)((r + rstep) / d.jtot);
@@ -324,10 +349,19 @@ __global__ __launch_bounds__(RT) void reduce_pass1(Dims d, int what, int kw0, co
             }
         }
     }
-    block_tree<RQ>(acc, is_max, partial + (int64_t)blockIdx.x * RQ);
+    block_tree<RQ>(acc, is_max, partial + (int64_t)b * RQ);
 }
 
-__global__ __launch_bounds__(RT) void reduce_pass2(int what, const double *partial, double *out)
+template <typename T, int V>
+__global__ __launch_bounds__(RT) void reduce_pass1(Dims d, int what, int kw0, const T *f0, const T *f1,
+                                                  const T *f2, const T *dzi, const T *dzhi,
+                                                  double *partial)
+{
+    reduce_block<T, V>(d, what, kw0, f0, f1, f2, dzi, dzhi, (int)blockIdx.x, partial);
+}
+
+// Pass 2 over the RB partials at `partial` into out[0 .. nout-1].
+__device__ __forceinline__ void reduce_final(int what, const double *partial, double *out)
 {
     double acc[RQ];
     int is_max[RQ];
@@ -344,6 +378,36 @@ __global__ __launch_bounds__(RT) void reduce_pass2(int what, const double *parti
     __syncthreads();
     const int nout = what == 0 ? 3 : 9;
     if ((int)threadIdx.x < nout) out[threadIdx.x] = res[threadIdx.x];
+}
+
+__global__ __launch_bounds__(RT) void reduce_pass2(int what, const double *partial, double *out)
+{
+    reduce_final(what, partial, out);
+}
+
+// Conservation sums (what = 0) of many grids in two launches: pass-1 block
+// blockIdx.x is block blockIdx.x % RB of job blockIdx.x / RB, into that job's
+// own RB partials; pass 2 reduces each slot's partials in one block.  Per
+// grid the blocks, their rows and the trees are those of the single-grid
+// reduction, so each grid's sums are bitwise those of kl_reduce_fp64.
+struct SumJob {
+    Dims d;
+    int kw0, slot;
+    const void *f0, *f1, *f2, *dzi, *dzhi;
+};
+
+template <typename T, int V>
+__global__ __launch_bounds__(RT) void sums_batch_pass1(const SumJob *__restrict__ jobs, double *partials)
+{
+    const SumJob j = jobs[blockIdx.x / RB];
+    reduce_block<T, V>(j.d, 0, j.kw0, as_global((const T *)j.f0), as_global((const T *)j.f1),
+                       as_global((const T *)j.f2), as_global((const T *)j.dzi), as_global((const T *)j.dzhi),
+                       (int)(blockIdx.x % RB), partials + (int64_t)j.slot * RB * RQ);
+}
+
+__global__ __launch_bounds__(RT) void sums_batch_pass2(const double *partials, double *out)
+{
+    reduce_final(0, partials + (int64_t)blockIdx.x * RB * RQ, out + 3 * (int64_t)blockIdx.x);
 }
 
 // Bit hash: sum over interior cells (mod 2^64) of SplitMix64(bits ^ cell key).
@@ -493,18 +557,25 @@ hipError_t launch_zero_interior(const HostArgs &a, void *f, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_reduce(const HostArgs &a, int what, const void *f0, const void *f1, const void *f2,
-                         double *out, void *scratch, hipStream_t s)
+// Vector width of the reductions' loads: 4 floats or 2 doubles (16 bytes)
+// when every row start of the interior and every field pointer is aligned to
+// it (true), else 1 (false).
+bool reduce_vectorized(const HostArgs &a, const void *f0, const void *f1, const void *f2)
 {
-    const Dims d = dims_of(a);
-    double *partial = (double *)scratch;
-    // vector width: 4 floats or 2 doubles (16 bytes) when every row start of
-    // the interior and every field pointer is aligned to it, else 1
     const int vw = a.dtype == KL_F32 ? 4 : 2;
     const size_t vb = (size_t)vw * (a.dtype == KL_F32 ? 4 : 8);
     bool vec = a.itot % vw == 0 && (a.off + 1) % vw == 0 && a.js % vw == 0 && a.ks % vw == 0;
     for (const void *p : {f0, f1, f2})
         if (p && (uintptr_t)p % vb) vec = false;
+    return vec;
+}
+
+hipError_t launch_reduce(const HostArgs &a, int what, const void *f0, const void *f1, const void *f2,
+                         double *out, void *scratch, hipStream_t s)
+{
+    const Dims d = dims_of(a);
+    double *partial = (double *)scratch;
+    const bool vec = reduce_vectorized(a, f0, f1, f2);
     if (a.dtype == KL_F32) {
         if (vec)
             hipLaunchKernelGGL((reduce_pass1<float, 4>), dim3(RB), dim3(RT), 0, s, d, what, a.kw0,
@@ -527,6 +598,88 @@ hipError_t launch_reduce(const HostArgs &a, int what, const void *f0, const void
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(reduce_pass2, dim3(1), dim3(RT), 0, s, what, (const double *)partial, out);
+    return hipGetLastError();
+}
+
+// ---- batched ghost fill and conservation sums (used by the batched form) ----
+
+size_t fill_job_bytes() { return sizeof(FillJob); }
+
+void append_fill_job(const HostArgs &a, void *u, void *v, void *w, std::vector<char> &jobs,
+                     std::vector<int2> &blocks)
+{
+    const int64_t gc = a.gc;
+    const int64_t ic = a.itot + 2 * gc, jc = a.jtot + 2 * gc;
+    FillJob j;
+    j.d = dims_of(a);
+    j.u = u;
+    j.v = v;
+    j.w = w;
+    j.n0 = 2 * ic * jc;
+    j.n1 = 2 * gc * ic * a.ktot;
+    j.n2 = 2 * gc * (int64_t)a.jtot * a.ktot;
+    j.n3 = a.bc != KL_BC_ZPERIODIC ? (int64_t)a.itot * a.jtot : 0;  // the velocity fill: w's wall faces
+    const int job = (int)(jobs.size() / sizeof(FillJob));
+    const char *p = (const char *)&j;
+    jobs.insert(jobs.end(), p, p + sizeof j);
+    const unsigned nb = cdiv(j.n0 + j.n1 + j.n2 + j.n3, 256);
+    for (unsigned b = 0; b < nb; ++b) blocks.push_back(make_int2(job, (int)b));
+}
+
+hipError_t launch_fill_batch(int dtype, const void *jobs, const void *blocks, int nblocks, hipStream_t s)
+{
+    if (nblocks <= 0) return hipSuccess;
+    if (dtype == KL_F32)
+        hipLaunchKernelGGL(fill_ghosts_batch_kernel<float>, dim3(nblocks), dim3(256), 0, s, (const FillJob *)jobs,
+                           (const int2 *)blocks);
+    else
+        hipLaunchKernelGGL(fill_ghosts_batch_kernel<double>, dim3(nblocks), dim3(256), 0, s, (const FillJob *)jobs,
+                           (const int2 *)blocks);
+    return hipGetLastError();
+}
+
+size_t sum_job_bytes() { return sizeof(SumJob); }
+
+size_t sums_partial_bytes(int nslots) { return (size_t)nslots * RB * RQ * sizeof(double); }
+
+void append_sum_job(const HostArgs &a, const void *ut, const void *vt, const void *wt, int slot, std::vector<char> &jobs)
+{
+    SumJob j;
+    j.d = dims_of(a);
+    j.kw0 = a.kw0;
+    j.slot = slot;
+    j.f0 = ut;
+    j.f1 = vt;
+    j.f2 = wt;
+    j.dzi = a.dzi;
+    j.dzhi = a.dzhi;
+    const char *p = (const char *)&j;
+    jobs.insert(jobs.end(), p, p + sizeof j);
+}
+
+hipError_t launch_sums_batch(int dtype, bool vec, const void *jobs, int njobs, double *partials, hipStream_t s)
+{
+    if (njobs <= 0) return hipSuccess;
+    const dim3 grid((unsigned)njobs * RB);
+    const SumJob *j = (const SumJob *)jobs;
+    if (dtype == KL_F32) {
+        if (vec)
+            hipLaunchKernelGGL((sums_batch_pass1<float, 4>), grid, dim3(RT), 0, s, j, partials);
+        else
+            hipLaunchKernelGGL((sums_batch_pass1<float, 1>), grid, dim3(RT), 0, s, j, partials);
+    } else {
+        if (vec)
+            hipLaunchKernelGGL((sums_batch_pass1<double, 2>), grid, dim3(RT), 0, s, j, partials);
+        else
+            hipLaunchKernelGGL((sums_batch_pass1<double, 1>), grid, dim3(RT), 0, s, j, partials);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sums_finish(const double *partials, int nslots, double *out, hipStream_t s)
+{
+    if (nslots <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sums_batch_pass2, dim3((unsigned)nslots), dim3(RT), 0, s, partials, out);
     return hipGetLastError();
 }
 

@@ -57,12 +57,21 @@ struct Batch {
     std::vector<void *> fields;  // 6 per grid
     double visc = 0;
     bool zero = false;
+    uint32_t flags = 0;        // KL_BATCH_* steps besides the tendencies
+    double *sums = nullptr;    // caller's device array of 3 doubles per grid (KL_BATCH_SUMS)
     int forced[2] = {-1, -1};  // configuration serving every grid it can, per dtype (-1: per-grid selection)
     void *d_desc[2] = {nullptr, nullptr};  // StencilArgs<float>[] and StencilArgs<double>[], indexed by grid
     std::vector<int4> ztiles[2];
     void *d_ztiles[2] = {nullptr, nullptr};
     int zblocks[2] = {0, 0};
     std::vector<Group> groups;
+    // ghost fill jobs and their blocks, per dtype
+    void *d_fjobs[2] = {nullptr, nullptr}, *d_fblocks[2] = {nullptr, nullptr};
+    int nfblocks[2] = {0, 0};
+    // conservation-sum jobs per dtype and vector width, and their partials
+    void *d_sjobs[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    int nsjobs[2][2] = {{0, 0}, {0, 0}};
+    double *d_partials = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int64_t ntiles = 0;
@@ -87,6 +96,16 @@ struct Batch {
             if (g.d_tiles) (void)hipFree(g.d_tiles);
             if (g.d_queue) (void)hipFree(g.d_queue);
         }
+        for (int d = 0; d < 2; ++d) {
+            for (void **p : {&d_fjobs[d], &d_fblocks[d], &d_sjobs[d][0], &d_sjobs[d][1]}) {
+                if (*p) (void)hipFree(*p);
+                *p = nullptr;
+            }
+            nfblocks[d] = 0;
+            nsjobs[d][0] = nsjobs[d][1] = 0;
+        }
+        if (d_partials) (void)hipFree(d_partials);
+        d_partials = nullptr;
         groups.clear();
         ntiles = 0;
         nkernels = 0;
@@ -370,12 +389,53 @@ int build(Batch &b, void *const *fields)
             b.zblocks[d] = (int)std::min<int64_t>((int64_t)b.ztiles[d].size(), (int64_t)ncu * 8);
         }
     }
+    // ghost fill and conservation-sum jobs, one per grid
+    if (b.flags & KL_BATCH_FILL_GHOSTS) {
+        std::vector<char> jobs[2];
+        std::vector<int2> blocks[2];
+        for (size_t n = 0; n < b.grids.size(); ++n) {
+            const kl_grid_t *g = &b.grids[n];
+            append_fill_job(make_args(g), fields[6 * n], fields[6 * n + 1], fields[6 * n + 2], jobs[g->dtype],
+                            blocks[g->dtype]);
+        }
+        for (int d = 0; d < 2; ++d) {
+            if (blocks[d].empty()) continue;
+            if ((e = upload(&b.d_fjobs[d], jobs[d].data(), jobs[d].size())) != hipSuccess ||
+                (e = upload(&b.d_fblocks[d], blocks[d].data(), blocks[d].size() * sizeof(int2))) != hipSuccess)
+                return hip_fail(e, "fill jobs");
+            b.nfblocks[d] = (int)blocks[d].size();
+        }
+    }
+    if (b.flags & KL_BATCH_SUMS) {
+        std::vector<char> jobs[2][2];
+        for (size_t n = 0; n < b.grids.size(); ++n) {
+            const kl_grid_t *g = &b.grids[n];
+            const HostArgs a = make_args(g);
+            void *const *f = fields + 6 * n;
+            const int vec = reduce_vectorized(a, f[3], f[4], f[5]) ? 1 : 0;
+            append_sum_job(a, f[3], f[4], f[5], (int)n, jobs[g->dtype][vec]);
+            ++b.nsjobs[g->dtype][vec];
+        }
+        for (int d = 0; d < 2; ++d)
+            for (int v = 0; v < 2; ++v)
+                if (b.nsjobs[d][v] &&
+                    (e = upload(&b.d_sjobs[d][v], jobs[d][v].data(), jobs[d][v].size())) != hipSuccess)
+                    return hip_fail(e, "sum jobs");
+        if ((e = hipMalloc((void **)&b.d_partials, sums_partial_bytes((int)b.grids.size()))) != hipSuccess)
+            return hip_fail(e, "sum partials");
+    }
     // capture the graph on a private stream
     hipStream_t cs;
     if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     int rc = KL_OK;
     if (e != hipSuccess) rc = hip_fail(e, "begin capture");
+    for (int d = 0; d < 2 && rc == KL_OK; ++d) {
+        if (!b.nfblocks[d]) continue;
+        e = launch_fill_batch(d, b.d_fjobs[d], b.d_fblocks[d], b.nfblocks[d], cs);
+        if (e != hipSuccess) rc = hip_fail(e, "fill launch");
+        ++b.nkernels;
+    }
     for (int d = 0; d < 2 && rc == KL_OK; ++d) {
         if (!b.zero || b.ztiles[d].empty()) continue;
         e = launch_zero_batch(d, b.d_desc[d], b.d_ztiles[d], (int)b.ztiles[d].size(), b.zblocks[d], cs);
@@ -388,6 +448,20 @@ int build(Batch &b, void *const *fields)
         e = v.batch(b.d_desc[gr.dtype], gr.d_tiles, (int)gr.tiles.size(), gr.nblocks, gr.d_queue, cs);
         if (e != hipSuccess) rc = hip_fail(e, v.name);
         ++b.nkernels;
+    }
+    if (b.flags & KL_BATCH_SUMS) {
+        for (int d = 0; d < 2 && rc == KL_OK; ++d)
+            for (int v = 0; v < 2 && rc == KL_OK; ++v) {
+                if (!b.nsjobs[d][v]) continue;
+                e = launch_sums_batch(d, v != 0, b.d_sjobs[d][v], b.nsjobs[d][v], b.d_partials, cs);
+                if (e != hipSuccess) rc = hip_fail(e, "sums launch");
+                ++b.nkernels;
+            }
+        if (rc == KL_OK) {
+            e = launch_sums_finish(b.d_partials, (int)b.grids.size(), b.sums, cs);
+            if (e != hipSuccess) rc = hip_fail(e, "sums finish");
+            ++b.nkernels;
+        }
     }
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(cs, &graph);
@@ -411,9 +485,19 @@ extern "C" {
 int kl_batch_create(const kl_grid_t *grids, void *const *fields, int32_t n, double visc, int32_t zero_tendencies,
                     void *stream, void **batch)
 {
+    return kl_batch_create_ex(grids, fields, n, visc, zero_tendencies ? KL_BATCH_ZERO_TENDENCIES : 0u, nullptr,
+                              stream, batch);
+}
+
+int kl_batch_create_ex(const kl_grid_t *grids, void *const *fields, int32_t n, double visc, uint32_t flags,
+                       double *sums, void *stream, void **batch)
+{
     clear_error();
     (void)stream;
     if (!grids || !fields || !batch || n < 1) return fail(KL_ERR_INVALID, "bad batch arguments");
+    const uint32_t known = KL_BATCH_ZERO_TENDENCIES | KL_BATCH_FILL_GHOSTS | KL_BATCH_SUMS;
+    if (flags & ~known) return fail(KL_ERR_INVALID, "unknown batch flags 0x%x", flags & ~known);
+    if ((flags & KL_BATCH_SUMS) && !sums) return fail(KL_ERR_INVALID, "KL_BATCH_SUMS needs a sums array");
     *batch = nullptr;
     for (int i = 0; i < n; ++i) {
         int rc = check_grid(&grids[i]);
@@ -426,7 +510,9 @@ int kl_batch_create(const kl_grid_t *grids, void *const *fields, int32_t n, doub
     b->grids.assign(grids, grids + n);
     b->fields.assign(fields, fields + 6 * (size_t)n);
     b->visc = visc;
-    b->zero = zero_tendencies != 0;
+    b->zero = (flags & KL_BATCH_ZERO_TENDENCIES) != 0;
+    b->flags = flags;
+    b->sums = (flags & KL_BATCH_SUMS) ? sums : nullptr;
     for (int dt = 0; dt < 2; ++dt) {
         int64_t np;
         int ng;

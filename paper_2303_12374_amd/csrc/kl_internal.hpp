@@ -92,6 +92,20 @@ hipError_t launch_hash(const HostArgs &a, const void *f, uint64_t *out, void *sc
 hipError_t launch_gen_uniform(const HostArgs &a, uint64_t seed, void *u, void *v, void *w,
                               hipStream_t s);
 size_t reduce_scratch_bytes();
+bool reduce_vectorized(const HostArgs &a, const void *f0, const void *f1, const void *f2);
+// Batched ghost fill of u, v, w (one job per grid: append_fill_job adds the
+// job and its 256-cell blocks {job, block}) and batched conservation sums
+// (one job per grid, written to out[3 slot ..]; jobs of one launch share a
+// dtype and reduce_vectorized; partials: sums_partial_bytes(slots) bytes).
+size_t fill_job_bytes();
+void append_fill_job(const HostArgs &a, void *u, void *v, void *w, std::vector<char> &jobs,
+                     std::vector<int2> &blocks);
+hipError_t launch_fill_batch(int dtype, const void *jobs, const void *blocks, int nblocks, hipStream_t s);
+size_t sum_job_bytes();
+size_t sums_partial_bytes(int nslots);
+void append_sum_job(const HostArgs &a, const void *ut, const void *vt, const void *wt, int slot, std::vector<char> &jobs);
+hipError_t launch_sums_batch(int dtype, bool vec, const void *jobs, int njobs, double *partials, hipStream_t s);
+hipError_t launch_sums_finish(const double *partials, int nslots, double *out, hipStream_t s);
 // Batched row-tile kernels: descs = StencilArgs<T>[], tiles = int4 {grid, row0, row1, 0}[].
 hipError_t launch_zero_batch(int dtype, const void *descs, const void *tiles, int ntiles, int nblocks,
                              hipStream_t s);

@@ -30,6 +30,7 @@ BC_ZWALL_ZEROGRAD, BC_ZWALL_NOPEN, BC_ZPERIODIC = 0, 1, 2
 ADVEC_U, DIFF_UVW, STEP, ADVEC_U_2I5, DIFF_SMAG, ADVEC_DIFF = 0, 1, 2, 3, 4, 5
 TUNE_ADVEC_U, TUNE_DIFF_UVW, TUNE_STEP, TUNE_PAIR, TUNE_ADVEC_U_2I5, TUNE_DIFF_SMAG, TUNE_ADVEC_DIFF = \
     1, 2, 4, 8, 16, 32, 64
+BATCH_ZERO_TENDENCIES, BATCH_FILL_GHOSTS, BATCH_SUMS = 1, 2, 4
 KERNEL_NAMES = {ADVEC_U: "advec_u", DIFF_UVW: "diff_uvw", STEP: "step", ADVEC_U_2I5: "advec_u_2i5",
                 DIFF_SMAG: "diff_smag", ADVEC_DIFF: "advec_diff"}
 OK, ERR_INVALID, ERR_DEVICE, ERR_NOMEM, ERR_BUDGET, ERR_AGAIN, ERR_NOTFOUND, ERR_IO = 0, -1, -2, -3, -4, -5, -6, -7
@@ -117,6 +118,8 @@ _sig = {
                                 POINTER(c_int32)]),
     "kl_batch_create": (c_int, [_G, POINTER(c_void_p), c_int32, c_double, c_int32, c_void_p,
                                 POINTER(c_void_p)]),
+    "kl_batch_create_ex": (c_int, [_G, POINTER(c_void_p), c_int32, c_double, c_uint32, c_void_p, c_void_p,
+                                   POINTER(c_void_p)]),
     "kl_batch_tune": (c_int, [c_void_p, c_char_p, c_double, c_void_p, c_void_p, c_int32, POINTER(c_int32)]),
     "kl_batch_group": (c_int, [c_void_p, c_int32, POINTER(c_int32), c_char_p, c_size_t, POINTER(c_int64)]),
     "kl_batch_run": (c_int, [c_void_p, c_void_p]),
@@ -362,6 +365,18 @@ def kl_batch_create(grids, fields, visc, zero_tendencies=True, stream=None):
     h = c_void_p()
     _check(_lib.kl_batch_create(arr, flat, n, float(visc), int(bool(zero_tendencies)), _stream(stream),
                                 byref(h)))
+    return h.value
+
+
+def kl_batch_create_ex(grids, fields, visc, flags, sums=None, stream=None):
+    """kl_batch_create with the graph's other steps (BATCH_* flags); sums: a
+    float64 device tensor of 3 * len(grids) values for BATCH_SUMS."""
+    n = len(grids)
+    arr = (kl_grid_t * n)(*[_cg(g) for g in grids])
+    flat = (c_void_p * (6 * n))(*[_ptr(f) for fs in fields for f in fs])
+    h = c_void_p()
+    _check(_lib.kl_batch_create_ex(arr, flat, n, float(visc), int(flags), _ptr(sums),
+                                   _stream(stream), byref(h)))
     return h.value
 
 

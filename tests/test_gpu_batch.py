@@ -173,3 +173,64 @@ def test_batch_tune_records_and_reuses_the_winner(tmp_path):
                 assert np.array_equal(x.cpu().numpy(), y)
     finally:
         m.kl_batch_destroy(b)
+
+
+def test_batch_graph_with_ghost_fill_zeroing_and_sums():
+    """kl_batch_create_ex with every step: [ghost fill] -> [tendencies := 0]
+    -> the fused groups -> [conservation sums].  On every replay (with eager
+    work between replays that undoes what the graph did) u, v, w come out
+    bitwise as kl_fill_ghosts leaves them, the tendencies bitwise those of the
+    single-grid launches on the filled fields, and each grid's sums bitwise
+    those of kl_reduce_fp64(what = 0) on them."""
+    m = kl()
+    dts = [0, 1, 0, 1, 0, 0, 1, 0]
+    bcs = [0, 2, 0, 0, 1, 2, 0, 1]
+    visc = 1e-5
+    grids, ref_f, ref_t, ref_s = [], [], [], []
+    for n, (shape, dt, bc) in enumerate(zip(SHAPES, dts, bcs)):
+        g = m.Grid(*shape, dtype=dt, bc=bc)
+        f = [g.full() for _ in range(3)]  # ghosts left NaN: only the graph's fill sets them
+        m.kl_generate_fields(g, 40 + n, *f)
+        t = [g.zeros_interior(fill=-3.0) for _ in range(3)]
+        rf = [x.clone() for x in f]
+        m.kl_fill_ghosts(g, *rf)
+        rt = [g.zeros_interior(fill=-3.0) for _ in range(3)]
+        m.kl_advec_u(g, rt[0], *rf)
+        m.kl_diff_uvw(g, *rt, *rf, visc)
+        rs = torch.zeros(3, dtype=torch.float64, device="cuda")
+        m.kl_reduce_fp64(g, 0, *rt, rs)
+        grids.append((g, f, t))
+        ref_f.append([x.cpu().numpy() for x in rf])
+        ref_t.append([x.cpu().numpy() for x in rt])
+        ref_s.append(rs.cpu().numpy())
+    sums = torch.full((3 * len(grids),), np.nan, dtype=torch.float64, device="cuda")
+    with pytest.raises(m.KLError):
+        m.kl_batch_create_ex([g for g, _, _ in grids], [f + t for _, f, t in grids], visc, 8)
+    with pytest.raises(m.KLError):
+        m.kl_batch_create_ex([g for g, _, _ in grids], [f + t for _, f, t in grids], visc, m.BATCH_SUMS)
+    flags = m.BATCH_FILL_GHOSTS | m.BATCH_ZERO_TENDENCIES | m.BATCH_SUMS
+    b = m.kl_batch_create_ex([g for g, _, _ in grids], [f + t for _, f, t in grids], visc, flags, sums)
+    try:
+        nk, _ = m.kl_batch_info(b)
+        assert nk >= 4  # fill, zero, at least one fused group, sums
+        for rep in range(3):
+            # undo the previous replay: ghosts back to NaN, tendencies to junk
+            for g, f, t in grids:
+                for x in f:
+                    keep = g.interior(x).clone()
+                    g.box(x).fill_(np.nan)
+                    g.interior(x).copy_(keep)
+                for x in t:
+                    g.interior(x).fill_(7.0)
+            sums.fill_(np.nan)
+            torch.cuda.synchronize()
+            m.kl_batch_run(b)
+            torch.cuda.synchronize()
+            s = sums.cpu().numpy()
+            for n, (g, f, t) in enumerate(grids):
+                for q in range(3):
+                    assert np.array_equal(f[q].cpu().numpy(), ref_f[n][q], equal_nan=True), (rep, n, "field", q)
+                    assert np.array_equal(t[q].cpu().numpy(), ref_t[n][q], equal_nan=True), (rep, n, "tendency", q)
+                assert np.array_equal(s[3 * n:3 * n + 3], ref_s[n]), (rep, n, s[3 * n:3 * n + 3], ref_s[n])
+    finally:
+        m.kl_batch_destroy(b)
