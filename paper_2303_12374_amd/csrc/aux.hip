@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <mutex>
 
 #include "kl_internal.hpp"
@@ -61,41 +62,46 @@ __device__ __forceinline__ int src_k(const Dims &d, int f, int k, int &sign)
 // w in wall modes).  Every source cell is an interior cell that no thread
 // writes, so the cells can be filled in any order.  kind[f] is the z rule
 // of field f (0 and 1: the u/v rule, 2: the w rule); a NULL field is skipped.
+// The cell index math is 32-bit: the launchers refuse grids with 2^32 or
+// more ghost cells (64-bit divisions cost tens of instructions each).
 template <typename T>
-__device__ __forceinline__ void fill_cell(const Dims &d, T *u, T *v, T *w, int k0, int k1, int k2, int64_t n0,
-                                          int64_t n1, int64_t n2, int64_t n3, int64_t t)
+__device__ __forceinline__ void fill_cell(const Dims &d, T *u, T *v, T *w, int k0, int k1, int k2, int64_t n0_,
+                                          int64_t n1_, int64_t n2_, int64_t n3_, int64_t t_)
 {
+    const uint32_t n0 = (uint32_t)n0_, n01 = (uint32_t)(n0_ + n1_), n012 = (uint32_t)(n0_ + n1_ + n2_),
+                   nall = (uint32_t)(n0_ + n1_ + n2_ + n3_);
+    if (t_ >= (int64_t)nall) return;
+    const uint32_t t = (uint32_t)t_;
     const int gc = d.gc;
-    const int ic = d.itot + 2 * gc, jc = d.jtot + 2 * gc;
+    const uint32_t ic = (uint32_t)(d.itot + 2 * gc), plane = ic * (uint32_t)(d.jtot + 2 * gc);
+    const uint32_t g2 = 2u * (uint32_t)gc;
     int i, j, k;
     bool w_only = false;
     if (t < n0) {
-        const int64_t p = t % ((int64_t)ic * jc);
-        k = t < (int64_t)ic * jc ? 0 : d.ktot + 1;
+        const uint32_t p = t < plane ? t : t - plane;
+        k = t < plane ? 0 : d.ktot + 1;
         j = (int)(p / ic) + 1 - gc;
         i = (int)(p % ic) + 1 - gc;
-    } else if (t < n0 + n1) {
-        const int64_t q = t - n0;
-        const int64_t r = q / ic;  // ghost row index over (level, row)
+    } else if (t < n01) {
+        const uint32_t q = t - n0;
+        const uint32_t r = q / ic;  // ghost row index over (level, row)
         i = (int)(q % ic) + 1 - gc;
-        k = 1 + (int)(r / (2 * gc));
-        const int jr = (int)(r % (2 * gc));
+        k = 1 + (int)(r / g2);
+        const int jr = (int)(r % g2);
         j = jr < gc ? 1 - gc + jr : d.jtot + 1 + (jr - gc);
-    } else if (t < n0 + n1 + n2) {
-        const int64_t q = t - n0 - n1;
-        const int c = (int)(q % (2 * gc));
-        const int64_t rest = q / (2 * gc);
-        j = 1 + (int)(rest % d.jtot);
-        k = 1 + (int)(rest / d.jtot);
+    } else if (t < n012) {
+        const uint32_t q = t - n01;
+        const int c = (int)(q % g2);
+        const uint32_t rest = q / g2;
+        j = 1 + (int)(rest % (uint32_t)d.jtot);
+        k = 1 + (int)(rest / (uint32_t)d.jtot);
         i = c < gc ? 1 - gc + c : d.itot + 1 + (c - gc);
-    } else if (t < n0 + n1 + n2 + n3) {
-        const int64_t q = t - n0 - n1 - n2;
-        k = 1;
-        j = 1 + (int)(q / d.itot);
-        i = 1 + (int)(q % d.itot);
-        w_only = true;
     } else {
-        return;
+        const uint32_t q = t - n012;
+        k = 1;
+        j = 1 + (int)(q / (uint32_t)d.itot);
+        i = 1 + (int)(q % (uint32_t)d.itot);
+        w_only = true;
     }
     const int si = wrap_i(d, i), sj = wrap_j(d, j);
     const int64_t dst = at(d, i, j, k);
@@ -330,8 +336,10 @@ __device__ __forceinline__ void reduce_block(const Dims &d, int what, int kw0, c
     if (slot < rpp) {
         int64_t r = (int64_t)b + (int64_t)slot * RB;
         for (; r + rstep < nrows; r += 2 * rstep) {
-            const int ja = 1 + (int)(r % d.jtot), ka = 1 + (int)(r / d.jtot);
-            const int jb = 1 + (int)((r + rstep) % d.jtot), kb = 1 + (int)((r + rstep) / d.jtot);
+            // 32-bit row arithmetic (the launchers refuse 2^31 or more rows)
+            const uint32_t ra = (uint32_t)r, rb = (uint32_t)(r + rstep), jt = (uint32_t)d.jtot;
+            const int ja = 1 + (int)(ra % jt), ka = 1 + (int)(ra / jt);
+            const int jb = 1 + (int)(rb % jt), kb = 1 + (int)(rb / jt);
             for (int c = c0; c < cpr; c += cstep) {
                 T xa[3][V], xb[3][V];
                 load(xa, at(d, 1 + c * V, ja, ka));
@@ -341,7 +349,8 @@ __device__ __forceinline__ void reduce_block(const Dims &d, int what, int kw0, c
             }
         }
         if (r < nrows) {
-            const int j = 1 + (int)(r % d.jtot), k = 1 + (int)(r / d.jtot);
+            const uint32_t ru = (uint32_t)r, jt = (uint32_t)d.jtot;
+            const int j = 1 + (int)(ru % jt), k = 1 + (int)(ru / jt);
             for (int c = c0; c < cpr; c += cstep) {
                 T x[3][V];
                 load(x, at(d, 1 + c * V, j, k));
@@ -386,10 +395,13 @@ __global__ __launch_bounds__(RT) void reduce_pass2(int what, const double *parti
 }
 
 // Conservation sums (what = 0) of many grids in two launches: pass-1 block
-// blockIdx.x is block blockIdx.x % RB of job blockIdx.x / RB, into that job's
-// own RB partials; pass 2 reduces each slot's partials in one block.  Per
-// grid the blocks, their rows and the trees are those of the single-grid
-// reduction, so each grid's sums are bitwise those of kl_reduce_fp64.
+// blockIdx.x is block b of job g, (g, b) = blocks[blockIdx.x], into that
+// job's own RB partials; pass 2 reduces each slot's partials in one block.
+// Per grid the blocks, their rows and the trees are those of the single-grid
+// reduction, so each grid's sums are bitwise those of kl_reduce_fp64.  Only
+// blocks that own rows (b < jtot*ktot) are launched: a block without rows
+// gives the partial +0.0, which the partials hold from their allocation, and
+// adding +0.0 changes no sum that pass 2 forms (its sums start at +0.0).
 struct SumJob {
     Dims d;
     int kw0, slot;
@@ -397,12 +409,14 @@ struct SumJob {
 };
 
 template <typename T, int V>
-__global__ __launch_bounds__(RT) void sums_batch_pass1(const SumJob *__restrict__ jobs, double *partials)
+__global__ __launch_bounds__(RT) void sums_batch_pass1(const SumJob *__restrict__ jobs,
+                                                      const int2 *__restrict__ blocks, double *partials)
 {
-    const SumJob j = jobs[blockIdx.x / RB];
+    const int2 gb = blocks[blockIdx.x];
+    const SumJob j = jobs[gb.x];
     reduce_block<T, V>(j.d, 0, j.kw0, as_global((const T *)j.f0), as_global((const T *)j.f1),
                        as_global((const T *)j.f2), as_global((const T *)j.dzi), as_global((const T *)j.dzhi),
-                       (int)(blockIdx.x % RB), partials + (int64_t)j.slot * RB * RQ);
+                       gb.y, partials + (int64_t)j.slot * RB * RQ);
 }
 
 __global__ __launch_bounds__(RT) void sums_batch_pass2(const double *partials, double *out)
@@ -508,6 +522,7 @@ hipError_t fill_launch(const HostArgs &a, void *u, void *v, void *w, int k0, int
     const int64_t ic = a.itot + 2 * gc, jc = a.jtot + 2 * gc;
     const int64_t n0 = 2 * ic * jc, n1 = 2 * gc * ic * a.ktot, n2 = 2 * gc * (int64_t)a.jtot * a.ktot;
     const int64_t n3 = (w_faces && a.bc != KL_BC_ZPERIODIC) ? (int64_t)a.itot * a.jtot : 0;
+    if (n0 + n1 + n2 + n3 >= ((int64_t)1 << 32)) return hipErrorInvalidValue;  // 32-bit cell index
     const unsigned nb = cdiv(n0 + n1 + n2 + n3, 256);
     if (a.dtype == KL_F32)
         hipLaunchKernelGGL(fill_ghosts_kernel<float>, dim3(nb), dim3(256), 0, s, d, (float *)u, (float *)v,
@@ -575,6 +590,7 @@ hipError_t launch_reduce(const HostArgs &a, int what, const void *f0, const void
 {
     const Dims d = dims_of(a);
     double *partial = (double *)scratch;
+    if ((int64_t)a.jtot * a.ktot >= ((int64_t)1 << 31)) return hipErrorInvalidValue;  // 32-bit row index
     const bool vec = reduce_vectorized(a, f0, f1, f2);
     if (a.dtype == KL_F32) {
         if (vec)
@@ -604,6 +620,14 @@ hipError_t launch_reduce(const HostArgs &a, int what, const void *f0, const void
 // ---- batched ghost fill and conservation sums (used by the batched form) ----
 
 size_t fill_job_bytes() { return sizeof(FillJob); }
+
+int64_t fill_cell_count(const HostArgs &a)
+{
+    const int64_t gc = a.gc;
+    const int64_t ic = a.itot + 2 * gc, jc = a.jtot + 2 * gc;
+    return 2 * ic * jc + 2 * gc * ic * a.ktot + 2 * gc * (int64_t)a.jtot * a.ktot +
+           (a.bc != KL_BC_ZPERIODIC ? (int64_t)a.itot * a.jtot : 0);
+}
 
 void append_fill_job(const HostArgs &a, void *u, void *v, void *w, std::vector<char> &jobs,
                      std::vector<int2> &blocks)
@@ -642,8 +666,12 @@ size_t sum_job_bytes() { return sizeof(SumJob); }
 
 size_t sums_partial_bytes(int nslots) { return (size_t)nslots * RB * RQ * sizeof(double); }
 
-void append_sum_job(const HostArgs &a, const void *ut, const void *vt, const void *wt, int slot, std::vector<char> &jobs)
+void append_sum_job(const HostArgs &a, const void *ut, const void *vt, const void *wt, int slot, std::vector<char> &jobs,
+                    std::vector<int2> &blocks)
 {
+    const int job = (int)(jobs.size() / sizeof(SumJob));
+    const int64_t nb = std::min<int64_t>(RB, (int64_t)a.jtot * a.ktot);
+    for (int b = 0; b < (int)nb; ++b) blocks.push_back(make_int2(job, b));
     SumJob j;
     j.d = dims_of(a);
     j.kw0 = a.kw0;
@@ -657,21 +685,23 @@ void append_sum_job(const HostArgs &a, const void *ut, const void *vt, const voi
     jobs.insert(jobs.end(), p, p + sizeof j);
 }
 
-hipError_t launch_sums_batch(int dtype, bool vec, const void *jobs, int njobs, double *partials, hipStream_t s)
+hipError_t launch_sums_batch(int dtype, bool vec, const void *jobs, const void *blocks, int nblocks, double *partials,
+                             hipStream_t s)
 {
-    if (njobs <= 0) return hipSuccess;
-    const dim3 grid((unsigned)njobs * RB);
+    if (nblocks <= 0) return hipSuccess;
+    const dim3 grid((unsigned)nblocks);
     const SumJob *j = (const SumJob *)jobs;
+    const int2 *bl = (const int2 *)blocks;
     if (dtype == KL_F32) {
         if (vec)
-            hipLaunchKernelGGL((sums_batch_pass1<float, 4>), grid, dim3(RT), 0, s, j, partials);
+            hipLaunchKernelGGL((sums_batch_pass1<float, 4>), grid, dim3(RT), 0, s, j, bl, partials);
         else
-            hipLaunchKernelGGL((sums_batch_pass1<float, 1>), grid, dim3(RT), 0, s, j, partials);
+            hipLaunchKernelGGL((sums_batch_pass1<float, 1>), grid, dim3(RT), 0, s, j, bl, partials);
     } else {
         if (vec)
-            hipLaunchKernelGGL((sums_batch_pass1<double, 2>), grid, dim3(RT), 0, s, j, partials);
+            hipLaunchKernelGGL((sums_batch_pass1<double, 2>), grid, dim3(RT), 0, s, j, bl, partials);
         else
-            hipLaunchKernelGGL((sums_batch_pass1<double, 1>), grid, dim3(RT), 0, s, j, partials);
+            hipLaunchKernelGGL((sums_batch_pass1<double, 1>), grid, dim3(RT), 0, s, j, bl, partials);
     }
     return hipGetLastError();
 }

@@ -68,9 +68,11 @@ struct Batch {
     // ghost fill jobs and their blocks, per dtype
     void *d_fjobs[2] = {nullptr, nullptr}, *d_fblocks[2] = {nullptr, nullptr};
     int nfblocks[2] = {0, 0};
-    // conservation-sum jobs per dtype and vector width, and their partials
+    // conservation-sum jobs per dtype and vector width, their pass-1 blocks, and the partials
     void *d_sjobs[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    void *d_sblocks[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     int nsjobs[2][2] = {{0, 0}, {0, 0}};
+    int nsblocks[2][2] = {{0, 0}, {0, 0}};
     double *d_partials = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -97,12 +99,14 @@ struct Batch {
             if (g.d_queue) (void)hipFree(g.d_queue);
         }
         for (int d = 0; d < 2; ++d) {
-            for (void **p : {&d_fjobs[d], &d_fblocks[d], &d_sjobs[d][0], &d_sjobs[d][1]}) {
+            for (void **p : {&d_fjobs[d], &d_fblocks[d], &d_sjobs[d][0], &d_sjobs[d][1], &d_sblocks[d][0],
+                             &d_sblocks[d][1]}) {
                 if (*p) (void)hipFree(*p);
                 *p = nullptr;
             }
             nfblocks[d] = 0;
             nsjobs[d][0] = nsjobs[d][1] = 0;
+            nsblocks[d][0] = nsblocks[d][1] = 0;
         }
         if (d_partials) (void)hipFree(d_partials);
         d_partials = nullptr;
@@ -408,22 +412,32 @@ int build(Batch &b, void *const *fields)
     }
     if (b.flags & KL_BATCH_SUMS) {
         std::vector<char> jobs[2][2];
+        std::vector<int2> blocks[2][2];
         for (size_t n = 0; n < b.grids.size(); ++n) {
             const kl_grid_t *g = &b.grids[n];
             const HostArgs a = make_args(g);
             void *const *f = fields + 6 * n;
             const int vec = reduce_vectorized(a, f[3], f[4], f[5]) ? 1 : 0;
-            append_sum_job(a, f[3], f[4], f[5], (int)n, jobs[g->dtype][vec]);
+            append_sum_job(a, f[3], f[4], f[5], (int)n, jobs[g->dtype][vec], blocks[g->dtype][vec]);
             ++b.nsjobs[g->dtype][vec];
         }
         for (int d = 0; d < 2; ++d)
-            for (int v = 0; v < 2; ++v)
-                if (b.nsjobs[d][v] &&
-                    (e = upload(&b.d_sjobs[d][v], jobs[d][v].data(), jobs[d][v].size())) != hipSuccess)
+            for (int v = 0; v < 2; ++v) {
+                if (!b.nsjobs[d][v]) continue;
+                if ((e = upload(&b.d_sjobs[d][v], jobs[d][v].data(), jobs[d][v].size())) != hipSuccess ||
+                    (e = upload(&b.d_sblocks[d][v], blocks[d][v].data(), blocks[d][v].size() * sizeof(int2))) !=
+                        hipSuccess)
                     return hip_fail(e, "sum jobs");
-        if ((e = hipMalloc((void **)&b.d_partials, sums_partial_bytes((int)b.grids.size()))) != hipSuccess)
-            return hip_fail(e, "sum partials");
+                b.nsblocks[d][v] = (int)blocks[d][v].size();
+            }
+        // the partials of blocks that own no rows stay +0.0 (they are never launched)
+        const size_t pb = sums_partial_bytes((int)b.grids.size());
+        if ((e = hipMalloc((void **)&b.d_partials, pb)) != hipSuccess) return hip_fail(e, "sum partials");
+        if ((e = hipMemset(b.d_partials, 0, pb)) != hipSuccess) return hip_fail(e, "sum partials");
     }
+    // the queue and partial-buffer clears above ran on the null stream: let
+    // them finish before any replay can start on another stream
+    if ((e = hipStreamSynchronize(nullptr)) != hipSuccess) return hip_fail(e, "batch set-up");
     // capture the graph on a private stream
     hipStream_t cs;
     if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
@@ -453,7 +467,8 @@ int build(Batch &b, void *const *fields)
         for (int d = 0; d < 2 && rc == KL_OK; ++d)
             for (int v = 0; v < 2 && rc == KL_OK; ++v) {
                 if (!b.nsjobs[d][v]) continue;
-                e = launch_sums_batch(d, v != 0, b.d_sjobs[d][v], b.nsjobs[d][v], b.d_partials, cs);
+                e = launch_sums_batch(d, v != 0, b.d_sjobs[d][v], b.d_sblocks[d][v], b.nsblocks[d][v], b.d_partials,
+                                      cs);
                 if (e != hipSuccess) rc = hip_fail(e, "sums launch");
                 ++b.nkernels;
             }
@@ -504,6 +519,10 @@ int kl_batch_create_ex(const kl_grid_t *grids, void *const *fields, int32_t n, d
         if (rc) return fail(rc, "grid %d: %s", i, kl_last_error());
         for (int f = 0; f < 6; ++f)
             if (!fields[6 * i + f]) return fail(KL_ERR_INVALID, "grid %d field %d is NULL", i, f);
+        if ((flags & KL_BATCH_FILL_GHOSTS) && fill_cell_count(make_args(&grids[i])) >= ((int64_t)1 << 32))
+            return fail(KL_ERR_INVALID, "grid %d: 2^32 or more ghost cells", i);
+        if ((flags & KL_BATCH_SUMS) && (int64_t)grids[i].jtot * grids[i].ktot >= ((int64_t)1 << 31))
+            return fail(KL_ERR_INVALID, "grid %d: 2^31 or more rows to sum", i);
     }
     Batch *b = new (std::nothrow) Batch();
     if (!b) return fail(KL_ERR_NOMEM, "batch");

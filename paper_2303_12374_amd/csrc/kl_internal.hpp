@@ -96,15 +96,19 @@ bool reduce_vectorized(const HostArgs &a, const void *f0, const void *f1, const 
 // Batched ghost fill of u, v, w (one job per grid: append_fill_job adds the
 // job and its 256-cell blocks {job, block}) and batched conservation sums
 // (one job per grid, written to out[3 slot ..]; jobs of one launch share a
-// dtype and reduce_vectorized; partials: sums_partial_bytes(slots) bytes).
+// dtype and reduce_vectorized; their pass-1 blocks {job, block} are those
+// that own rows; partials: sums_partial_bytes(slots) bytes, zeroed once).
 size_t fill_job_bytes();
+int64_t fill_cell_count(const HostArgs &a);  // ghost cells of the velocity fill (must be < 2^32)
 void append_fill_job(const HostArgs &a, void *u, void *v, void *w, std::vector<char> &jobs,
                      std::vector<int2> &blocks);
 hipError_t launch_fill_batch(int dtype, const void *jobs, const void *blocks, int nblocks, hipStream_t s);
 size_t sum_job_bytes();
 size_t sums_partial_bytes(int nslots);
-void append_sum_job(const HostArgs &a, const void *ut, const void *vt, const void *wt, int slot, std::vector<char> &jobs);
-hipError_t launch_sums_batch(int dtype, bool vec, const void *jobs, int njobs, double *partials, hipStream_t s);
+void append_sum_job(const HostArgs &a, const void *ut, const void *vt, const void *wt, int slot, std::vector<char> &jobs,
+                    std::vector<int2> &blocks);
+hipError_t launch_sums_batch(int dtype, bool vec, const void *jobs, const void *blocks, int nblocks, double *partials,
+                             hipStream_t s);
 hipError_t launch_sums_finish(const double *partials, int nslots, double *out, hipStream_t s);
 // Batched row-tile kernels: descs = StencilArgs<T>[], tiles = int4 {grid, row0, row1, 0}[].
 hipError_t launch_zero_batch(int dtype, const void *descs, const void *tiles, int ntiles, int nblocks,
