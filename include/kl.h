@@ -219,9 +219,11 @@ int kl_euler(const kl_grid_t *g, double dt, void *u, void *v, void *w,
 int kl_step(const kl_grid_t *g, double visc, double dt, void *u, void *v, void *w,
             void *ut, void *vt, void *wt, void *stream);
 
-/* One time step fused into a single kernel: reads u, v, w (ghost-filled, not
- * modified) and writes the next state into u_out, v_out, w_out, ghost cells
- * included.  The arithmetic and its order are those of kl_step (tendencies
+/* One time step fused into a single pass over the grid: reads u, v, w
+ * (ghost-filled, not modified) and writes the next state into u_out, v_out,
+ * w_out, ghost cells included (some configurations store the y and z ghost
+ * cells with a second, small kernel that copies them from the new values).
+ * The arithmetic and its order are those of kl_step (tendencies
  * zeroed, advec_u, diff_uvw, forward Euler, ghost refill), so the result is
  * bitwise identical to kl_step's, while the kernel moves 6 values per point
  * instead of 26.  Inputs and outputs must not overlap; the outputs' padding

@@ -64,9 +64,11 @@ __device__ __forceinline__ int src_k(const Dims &d, int f, int k, int &sign)
 // of field f (0 and 1: the u/v rule, 2: the w rule); a NULL field is skipped.
 // The cell index math is 32-bit: the launchers refuse grids with 2^32 or
 // more ghost cells (64-bit divisions cost tens of instructions each).
+// r3_wide: region R3 spans the x ghost columns of plane k = 1 too (for a
+// refill that skips R2, whose columns at k = 1 belong to w's wall plane).
 template <typename T>
 __device__ __forceinline__ void fill_cell(const Dims &d, T *u, T *v, T *w, int k0, int k1, int k2, int64_t n0_,
-                                          int64_t n1_, int64_t n2_, int64_t n3_, int64_t t_)
+                                          int64_t n1_, int64_t n2_, int64_t n3_, int64_t t_, bool r3_wide = false)
 {
     const uint32_t n0 = (uint32_t)n0_, n01 = (uint32_t)(n0_ + n1_), n012 = (uint32_t)(n0_ + n1_ + n2_),
                    nall = (uint32_t)(n0_ + n1_ + n2_ + n3_);
@@ -98,9 +100,10 @@ __device__ __forceinline__ void fill_cell(const Dims &d, T *u, T *v, T *w, int k
         i = c < gc ? 1 - gc + c : d.itot + 1 + (c - gc);
     } else {
         const uint32_t q = t - n012;
+        const uint32_t rw = r3_wide ? ic : (uint32_t)d.itot;
         k = 1;
-        j = 1 + (int)(q / (uint32_t)d.itot);
-        i = 1 + (int)(q % (uint32_t)d.itot);
+        j = 1 + (int)(q / rw);
+        i = 1 + (int)(q % rw) - (r3_wide ? gc : 0);
         w_only = true;
     }
     const int si = wrap_i(d, i), sj = wrap_j(d, j);
@@ -119,9 +122,10 @@ __device__ __forceinline__ void fill_cell(const Dims &d, T *u, T *v, T *w, int k
 
 template <typename T>
 __global__ __launch_bounds__(256) void fill_ghosts_kernel(Dims d, T *u, T *v, T *w, int k0, int k1, int k2,
-                                                         int64_t n0, int64_t n1, int64_t n2, int64_t n3)
+                                                         int64_t n0, int64_t n1, int64_t n2, int64_t n3,
+                                                         bool r3_wide)
 {
-    fill_cell<T>(d, u, v, w, k0, k1, k2, n0, n1, n2, n3, (int64_t)blockIdx.x * 256 + threadIdx.x);
+    fill_cell<T>(d, u, v, w, k0, k1, k2, n0, n1, n2, n3, (int64_t)blockIdx.x * 256 + threadIdx.x, r3_wide);
 }
 
 // Ghost fill of the velocity fields of many grids in one launch: block b
@@ -515,21 +519,23 @@ size_t reduce_scratch_bytes() { return (size_t)RB * RQ * sizeof(double); }
 
 namespace {
 hipError_t fill_launch(const HostArgs &a, void *u, void *v, void *w, int k0, int k1, int k2, bool w_faces,
-                       hipStream_t s)
+                       hipStream_t s, bool x_columns = true)
 {
     const Dims d = dims_of(a);
     const int64_t gc = a.gc;
     const int64_t ic = a.itot + 2 * gc, jc = a.jtot + 2 * gc;
-    const int64_t n0 = 2 * ic * jc, n1 = 2 * gc * ic * a.ktot, n2 = 2 * gc * (int64_t)a.jtot * a.ktot;
-    const int64_t n3 = (w_faces && a.bc != KL_BC_ZPERIODIC) ? (int64_t)a.itot * a.jtot : 0;
+    const int64_t n0 = 2 * ic * jc, n1 = 2 * gc * ic * a.ktot;
+    const int64_t n2 = x_columns ? 2 * gc * (int64_t)a.jtot * a.ktot : 0;  // region R2 (x ghost columns)
+    // R3 (w's plane k = 1 in wall modes) with its x ghost columns when R2 is skipped
+    const int64_t n3 = (w_faces && a.bc != KL_BC_ZPERIODIC) ? (x_columns ? a.itot : ic) * (int64_t)a.jtot : 0;
     if (n0 + n1 + n2 + n3 >= ((int64_t)1 << 32)) return hipErrorInvalidValue;  // 32-bit cell index
     const unsigned nb = cdiv(n0 + n1 + n2 + n3, 256);
     if (a.dtype == KL_F32)
         hipLaunchKernelGGL(fill_ghosts_kernel<float>, dim3(nb), dim3(256), 0, s, d, (float *)u, (float *)v,
-                           (float *)w, k0, k1, k2, n0, n1, n2, n3);
+                           (float *)w, k0, k1, k2, n0, n1, n2, n3, !x_columns);
     else
         hipLaunchKernelGGL(fill_ghosts_kernel<double>, dim3(nb), dim3(256), 0, s, d, (double *)u,
-                           (double *)v, (double *)w, k0, k1, k2, n0, n1, n2, n3);
+                           (double *)v, (double *)w, k0, k1, k2, n0, n1, n2, n3, !x_columns);
     return hipGetLastError();
 }
 }  // namespace
@@ -537,6 +543,11 @@ hipError_t fill_launch(const HostArgs &a, void *u, void *v, void *w, int k0, int
 hipError_t launch_fill_ghosts(const HostArgs &a, void *u, void *v, void *w, hipStream_t s)
 {
     return fill_launch(a, u, v, w, 0, 1, 2, true, s);
+}
+
+hipError_t launch_fill_yz_images(const HostArgs &a, void *u, void *v, void *w, hipStream_t s)
+{
+    return fill_launch(a, u, v, w, 0, 1, 2, true, s, false);
 }
 
 hipError_t launch_fill_scalar(const HostArgs &a, void *f, hipStream_t s)

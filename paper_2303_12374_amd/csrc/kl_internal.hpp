@@ -83,6 +83,10 @@ void *workspace(size_t bytes, hipStream_t s);
 // Auxiliary kernels (aux.hip).
 hipError_t launch_fill_ghosts(const HostArgs &a, void *u, void *v, void *w, hipStream_t s);
 hipError_t launch_fill_scalar(const HostArgs &a, void *f, hipStream_t s);
+// The y and z ghost cells of u, v, w from their interior (the ghost fill
+// without the x ghost columns of interior rows): after a step that stored
+// the new values and their x images only.
+hipError_t launch_fill_yz_images(const HostArgs &a, void *u, void *v, void *w, hipStream_t s);
 hipError_t launch_euler(const HostArgs &a, double dt, void *u, void *v, void *w, hipStream_t s);
 hipError_t launch_zero_interior(const HostArgs &a, void *f, hipStream_t s);
 hipError_t launch_reduce(const HostArgs &a, int what, const void *f0, const void *f1,

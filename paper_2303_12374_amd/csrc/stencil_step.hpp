@@ -22,6 +22,18 @@
 
 namespace kl {
 
+// Store a VX-vector of new values at (i0.., j, k) and at its x images (the
+// ghost columns 0 and itot+1 of the same row, periodic x).
+template <typename T, int VX, int NT>
+__device__ __forceinline__ void put_with_x_images(T *f, const StencilArgs<T> &a, int i0, int j, int k,
+                                                  const T (&val)[VX])
+{
+    const int64_t base = a.off + (int64_t)j * a.js + (int64_t)k * a.ks;
+    tstore<NT, T, VX>(f + base + i0, val);
+    if (i0 == 1) f[base + a.itot + 1] = val[0];
+    if (i0 + VX - 1 == a.itot) f[base] = val[VX - 1];
+}
+
 // Store a VX-vector of new values at (i0.., j, k) of field `fld` and at all
 // ghost cells whose source it is (periodic x and y; z by the boundary rule).
 // The point itself and its x images are stored on every row; the y and z
@@ -86,8 +98,13 @@ __device__ __forceinline__ void put_with_images(T *f, const StencilArgs<T> &a, i
 // MODE: FUSE_STEP or FUSE_PAIR, plus FUSE_HALO3 to load the halo rows as far
 // ahead as the field ring (three levels for the 4-slot ring, two for the
 // 6-slot one) instead of one, plus FUSE_RING6 for a 6-slot field ring (own
-// rows loaded five levels ahead instead of three).
-enum { FUSE_STEP = 0, FUSE_PAIR = 1, FUSE_HALO3 = 2, FUSE_RING6 = 4 };
+// rows loaded five levels ahead instead of three), plus FUSE_NOYZ (step
+// only): the kernel stores the new values and their x images only, and the
+// launcher refills the y and z ghost cells afterwards with the ghost fill's
+// copies (the same values: every image is a copy, a negation or a zero of a
+// new value), which keeps the slow path of the first and last rows and
+// levels out of the level loop.
+enum { FUSE_STEP = 0, FUSE_PAIR = 1, FUSE_HALO3 = 2, FUSE_RING6 = 4, FUSE_NOYZ = 8 };
 
 template <typename T, int VX, int BY, int KB, int NT, int MODE = FUSE_STEP>
 __device__ __forceinline__ void step_zl_tile(const StencilArgs<T> &a, int tx, int ty, int tz)
@@ -257,9 +274,15 @@ __device__ __forceinline__ void step_zl_tile(const StencilArgs<T> &a, int tx, in
                         tstore<NT, T, VX>(O[1] + o, nv);
                         if (k >= kw0) tstore<NT, T, VX>(O[2] + o, nw);
                     } else {
-                        put_with_images<T, VX, NT>(O[0], a, 0, t.i0, j, k, nu);
-                        put_with_images<T, VX, NT>(O[1], a, 1, t.i0, j, k, nv);
-                        if (k >= kw0) put_with_images<T, VX, NT>(O[2], a, 2, t.i0, j, k, nw);
+                        if constexpr ((MODE & FUSE_NOYZ) != 0) {
+                            put_with_x_images<T, VX, NT>(O[0], a, t.i0, j, k, nu);
+                            put_with_x_images<T, VX, NT>(O[1], a, t.i0, j, k, nv);
+                            if (k >= kw0) put_with_x_images<T, VX, NT>(O[2], a, t.i0, j, k, nw);
+                        } else {
+                            put_with_images<T, VX, NT>(O[0], a, 0, t.i0, j, k, nu);
+                            put_with_images<T, VX, NT>(O[1], a, 1, t.i0, j, k, nv);
+                            if (k >= kw0) put_with_images<T, VX, NT>(O[2], a, 2, t.i0, j, k, nw);
+                        }
                     }
                 }
             }

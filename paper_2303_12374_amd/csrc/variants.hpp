@@ -133,7 +133,9 @@ hipError_t launch_step(const HostArgs &h, hipStream_t s)
     const uint64_t nb = (uint64_t)a.nbx * a.nby * a.nbz;
     if (!grid_fits(nb, 64 * BY)) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL((step_zl<T, VX, BY, KB, XCD, NT, WPE, MODE>), dim3((unsigned)nb), dim3(64, BY), 0, s, a);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && (MODE & FUSE_NOYZ)) e = launch_fill_yz_images(h, h.ut, h.vt, h.wt, s);
+    return e;
 }
 
 template <typename T, int VX, int BY, int KB, int NT = 0, int WPE = 1, int MODE = FUSE_STEP>
@@ -283,6 +285,14 @@ hipError_t launch_smag_zl(const HostArgs &h, hipStream_t s)
             "_w" KL_STR(WPE) TAG,                                                                        \
             KL_KERNEL_STEP, DT, FAMILY_ZL, VX, 64, BY, KB, XCD, &launch_step<T, VX, BY, KB, XCD, NT, WPE, MODE>, \
             &launch_step_batch<T, VX, BY, KB, NT, WPE, MODE>, &step_batch_occupancy<T, VX, BY, KB, NT, WPE, MODE>}
+
+// A fused step whose y and z ghost cells are refilled by a second kernel
+// (FUSE_NOYZ); no persistent form, so batched and served ticks never use it.
+#define KL_STY(T, DT, VX, BY, KB, XCD, NT, MODE, TAG)                                                    \
+    Variant{"step_v" KL_STR(VX) "_b64x" KL_STR(BY) "_k" KL_STR(KB) "_x" KL_STR(XCD) "_nt" KL_STR(NT)     \
+            "_w1" TAG,                                                                                   \
+            KL_KERNEL_STEP, DT, FAMILY_ZL, VX, 64, BY, KB, XCD, &launch_step<T, VX, BY, KB, XCD, NT, 1, (MODE) | FUSE_NOYZ>, \
+            nullptr, nullptr}
 
 #define KL_ST_SET(T, DT, VX)                                                                             \
     KL_ST(T, DT, VX, 8, 32, 0, 0), KL_ST(T, DT, VX, 4, 64, 2, 1), KL_ST(T, DT, VX, 8, 32, 2, 1),         \
