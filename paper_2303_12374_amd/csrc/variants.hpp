@@ -287,12 +287,14 @@ hipError_t launch_smag_zl(const HostArgs &h, hipStream_t s)
             &launch_step_batch<T, VX, BY, KB, NT, WPE, MODE>, &step_batch_occupancy<T, VX, BY, KB, NT, WPE, MODE>}
 
 // A fused step whose y and z ghost cells are refilled by a second kernel
-// (FUSE_NOYZ); no persistent form, so batched and served ticks never use it.
+// (FUSE_NOYZ).  Its persistent form (served ticks) is the same tile writing
+// those ghost cells itself, which gives the same bits without a refill
+// launch per tick.
 #define KL_STY(T, DT, VX, BY, KB, XCD, NT, MODE, TAG)                                                    \
     Variant{"step_v" KL_STR(VX) "_b64x" KL_STR(BY) "_k" KL_STR(KB) "_x" KL_STR(XCD) "_nt" KL_STR(NT)     \
             "_w1" TAG,                                                                                   \
             KL_KERNEL_STEP, DT, FAMILY_ZL, VX, 64, BY, KB, XCD, &launch_step<T, VX, BY, KB, XCD, NT, 1, (MODE) | FUSE_NOYZ>, \
-            nullptr, nullptr}
+            &launch_step_batch<T, VX, BY, KB, NT, 1, MODE>, &step_batch_occupancy<T, VX, BY, KB, NT, 1, MODE>}
 
 #define KL_ST_SET(T, DT, VX)                                                                             \
     KL_ST(T, DT, VX, 8, 32, 0, 0), KL_ST(T, DT, VX, 4, 64, 2, 1), KL_ST(T, DT, VX, 8, 32, 2, 1),         \

@@ -112,7 +112,10 @@ def zgrid(ktot: int, Lz: float, gamma: float = 1.5) -> dict:
     if gamma == 0.0:
         z[1:ktot + 1] = (k - 0.5) * (Lz / ktot)
     else:
-        z[1:ktot + 1] = Lz * (1.0 - np.tanh(gamma * (1.0 - (k - 0.5) / ktot)) / math.tanh(gamma))
+        # the C library's tanh, one level at a time: numpy's vector tanh can
+        # differ from it in the last bit, and the served form computes the
+        # same grid in C
+        z[1:ktot + 1] = [Lz * (1.0 - math.tanh(gamma * (1.0 - (kk - 0.5) / ktot)) / math.tanh(gamma)) for kk in k]
     z[0] = -z[1]
     z[ktot + 1] = 2.0 * Lz - z[ktot]
     zh = np.zeros(kc)

@@ -1,6 +1,7 @@
 """Served form: continuous batching of stencil-step requests.  Each result
 matches the CPU oracle, is bitwise the same alone and in a mix, and
 admission respects the memory budget."""
+import json
 import time
 
 import numpy as np
@@ -222,3 +223,45 @@ def test_budget_admission_and_errors():
         assert e.value.code == m.ERR_NOTFOUND
     finally:
         S.close()
+
+
+@pytest.mark.parametrize("dtype,shape,bc", [(0, (256, 20, 40), 0), (1, (128, 20, 40), 1)])
+def test_every_step_configuration_served_bitwise(tmp_path, dtype, shape, bc):
+    """Each fused-step configuration, forced by a wisdom record for the
+    request's shape, serves a request (ragged y and z tiles) bitwise equal to
+    kl_step on its own grid; a configuration without a persistent form falls
+    back to one sized to the grid, which must agree just the same."""
+    m = kl()
+    itot, jtot, ktot = shape
+    nsteps, dt, visc, seed = 2, 1e-3, 1e-5, 21
+    g = m.Grid(itot, jtot, ktot, dtype=dtype, bc=bc)
+    f = [g.full() for _ in range(3)]
+    m.kl_generate_fields(g, seed, *f)
+    m.kl_fill_ghosts(g, *f)
+    tend = [g.zeros_interior(fill=0.0) for _ in range(3)]
+    for _ in range(nsteps):
+        m.kl_step(g, visc, dt, *f, *tend)
+    ref = [g.box(x).cpu().numpy().astype(np.float64) for x in f]
+    wdir = tmp_path / "forced"
+    wdir.mkdir()
+    req = (itot, jtot, ktot, dtype, bc, nsteps, dt, visc, seed)
+    S = Server(arena_bytes=1 << 28)
+    served = 0
+    try:
+        for i in range(m.kl_num_variants(m.STEP, dtype)):
+            name = m.kl_variant_name(m.STEP, dtype, i)
+            rec = {"kernel": "step", "dtype": "f32" if dtype == 0 else "f64", "problem_size": list(shape),
+                   "variant": name, "device": "forced", "arch": "gfx950", "time_ms": 1.0}
+            (wdir / "step.wisdom").write_text(json.dumps(rec) + "\n")
+            m.kl_set_wisdom_dir(str(wdir))
+            if m.kl_selected_variant(g, m.STEP) != i:
+                continue  # not eligible for this grid
+            t = S.m.kl_submit(S.h, *req)
+            got = S.fields(S.wait(t), req)
+            S.m.kl_release(S.h, t)
+            for n in range(3):
+                assert np.array_equal(got[n], ref[n]), f"{name}: field {n} differs from kl_step"
+            served += 1
+    finally:
+        S.close()
+    assert served >= 10
