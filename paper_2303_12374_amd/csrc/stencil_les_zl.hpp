@@ -546,6 +546,210 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zlp(StencilArgs<T> a
 
 namespace kl {
 
+// The tile of advec_u_2i5_zl with its level loop unrolled by two and every
+// value loaded ahead held in a slot chosen by the level's parity at compile
+// time, so no register is copied at the end of a level:
+//   * level k+1's rows, the edge values, w at k+2 and ut at k+1 are loaded
+//     during level k into the other parity's slots; the u window's next top
+//     level (k+5) is loaded two levels before it enters the window;
+//   * every wave and lane runs every LDS write and the whole arithmetic
+//     (clamped loads keep idle rows and lanes on valid data; their LDS writes
+//     go to a spare row); only the store of ut is predicated.
+// A register filled by a load and copied or left unused on some path in the
+// same level makes the compiler wait for every load in flight at that point,
+// which reduces the prefetch to nothing; here each load is waited for only
+// when the level it belongs to begins.  The field accesses take a uniform
+// base (the tile's corner row j0-3 at i = 1, on the level) and a 32-bit
+// per-lane offset from it.  Same operands, same order, so results equal the
+// other configurations bitwise.
+template <typename T, int VX, int BY, int KB, int XCD, int NT, int WPE>
+__global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zr(StencilArgs<T> a)
+{
+    constexpr int TX = 64 * VX;
+    constexpr int SW = TX + 6;               // u row in LDS: columns i0w-3 .. i0w+TX+2
+    constexpr int VW = TX + 1;               // v row in LDS: columns i0w-1 .. i0w+TX-1
+    constexpr int NH = (6 + BY - 1) / BY;    // u halo rows per wave (upper bound)
+    constexpr int SU = BY + 6, SV = BY + 1;  // spare LDS rows (never read)
+    typedef PlanarRow<planar_vx<T, VX>(), SW> UR;
+    typedef PlanarRow<planar_vx<T, VX>(), VW> VR;
+    static_assert(SW >= 64 && VW >= 64, "a spare row holds one column per lane");
+    __shared__ __align__(16) T su[2][BY + 7][UR::SIZE];
+    __shared__ __align__(16) T sv[2][BY + 2][VR::SIZE];
+
+    int tx, ty, tz;
+    tile_of<64, BY, XCD>(a.nbx, a.nby, a.nbz, tx, ty, tz);
+    const int lane = (int)threadIdx.x, r = wave_row();
+    const int i0w = 1 + tx * TX;
+    const int nlanes = min(64, (a.itot - i0w + 1) / VX);
+    const int xo = lane * VX;
+    const int j0 = 1 + ty * BY;
+    const int nv = min(BY, a.jtot - j0 + 1);
+    const bool own = r < nv;
+    const bool st_on = own && lane < nlanes;
+    const int k0 = 1 + tz * KB, k1 = min(k0 + KB, a.ktot + 1);
+    const int kt = a.ktot;
+    const int64_t ks = a.ks;
+    const int js = (int)a.js;
+    const T dxi = a.dxi, dyi = a.dyi;
+
+    // Offsets (elements) from the uniform base (i = 1, j = j0 - 3) of the
+    // level; the grid's rows j0-3 .. j0+BY+2 and columns 1 .. itot keep them
+    // non-negative.  Lanes beyond the grid read the last active lane's
+    // points, waves beyond the last row read the last row, waves without a
+    // halo row read their own row.
+    const int lane_c = min(lane, nlanes - 1);
+    const int rown = 3 + min(r, a.jtot - j0);                     // own row (relative)
+    const int cx = i0w - 1 + lane_c * VX;                         // a lane's first column (relative)
+    const int o_own = rown * js + cx;
+    const int ecol = lane < 3 ? wrap_x(i0w - 3 + lane, a.itot) - 1
+                              : (lane < 6 ? wrap_x(i0w + nlanes * VX + lane - 3, a.itot) - 1 : cx);
+    const int o_eown = rown * js + ecol;
+    const int xl1 = wrap_x(i0w - 1, a.itot) - 1;                  // column left of the tile
+    int hrow[NH], o_hc[NH], o_he[NH];                             // LDS row (SU: none), offsets
+#pragma unroll
+    for (int m = 0; m < NH; ++m) {
+        const int h = r + m * BY;
+        const int rho = h < 6 ? (h < 3 ? h : nv + h) : -1;
+        hrow[m] = rho >= 0 ? rho : SU;
+        o_hc[m] = rho >= 0 ? rho * js + cx : o_own;
+        o_he[m] = rho >= 0 ? rho * js + ecol : o_own;
+    }
+    const bool vhalo = r == BY - 1;                               // loads v row j0 + nv
+    const int vrel = 3 + nv;
+    const int o_vh = vhalo ? vrel * js + cx : o_own;
+    const int o_ev = lane == 0 ? rown * js + xl1 : (lane == 1 && vhalo ? vrel * js + xl1 : o_own);
+    const int o_ew = lane == 0 ? rown * js + xl1 : o_own;
+    // LDS destinations: rows of this wave (spare when it has none), and the
+    // x-halo values of lanes 0..5 (u) and 0..1 (v); other lanes write a
+    // column of the spare row
+    const int ou = own ? r + 3 : SU, ov = own ? r : SV, vhr = vhalo ? nv : SV;
+    const int lx_u = lane < 3 ? lane : nlanes * VX + lane;
+    const int eu_col = lane < 6 ? UR::at(lx_u) : UR::at(lane);
+    const int eu_row = lane < 6 ? ou : SU;
+    const int ev_row = lane == 0 ? ov : (lane == 1 ? vhr : SV);
+    const int ev_col = VR::at(lane < 2 ? 0 : lane);
+
+    const int64_t tb = a.off + 1 + (int64_t)(j0 - 3) * a.js;
+    const T *u = a.u + tb, *v = a.v + tb, *w = a.w + tb;
+    T *ut = a.ut + tb;
+    auto at = [&](auto *f, int l, int o) { return boff(f + (int64_t)l * ks, (uint32_t)o * (uint32_t)sizeof(T)); };
+
+    T S[6][VX];                              // u(k-2) .. u(k+3) of the own column
+    T UN[2][VX];                             // window tops in flight
+    T HU[2][NH][VX], HE[2][NH], OE[2];       // u halo rows, x-halo values (level by parity)
+    T VO[2][VX], VH[2][VX], VE[2];           // own v row, v halo row, left halo values
+    T WR[2][VX], WL[2];                      // w one level up, left neighbour cell (lane 0)
+    T UT[2][VX];                             // ut of the level
+
+    auto load_level = [&](int q, int k) {    // level k's operands into slot q (k <= ktot)
+#pragma unroll
+        for (int m = 0; m < NH; ++m) {
+            vload<T, VX>(HU[q][m], at(u, k, o_hc[m]));
+            HE[q][m] = *at(u, k, o_he[m]);
+        }
+        OE[q] = *at(u, k, o_eown);
+        vload<T, VX>(VO[q], at(v, k, o_own));
+        vload<T, VX>(VH[q], at(v, k, o_vh));
+        VE[q] = *at(v, k, o_ev);
+        vload<T, VX>(WR[q], at(w, k + 1, o_own));
+        WL[q] = *at(w, k + 1, o_ew);
+        tload<NT, T, VX>(UT[q], at(ut, k, o_own));
+    };
+
+    // prologue: the u window (levels outside [0, ktot+1] clamped: the z
+    // fluxes never use them), the flux through face k0, level k0's operands
+    // and the window top of level k0+1
+#pragma unroll
+    for (int m = 0; m < 6; ++m) vload<T, VX>(S[m], at(u, min(max(k0 - 2 + m, 0), kt + 1), o_own));
+    T FB[VX];
+    {
+        T ub3[VX], w0[VX];
+        vload<T, VX>(ub3, at(u, max(k0 - 3, 0), o_own));
+        vload<T, VX>(w0, at(w, k0, o_own));
+        const T wl0 = *at(w, k0, o_ew);
+        const T sh = shfl_up1(w0[VX - 1]);
+        const T wl = lane == 0 ? wl0 : sh;
+#pragma unroll
+        for (int n = 0; n < VX; ++n) {
+            const T wm = n == 0 ? wl : w0[n - 1];
+            FB[n] = flux_z_2i5(mid(wm, w0[n]), ub3[n], S[0][n], S[1][n], S[2][n], S[3][n], S[4][n], k0, kt);
+        }
+    }
+    load_level(0, k0);
+    vload<T, VX>(UN[1], at(u, min(k0 + 4, kt + 1), o_own));
+
+    vm_drain();
+    for (int kk = k0;; kk += 2) {
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const int k = kk + p;
+            if (k >= k1) return;
+            const int q = p ^ 1;
+            // 1. operands of level k+1 (clamped at the tile's last level,
+            //    where they are unused) and the window top of level k+2
+            load_level(q, min(k + 1, k1 - 1));
+            vload<T, VX>(UN[p], at(u, min(k + 5, kt + 1), o_own));
+            // 2. level k into LDS plane p
+#pragma unroll
+            for (int n = 0; n < VX; ++n) {
+                su[p][ou][UR::at(3 + xo + n)] = S[2][n];
+                sv[p][ov][VR::at(1 + xo + n)] = VO[p][n];
+                sv[p][vhr][VR::at(1 + xo + n)] = VH[p][n];
+            }
+#pragma unroll
+            for (int m = 0; m < NH; ++m)
+#pragma unroll
+                for (int n = 0; n < VX; ++n) su[p][hrow[m]][UR::at(3 + xo + n)] = HU[p][m][n];
+            // the x-halo values after the rows: a lane beyond the grid writes
+            // its row values into the right halo columns, which these replace
+            su[p][eu_row][eu_col] = OE[p];
+#pragma unroll
+            for (int m = 0; m < NH; ++m) su[p][lane < 6 ? hrow[m] : SU][eu_col] = HE[p][m];
+            sv[p][ev_row][ev_col] = VE[p];
+            __syncthreads();
+
+            // 3. level k
+            const T sh = shfl_up1(WR[p][VX - 1]);
+            const T wl = lane == 0 ? WL[p] : sh;
+            T uxr[VX + 6];
+#pragma unroll
+            for (int m = 0; m < VX + 6; ++m) uxr[m] = su[p][r + 3][UR::at(xo + m)];
+            T FX[VX + 1];
+#pragma unroll
+            for (int f = 0; f <= VX; ++f)
+                FX[f] = flux5(mid(uxr[f + 2], uxr[f + 3]), uxr[f], uxr[f + 1], uxr[f + 2], uxr[f + 3], uxr[f + 4],
+                              uxr[f + 5]);
+            const T dzik = kload(a.dzi, k);
+            T res[VX];
+#pragma unroll
+            for (int n = 0; n < VX; ++n) {
+                const int xu = UR::at(3 + xo + n);
+                T col[7];
+#pragma unroll
+                for (int m = 0; m < 7; ++m) col[m] = su[p][r + m][xu];
+                const T vn = mid(sv[p][r + 1][VR::at(xo + n)], sv[p][r + 1][VR::at(xo + n + 1)]);
+                const T vs = mid(sv[p][r][VR::at(xo + n)], sv[p][r][VR::at(xo + n + 1)]);
+                const T fn = flux5(vn, col[1], col[2], col[3], col[4], col[5], col[6]);
+                const T fs = flux5(vs, col[0], col[1], col[2], col[3], col[4], col[5]);
+                const T wm = n == 0 ? wl : WR[p][n - 1];
+                const T ft = flux_z_2i5(mid(wm, WR[p][n]), S[0][n], S[1][n], S[2][n], S[3][n], S[4][n], S[5][n],
+                                        k + 1, kt);
+                res[n] = UT[p][n] + advec_2i5_combine(FX[n + 1], FX[n], fn, fs, ft, FB[n], dxi, dyi, dzik);
+                FB[n] = ft;
+            }
+            if (st_on) tstore<NT, T, VX>(at(ut, k, o_own), res);
+
+            // 4. the window moves up one level; its new top was loaded a level ago
+#pragma unroll
+            for (int m = 0; m < 5; ++m)
+#pragma unroll
+                for (int n = 0; n < VX; ++n) S[m][n] = S[m + 1][n];
+#pragma unroll
+            for (int n = 0; n < VX; ++n) S[5][n] = UN[q][n];
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // LDS-staged z-marching configuration of diff_smag.
 //

@@ -29,6 +29,18 @@ void add_variants_f32_les(int kernel, std::vector<Variant> &out)
     if (kernel == KL_KERNEL_ADVEC_U_2I5) {
         static const std::vector<Variant> v = {
         KL_A5P(float, KL_F32, 2, 8, 64, 2, 1),
+        KL_A5R(float, KL_F32, 4, 4, 64, 2, 1),
+        KL_A5R(float, KL_F32, 4, 4, 128, 2, 1),
+        KL_A5R(float, KL_F32, 4, 8, 64, 2, 1),
+        KL_A5R(float, KL_F32, 2, 4, 64, 2, 1),
+        KL_A5R(float, KL_F32, 2, 8, 64, 2, 1),
+        KL_A5R(float, KL_F32, 4, 2, 64, 2, 1),
+        KL_A5R(float, KL_F32, 4, 8, 128, 2, 1),
+        KL_A5R(float, KL_F32, 4, 8, 256, 3, 1),
+        KL_A5R(float, KL_F32, 4, 8, 32, 2, 1),
+        KL_A5R(float, KL_F32, 1, 8, 64, 2, 1),
+        KL_A5R(float, KL_F32, 1, 16, 64, 2, 1),
+        KL_A5R(float, KL_F32, 2, 16, 64, 2, 1),
         KL_A5S(float, KL_F32, 4, 8, 64, 2, 1),
         KL_A5S(float, KL_F32, 4, 8, 128, 2, 1),
         KL_A5P(float, KL_F32, 2, 4, 64, 2, 1),

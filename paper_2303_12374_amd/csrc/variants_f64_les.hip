@@ -22,6 +22,12 @@ void add_variants_f64_les(int kernel, std::vector<Variant> &out)
     if (kernel == KL_KERNEL_ADVEC_U_2I5) {
         static const std::vector<Variant> v = {
         KL_A5P(double, KL_F64, 2, 8, 64, 2, 1),
+        KL_A5R(double, KL_F64, 2, 4, 64, 2, 1),
+        KL_A5R(double, KL_F64, 2, 4, 128, 2, 1),
+        KL_A5R(double, KL_F64, 2, 8, 64, 2, 1),
+        KL_A5R(double, KL_F64, 1, 8, 64, 2, 1),
+        KL_A5R(double, KL_F64, 2, 8, 128, 2, 1),
+        KL_A5R(double, KL_F64, 1, 16, 64, 2, 1),
         KL_A5S(double, KL_F64, 2, 8, 64, 2, 1),
         KL_A5S(double, KL_F64, 2, 4, 64, 2, 1),
         KL_A5P(double, KL_F64, 1, 8, 64, 2, 1),

@@ -240,6 +240,60 @@ def a5_spans(itot, jtot, ktot, vx, by, kb, off, js, ks, pair):
     return sp
 
 
+def a5r_spans(itot, jtot, ktot, vx, by, kb, off, js, ks, esize):
+    """advec_u_2i5 parity-slot tiles (a5r): a uniform base per level (i = 1,
+    j = j0 - 3) plus unsigned 32-bit per-lane byte offsets, which must be
+    non-negative and below 2^32."""
+    sp = Span()
+    nh = (6 + by - 1) // by
+    r = np.arange(by)[:, None]
+    lane = LANES[None, :]
+    for tx, ty, tz in tiles(itot, jtot, ktot, vx, by, kb):
+        i0w = 1 + tx * 64 * vx
+        nlanes = min(64, (itot - i0w + 1) // vx)
+        j0 = 1 + ty * by
+        nv = min(by, jtot - j0 + 1)
+        k0 = 1 + tz * kb
+        k1 = min(k0 + kb, ktot + 1)
+        tb = off + 1 + (j0 - 3) * js
+        lane_c = np.minimum(lane, nlanes - 1)
+        rown = 3 + np.minimum(r, jtot - j0)
+        cx = i0w - 1 + lane_c * vx
+        o_own = rown * js + cx
+        ecol = np.where(lane < 3, wrap_x(i0w - 3 + lane, itot) - 1,
+                        np.where(lane < 6, wrap_x(i0w + nlanes * vx + lane - 3, itot) - 1, cx))
+        o_eown = rown * js + ecol
+        xl1 = wrap_x(i0w - 1, itot) - 1
+        o_hc, o_he = [], []
+        for m in range(nh):
+            h = r + m * by
+            rho = np.where(h < 6, np.where(h < 3, h, nv + h), -1)
+            o_hc.append(np.where(rho >= 0, rho * js + cx, o_own))
+            o_he.append(np.where(rho >= 0, rho * js + ecol, o_own))
+        vhalo = r == by - 1
+        vrel = 3 + nv
+        o_vh = np.where(vhalo, vrel * js + cx, o_own)
+        o_ev = np.where(lane == 0, rown * js + xl1, np.where((lane == 1) & vhalo, vrel * js + xl1, o_own))
+        o_ew = np.where(lane == 0, rown * js + xl1, o_own)
+        for o in [o_own, o_eown, o_vh, o_ev, o_ew] + o_hc + o_he:
+            o = np.broadcast_to(o, (by, 64))
+            assert o.min() >= 0 and (o.max() + vx) * esize < 2 ** 32, "a5r offset outside [0, 2^32)"
+        lo, hi = k0, k1 - 1  # levels of load_level and of the ut store
+        top = lambda k: min(k, ktot + 1)
+        sp.add(tb + o_own, max(k0 - 3, 0), top(k0 + 3), ks, vx)   # window and face k0's bottom value
+        sp.add(tb + o_own, top(k0 + 4), top(hi + 5), ks, vx)      # window tops
+        sp.add(tb + o_own, k0, hi + 1, ks, vx)                    # own v row, w one level up, ut
+        sp.add(tb + o_ew, k0, hi + 1, ks)                          # w's left neighbour (face k0: level k0)
+        for o in o_hc:
+            sp.add(tb + o, lo, hi, ks, vx)
+        for o in o_he:
+            sp.add(tb + o, lo, hi, ks)
+        sp.add(tb + o_eown, lo, hi, ks)
+        sp.add(tb + o_vh, lo, hi, ks, vx)
+        sp.add(tb + o_ev, lo, hi, ks)
+    return sp
+
+
 def s2_spans(itot, jtot, ktot, vx, by, kb, off, js, ks):
     """diff_smag tiles: rows from a wave-uniform row start (column 0) plus a
     per-lane offset."""
@@ -288,6 +342,8 @@ def test_les_tiles_stay_inside_the_fields(shape, dtype):
             what = f"{shape} layout=({off},{js},{ks}) vx={vx} by={by} kb={kb}"
             check(a5_spans(itot, jtot, ktot, vx, by, kb, off, js, ks, False), alloc, f"a5 {what}")
             check(a5_spans(itot, jtot, ktot, vx, by, kb, off, js, ks, True), alloc, f"a5p {what}")
+            check(a5r_spans(itot, jtot, ktot, vx, by, kb, off, js, ks, 4 if dtype == 0 else 8), alloc,
+                  f"a5r {what}")
             check(s2_spans(itot, jtot, ktot, vx, by, kb, off, js, ks), alloc, f"s2 {what}")
             ran += 1
     assert ran > 0
