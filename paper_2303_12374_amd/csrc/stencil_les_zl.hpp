@@ -562,7 +562,12 @@ namespace kl {
 // base (the tile's corner row j0-3 at i = 1, on the level) and a 32-bit
 // per-lane offset from it.  Same operands, same order, so results equal the
 // other configurations bitwise.
-template <typename T, int VX, int BY, int KB, int XCD, int NT, int WPE>
+//
+// HL > 1 loads the u halo rows HL levels ahead, into a ring of HL + 1
+// slots: the neighbouring tile loads the same row as its own (the window's
+// top) five levels ahead, so with HL = 5 both requests meet in L2 and the
+// row is fetched from HBM once.
+template <typename T, int VX, int BY, int KB, int XCD, int NT, int WPE, int HL = 1>
 __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zr(StencilArgs<T> a)
 {
     constexpr int TX = 64 * VX;
@@ -636,17 +641,22 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zr(StencilArgs<T> a)
 
     T S[6][VX];                              // u(k-2) .. u(k+3) of the own column
     T UN[2][VX];                             // window tops in flight
-    T HU[2][NH][VX], HE[2][NH], OE[2];       // u halo rows, x-halo values (level by parity)
+    constexpr int HS = HL + 1;               // halo ring slots
+    constexpr int RS = HS % 2 ? 2 * HS : HS; // levels per unrolled pass (slot indices fixed)
+    T HU[HS][NH][VX], HE[HS][NH];            // u halo rows and their x-halo values (ring)
+    T OE[2];                                 // x-halo values of the own u row (by parity)
     T VO[2][VX], VH[2][VX], VE[2];           // own v row, v halo row, left halo values
     T WR[2][VX], WL[2];                      // w one level up, left neighbour cell (lane 0)
     T UT[2][VX];                             // ut of the level
 
-    auto load_level = [&](int q, int k) {    // level k's operands into slot q (k <= ktot)
+    auto load_halo = [&](int h, int k) {     // u halo rows of level k into ring slot h
 #pragma unroll
         for (int m = 0; m < NH; ++m) {
-            vload<T, VX>(HU[q][m], at(u, k, o_hc[m]));
-            HE[q][m] = *at(u, k, o_he[m]);
+            vload<T, VX>(HU[h][m], at(u, k, o_hc[m]));
+            HE[h][m] = *at(u, k, o_he[m]);
         }
+    };
+    auto load_level = [&](int q, int k) {    // level k's other operands into slot q (k <= ktot)
         OE[q] = *at(u, k, o_eown);
         vload<T, VX>(VO[q], at(v, k, o_own));
         vload<T, VX>(VH[q], at(v, k, o_vh));
@@ -675,18 +685,22 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zr(StencilArgs<T> a)
             FB[n] = flux_z_2i5(mid(wm, w0[n]), ub3[n], S[0][n], S[1][n], S[2][n], S[3][n], S[4][n], k0, kt);
         }
     }
+#pragma unroll
+    for (int h = 0; h < HL; ++h) load_halo(h, min(k0 + h, k1 - 1));
     load_level(0, k0);
     vload<T, VX>(UN[1], at(u, min(k0 + 4, kt + 1), o_own));
 
     vm_drain();
-    for (int kk = k0;; kk += 2) {
+    for (int kk = k0;; kk += RS) {
 #pragma unroll
-        for (int p = 0; p < 2; ++p) {
-            const int k = kk + p;
+        for (int s = 0; s < RS; ++s) {
+            const int k = kk + s;
             if (k >= k1) return;
-            const int q = p ^ 1;
-            // 1. operands of level k+1 (clamped at the tile's last level,
-            //    where they are unused) and the window top of level k+2
+            const int p = s & 1, q = p ^ 1, hs = s % HS;
+            // 1. operands of level k+1 and halo rows of level k+HL (clamped at
+            //    the tile's last level, where they are unused), the window top
+            //    of level k+2
+            load_halo((s + HL) % HS, min(k + HL, k1 - 1));
             load_level(q, min(k + 1, k1 - 1));
             vload<T, VX>(UN[p], at(u, min(k + 5, kt + 1), o_own));
             // 2. level k into LDS plane p
@@ -699,12 +713,12 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zr(StencilArgs<T> a)
 #pragma unroll
             for (int m = 0; m < NH; ++m)
 #pragma unroll
-                for (int n = 0; n < VX; ++n) su[p][hrow[m]][UR::at(3 + xo + n)] = HU[p][m][n];
+                for (int n = 0; n < VX; ++n) su[p][hrow[m]][UR::at(3 + xo + n)] = HU[hs][m][n];
             // the x-halo values after the rows: a lane beyond the grid writes
             // its row values into the right halo columns, which these replace
             su[p][eu_row][eu_col] = OE[p];
 #pragma unroll
-            for (int m = 0; m < NH; ++m) su[p][lane < 6 ? hrow[m] : SU][eu_col] = HE[p][m];
+            for (int m = 0; m < NH; ++m) su[p][lane < 6 ? hrow[m] : SU][eu_col] = HE[hs][m];
             sv[p][ev_row][ev_col] = VE[p];
             __syncthreads();
 

@@ -222,9 +222,9 @@ __device__ __forceinline__ void advec_u_zl_tile(const StencilArgs<T> &a, int tx,
     static_assert(BY >= 2, "two halo rows need two waves");
     constexpr int TX = 64 * VX;
     typedef T RowT[TX];
-    __shared__ __align__(16) RowT shu[2][BY + 2];  // u rows j0-1 .. j0+nv
-    __shared__ __align__(16) RowT shv[2][BY + 2];  // v rows j0 .. j0+nv (LDS row r+1 = tile row r)
-    __shared__ T shvl[2][BY + 2];                   // v left of the segment, same rows
+    __shared__ __align__(16) RowT shu[2][BY + 3];  // u rows j0-1 .. j0+nv; row BY+2 is a spare
+    __shared__ __align__(16) RowT shv[2][BY + 3];  // v rows j0 .. j0+nv (LDS row r+1 = tile row r); spare
+    __shared__ T shvl[2][BY + 2 + 64];              // v left of the segment, same rows; one spare per lane
     __syncthreads();
 
     const ZlTile<VX, BY, KB> t(a.itot, a.jtot, a.ktot, tx, ty, tz);
@@ -242,6 +242,11 @@ __device__ __forceinline__ void advec_u_zl_tile(const StencilArgs<T> &a, int tx,
     const bool ld_own = t.own && t.lane_on;
     const T dxi = a.dxi, dyi = a.dyi;
     const T *U = a.u, *V = a.v, *W = a.w;
+    constexpr int SPARE = BY + 2;
+    const int orow = t.own ? t.r + 1 : SPARE;
+    const int xrow = t.xrow_l >= 0 ? t.xrow_l : SPARE;
+    const int xvrow = x_is_top ? t.xrow_l : SPARE;
+    const int evslot = t.own && t.lane == 0 ? t.r + 1 : (x_is_top && t.lane == 1 ? t.xrow_l : BY + 2 + t.lane);
 
     T RU[4][VX], RW[4][VX];   // u and w rings (u: k-1..k+2, w: k..k+2)
     T RV[2][VX];              // v at level k, k+1
@@ -287,22 +292,27 @@ __device__ __forceinline__ void advec_u_zl_tile(const StencilArgs<T> &a, int tx,
             fload<NT, T, VX>(wnx, W + c_own + l3);
             EW[(s + 3) & 3] = W[c_ew + l3];
             fload<NT, T, VX>(RV[q], V + c_own + l1);
+            // Q[q] still holds the values stored a level ago: reading them here
+            // keeps those registers out of the allocator's hands until this
+            // reload, so no other write to them has to wait for that store
+            settle(Q[q]);
             tload<NT, T, VX>(Q[q], a.ut + c_own + l1);
             vload<T, VX>(XU[q], U + c_x + l1);
             vload<T, VX>(XV[q], V + c_x + l1);
             EU[q] = U[c_eu + l1];
             EV[q] = V[c_ev + l1];
-            // level-k rows into LDS: u (own + halo rows), v (own + top halo) and v's left edge
-            if (t.own) {
-                vstore<T, VX>(&shu[p][t.r + 1][t.lane * VX], uc);
-                vstore<T, VX>(&shv[p][t.r + 1][t.lane * VX], RV[p]);
-                if (t.lane == 0) shvl[p][t.r + 1] = EV[p];
-            }
-            if (t.xrow_l >= 0) vstore<T, VX>(&shu[p][t.xrow_l][t.lane * VX], XU[p]);
-            if (x_is_top) {
-                vstore<T, VX>(&shv[p][t.xrow_l][t.lane * VX], XV[p]);
-                if (t.lane == 1) shvl[p][t.xrow_l] = EV[p];
-            }
+            // level-k rows into LDS: u (own + halo rows), v (own + top halo) and
+            // v's left edge.  Every wave and lane writes (a wave without such
+            // a row into the spare row, lanes without an edge value into
+            // their spare slot) and every lane computes, only the store being
+            // predicated: a loaded value consumed on one path only makes the
+            // compiler wait for all loads in flight where its register is
+            // next written, which undoes the prefetch.
+            vstore<T, VX>(&shu[p][orow][t.lane * VX], uc);
+            vstore<T, VX>(&shv[p][orow][t.lane * VX], RV[p]);
+            vstore<T, VX>(&shu[p][xrow][t.lane * VX], XU[p]);
+            vstore<T, VX>(&shv[p][xvrow][t.lane * VX], XV[p]);
+            shvl[p][evslot] = EV[p];
             __syncthreads();
             T un[VX], us[VX], vn[VX];
             vload<T, VX>(un, &shu[p][t.r + 2][t.lane * VX]);
@@ -325,7 +335,7 @@ __device__ __forceinline__ void advec_u_zl_tile(const StencilArgs<T> &a, int tx,
                 wtleft = EW[(s + 1) & 3];
             }
             if (t.lane == t.nlanes - 1) uright = ur;
-            if (ld_own) {
+            {
                 const T dzik = kload(a.dzi, k);
 #pragma unroll
                 for (int n = 0; n < VX; ++n) {
@@ -339,7 +349,16 @@ __device__ __forceinline__ void advec_u_zl_tile(const StencilArgs<T> &a, int tx,
                                                          RV[p][n], v_nw, vn[n], w_w, wc[n], w_tw, wt[n], dxi,
                                                          dyi, dzik);
                 }
-                tstore<NT, T, VX>(a.ut + c_own + (int64_t)k * ks, Q[p]);
+                // the compiler sinks this arithmetic into the predicated store:
+                // its loaded operands are marked as read on every path
+                settle(Q[p]);
+                settle(ub);
+                settle(ut_);
+                settle(wc);
+                settle(wt);
+                const T ew2[3] = {EU[p], EW[s & 3], EW[(s + 1) & 3]};
+                settle(ew2);
+                if (ld_own) tstore<NT, T, VX>(a.ut + c_own + (int64_t)k * ks, Q[p]);
             }
             fload<NT, T, VX>(ub, U + c_own + l3);
         }

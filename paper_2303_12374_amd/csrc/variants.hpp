@@ -191,7 +191,7 @@ hipError_t launch_advec5_zl(const HostArgs &h, hipStream_t s)
     return hipGetLastError();
 }
 
-template <typename T, int VX, int BY, int KB, int XCD, int NT = 0, int WPE = 1>
+template <typename T, int VX, int BY, int KB, int XCD, int NT = 0, int HL = 1>
 hipError_t launch_advec5_zr(const HostArgs &h, hipStream_t s)
 {
     StencilArgs<T> a = device_args<T>(h);
@@ -200,7 +200,7 @@ hipError_t launch_advec5_zr(const HostArgs &h, hipStream_t s)
     a.nbz = (int)cdivu(h.ktot, KB);
     const uint64_t nb = (uint64_t)a.nbx * a.nby * a.nbz;
     if (!grid_fits(nb, 64 * BY)) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((advec_u_2i5_zr<T, VX, BY, KB, XCD, NT, WPE>), dim3((unsigned)nb), dim3(64, BY), 0, s, a);
+    hipLaunchKernelGGL((advec_u_2i5_zr<T, VX, BY, KB, XCD, NT, 1, HL>), dim3((unsigned)nb), dim3(64, BY), 0, s, a);
     return hipGetLastError();
 }
 
@@ -373,6 +373,13 @@ hipError_t launch_smag_zl(const HostArgs &h, hipStream_t s)
     Variant{"a5r_v" KL_STR(VX) "_b64x" KL_STR(BY) "_k" KL_STR(KB) "_x" KL_STR(XCD) "_nt" KL_STR(NT),       \
             KL_KERNEL_ADVEC_U_2I5, DT, FAMILY_ZL, VX, 64, BY, KB, XCD,                                     \
             &launch_advec5_zr<T, VX, BY, KB, XCD, NT>, nullptr, nullptr}
+
+// The same with the u halo rows loaded HL levels ahead, named a5r_..._h<HL>.
+#define KL_A5RH(T, DT, VX, BY, KB, XCD, NT, HL)                                                             \
+    Variant{"a5r_v" KL_STR(VX) "_b64x" KL_STR(BY) "_k" KL_STR(KB) "_x" KL_STR(XCD) "_nt" KL_STR(NT)        \
+            "_h" KL_STR(HL),                                                                                \
+            KL_KERNEL_ADVEC_U_2I5, DT, FAMILY_ZL, VX, 64, BY, KB, XCD,                                     \
+            &launch_advec5_zr<T, VX, BY, KB, XCD, NT, HL>, nullptr, nullptr}
 
 #define KL_A5(T, DT, VX, BY, KB, XCD, NT)                                                                   \
     Variant{"a5_v" KL_STR(VX) "_b64x" KL_STR(BY) "_k" KL_STR(KB) "_x" KL_STR(XCD) "_nt" KL_STR(NT),        \

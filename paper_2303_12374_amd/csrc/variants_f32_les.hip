@@ -38,6 +38,11 @@ void add_variants_f32_les(int kernel, std::vector<Variant> &out)
         KL_A5R(float, KL_F32, 4, 8, 128, 2, 1),
         KL_A5R(float, KL_F32, 4, 8, 256, 3, 1),
         KL_A5R(float, KL_F32, 4, 8, 32, 2, 1),
+        KL_A5RH(float, KL_F32, 4, 8, 256, 3, 1, 5),
+        KL_A5RH(float, KL_F32, 4, 8, 64, 2, 1, 5),
+        KL_A5RH(float, KL_F32, 4, 8, 256, 3, 1, 3),
+        KL_A5RH(float, KL_F32, 4, 4, 128, 2, 1, 5),
+        KL_A5RH(float, KL_F32, 2, 8, 64, 2, 1, 5),
         KL_A5R(float, KL_F32, 1, 8, 64, 2, 1),
         KL_A5R(float, KL_F32, 1, 16, 64, 2, 1),
         KL_A5R(float, KL_F32, 2, 16, 64, 2, 1),

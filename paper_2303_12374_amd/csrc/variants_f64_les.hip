@@ -27,6 +27,9 @@ void add_variants_f64_les(int kernel, std::vector<Variant> &out)
         KL_A5R(double, KL_F64, 2, 8, 64, 2, 1),
         KL_A5R(double, KL_F64, 1, 8, 64, 2, 1),
         KL_A5R(double, KL_F64, 2, 8, 128, 2, 1),
+        KL_A5RH(double, KL_F64, 2, 8, 128, 2, 1, 5),
+        KL_A5RH(double, KL_F64, 2, 8, 64, 2, 1, 5),
+        KL_A5RH(double, KL_F64, 2, 8, 128, 2, 1, 3),
         KL_A5R(double, KL_F64, 1, 16, 64, 2, 1),
         KL_A5S(double, KL_F64, 2, 8, 64, 2, 1),
         KL_A5S(double, KL_F64, 2, 4, 64, 2, 1),
