@@ -45,7 +45,7 @@ def kernel_of_symbol(sym):
     step tile serves both the fused step (last template argument 0) and the
     fused advec_u + diff_uvw pass (1)."""
     import re
-    m = re.search(r"kl::(\w+?)_(zl3|zlp|zl|zc|plain)(_batch)?<([^>]*)>", sym)
+    m = re.search(r"kl::(\w+?)_(zl3|zlp|zl|zr|zc|plain)(_batch)?<([^>]*)>", sym)
     if not m:
         m = re.search(r"kl::(step)_zl(_batch)?<([^>]*)>", sym)
         if not m:
