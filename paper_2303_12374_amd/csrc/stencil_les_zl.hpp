@@ -985,4 +985,235 @@ __global__ __launch_bounds__(64 * BY, WPE) void diff_smag_zl(StencilArgs<T> a)
     }
 }
 
+// diff_smag_zl with the staged rows loaded one level further ahead into two
+// register slots chosen by the level's parity at compile time (level loop
+// unrolled by two), every wave and lane writing LDS and computing, and only
+// the stores predicated, as in advec_u_2i5_zr: a level then waits only for
+// loads issued a level earlier.  Same operands, same order: bitwise the
+// other configurations.
+template <typename T, int VX, int BY, int KB, int XCD, int NT, int WPE>
+__global__ __launch_bounds__(64 * BY, WPE) void diff_smag_zr(StencilArgs<T> a)
+{
+    constexpr int TX = 64 * VX;
+    constexpr int PW = TX + 2;              // plane row: columns i0w-1 .. i0w+TX
+    constexpr int PH = BY + 2;              // plane rows: j0-1 .. j0+BY
+    constexpr int NH = (8 + BY - 1) / BY;   // halo rows per wave (8 = 2 rows x 4 fields)
+    typedef PlanarRow<planar_vx<T, VX>(), PW> SR;  // plane rows, planar by VX (4-byte T)
+    __shared__ __align__(16) T pl[4][3][PH + 1][SR::SIZE];  // [field][ring plane][row][column]; row PH is a spare
+
+    int tx, ty, tz;
+    tile_of<64, BY, XCD>(a.nbx, a.nby, a.nbz, tx, ty, tz);
+    const int lane = (int)threadIdx.x, r = wave_row();
+    const int i0w = 1 + tx * TX;
+    const int nlanes = min(64, (a.itot - i0w + 1) / VX);
+    const bool lane_on = lane < nlanes;
+    const int xo = lane * VX;
+    const int j0 = 1 + ty * BY;
+    const int nv = min(BY, a.jtot - j0 + 1);
+    const bool own = r < nv;
+    const int k0 = 1 + tz * KB, k1 = min(k0 + KB, a.ktot + 1);
+    const int64_t js = a.js, ks = a.ks;
+    const T *F[4] = {a.u, a.v, a.w, a.evisc};
+    const int xr = 1 + nlanes * VX;         // LDS column of the right halo cell
+
+    // Every global load below is unconditional, from an address inside the
+    // field: lanes beyond the grid re-read the last active lane's points,
+    // waves beyond the last row re-read the last row, waves without a halo
+    // row re-read their own row, and one scalar load per row carries both
+    // halo columns (the left one in lane 0, the right one in lane le).  No
+    // load sits behind a branch, so the compiler counts the loads in flight
+    // exactly and does not drain the prefetch of level k+2 before it is due.
+    const int lane_c = min(lane, nlanes - 1);
+    const int le = max(nlanes - 1, 1);      // lane loading the right halo cell
+    // Addresses: a wave-uniform row start (column 0) plus a per-lane byte
+    // offset, own point (i0w + lane_c*VX) or halo column (in lane 0 the
+    // periodic image of column i0w-1, in lane le that of i0w + nlanes*VX:
+    // x is periodic, so the halo columns come from the row's interior and no
+    // x ghost line is fetched); the level offset goes into the uniform part.
+    const int64_t row_c = a.off + (int64_t)min(j0 + r, a.jtot) * js;
+    const uint32_t o_pt = (uint32_t)(i0w + lane_c * VX) * sizeof(T);
+    const uint32_t o_e = lane == 0 ? (uint32_t)wrap_x(i0w - 1, a.itot) * sizeof(T)
+                                   : (lane == le ? (uint32_t)wrap_x(i0w + nlanes * VX, a.itot) * sizeof(T) : o_pt);
+
+    // rows this wave stages: its own (LDS row r+1) and halo rows h = r, r+BY,
+    // ... of the 8 (field h/2; LDS row 0 for even h, nv+1 for odd h)
+    int hf[NH], hrow[NH];
+    int64_t hr0[NH];
+#pragma unroll
+    for (int m = 0; m < NH; ++m) {
+        const int h = r + m * BY;
+        hf[m] = h < 8 ? h >> 1 : -1;
+        hrow[m] = (h & 1) ? nv + 1 : 0;
+        hr0[m] = hf[m] < 0 ? row_c : a.off + (int64_t)(j0 - 1 + hrow[m]) * js;
+    }
+
+    // Staged rows in two slots by level parity: level l's rows are loaded
+    // two levels before they are written to LDS (at the end of level l-2,
+    // into the plane of level l-3), so no level waits for the rows it
+    // loads.  The tendencies of level k are loaded first in level k and
+    // waited for by its arithmetic only.
+    T O[2][4][VX], OE[2][4];                // own row of the 4 inputs, halo columns
+    T H[2][NH][VX], HE[2][NH];              // halo rows
+    T TT[3][VX];                            // ut, vt, wt of the level
+    // LDS destinations: every wave writes every row it could stage (the
+    // spare row PH when it has none) and every lane writes an edge value
+    // (lanes other than 0 and le into a column of the spare row)
+    const int orow = own ? r + 1 : PH;
+    const int ecol = lane == 0 ? SR::at(0) : (lane == le ? SR::at(xr) : SR::at(lane));
+    const int erow = lane == 0 || lane == le ? orow : PH;
+    int hfs[NH], hrs[NH], hre[NH];
+#pragma unroll
+    for (int m = 0; m < NH; ++m) {
+        hfs[m] = hf[m] < 0 ? 0 : hf[m];
+        hrs[m] = hf[m] < 0 ? PH : hrow[m];
+        hre[m] = lane == 0 || lane == le ? hrs[m] : PH;
+    }
+
+    auto load_plane = [&](int q, int l) {    // level l of everything this wave stages, into slot q
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            const T *row = F[f] + row_c + (int64_t)l * ks;
+            vload<T, VX>(O[q][f], boff(row, o_pt));
+            OE[q][f] = *boff(row, o_e);
+        }
+#pragma unroll
+        for (int m = 0; m < NH; ++m) {
+            // a select, not an indexed pointer array, keeps these global loads
+            const T *p = hf[m] == 1 ? a.v : (hf[m] == 2 ? a.w : (hf[m] == 3 ? a.evisc : a.u));
+            const T *row = p + hr0[m] + (int64_t)l * ks;
+            vload<T, VX>(H[q][m], boff(row, o_pt));
+            HE[q][m] = *boff(row, o_e);
+        }
+    };
+    auto load_tend = [&](int l) {
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+            tload<NT, T, VX>(TT[f], boff((f == 0 ? a.ut : (f == 1 ? a.vt : a.wt)) + row_c + (int64_t)l * ks, o_pt));
+    };
+    auto store_plane = [&](int q, int b) {   // slot q into ring plane b; the edge values after the rows
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+#pragma unroll
+            for (int n = 0; n < VX; ++n) pl[f][b][orow][SR::at(1 + xo + n)] = O[q][f][n];
+        }
+#pragma unroll
+        for (int m = 0; m < NH; ++m) {
+#pragma unroll
+            for (int n = 0; n < VX; ++n) pl[hfs[m]][b][hrs[m]][SR::at(1 + xo + n)] = H[q][m][n];
+        }
+#pragma unroll
+        for (int f = 0; f < 4; ++f) pl[f][b][erow][ecol] = OE[q][f];
+#pragma unroll
+        for (int m = 0; m < NH; ++m) pl[hfs[m]][b][hre[m]][ecol] = HE[q][m];
+    };
+
+    // prologue: levels k0-1, k0 and k0+1 into ring planes 0, 1 and 2; the
+    // operands and vertical faces of level k0-1 into registers
+    load_plane(0, k0 - 1);
+    store_plane(0, 0);
+    load_plane(0, k0);
+    store_plane(0, 1);
+    load_plane(1, k0 + 1);
+    load_plane(0, min(k0 + 2, k1));
+    const T dxi = a.dxi, dyi = a.dyi;
+    SmagFace<T> BU[VX], BV[VX];
+    T BW[VX];
+    SmagBelow<T> L[VX];
+    __syncthreads();
+    {
+        const int rr = r + 1;
+        const T dzhik = kload(a.dzhi, k0);
+#pragma unroll
+        for (int n = 0; n < VX; ++n) {
+            const int x = 1 + xo + n;
+#define P(f, b, dj, di) pl[f][b][rr + (dj)][SR::at(x + (di))]
+            const T uc = P(0, 1, 0, 0), ub = P(0, 0, 0, 0), vc = P(1, 1, 0, 0), vb = P(1, 0, 0, 0);
+            const T wc = P(2, 1, 0, 0), ww = P(2, 1, 0, -1), ws = P(2, 1, -1, 0), wb = P(2, 0, 0, 0);
+            const T ec = P(3, 1, 0, 0), ew = P(3, 1, 0, -1), es = P(3, 1, -1, 0), eb = P(3, 0, 0, 0),
+                    ebw = P(3, 0, 0, -1), ebs = P(3, 0, -1, 0);
+            L[n] = {ub, P(0, 0, 0, 1), vb, P(1, 0, 1, 0), eb, ebw, P(3, 0, 0, 1), ebs, P(3, 0, 1, 0)};
+#undef P
+            BU[n] = smag_u_zface<T>(ebw, eb, ew, ec, uc, ub, wc, ww, dxi, dzhik);
+            BV[n] = smag_v_zface<T>(ebs, eb, es, ec, vc, vb, wc, ws, dyi, dzhik);
+            BW[n] = smag_w_zcenter<T>(eb, wc, wb);
+        }
+    }
+    store_plane(1, 2);
+    vm_drain();
+
+    // ring planes of levels k-1, k and k+1, rotated every level
+    int bm = 0, bc = 1, bp = 2;
+    for (int kk = k0;; kk += 2) {
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+        const int k = kk + p;
+        if (k >= k1) return;
+        const int q = p ^ 1;
+        __syncthreads();                     // level k+1 visible, level k-1 no longer read
+        // level k's tendencies, then level k+3's rows (clamped at the end of
+        // the tile, where they are unused) into the other slot
+        load_tend(k);
+        load_plane(q, min(k + 3, k1));
+
+        {
+            const T dzik = kload(a.dzi, k), dzikm1 = kload(a.dzi, k - 1), dzhik = kload(a.dzhi, k), dzhik1 = kload(a.dzhi, k + 1);
+            const int rr = r + 1;
+            T o0[VX], o1[VX], o2[VX];
+#pragma unroll
+            for (int n = 0; n < VX; ++n) {
+                const int x = 1 + xo + n;
+                // operand names: <field><offset>; offsets e/w (x), n/s (y), t/b (z)
+#define P(f, b, dj, di) pl[f][b][rr + (dj)][SR::at(x + (di))]
+                const T uc = P(0, bc, 0, 0), ue = P(0, bc, 0, 1), uw = P(0, bc, 0, -1), un = P(0, bc, 1, 0),
+                        us = P(0, bc, -1, 0), ut_ = P(0, bp, 0, 0), use = P(0, bc, -1, 1);
+                const T vc = P(1, bc, 0, 0), ve = P(1, bc, 0, 1), vw = P(1, bc, 0, -1), vn = P(1, bc, 1, 0),
+                        vs = P(1, bc, -1, 0), vt_ = P(1, bp, 0, 0), vnw = P(1, bc, 1, -1);
+                const T wc = P(2, bc, 0, 0), we = P(2, bc, 0, 1), ww = P(2, bc, 0, -1), wn = P(2, bc, 1, 0),
+                        ws = P(2, bc, -1, 0), wt_ = P(2, bp, 0, 0), wtw = P(2, bp, 0, -1),
+                        wts = P(2, bp, -1, 0);
+                const T ec = P(3, bc, 0, 0), ee = P(3, bc, 0, 1), ew = P(3, bc, 0, -1), en = P(3, bc, 1, 0),
+                        es = P(3, bc, -1, 0), et = P(3, bp, 0, 0), enw = P(3, bc, 1, -1),
+                        esw = P(3, bc, -1, -1), ese = P(3, bc, -1, 1), etw = P(3, bp, 0, -1), ets = P(3, bp, -1, 0);
+#undef P
+                const SmagBelow<T> b = L[n];
+                // the same operations as smag_u/v/w, with the bottom faces carried
+                const SmagFace<T> tu = smag_u_zface<T>(ew, ec, etw, et, ut_, uc, wt_, wtw, dxi, dzhik1);
+                const SmagFace<T> tv = smag_v_zface<T>(es, ec, ets, et, vt_, vc, wt_, wts, dyi, dzhik1);
+                const T tw = smag_w_zcenter<T>(ec, wt_, wc);
+                o0[n] = TT[0][n] + smag_uv_total<T>(smag_u_xy<T>(uc, ue, uw, un, us, vn, vnw, vc, vw, ec, ew, en,
+                                                                 enw, es, esw, dxi, dyi),
+                                                    tu, BU[n], dzik);
+                o1[n] = TT[1][n] + smag_uv_total<T>(smag_v_xy<T>(vc, ve, vw, vn, vs, ue, use, uc, us, ec, es, ee,
+                                                                 ese, ew, esw, dxi, dyi),
+                                                    tv, BV[n], dzik);
+                o2[n] = TT[2][n] + smag_w_total<T>(smag_w_xy<T>(wc, we, ww, wn, ws, ue, b.ue, uc, b.u, vn, b.vn, vc,
+                                                                b.v, ec, b.e, ee, b.ee, ew, b.ew, en, b.en, es, b.es,
+                                                                dxi, dyi, dzhik),
+                                                   tw, BW[n], dzik, dzikm1, dzhik);
+                BU[n] = tu;
+                BV[n] = tv;
+                BW[n] = tw;
+                L[n] = {uc, ue, vc, vn, ec, ew, ee, es, en};
+            }
+            // the arithmetic only feeds the predicated stores: its loaded
+            // operands are marked as read on every path
+#pragma unroll
+            for (int f = 0; f < 3; ++f) settle(TT[f]);
+            if (own && lane_on) {
+                tstore<NT, T, VX>(boff(a.ut + row_c + (int64_t)k * ks, o_pt), o0);
+                tstore<NT, T, VX>(boff(a.vt + row_c + (int64_t)k * ks, o_pt), o1);
+                if (k >= a.kw0) tstore<NT, T, VX>(boff(a.wt + row_c + (int64_t)k * ks, o_pt), o2);
+            }
+        }
+
+        store_plane(p, bm);                  // level k+2 (loaded a level ago) over level k-1
+        const int t = bm;
+        bm = bc;
+        bc = bp;
+        bp = t;
+        }
+    }
+}
+
+
 }  // namespace kl

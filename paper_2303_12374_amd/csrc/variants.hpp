@@ -204,7 +204,7 @@ hipError_t launch_advec5_zr(const HostArgs &h, hipStream_t s)
     return hipGetLastError();
 }
 
-template <typename T, int VX, int BY, int KB, int XCD, int NT = 0, int WPE = 1>
+template <typename T, int VX, int BY, int KB, int XCD, int NT = 0, int WPE = 1, int RING = 0>
 hipError_t launch_smag_zl(const HostArgs &h, hipStream_t s)
 {
     StencilArgs<T> a = device_args<T>(h);
@@ -213,7 +213,10 @@ hipError_t launch_smag_zl(const HostArgs &h, hipStream_t s)
     a.nbz = (int)cdivu(h.ktot, KB);
     const uint64_t nb = (uint64_t)a.nbx * a.nby * a.nbz;
     if (!grid_fits(nb, 64 * BY)) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((diff_smag_zl<T, VX, BY, KB, XCD, NT, WPE>), dim3((unsigned)nb), dim3(64, BY), 0, s, a);
+    if constexpr (RING)
+        hipLaunchKernelGGL((diff_smag_zr<T, VX, BY, KB, XCD, NT, WPE>), dim3((unsigned)nb), dim3(64, BY), 0, s, a);
+    else
+        hipLaunchKernelGGL((diff_smag_zl<T, VX, BY, KB, XCD, NT, WPE>), dim3((unsigned)nb), dim3(64, BY), 0, s, a);
     return hipGetLastError();
 }
 
@@ -391,6 +394,12 @@ hipError_t launch_smag_zl(const HostArgs &h, hipStream_t s)
     Variant{"s2_v" KL_STR(VX) "_b64x" KL_STR(BY) "_k" KL_STR(KB) "_x" KL_STR(XCD) "_nt" KL_STR(NT),        \
             KL_KERNEL_DIFF_SMAG, DT, FAMILY_ZL, VX, 64, BY, KB, XCD,                                       \
             &launch_smag_zl<T, VX, BY, KB, XCD, NT>, nullptr, nullptr}
+
+// diff_smag with the parity-slot march, named s2r_v<VX>_b64x<BY>_k<KB>_x<XCD>_nt<NT>.
+#define KL_S2R(T, DT, VX, BY, KB, XCD, NT)                                                                  \
+    Variant{"s2r_v" KL_STR(VX) "_b64x" KL_STR(BY) "_k" KL_STR(KB) "_x" KL_STR(XCD) "_nt" KL_STR(NT),       \
+            KL_KERNEL_DIFF_SMAG, DT, FAMILY_ZL, VX, 64, BY, KB, XCD,                                       \
+            &launch_smag_zl<T, VX, BY, KB, XCD, NT, 1, 1>, nullptr, nullptr}
 
 // diff_uvw split into per-component passes, named zl3_v<VX>_b64x<BY>_k<KB>_x<XCD>_nt<NT>.
 #define KL_ZL3(T, DT, VX, BY, KB, XCD, NT)                                                                  \

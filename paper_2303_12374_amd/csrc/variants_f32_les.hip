@@ -83,7 +83,11 @@ void add_variants_f32_les(int kernel, std::vector<Variant> &out)
         KL_S2(float, KL_F32, 1, 8, 16, 0, 0),
         KL_S2(float, KL_F32, 2, 2, 64, 2, 1),
         KL_S2(float, KL_F32, 4, 8, 64, 2, 1),
-        KL_S2(float, KL_F32, 4, 8, 128, 2, 1)};
+        KL_S2(float, KL_F32, 4, 8, 128, 2, 1),
+        KL_S2R(float, KL_F32, 4, 8, 64, 2, 1),
+        KL_S2R(float, KL_F32, 4, 8, 128, 2, 1),
+        KL_S2R(float, KL_F32, 2, 8, 64, 2, 1),
+        KL_S2R(float, KL_F32, 1, 8, 64, 2, 1)};
         out.insert(out.end(), v.begin(), v.end());
     }
 }

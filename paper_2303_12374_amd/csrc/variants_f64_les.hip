@@ -56,7 +56,8 @@ void add_variants_f64_les(int kernel, std::vector<Variant> &out)
         KL_S2(double, KL_F64, 1, 16, 64, 2, 1),
         KL_S2(double, KL_F64, 1, 8, 16, 0, 0),
         KL_S2(double, KL_F64, 2, 8, 64, 2, 1),
-        KL_S2(double, KL_F64, 2, 8, 128, 2, 1)};
+        KL_S2(double, KL_F64, 2, 8, 128, 2, 1),
+        KL_S2R(double, KL_F64, 1, 8, 64, 2, 1)};
         out.insert(out.end(), v.begin(), v.end());
     }
 }

@@ -296,7 +296,9 @@ def a5r_spans(itot, jtot, ktot, vx, by, kb, off, js, ks, esize):
 
 def s2_spans(itot, jtot, ktot, vx, by, kb, off, js, ks):
     """diff_smag tiles: rows from a wave-uniform row start (column 0) plus a
-    per-lane offset."""
+    per-lane offset.  The parity-slot tile (s2r) loads the same rows over
+    the same levels (its prefetch of level k+3 is clamped to k1 as the
+    s2 tile's of level k+2), so this span covers both."""
     sp = Span()
     nh = (8 + by - 1) // by
     r = np.arange(by)[:, None]
