@@ -216,10 +216,16 @@ __device__ __forceinline__ void diff_uvw_zl_tile(const StencilArgs<T> &a, int tx
 // per field one scalar load carries the x-edge values (u: left in lane 0,
 // right in the last active lane or lane 1; v: the own row's left value in
 // lane 0, the top halo row's in lane 1; w: left in lane 0).
-template <typename T, int VX, int BY, int KB, int NT>
+template <typename T, int VX, int BY, int KB, int NT, int WPE = 1>
 __device__ __forceinline__ void advec_u_zl_tile(const StencilArgs<T> &a, int tx, int ty, int tz)
 {
     static_assert(BY >= 2, "two halo rows need two waves");
+    // Every wave and lane writes LDS and computes (ALL) only where the
+    // launch's register cap (512 / the waves per SIMD it needs) is above 128
+    // per lane: at 128 the longer live ranges spill, and the predicated form
+    // is kept there.
+    constexpr int NW = BY / 4 > WPE ? BY / 4 : WPE;
+    constexpr bool ALL = 512 / NW > 128;
     constexpr int TX = 64 * VX;
     typedef T RowT[TX];
     __shared__ __align__(16) RowT shu[2][BY + 3];  // u rows j0-1 .. j0+nv; row BY+2 is a spare
@@ -292,10 +298,6 @@ __device__ __forceinline__ void advec_u_zl_tile(const StencilArgs<T> &a, int tx,
             fload<NT, T, VX>(wnx, W + c_own + l3);
             EW[(s + 3) & 3] = W[c_ew + l3];
             fload<NT, T, VX>(RV[q], V + c_own + l1);
-            // Q[q] still holds the values stored a level ago: reading them here
-            // keeps those registers out of the allocator's hands until this
-            // reload, so no other write to them has to wait for that store
-            settle(Q[q]);
             tload<NT, T, VX>(Q[q], a.ut + c_own + l1);
             vload<T, VX>(XU[q], U + c_x + l1);
             vload<T, VX>(XV[q], V + c_x + l1);
@@ -308,11 +310,24 @@ __device__ __forceinline__ void advec_u_zl_tile(const StencilArgs<T> &a, int tx,
             // predicated: a loaded value consumed on one path only makes the
             // compiler wait for all loads in flight where its register is
             // next written, which undoes the prefetch.
-            vstore<T, VX>(&shu[p][orow][t.lane * VX], uc);
-            vstore<T, VX>(&shv[p][orow][t.lane * VX], RV[p]);
-            vstore<T, VX>(&shu[p][xrow][t.lane * VX], XU[p]);
-            vstore<T, VX>(&shv[p][xvrow][t.lane * VX], XV[p]);
-            shvl[p][evslot] = EV[p];
+            if constexpr (ALL) {
+                vstore<T, VX>(&shu[p][orow][t.lane * VX], uc);
+                vstore<T, VX>(&shv[p][orow][t.lane * VX], RV[p]);
+                vstore<T, VX>(&shu[p][xrow][t.lane * VX], XU[p]);
+                vstore<T, VX>(&shv[p][xvrow][t.lane * VX], XV[p]);
+                shvl[p][evslot] = EV[p];
+            } else {
+                if (t.own) {
+                    vstore<T, VX>(&shu[p][t.r + 1][t.lane * VX], uc);
+                    vstore<T, VX>(&shv[p][t.r + 1][t.lane * VX], RV[p]);
+                    if (t.lane == 0) shvl[p][t.r + 1] = EV[p];
+                }
+                if (t.xrow_l >= 0) vstore<T, VX>(&shu[p][t.xrow_l][t.lane * VX], XU[p]);
+                if (x_is_top) {
+                    vstore<T, VX>(&shv[p][t.xrow_l][t.lane * VX], XV[p]);
+                    if (t.lane == 1) shvl[p][t.xrow_l] = EV[p];
+                }
+            }
             __syncthreads();
             T un[VX], us[VX], vn[VX];
             vload<T, VX>(un, &shu[p][t.r + 2][t.lane * VX]);
@@ -335,7 +350,7 @@ __device__ __forceinline__ void advec_u_zl_tile(const StencilArgs<T> &a, int tx,
                 wtleft = EW[(s + 1) & 3];
             }
             if (t.lane == t.nlanes - 1) uright = ur;
-            {
+            if (ALL || ld_own) {
                 const T dzik = kload(a.dzi, k);
 #pragma unroll
                 for (int n = 0; n < VX; ++n) {
@@ -349,15 +364,17 @@ __device__ __forceinline__ void advec_u_zl_tile(const StencilArgs<T> &a, int tx,
                                                          RV[p][n], v_nw, vn[n], w_w, wc[n], w_tw, wt[n], dxi,
                                                          dyi, dzik);
                 }
-                // the compiler sinks this arithmetic into the predicated store:
-                // its loaded operands are marked as read on every path
-                settle(Q[p]);
-                settle(ub);
-                settle(ut_);
-                settle(wc);
-                settle(wt);
-                const T ew2[3] = {EU[p], EW[s & 3], EW[(s + 1) & 3]};
-                settle(ew2);
+                if constexpr (ALL) {
+                    // the compiler sinks this arithmetic into the predicated
+                    // store: its loaded operands are marked as read on every path
+                    settle(Q[p]);
+                    settle(ub);
+                    settle(ut_);
+                    settle(wc);
+                    settle(wt);
+                    const T ew2[3] = {EU[p], EW[s & 3], EW[(s + 1) & 3]};
+                    settle(ew2);
+                }
                 if (ld_own) tstore<NT, T, VX>(a.ut + c_own + (int64_t)k * ks, Q[p]);
             }
             fload<NT, T, VX>(ub, U + c_own + l3);
@@ -380,7 +397,7 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_zl(StencilArgs<T> a)
 {
     int tx, ty, tz;
     tile_of<64, BY, XCD>(a.nbx, a.nby, a.nbz, tx, ty, tz);
-    advec_u_zl_tile<T, VX, BY, KB, NT>(a, tx, ty, tz);
+    advec_u_zl_tile<T, VX, BY, KB, NT, WPE>(a, tx, ty, tz);
 }
 
 // Next tile of a block in a persistent walk over a tile list (prev = -1 for
@@ -436,7 +453,7 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_zl_batch(const StencilAr
     for (int n = next_tile(queue, -1); n < ntiles; n = next_tile(queue, n)) {
         const int4 tl = tiles[n];
         const StencilArgs<T> a = global_args(grids[tl.x]);
-        advec_u_zl_tile<T, VX, BY, KB, NT>(a, tl.y, tl.z, tl.w);
+        advec_u_zl_tile<T, VX, BY, KB, NT, WPE>(a, tl.y, tl.z, tl.w);
     }
     walk_done(queue);
 }
