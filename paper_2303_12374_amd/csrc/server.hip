@@ -94,6 +94,27 @@ struct DevBuf {
     }
 };
 
+// Pinned host memory that kernels write directly (the checksums of the
+// requests a tick finishes), grown on demand.
+struct PinBuf {
+    double *h = nullptr;
+    size_t cap = 0;  // doubles
+    ~PinBuf()
+    {
+        if (h) (void)hipHostFree(h);
+    }
+    hipError_t ensure(size_t n)
+    {
+        if (n <= cap) return hipSuccess;
+        if (h) (void)hipHostFree(h);
+        h = nullptr;
+        cap = std::max(n, (size_t)4096) * 2;
+        hipError_t e = hipHostMalloc((void **)&h, cap * sizeof(double), hipHostMallocDefault);
+        if (e != hipSuccess) cap = 0;
+        return e;
+    }
+};
+
 // The served form's device work (the executor of served::Server): request
 // set-up, one persistent fused-step launch per configuration group per tick,
 // FP64 checksums of finished requests, and one event per tick slot, all on
@@ -103,6 +124,13 @@ struct GpuExec {
     hipStream_t stream = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};
     DevBuf tab[2];  // per-tick tables (descriptors, tiles), one per tick in flight
+    // Checksums of the requests a tick finishes, written by the reduction's
+    // last pass straight into pinned host memory of the tick's slot (reused
+    // only after that tick has completed), so that publishing a finished
+    // request takes no copy or synchronisation of its own.
+    PinBuf sums[2];
+    int cur_slot = 0;
+    std::unordered_map<const Req *, const double *> pending;
     std::map<const Variant *, int> occ;  // resident blocks per CU of batched kernels
     // work queue of the persistent step kernels (two device ints): the kernels
     // run one after another on the server stream, and each returns it to zero
@@ -196,6 +224,7 @@ struct GpuExec {
     // slot `slot`, which the previous use has released.
     int run_tick(int slot, const std::vector<Req *> &act, int64_t *launches)
     {
+        cur_slot = slot;
         std::vector<StencilArgs<float>> df;
         std::vector<StencilArgs<double>> dd;
         std::vector<int> didx(act.size()), sel(act.size());
@@ -302,10 +331,16 @@ struct GpuExec {
         if (done.empty()) return KL_OK;
         void *ws = workspace(reduce_scratch_bytes(), stream);
         if (!ws) return fail(KL_ERR_NOMEM, "server workspace");
-        for (Req *q : done) {
+        PinBuf &pb = sums[cur_slot];
+        const hipError_t ea = pb.ensure(9 * done.size());
+        if (ea != hipSuccess) return hip_fail(ea, "checksum buffer");
+        for (size_t n = 0; n < done.size(); ++n) {
+            Req *q = done[n];
             void *const *cur = q->f + 3 * q->cur;
-            const hipError_t e = launch_reduce(make_args(&q->g), 1, cur[0], cur[1], cur[2], q->d_sum, ws, stream);
+            double *out = pb.h + 9 * n;
+            const hipError_t e = launch_reduce(make_args(&q->g), 1, cur[0], cur[1], cur[2], out, ws, stream);
             if (e != hipSuccess) return hip_fail(e, "checksum");
+            pending[q] = out;
             ++*launches;
         }
         return KL_OK;
@@ -325,8 +360,12 @@ struct GpuExec {
 
     int fetch_checksum(Req &q)
     {
-        const hipError_t e = hipMemcpy(q.checksum, q.d_sum, 9 * sizeof(double), hipMemcpyDeviceToHost);
-        return e == hipSuccess ? KL_OK : hip_fail(e, "checksum copy");
+        auto it = pending.find(&q);
+        if (it == pending.end()) return fail(KL_ERR_INVALID, "no checksum pending for request %llu",
+                                             (unsigned long long)q.ticket);
+        memcpy(q.checksum, it->second, 9 * sizeof(double));
+        pending.erase(it);
+        return KL_OK;
     }
 };
 
