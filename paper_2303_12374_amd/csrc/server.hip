@@ -163,7 +163,7 @@ struct GpuExec {
     {
         kl_layout(q.itot, q.jtot, q.ktot, q.dtype, off, js, ks, alloc);
         const size_t s = q.dtype == KL_F32 ? 4 : 8;
-        return 6 * round_up((size_t)*alloc * s) + 2 * round_up((size_t)(q.ktot + 2) * s) + ALIGN;
+        return 6 * round_up((size_t)*alloc * s) + 2 * round_up((size_t)(q.ktot + 2) * s);
     }
 
     // Lay out an admitted request in its arena block and queue its initial state.
@@ -180,8 +180,6 @@ struct GpuExec {
         char *dzi = p;
         p += round_up((size_t)(q.r.ktot + 2) * s);
         char *dzhi = p;
-        p += round_up((size_t)(q.r.ktot + 2) * s);
-        q.d_sum = (double *)p;
         std::vector<double> mi, mhi;
         double dzmin;
         served_metrics(q.r, mi, mhi, &dzmin);

@@ -103,7 +103,6 @@ struct Req {
     double dt = 0;
     kl_grid_t g;
     void *f[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-    double *d_sum = nullptr;
     double checksum[9];
     std::vector<char> metrics;  // host copy of dzi | dzhi in the field dtype
 };

@@ -70,7 +70,6 @@ struct FakeExec {
         q.f[0] = block;
         q.g.off = 0;
         q.checksum[0] = 0;
-        q.d_sum = (double *)nullptr;
         q.dt = 0.1;
         return KL_OK;
     }

@@ -198,7 +198,7 @@ def test_budget_admission_and_errors():
     m = kl()
     small = (32, 32, 16, 0, 0, 2, 1e-3, 1e-5, 1)
     off, js, ks, alloc = m.kl_layout(32, 32, 16, 0)
-    one = 6 * ((alloc * 4 + 255) // 256 * 256) + 2 * 256 + 256
+    one = 6 * ((alloc * 4 + 255) // 256 * 256) + 2 * 256
     S = Server(arena_bytes=64 << 20, budget=int(one * 1.5))
     try:
         with pytest.raises(m.KLError) as e:
