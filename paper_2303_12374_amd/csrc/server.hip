@@ -177,9 +177,9 @@ struct GpuExec {
             q.f[n] = p;
             p += round_up((size_t)alloc * s);
         }
+        // dzi and dzhi back to back, as in the host copy: one upload
         char *dzi = p;
-        p += round_up((size_t)(q.r.ktot + 2) * s);
-        char *dzhi = p;
+        char *dzhi = p + (size_t)(q.r.ktot + 2) * s;
         std::vector<double> mi, mhi;
         double dzmin;
         served_metrics(q.r, mi, mhi, &dzmin);
@@ -208,8 +208,7 @@ struct GpuExec {
         q.g.dtype = q.r.dtype;
         q.g.bc = q.r.bc;
         q.dt = q.r.dt > 0 ? q.r.dt : 0.1 * std::min(std::min(1.0 / q.r.itot, 1.0 / q.r.jtot), dzmin);
-        hipError_t e = hipMemcpyAsync(dzi, q.metrics.data(), kc * s, hipMemcpyHostToDevice, stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(dzhi, q.metrics.data() + kc * s, kc * s, hipMemcpyHostToDevice, stream);
+        hipError_t e = hipMemcpyAsync(dzi, q.metrics.data(), 2 * kc * s, hipMemcpyHostToDevice, stream);
         HostArgs a = make_args(&q.g);
         if (e == hipSuccess) e = launch_gen_uniform(a, q.r.seed, q.f[0], q.f[1], q.f[2], stream);
         if (e == hipSuccess) e = launch_fill_ghosts(a, q.f[0], q.f[1], q.f[2], stream);
