@@ -546,9 +546,10 @@ __global__ __launch_bounds__(64 * BY, WPE) void advec_u_2i5_zlp(StencilArgs<T> a
 
 namespace kl {
 
-// The tile of advec_u_2i5_zl with its level loop unrolled by two and every
-// value loaded ahead held in a slot chosen by the level's parity at compile
-// time, so no register is copied at the end of a level:
+// The tile of advec_u_2i5_zl with its level loop unrolled by two (by the
+// halo ring's period when HL > 1, below) and every value loaded ahead held
+// in a slot chosen by the level's parity at compile time, so no register is
+// copied at the end of a level:
 //   * level k+1's rows, the edge values, w at k+2 and ut at k+1 are loaded
 //     during level k into the other parity's slots; the u window's next top
 //     level (k+5) is loaded two levels before it enters the window;
